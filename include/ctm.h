@@ -1,0 +1,197 @@
+/*
+ * ctm.h -- C ABI of the MI355X library for the parallel-in-time sparse-grid
+ * combination method (Griebel, Schweitzer, Troska, "A Parallel-in-Time
+ * Combination Method for Parabolic Problems").
+ *
+ * The library solves u_t + L u = 0 on a box Omega in d dimensions by the
+ * combination technique (Section 2.1.1): every anisotropic component grid
+ * Omega_l, |l|_1 = n + d - 1 - w, is advanced in time by backward Euler,
+ * Phi = (I + dt L_l)^-1 (Section 2, time propagation), with MGRIT over each
+ * recombination block (Section 2.3.1, Algorithm 2; Algorithm 3), and the
+ * component solutions are combined with the coefficients
+ * (-1)^w binom(d-1, w). Every implicit step is solved matrix-free by CG
+ * (symmetric L) or BiCGStab (Section 4.1).
+ *
+ * Conventions for every entry point:
+ *  - All floating-point data is IEEE float64. Device pointers must point to
+ *    memory of the device that was current when the plan was created.
+ *  - Packed state layout ("packed vector"): the component grids in canonical
+ *    order (layer w ascending, then the level vector l lexicographically),
+ *    each grid's unknowns contiguous, row-major with axis d-1 fastest.
+ *    Grid g starts at the offset returned by ctm_plan_grid_info; the total
+ *    length is ctm_plan_state_len.
+ *  - Unknowns: Dirichlet grids hold the 2^{l_i}-1 interior nodes
+ *    x = lo + J h, J = 1..2^{l_i}-1, h = (hi-lo)/2^{l_i}, per axis (Section
+ *    2.1.2). The master-equation lattice (CTM_OP_CME) holds 2^{l_i} states
+ *    x = lo + J h, J = 0..2^{l_i}-1, with hi - lo = 2^n.
+ *  - Asynchronous entry points enqueue work on the given stream and return;
+ *    their device outputs are valid after the stream is synchronised.
+ *    ctm_solve synchronises the stream (it reads a convergence scalar after
+ *    every MGRIT iteration).
+ *  - Errors are returned as ctm_status; ctm_last_error() gives a message for
+ *    the calling thread. No entry point throws or aborts. On an error no
+ *    output is guaranteed to be written, except CTM_ERR_NOCONV, which still
+ *    writes the last iterate.
+ *  - Ownership: the caller owns the problem struct, all host arrays it
+ *    points to (copied by ctm_plan_create), every device buffer passed in and
+ *    the stream. The plan owns small device tables allocated at creation.
+ *    A plan may be used from one host thread at a time.
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTM_MAXD 8          /* largest dimension d */
+#define CTM_MAX_IC_TERMS 16 /* largest number of product terms in u0 */
+#define CTM_MAX_HISTORY 256 /* residual history entries kept in ctm_stats */
+
+typedef struct ctm_plan ctm_plan;
+typedef struct ihipStream_t* ctm_stream; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  CTM_OK = 0,
+  CTM_ERR_INVALID = 1,   /* invalid argument or problem */
+  CTM_ERR_NOMEM = 2,     /* device or host allocation failed, or workspace too small */
+  CTM_ERR_HIP = 3,       /* a HIP runtime call failed */
+  CTM_ERR_NOCONV = 4,    /* Krylov, refinement or MGRIT did not converge */
+  CTM_ERR_BREAKDOWN = 5, /* BiCGStab breakdown (rho or (t,t) vanished) */
+  CTM_ERR_NONFINITE = 6  /* NaN or Inf met in a solve */
+} ctm_status;
+
+/* Spatial operator kinds, u_t + L u = 0 (Section 2; Sections 4.2-4.4). */
+typedef enum {
+  CTM_OP_HEAT = 0,    /* L = -Laplacian, (2d+1)-point stencil */
+  CTM_OP_VARCOEF = 1, /* L u = -div(a grad u), a = 1 + amp prod_k sin(2 pi x_k), face midpoints */
+  CTM_OP_OU = 2,      /* Fokker-Planck of dX = -theta X dt + sigma dW: central diffusion
+                         sigma^2/2, donor-cell drift fluxes with face velocity -theta_i x */
+  CTM_OP_CME = 3      /* immigration-death master equation per species on the lattice
+                         embedding: births +h at rate k_i/h (none at the last state),
+                         deaths -h at rate gamma_i x/h (Section 4.3) */
+} ctm_op_kind;
+
+typedef enum { CTM_PREC_FP64 = 0, CTM_PREC_MIXED = 1 } ctm_precision;
+typedef enum { CTM_KRYLOV_AUTO = 0, CTM_KRYLOV_CG = 1, CTM_KRYLOV_BICGSTAB = 2 } ctm_krylov;
+typedef enum { CTM_RELAX_F = 0, CTM_RELAX_FCF = 1 } ctm_relax;
+
+typedef struct {
+  int d;         /* 1..CTM_MAXD */
+  int level_n;   /* sparse-grid level n (the paper's L) */
+  int level_min; /* L0 >= 1: every l_i >= L0 (Section 2.1.1) */
+  double lo[CTM_MAXD], hi[CTM_MAXD]; /* Omega = prod [lo_i, hi_i] */
+  ctm_op_kind op;
+  double amp;                            /* CTM_OP_VARCOEF */
+  double theta[CTM_MAXD], sigma;         /* CTM_OP_OU */
+  double k[CTM_MAXD], gamma[CTM_MAXD];   /* CTM_OP_CME */
+  double t0, t1;                         /* time interval */
+  long long nsteps;                      /* N backward-Euler steps (uniform dt) */
+  int nrecomb;                           /* s >= 1 recombination blocks (Section 2.2.1) */
+  int mgrit_levels;                      /* 1 = time-sequential stepping, >= 2 MGRIT */
+  int mgrit_cf;                          /* coarsening factor c >= 2 */
+  ctm_relax relax;                       /* F or FCF relaxation */
+  double mgrit_tol;   /* stop when max over grids and C-points of ||r_m||_2 / ||u_start,g||_2 <= tol */
+  int mgrit_maxit;
+  ctm_krylov krylov;
+  double krylov_tol;  /* FP64 path: ||b - A x||_2 <= tol ||b||_2 per implicit step */
+  int krylov_maxit;   /* per solve (per refinement sweep in the mixed path) */
+  ctm_precision prec;
+  double refine_tol;  /* mixed path: FP64 residual target, relative to ||b||_2 */
+  double inner_tol;   /* mixed path: FP32 inner Krylov relative tolerance */
+  int refine_maxit;   /* mixed path: refinement sweeps per implicit step */
+  int ic_terms;       /* u0(x) = sum_r ic_weight[r] prod_i ic_factor[r][i][J_i] */
+  const double* ic_weight; /* host [ic_terms] */
+  const double* ic_factor; /* host [ic_terms][d][2^n + 1]: factor r on axis i at the finest
+                              1-D node x = lo_i + J (hi_i - lo_i) / 2^n, J = 0..2^n */
+} ctm_problem;
+
+typedef struct {
+  int blocks;                         /* recombination blocks run */
+  int mgrit_iterations;               /* total MGRIT iterations over all blocks */
+  int history_len;                    /* entries in mgrit_residual */
+  double mgrit_residual[CTM_MAX_HISTORY]; /* per iteration: max relative C-point residual */
+  long long phi_solves;               /* implicit solves (one per system per step) */
+  long long krylov_iterations;        /* Krylov iterations summed over all solves */
+  long long krylov_max;               /* largest Krylov count of one solve */
+  long long refine_sweeps;            /* refinement sweeps summed (mixed path) */
+  long long refine_max;               /* largest sweep count of one solve */
+  int status_flags;                   /* OR of (1 << ctm_status) met inside kernels */
+} ctm_stats;
+
+/* Fill *p with the paper's solver defaults (Section 4.1): two-level MGRIT,
+ * c = 2, FCF, tolerances 1e-8, CG, FP64, L0 = 1, s = 1, and the unit box. */
+ctm_status ctm_problem_defaults(ctm_problem* p);
+
+/* Validate *p, enumerate the component grids (Section 2.1.1, combination
+ * formula), build per-grid geometry and coefficient tables and upload them
+ * to the current device. Rejects: d outside 1..CTM_MAXD, n + d - 1 > 30,
+ * no grid with l >= L0, N not divisible by s * c^(levels-1), nonpositive
+ * tolerances, CG for a non-symmetric operator, a grid larger than the
+ * on-chip solver holds (8192 unknowns), lattice box with hi - lo != 2^n. */
+ctm_status ctm_plan_create(const ctm_problem* p, ctm_plan** plan);
+void ctm_plan_destroy(ctm_plan* plan);
+
+/* Number of component grids G. */
+ctm_status ctm_plan_grids(const ctm_plan* plan, int* G);
+/* Grid g (0 <= g < G): levels[d] (may be NULL), combination coefficient
+ * (-1)^w binom(d-1, w), offset in the packed vector, number of unknowns. */
+ctm_status ctm_plan_grid_info(const ctm_plan* plan, int g, int* levels, double* coef,
+                              long long* offset, long long* npoints);
+/* Length of a packed vector (sum of unknowns over all grids). */
+ctm_status ctm_plan_state_len(const ctm_plan* plan, long long* len);
+/* Bytes of device workspace ctm_solve needs (MGRIT state of all levels). */
+ctm_status ctm_plan_workspace_bytes(const ctm_plan* plan, size_t* bytes);
+
+/* u0_out[packed] = u0 sampled at the unknowns of every grid. Async. */
+ctm_status ctm_initial_state(ctm_plan* plan, double* u0_out, ctm_stream s);
+
+/* y = (I + dt_level L_l) x on every grid, dt_level = (t1-t0)/N * c^level
+ * (the system matrix of one backward-Euler step, Section 2). FP64. x and y
+ * are packed vectors and must not overlap. Async. */
+ctm_status ctm_apply(ctm_plan* plan, int level, const double* x, double* y, ctm_stream s);
+
+/* y = Phi_level^nsteps x on every grid: nsteps backward-Euler steps of size
+ * dt_level, all grids in one batched launch (time-sequential stepping,
+ * Algorithm 1 inside one block), with the plan's Krylov/precision setting.
+ * per_grid != 0 selects the plain reference schedule instead: one grid and
+ * one step per launch, FP64 regardless of the plan's precision. x == y is
+ * allowed. Async; returns CTM_ERR_NOCONV etc. only through ctm_get_stats
+ * status_flags (call after synchronising). */
+ctm_status ctm_propagate(ctm_plan* plan, int level, long long nsteps, const double* x, double* y,
+                         int per_grid, ctm_stream s);
+
+/* The whole method (Algorithm 3): for each of the s recombination blocks,
+ * MGRIT (or time-sequential stepping when mgrit_levels = 1) on every grid
+ * from the block's start state, then combine-and-project onto every grid
+ * before the next block (Section 2.2.2). u0 (packed, may be NULL = the
+ * problem's sampled initial value) is the start state; u_final receives the
+ * packed component states at t1. ws must hold ctm_plan_workspace_bytes.
+ * Synchronises s. Statistics are available through ctm_get_stats. */
+ctm_status ctm_solve(ctm_plan* plan, void* ws, size_t ws_bytes, const double* u0,
+                     double* u_final, ctm_stream s);
+
+/* Combination at arbitrary points (Section 2.1.1): out[j] = sum_g coef_g
+ * (I_g u_g)(pts[j]), I_g the d-linear interpolant on grid g with zero
+ * boundary values; pts is device [npts][d] row-major. Async. */
+ctm_status ctm_gather(ctm_plan* plan, const double* u, const double* pts, long long npts,
+                      double* out, ctm_stream s);
+
+/* Combine, then project onto every component grid (Section 2.2.2,
+ * combine-then-project operator): out[packed] = u^(c) at the unknowns of
+ * every grid. u and out must not overlap. Async. */
+ctm_status ctm_combine_project(ctm_plan* plan, const double* u, double* out, ctm_stream s);
+
+/* Statistics of the last ctm_solve / ctm_propagate (reset by each). */
+ctm_status ctm_get_stats(const ctm_plan* plan, ctm_stats* st);
+
+const char* ctm_status_string(ctm_status st);
+/* Message of the last error on the calling thread ("" if none). */
+const char* ctm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTM_H */

@@ -1,0 +1,347 @@
+// Auxiliary kernels: initial value sampling, standalone stencil apply,
+// combination gather / combine-then-project, norms and vector updates of
+// the MGRIT driver, and the dispatch of the chain kernel instantiations.
+#include "device_common.hpp"
+
+namespace ctm {
+
+hipError_t launch_chain_heat_cg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
+hipError_t launch_chain_heat_bicg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
+hipError_t launch_chain_sep_bicg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
+hipError_t launch_chain_var_cg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
+hipError_t launch_chain_var_bicg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
+
+hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
+                        int ntasks, size_t smem, int tabmax, hipStream_t s) {
+  if (opc == OPC_HEAT && solver == SOLV_CG)
+    return launch_chain_heat_cg(mixed, shape, a, ntasks, smem, tabmax, s);
+  if (opc == OPC_HEAT && solver == SOLV_BICG)
+    return launch_chain_heat_bicg(mixed, shape, a, ntasks, smem, tabmax, s);
+  if (opc == OPC_SEP && solver == SOLV_BICG)
+    return launch_chain_sep_bicg(mixed, shape, a, ntasks, smem, tabmax, s);
+  if (opc == OPC_VAR && solver == SOLV_CG)
+    return launch_chain_var_cg(mixed, shape, a, ntasks, smem, tabmax, s);
+  if (opc == OPC_VAR && solver == SOLV_BICG)
+    return launch_chain_var_bicg(mixed, shape, a, ntasks, smem, tabmax, s);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ initial value
+// u0 at the unknowns of grid blockIdx.y: sum_r w_r prod_i F[r][i][J_i], with
+// J_i = (j_i + j0) 2^{n - l_i} the index of the node on the finest 1-D grid.
+__global__ void initial_state_kernel(const GridDev* __restrict__ grids, int nlev, int terms,
+                                     const double* __restrict__ icw,
+                                     const double* __restrict__ icf, double* __restrict__ out) {
+  const GridDev& g = grids[blockIdx.y];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.npts) return;
+  const int F = (1 << nlev) + 1;
+  int J[MAXD];
+  int rem = p;
+#pragma unroll
+  for (int i = MAXD - 1; i >= 0; --i) {
+    J[i] = 0;
+    if (i < g.d) {
+      const int j = rem % g.n[i];
+      rem /= g.n[i];
+      J[i] = (j + g.j0) << (nlev - g.lev[i]);
+    }
+  }
+  double u = 0.0;
+  for (int r = 0; r < terms; ++r) {
+    double t = icw[r];
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i)
+      if (i < g.d) t *= icf[((size_t)r * g.d + i) * F + J[i]];
+    u += t;
+  }
+  out[g.off + p] = u;
+}
+
+hipError_t launch_initial_state(const GridDev* grids, int G, int maxpts, int nlev, int terms,
+                                const double* icw, const double* icf, double* out,
+                                hipStream_t s) {
+  dim3 grid((maxpts + 255) / 256, G);
+  hipLaunchKernelGGL(initial_state_kernel, grid, dim3(256), 0, s, grids, nlev, terms, icw, icf,
+                     out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- stencil apply
+// y = (I + dt L_l) x on every grid, one work-group per grid, FP64; the same
+// device stencil the Krylov solvers use.
+template <int OPC, int W, int K>
+__global__ void __launch_bounds__(64 * W)
+    apply_kernel(const GridDev* __restrict__ grids, const double* __restrict__ tab64, double amp,
+                 double dt, const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int BS = 64 * W;
+  constexpr int CAP = BS * K;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* xl = reinterpret_cast<double*>(smem);
+  double* tl = xl + CAP;
+  __shared__ GridDev gs;
+  {
+    const int* src = reinterpret_cast<const int*>(grids + blockIdx.x);
+    int* dst = reinterpret_cast<int*>(&gs);
+    for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += BS) dst[t] = src[t];
+  }
+  __syncthreads();
+  const GridDev& g = gs;
+  load_tables<OPC, double, BS>(g, tab64, dt, tl);
+  Pts<K> P;
+  setup_points<BS, K>(g, P);
+  double xs[K], ys[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    xs[k] = (P.p[k] >= 0) ? x[g.off + P.p[k]] : 0.0;
+    if (P.p[k] >= 0) xl[P.p[k]] = xs[k];
+  }
+  __syncthreads();
+  Stencil<OPC, double, K> S;
+  stencil_setup<OPC, double, K>(g, P, dt, amp, tl, S);
+  stencil_apply<OPC, double, K>(g, P, S, tl, xl, xs, ys);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (P.p[k] >= 0) y[g.off + P.p[k]] = ys[k];
+}
+
+template <int OPC>
+static hipError_t launch_apply_t(int shape, const GridDev* grids, int G, const double* tab64,
+                                 double amp, double dt, int tabmax, const double* x, double* y,
+                                 hipStream_t s) {
+  const size_t smem = (size_t)(64 * kShapes[shape].W * kShapes[shape].K + tabmax) * sizeof(double);
+#define CTM_ACASE(IDX, W, K)                                                                   \
+  case IDX:                                                                                    \
+    hipLaunchKernelGGL((apply_kernel<OPC, W, K>), dim3(G), dim3(64 * W), smem, s, grids, tab64, \
+                       amp, dt, x, y);                                                         \
+    break;
+  switch (shape) {
+    CTM_ACASE(0, 1, 1)
+    CTM_ACASE(1, 1, 2)
+    CTM_ACASE(2, 1, 4)
+    CTM_ACASE(3, 2, 4)
+    CTM_ACASE(4, 4, 4)
+    CTM_ACASE(5, 4, 8)
+    CTM_ACASE(6, 8, 8)
+    CTM_ACASE(7, 16, 8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CTM_ACASE
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(int opc, int shape, const GridDev* grids, int G, const double* tab64,
+                        double amp, double dt, int tabmax, const double* x, double* y,
+                        hipStream_t s) {
+  if (G <= 0) return hipSuccess;
+  switch (opc) {
+    case OPC_HEAT:
+      return launch_apply_t<OPC_HEAT>(shape, grids, G, tab64, amp, dt, tabmax, x, y, s);
+    case OPC_SEP:
+      return launch_apply_t<OPC_SEP>(shape, grids, G, tab64, amp, dt, tabmax, x, y, s);
+    case OPC_VAR:
+      return launch_apply_t<OPC_VAR>(shape, grids, G, tab64, amp, dt, tabmax, x, y, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// --------------------------------------------------------------- gather
+// (I_g u_g)(x): d-linear interpolation on grid g with zero values at the
+// Dirichlet boundary nodes and at the implicit node hi of a lattice axis.
+__device__ double interp_grid(const GridDev& g, const double* __restrict__ u, const double* x) {
+  int base = 0;
+  int cidx[MAXD];
+  double w[MAXD];
+  unsigned ok0 = 0, ok1 = 0;  // corner 0 / corner 1 along axis i is an unknown
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) {
+    cidx[i] = 0;
+    w[i] = 0.0;
+    if (i < g.d) {
+      const double t = (x[i] - g.lo[i]) / g.h[i];
+      const int top = (1 << g.lev[i]) - 1;
+      int J = (int)floor(t);
+      J = J < 0 ? 0 : (J > top ? top : J);
+      w[i] = t - (double)J;
+      const int u0i = J - g.j0;
+      cidx[i] = u0i;
+      if (u0i >= 0 && u0i < g.n[i]) ok0 |= 1u << i;
+      if (u0i + 1 >= 0 && u0i + 1 < g.n[i]) ok1 |= 1u << i;
+      base += u0i * g.stride[i];
+    }
+  }
+  double acc = 0.0;
+  const int ncorner = 1 << g.d;
+  for (int c = 0; c < ncorner; ++c) {
+    double wt = 1.0;
+    int idx = base;
+    bool valid = true;
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i) {
+      if (i < g.d) {
+        const int bit = (c >> (g.d - 1 - i)) & 1;
+        wt *= bit ? w[i] : 1.0 - w[i];
+        idx += bit * g.stride[i];
+        valid = valid && (((bit ? ok1 : ok0) >> i) & 1u);
+      }
+    }
+    if (valid && wt != 0.0) acc += wt * u[g.off + idx];
+  }
+  return acc;
+}
+
+__global__ void gather_kernel(const GridDev* __restrict__ grids, int G,
+                              const double* __restrict__ u, const double* __restrict__ pts,
+                              long long npts, double* __restrict__ out) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npts) return;
+  const int d = grids[0].d;
+  double x[MAXD];
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) x[i] = (i < d) ? pts[j * d + i] : 0.0;
+  double acc = 0.0;
+  for (int gi = 0; gi < G; ++gi) {
+    const GridDev& g = grids[gi];
+    acc += g.coef * interp_grid(g, u, x);
+  }
+  out[j] = acc;
+}
+
+hipError_t launch_gather(const GridDev* grids, int G, const double* u, const double* pts,
+                         long long npts, double* out, hipStream_t s) {
+  if (npts <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, grids,
+                     G, u, pts, npts, out);
+  return hipGetLastError();
+}
+
+// Combine-then-project: the combination evaluated at the unknowns of every
+// grid (packed index -> grid by binary search over the offsets).
+__global__ void project_kernel(const GridDev* __restrict__ grids,
+                               const long long* __restrict__ offsets, int G, long long slen,
+                               const double* __restrict__ u, double* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= slen) return;
+  int lo = 0, hi = G - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  const GridDev& tg = grids[lo];
+  int rem = (int)(e - tg.off);
+  double x[MAXD];
+#pragma unroll
+  for (int i = MAXD - 1; i >= 0; --i) {
+    x[i] = 0.0;
+    if (i < tg.d) {
+      const int j = rem % tg.n[i];
+      rem /= tg.n[i];
+      x[i] = tg.lo[i] + (double)(j + tg.j0) * tg.h[i];
+    }
+  }
+  double acc = 0.0;
+  for (int gi = 0; gi < G; ++gi) {
+    const GridDev& g = grids[gi];
+    acc += g.coef * interp_grid(g, u, x);
+  }
+  out[e] = acc;
+}
+
+hipError_t launch_project(const GridDev* grids, const long long* offsets, int G, long long slen,
+                          const double* u, double* out, hipStream_t s) {
+  if (slen <= 0) return hipSuccess;
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)((slen + 255) / 256)), dim3(256), 0, s, grids,
+                     offsets, G, slen, u, out);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- reductions
+__global__ void __launch_bounds__(256)
+    grid_norms2_kernel(const GridDev* __restrict__ grids, const double* __restrict__ u,
+                       double* __restrict__ out) {
+  __shared__ double slots[2 * 64];
+  const GridDev& g = grids[blockIdx.x];
+  double s = 0.0;
+  for (int p = threadIdx.x; p < g.npts; p += 256) {
+    const double v = u[g.off + p];
+    s += v * v;
+  }
+  double v[1] = {s};
+  RedRing ring{slots, 0};
+  block_sum<4, 1, double>(v, ring);
+  if (threadIdx.x == 0) out[blockIdx.x] = v[0];
+}
+
+hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, double* out,
+                              hipStream_t s) {
+  if (G <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grid_norms2_kernel, dim3(G), dim3(256), 0, s, grids, u, out);
+  return hipGetLastError();
+}
+
+// out[0] = max over tasks t of sqrt(res2[t] / norm2[grid(t)]) (norm2 = 0 -> 1).
+__global__ void __launch_bounds__(256)
+    residual_max_kernel(const int2* __restrict__ tasks, int ntasks,
+                        const double* __restrict__ res2, const double* __restrict__ norm2,
+                        double* __restrict__ out) {
+  __shared__ double part[256];
+  double m = 0.0;
+  for (int t = threadIdx.x; t < ntasks; t += 256) {
+    const double n2 = norm2[tasks[t].x];
+    const double r = sqrt(res2[t] / (n2 > 0.0 ? n2 : 1.0));
+    m = (r > m || r != r) ? r : m;
+  }
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double a = part[threadIdx.x], b = part[threadIdx.x + w];
+      part[threadIdx.x] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0];
+}
+
+hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
+                               const double* norm2, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(residual_max_kernel, dim3(1), dim3(256), 0, s, tasks, ntasks, res2, norm2,
+                     out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ vector ops
+__global__ void vec_add_kernel(VecRef dst, VecRef x, VecRef y, long long slen) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= slen) return;
+  const long long q = blockIdx.y;
+  double v = x.base[(x.a * q + x.b) * slen + e];
+  if (y.base) v += y.base[(y.a * q + y.b) * slen + e];
+  dst.base[(dst.a * q + dst.b) * slen + e] = v;
+}
+
+hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
+                          hipStream_t s) {
+  if (nvec <= 0 || slen <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vec_add_kernel, dim3((unsigned)((slen + 255) / 256), nvec), dim3(256), 0, s,
+                     dst, x, y, slen);
+  return hipGetLastError();
+}
+
+__global__ void fill_zero_kernel(double* p, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    p[e] = 0.0;
+}
+
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace ctm

@@ -1,0 +1,841 @@
+// Host side of the library: problem validation, enumeration of the
+// combination index set, per-grid geometry and coefficient tables, the
+// MGRIT driver and the C entry points declared in ctm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ctm_internal.h"
+
+using namespace ctm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ctm_status fail(ctm_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define CTM_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(CTM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+struct GridHost {
+  int lev[MAXD];
+  int w;
+  double coef;
+  long long npts, off;
+  double cost;
+};
+
+// All compositions of `total` into `parts` integers >= lmin, lexicographic.
+void compositions(int total, int parts, int lmin, std::vector<int>& cur,
+                  std::vector<std::vector<int>>& out) {
+  if (parts == 1) {
+    if (total >= lmin) {
+      cur.push_back(total);
+      out.push_back(cur);
+      cur.pop_back();
+    }
+    return;
+  }
+  for (int first = lmin; first <= total - lmin * (parts - 1); ++first) {
+    cur.push_back(first);
+    compositions(total - first, parts - 1, lmin, cur, out);
+    cur.pop_back();
+  }
+}
+
+long long binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+}  // namespace
+
+struct ctm_plan {
+  ctm_problem prob;
+  std::vector<double> icw, icf;
+  int d = 0, n = 0, G = 0;
+  long long slen = 0;
+  int maxpts = 0;
+  bool lattice = false;
+  int opc = OPC_HEAT, solver = SOLV_CG;
+  bool mixed = false;
+  int shape = 0;
+  int tabmax = 0;
+  size_t smem_chain = 0;
+  std::vector<GridHost> grids;
+  std::vector<GridDev> hdev;
+  std::vector<double> htab;
+  std::vector<int> order;  // grid indices by decreasing estimated cost
+  int device = 0;
+  // device data owned by the plan
+  GridDev* dgrids = nullptr;
+  double* dtab = nullptr;
+  long long* doffsets = nullptr;
+  double* dicw = nullptr;
+  double* dicf = nullptr;
+  unsigned long long* dcounters = nullptr;
+  double* dsync = nullptr;    // [0] residual max, [1] status word (int in low bytes)
+  double* dnorm2 = nullptr;   // [G]
+  double* hsync = nullptr;    // pinned mirror of dsync
+  int2* dsingle = nullptr;    // (g, 0) in cost order
+  int2* didentity = nullptr;  // (g, 0) in canonical order
+  std::map<long long, int2*> interval_tasks;  // M -> (g, q) tasks
+  ctm_stats stats;
+
+  ~ctm_plan() {
+    hipFree(dgrids);
+    hipFree(dtab);
+    hipFree(doffsets);
+    hipFree(dicw);
+    hipFree(dicf);
+    hipFree(dcounters);
+    hipFree(dsync);
+    hipFree(dnorm2);
+    hipFree(dsingle);
+    hipFree(didentity);
+    if (hsync) hipHostFree(hsync);
+    for (auto& kv : interval_tasks) hipFree(kv.second);
+  }
+};
+
+namespace {
+
+double level_dt(const ctm_plan* P, int level) {
+  double dt = (P->prob.t1 - P->prob.t0) / (double)P->prob.nsteps;
+  for (int l = 0; l < level; ++l) dt *= P->prob.mgrit_cf;
+  return dt;
+}
+
+// Coefficient tables of one grid. SEP (OU, CME): per axis the 1-D rows
+// (Lo, D, Up) of L, unscaled; VAR: per axis the node sines sin(2 pi x_j)
+// and the face sines sin(2 pi (x_j - h/2)), faces j = 0..n_i.
+void build_tables(ctm_plan* P, const GridHost& gh, GridDev& gd) {
+  const ctm_problem& p = P->prob;
+  gd.tab0 = (long long)P->htab.size();
+  int pos = 0;
+  for (int i = 0; i < P->d; ++i) {
+    const int ni = gd.n[i];
+    const double h = gd.h[i];
+    gd.tab[i] = pos;
+    if (P->opc == OPC_SEP) {
+      for (int part = 0; part < 3; ++part) {
+        for (int j = 0; j < ni; ++j) {
+          const double x = gd.lo[i] + (double)(j + gd.j0) * h;
+          double lo = 0, dg = 0, up = 0;
+          if (p.op == CTM_OP_OU) {
+            // flux form with donor-cell drift, face velocity w = -theta x
+            const double th = p.theta[i], D = 0.5 * p.sigma * p.sigma;
+            const double wu = -th * (x + 0.5 * h), wd = -th * (x - 0.5 * h);
+            dg = (std::max(wu, 0.0) - std::min(wd, 0.0)) / h + 2.0 * D / (h * h);
+            up = std::min(wu, 0.0) / h - D / (h * h);
+            lo = -std::max(wd, 0.0) / h - D / (h * h);
+          } else {
+            // immigration-death jump chain with spacing h; no births at the last state
+            const double k = p.k[i], gm = p.gamma[i];
+            const bool last = (j == ni - 1);
+            dg = (last ? 0.0 : k / h) + gm * x / h;
+            lo = -k / h;
+            up = -gm * (x + h) / h;
+          }
+          P->htab.push_back(part == 0 ? lo : (part == 1 ? dg : up));
+        }
+      }
+      pos += 3 * ni;
+    } else if (P->opc == OPC_VAR) {
+      for (int j = 0; j < ni; ++j) {
+        const double x = gd.lo[i] + (double)(j + gd.j0) * h;
+        P->htab.push_back(std::sin(2.0 * M_PI * x));
+      }
+      for (int j = 0; j <= ni; ++j) {
+        const double x = gd.lo[i] + ((double)(j + gd.j0) - 0.5) * h;
+        P->htab.push_back(std::sin(2.0 * M_PI * x));
+      }
+      pos += 2 * ni + 1;
+    }
+  }
+  gd.tabsz = pos;
+  (void)gh;
+}
+
+ctm_status validate(const ctm_problem* p) {
+  if (!p) return fail(CTM_ERR_INVALID, "problem is NULL");
+  if (p->d < 1 || p->d > CTM_MAXD) return fail(CTM_ERR_INVALID, "d must be in 1..8");
+  if (p->level_min < 1) return fail(CTM_ERR_INVALID, "level_min must be >= 1");
+  if (p->level_n < 1 || p->level_n + p->d - 1 > 30)
+    return fail(CTM_ERR_INVALID, "level_n must satisfy 1 <= n and n + d - 1 <= 30");
+  if (p->level_n + p->d - 1 < p->d * p->level_min)
+    return fail(CTM_ERR_INVALID, "no component grid with l >= level_min");
+  for (int i = 0; i < p->d; ++i)
+    if (!(p->hi[i] > p->lo[i])) return fail(CTM_ERR_INVALID, "box must have hi > lo");
+  if (p->op < CTM_OP_HEAT || p->op > CTM_OP_CME) return fail(CTM_ERR_INVALID, "unknown operator");
+  if (p->op == CTM_OP_CME)
+    for (int i = 0; i < p->d; ++i) {
+      const double span = p->hi[i] - p->lo[i];
+      if (span != std::ldexp(1.0, p->level_n))
+        return fail(CTM_ERR_INVALID, "lattice box needs hi - lo = 2^n");
+      if (p->k[i] < 0 || p->gamma[i] < 0)
+        return fail(CTM_ERR_INVALID, "rates must be nonnegative");
+    }
+  if (!(p->t1 > p->t0)) return fail(CTM_ERR_INVALID, "t1 must exceed t0");
+  if (p->nsteps < 1) return fail(CTM_ERR_INVALID, "nsteps must be >= 1");
+  if (p->nrecomb < 1 || p->nsteps % p->nrecomb)
+    return fail(CTM_ERR_INVALID, "nrecomb must divide nsteps");
+  if (p->mgrit_levels < 1 || p->mgrit_levels > 8)
+    return fail(CTM_ERR_INVALID, "mgrit_levels must be in 1..8");
+  if (p->mgrit_levels > 1) {
+    if (p->mgrit_cf < 2) return fail(CTM_ERR_INVALID, "mgrit_cf must be >= 2");
+    long long div = 1;
+    for (int l = 1; l < p->mgrit_levels; ++l) div *= p->mgrit_cf;
+    if ((p->nsteps / p->nrecomb) % div)
+      return fail(CTM_ERR_INVALID, "steps per block must be divisible by cf^(levels-1)");
+    if (!(p->mgrit_tol > 0) || p->mgrit_maxit < 1)
+      return fail(CTM_ERR_INVALID, "mgrit_tol must be > 0 and mgrit_maxit >= 1");
+  }
+  if (!(p->krylov_tol > 0) || p->krylov_maxit < 1)
+    return fail(CTM_ERR_INVALID, "krylov_tol must be > 0 and krylov_maxit >= 1");
+  if (p->prec == CTM_PREC_MIXED &&
+      (!(p->refine_tol > 0) || !(p->inner_tol > 0) || p->refine_maxit < 1))
+    return fail(CTM_ERR_INVALID, "mixed precision needs refine_tol, inner_tol > 0, refine_maxit >= 1");
+  const bool sym = (p->op == CTM_OP_HEAT || p->op == CTM_OP_VARCOEF);
+  if (p->krylov == CTM_KRYLOV_CG && !sym)
+    return fail(CTM_ERR_INVALID, "CG needs a symmetric operator (heat or varcoef)");
+  if (p->ic_terms < 1 || p->ic_terms > CTM_MAX_IC_TERMS || !p->ic_weight || !p->ic_factor)
+    return fail(CTM_ERR_INVALID, "initial value needs 1..16 terms with weight and factor arrays");
+  return CTM_OK;
+}
+
+int pick_shape(int maxpts) {
+  if (const char* env = std::getenv("CTM_SHAPE")) {
+    const int s = std::atoi(env);
+    if (s >= 0 && s < kNumShapes && 64 * kShapes[s].W * kShapes[s].K >= maxpts) return s;
+  }
+  for (int s = 0; s < kNumShapes; ++s)
+    if (64 * kShapes[s].W * kShapes[s].K >= maxpts) return s;
+  return -1;
+}
+
+ctm_status tasks_for(ctm_plan* P, long long M, int2** out) {
+  auto it = P->interval_tasks.find(M);
+  if (it != P->interval_tasks.end()) {
+    *out = it->second;
+    return CTM_OK;
+  }
+  std::vector<int2> t;
+  t.reserve((size_t)P->G * M);
+  for (int g : P->order)
+    for (long long q = 0; q < M; ++q) t.push_back(make_int2(g, (int)q));
+  int2* d = nullptr;
+  CTM_HIP(hipMalloc(&d, t.size() * sizeof(int2)));
+  CTM_HIP(hipMemcpy(d, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice));
+  P->interval_tasks[M] = d;
+  *out = d;
+  return CTM_OK;
+}
+
+ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) {
+  ChainArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.grids = P->dgrids;
+  a.tab64 = P->dtab;
+  a.amp = P->prob.amp;
+  a.dt = level_dt(P, level);
+  a.slen = P->slen;
+  a.nsteps = nsteps;
+  a.maxit = P->prob.krylov_maxit;
+  a.refine_maxit = P->prob.refine_maxit;
+  const bool mixed = P->mixed && !fp64_only;
+  a.tol = mixed ? P->prob.refine_tol : P->prob.krylov_tol;
+  a.inner_tol = P->prob.inner_tol;
+  a.counters = P->dcounters;
+  a.status = reinterpret_cast<int*>(P->dsync + 1);
+  return a;
+}
+
+VecRef vref(double* base, long long a, long long b) { return VecRef{base, a, b}; }
+
+ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const int2* tasks, long long ntasks,
+                     hipStream_t s, bool fp64_only = false) {
+  ChainArgs c = a;
+  c.tasks = tasks;
+  const bool mixed = P->mixed && !fp64_only;
+  const size_t smem = chain_smem_bytes(P->shape, P->tabmax, mixed);
+  hipError_t e = launch_chain(P->opc, P->solver, mixed, P->shape, c, (int)ntasks, smem,
+                              P->tabmax, s);
+  if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("chain launch: ") + hipGetErrorString(e));
+  return CTM_OK;
+}
+
+void reset_stats(ctm_plan* P) {
+  std::memset(&P->stats, 0, sizeof(P->stats));
+}
+
+ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
+  CTM_HIP(hipMemsetAsync(P->dcounters, 0, CNT_N * sizeof(unsigned long long), s));
+  CTM_HIP(hipMemsetAsync(P->dsync, 0, 2 * sizeof(double), s));
+  return CTM_OK;
+}
+
+ctm_status collect_device_stats(ctm_plan* P, hipStream_t s) {
+  unsigned long long c[CNT_N];
+  CTM_HIP(hipMemcpyAsync(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost, s));
+  CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  CTM_HIP(hipStreamSynchronize(s));
+  P->stats.krylov_iterations = (long long)c[CNT_KRYLOV];
+  P->stats.krylov_max = (long long)c[CNT_KRYLOV_MAX];
+  P->stats.refine_sweeps = (long long)c[CNT_REFINE];
+  P->stats.refine_max = (long long)c[CNT_REFINE_MAX];
+  P->stats.phi_solves = (long long)c[CNT_SOLVES];
+  P->stats.status_flags = *reinterpret_cast<int*>(P->hsync + 1);
+  return CTM_OK;
+}
+
+ctm_status status_from_flags(int flags) {
+  if (flags & (1 << CTM_ERR_NONFINITE)) return fail(CTM_ERR_NONFINITE, "non-finite value in a solve");
+  if (flags & (1 << CTM_ERR_BREAKDOWN)) return fail(CTM_ERR_BREAKDOWN, "BiCGStab breakdown");
+  if (flags & (1 << CTM_ERR_NOCONV)) return fail(CTM_ERR_NOCONV, "an implicit solve did not converge");
+  return CTM_OK;
+}
+
+// ------------------------------------------------------------- MGRIT
+// Workspace layout for one block (all vectors packed, float64):
+//   U, Un     level-0 C-points, (M0 + 1) vectors each (Un only with FCF)
+//   R[l]      residual on level l-1's C-points = right-hand side of level l, l >= 1
+//   E[l]      all points of level l >= 1 (N_l + 1 vectors)
+//   Cn[l]     C-relaxed C-points of level l (1 <= l < L-1, FCF)
+//   X, Y      block start / end states; res2 per task; scalars
+struct Layout {
+  int L;
+  long long c;
+  std::vector<long long> N;  // N[l], steps on level l
+  double* U = nullptr;
+  double* Un = nullptr;
+  std::vector<double*> R, E, Cn;
+  double* X = nullptr;
+  double* Y = nullptr;
+  double* res2 = nullptr;
+  size_t bytes = 0;
+};
+
+Layout make_layout(const ctm_plan* P, char* base) {
+  Layout lay;
+  const ctm_problem& p = P->prob;
+  lay.L = p.mgrit_levels;
+  lay.c = p.mgrit_cf;
+  const long long Nb = p.nsteps / p.nrecomb;
+  lay.N.resize(lay.L);
+  lay.N[0] = Nb;
+  for (int l = 1; l < lay.L; ++l) lay.N[l] = lay.N[l - 1] / lay.c;
+  lay.R.assign(lay.L + 1, nullptr);
+  lay.E.assign(lay.L + 1, nullptr);
+  lay.Cn.assign(lay.L + 1, nullptr);
+  size_t off = 0;
+  const size_t vb = (size_t)P->slen * sizeof(double);
+  auto take = [&](long long nvec) {
+    double* ptr = base ? reinterpret_cast<double*>(base + off) : nullptr;
+    off += (size_t)nvec * vb;
+    off = (off + 255) & ~size_t(255);
+    return ptr;
+  };
+  const bool fcf = (p.relax == CTM_RELAX_FCF);
+  if (lay.L > 1) {
+    const long long M0 = lay.N[0] / lay.c;
+    lay.U = take(M0 + 1);
+    if (fcf) lay.Un = take(M0 + 1);
+    for (int l = 1; l < lay.L; ++l) {
+      lay.R[l] = take(lay.N[l] + 1);
+      lay.E[l] = take(lay.N[l] + 1);
+      if (l < lay.L - 1 && fcf) lay.Cn[l] = take(lay.N[l] / lay.c + 1);
+    }
+  }
+  lay.X = take(1);
+  lay.Y = take(1);
+  const long long maxtasks = (long long)P->G * std::max<long long>(1, lay.N[0] / std::max<long long>(1, lay.c));
+  double* r2 = base ? reinterpret_cast<double*>(base + off) : nullptr;
+  off += (size_t)maxtasks * sizeof(double);
+  off = (off + 255) & ~size_t(255);
+  lay.res2 = r2;
+  lay.bytes = off;
+  return lay;
+}
+
+// One cycle on level l >= 1 for e_0 = g_0, e_n = Phi_l e_{n-1} + g_n from a
+// zero initial guess; writes all points of E[l].
+ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
+  const long long c = lay.c;
+  double* G = lay.R[l];
+  double* E = lay.E[l];
+  ctm_status st;
+  if (l == lay.L - 1) {
+    ChainArgs a = base_args(P, l, (int)lay.N[l]);
+    a.start = vref(nullptr, 0, 0);
+    a.forcing = vref(G, 0, 0);
+    a.inter = vref(E, 0, 0);
+    a.fin = vref(E, 0, lay.N[l]);
+    CTM_HIP(launch_fill_zero(E, P->slen, s));  // e_0 = g_0 = 0
+    return run_chain(P, a, P->dsingle, P->G, s);
+  }
+  const long long M = lay.N[l] / c;
+  int2* tasks = nullptr;
+  if ((st = tasks_for(P, M, &tasks)) != CTM_OK) return st;
+  const long long nt = (long long)P->G * M;
+  CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s));
+  double* csrc;
+  long long ca;
+  if (P->prob.relax == CTM_RELAX_FCF) {
+    double* Cn = lay.Cn[l];
+    CTM_HIP(launch_fill_zero(Cn, P->slen, s));
+    ChainArgs fc = base_args(P, l, (int)c);
+    fc.start = vref(E, c, 0);
+    fc.forcing = vref(G, c, 0);
+    fc.inter = vref(E, c, 0);
+    fc.fin = vref(Cn, 1, 1);
+    if ((st = run_chain(P, fc, tasks, nt, s)) != CTM_OK) return st;
+    ChainArgs fr = base_args(P, l, (int)c);
+    fr.start = vref(Cn, 1, 0);
+    fr.start_wb = vref(E, c, 0);
+    fr.forcing = vref(G, c, 0);
+    fr.inter = vref(E, c, 0);
+    fr.fin = vref(lay.R[l + 1], 1, 1);
+    fr.target = vref(Cn, 1, 1);
+    if ((st = run_chain(P, fr, tasks, nt, s)) != CTM_OK) return st;
+    csrc = Cn;
+    ca = 1;
+  } else {
+    ChainArgs fr = base_args(P, l, (int)c);
+    fr.start = vref(E, c, 0);
+    fr.forcing = vref(G, c, 0);
+    fr.inter = vref(E, c, 0);
+    fr.fin = vref(lay.R[l + 1], 1, 1);
+    fr.target = vref(E, c, c);
+    if ((st = run_chain(P, fr, tasks, nt, s)) != CTM_OK) return st;
+    csrc = E;
+    ca = c;
+  }
+  CTM_HIP(launch_fill_zero(lay.R[l + 1], P->slen, s));  // r_0 = 0
+  if ((st = cycle(P, lay, l + 1, s)) != CTM_OK) return st;
+  // correction at the C-points, then F-relaxation (ideal interpolation)
+  CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0), (int)(M + 1),
+                         P->slen, s));
+  ChainArgs fi = base_args(P, l, (int)(c - 1));
+  fi.start = vref(E, c, 0);
+  fi.forcing = vref(G, c, 0);
+  fi.inter = vref(E, c, 0);
+  fi.fin = vref(E, c, c - 1);
+  return run_chain(P, fi, tasks, nt, s);
+}
+
+// MGRIT on one block: X (start) -> Y (state at the block end).
+ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
+  const ctm_problem& p = P->prob;
+  ctm_status st;
+  if (lay.L == 1) {
+    ChainArgs a = base_args(P, 0, (int)lay.N[0]);
+    a.start = vref(lay.X, 0, 0);
+    a.fin = vref(lay.Y, 0, 0);
+    return run_chain(P, a, P->dsingle, P->G, s);
+  }
+  const long long c = lay.c;
+  const long long M0 = lay.N[0] / c;
+  int2* tasks = nullptr;
+  if ((st = tasks_for(P, M0, &tasks)) != CTM_OK) return st;
+  const long long nt = (long long)P->G * M0;
+  const bool fcf = (p.relax == CTM_RELAX_FCF);
+  // initial guess: the start state at every C-point
+  CTM_HIP(launch_vec_add(vref(lay.U, 1, 0), vref(lay.X, 0, 0), vref(nullptr, 0, 0), (int)(M0 + 1),
+                         P->slen, s));
+  if (fcf) CTM_HIP(hipMemcpyAsync(lay.Un, lay.X, P->slen * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CTM_HIP(launch_fill_zero(lay.R[1], P->slen, s));
+  CTM_HIP(launch_grid_norms2(P->dgrids, P->G, lay.X, P->dnorm2, s));
+  double* U = lay.U;
+  double* Un = lay.Un;
+  for (int it = 1; it <= p.mgrit_maxit; ++it) {
+    double* C;
+    if (fcf) {
+      ChainArgs fc = base_args(P, 0, (int)c);
+      fc.start = vref(U, 1, 0);
+      fc.fin = vref(Un, 1, 1);
+      if ((st = run_chain(P, fc, tasks, nt, s)) != CTM_OK) return st;
+      C = Un;
+    } else {
+      C = U;
+    }
+    ChainArgs fr = base_args(P, 0, (int)c);
+    fr.start = vref(C, 1, 0);
+    fr.fin = vref(lay.R[1], 1, 1);
+    fr.target = vref(C, 1, 1);
+    fr.res2 = lay.res2;
+    if ((st = run_chain(P, fr, tasks, nt, s)) != CTM_OK) return st;
+    CTM_HIP(launch_residual_max(tasks, (int)nt, lay.res2, P->dnorm2, P->dsync, s));
+    CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CTM_HIP(hipStreamSynchronize(s));
+    const double res = P->hsync[0];
+    const int flags = *reinterpret_cast<int*>(P->hsync + 1);
+    P->stats.mgrit_iterations += 1;
+    if (P->stats.history_len < CTM_MAX_HISTORY) P->stats.mgrit_residual[P->stats.history_len++] = res;
+    if (flags & (1 << CTM_ERR_NONFINITE)) return fail(CTM_ERR_NONFINITE, "non-finite value in MGRIT");
+    if (res <= p.mgrit_tol) {
+      CTM_HIP(hipMemcpyAsync(lay.Y, C + M0 * P->slen, P->slen * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      return CTM_OK;
+    }
+    if ((st = cycle(P, lay, 1, s)) != CTM_OK) return st;
+    CTM_HIP(launch_vec_add(vref(C, 1, 0), vref(C, 1, 0), vref(lay.E[1], 1, 0), (int)(M0 + 1),
+                           P->slen, s));
+    if (fcf) std::swap(U, Un);
+    if (it == p.mgrit_maxit) {
+      CTM_HIP(hipMemcpyAsync(lay.Y, C + M0 * P->slen, P->slen * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      return fail(CTM_ERR_NOCONV, "MGRIT reached mgrit_maxit");
+    }
+  }
+  return CTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ctm_last_error(void) { return g_last_error.c_str(); }
+
+const char* ctm_status_string(ctm_status st) {
+  switch (st) {
+    case CTM_OK: return "ok";
+    case CTM_ERR_INVALID: return "invalid argument";
+    case CTM_ERR_NOMEM: return "out of memory";
+    case CTM_ERR_HIP: return "HIP error";
+    case CTM_ERR_NOCONV: return "no convergence";
+    case CTM_ERR_BREAKDOWN: return "Krylov breakdown";
+    case CTM_ERR_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+ctm_status ctm_problem_defaults(ctm_problem* p) {
+  if (!p) return fail(CTM_ERR_INVALID, "problem is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->d = 2;
+  p->level_n = 4;
+  p->level_min = 1;
+  for (int i = 0; i < CTM_MAXD; ++i) {
+    p->lo[i] = 0.0;
+    p->hi[i] = 1.0;
+  }
+  p->op = CTM_OP_HEAT;
+  p->t0 = 0.0;
+  p->t1 = 1.0;
+  p->nsteps = 16;
+  p->nrecomb = 1;
+  p->mgrit_levels = 2;
+  p->mgrit_cf = 2;
+  p->relax = CTM_RELAX_FCF;
+  p->mgrit_tol = 1e-8;
+  p->mgrit_maxit = 100;
+  p->krylov = CTM_KRYLOV_AUTO;
+  p->krylov_tol = 1e-8;
+  p->krylov_maxit = 10000;
+  p->prec = CTM_PREC_FP64;
+  p->refine_tol = 1e-8;
+  p->inner_tol = 1e-5;
+  p->refine_maxit = 10;
+  return CTM_OK;
+}
+
+ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
+  if (!out) return fail(CTM_ERR_INVALID, "plan output pointer is NULL");
+  *out = nullptr;
+  ctm_status st = validate(prob);
+  if (st != CTM_OK) return st;
+  ctm_plan* P = new (std::nothrow) ctm_plan();
+  if (!P) return fail(CTM_ERR_NOMEM, "host allocation failed");
+  P->prob = *prob;
+  P->d = prob->d;
+  P->n = prob->level_n;
+  const int F = (1 << P->n) + 1;
+  P->icw.assign(prob->ic_weight, prob->ic_weight + prob->ic_terms);
+  P->icf.assign(prob->ic_factor, prob->ic_factor + (size_t)prob->ic_terms * P->d * F);
+  P->prob.ic_weight = nullptr;
+  P->prob.ic_factor = nullptr;
+  P->lattice = (prob->op == CTM_OP_CME);
+  P->opc = prob->op == CTM_OP_HEAT ? OPC_HEAT : (prob->op == CTM_OP_VARCOEF ? OPC_VAR : OPC_SEP);
+  const bool sym = (prob->op == CTM_OP_HEAT || prob->op == CTM_OP_VARCOEF);
+  P->solver = (prob->krylov == CTM_KRYLOV_BICGSTAB || (prob->krylov == CTM_KRYLOV_AUTO && !sym))
+                  ? SOLV_BICG : SOLV_CG;
+  P->mixed = (prob->prec == CTM_PREC_MIXED);
+  hipGetDevice(&P->device);
+
+  // combination index set: layer w ascending, l lexicographic
+  const int d = P->d;
+  long long off = 0;
+  for (int w = 0; w < d; ++w) {
+    const int total = P->n + d - 1 - w;
+    if (total < d * prob->level_min) continue;
+    std::vector<std::vector<int>> ls;
+    std::vector<int> cur;
+    compositions(total, d, prob->level_min, cur, ls);
+    const double coef = ((w & 1) ? -1.0 : 1.0) * (double)binom(d - 1, w);
+    for (auto& l : ls) {
+      GridHost gh;
+      std::memset(&gh, 0, sizeof(gh));
+      long long np = 1;
+      for (int i = 0; i < d; ++i) {
+        gh.lev[i] = l[i];
+        np *= P->lattice ? (1LL << l[i]) : ((1LL << l[i]) - 1);
+      }
+      gh.w = w;
+      gh.coef = coef;
+      gh.npts = np;
+      gh.off = off;
+      off += np;
+      P->grids.push_back(gh);
+    }
+  }
+  P->G = (int)P->grids.size();
+  P->slen = off;
+  for (auto& gh : P->grids) P->maxpts = (int)std::max<long long>(P->maxpts, gh.npts);
+  P->shape = pick_shape(P->maxpts);
+  if (P->shape < 0) {
+    delete P;
+    return fail(CTM_ERR_INVALID, "a component grid exceeds 8192 unknowns (on-chip solver limit)");
+  }
+
+  const double dt0 = (prob->t1 - prob->t0) / (double)prob->nsteps;
+  for (auto& gh : P->grids) {
+    GridDev gd;
+    std::memset(&gd, 0, sizeof(gd));
+    gd.npts = (int)gh.npts;
+    gd.d = d;
+    gd.off = gh.off;
+    gd.j0 = P->lattice ? 0 : 1;
+    gd.coef = gh.coef;
+    int bits = 0;
+    long long stride = 1;
+    for (int i = d - 1; i >= 0; --i) {
+      gd.lev[i] = gh.lev[i];
+      gd.n[i] = P->lattice ? (1 << gh.lev[i]) : ((1 << gh.lev[i]) - 1);
+      gd.stride[i] = (int)stride;
+      stride *= gd.n[i];
+      gd.boff[i] = bits;
+      gd.bmask[i] = (1 << gh.lev[i]) - 1;
+      bits += gh.lev[i];
+      gd.lo[i] = prob->lo[i];
+      gd.h[i] = (prob->hi[i] - prob->lo[i]) / (double)(1LL << gh.lev[i]);
+      gd.ih2[i] = 1.0 / (gd.h[i] * gd.h[i]);
+    }
+    build_tables(P, gh, gd);
+    P->tabmax = std::max(P->tabmax, gd.tabsz);
+    // cost estimate for longest-first scheduling: unknowns * sqrt(condition)
+    double lam = 0.0;
+    for (int i = 0; i < d; ++i) lam += 4.0 * gd.ih2[i];
+    gh.cost = (double)gh.npts * std::sqrt(1.0 + dt0 * lam);
+    P->hdev.push_back(gd);
+  }
+  if (P->htab.empty()) P->htab.push_back(0.0);
+  P->order.resize(P->G);
+  for (int g = 0; g < P->G; ++g) P->order[g] = g;
+  std::stable_sort(P->order.begin(), P->order.end(),
+                   [&](int a, int b) { return P->grids[a].cost > P->grids[b].cost; });
+
+  auto cleanup = [&](ctm_status s2) {
+    delete P;
+    return s2;
+  };
+#define CTM_HIPC(call)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return cleanup(fail(CTM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  CTM_HIPC(hipMalloc(&P->dgrids, P->G * sizeof(GridDev)));
+  CTM_HIPC(hipMemcpy(P->dgrids, P->hdev.data(), P->G * sizeof(GridDev), hipMemcpyHostToDevice));
+  CTM_HIPC(hipMalloc(&P->dtab, P->htab.size() * sizeof(double)));
+  CTM_HIPC(hipMemcpy(P->dtab, P->htab.data(), P->htab.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<long long> offs(P->G);
+  for (int g = 0; g < P->G; ++g) offs[g] = P->grids[g].off;
+  CTM_HIPC(hipMalloc(&P->doffsets, P->G * sizeof(long long)));
+  CTM_HIPC(hipMemcpy(P->doffsets, offs.data(), P->G * sizeof(long long), hipMemcpyHostToDevice));
+  CTM_HIPC(hipMalloc(&P->dicw, P->icw.size() * sizeof(double)));
+  CTM_HIPC(hipMemcpy(P->dicw, P->icw.data(), P->icw.size() * sizeof(double), hipMemcpyHostToDevice));
+  CTM_HIPC(hipMalloc(&P->dicf, P->icf.size() * sizeof(double)));
+  CTM_HIPC(hipMemcpy(P->dicf, P->icf.data(), P->icf.size() * sizeof(double), hipMemcpyHostToDevice));
+  CTM_HIPC(hipMalloc(&P->dcounters, CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMemset(P->dcounters, 0, CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMalloc(&P->dsync, 2 * sizeof(double)));
+  CTM_HIPC(hipMemset(P->dsync, 0, 2 * sizeof(double)));
+  CTM_HIPC(hipMalloc(&P->dnorm2, P->G * sizeof(double)));
+  CTM_HIPC(hipHostMalloc(&P->hsync, 2 * sizeof(double), hipHostMallocDefault));
+  std::vector<int2> single(P->G), ident(P->G);
+  for (int g = 0; g < P->G; ++g) {
+    single[g] = make_int2(P->order[g], 0);
+    ident[g] = make_int2(g, 0);
+  }
+  CTM_HIPC(hipMalloc(&P->dsingle, P->G * sizeof(int2)));
+  CTM_HIPC(hipMemcpy(P->dsingle, single.data(), P->G * sizeof(int2), hipMemcpyHostToDevice));
+  CTM_HIPC(hipMalloc(&P->didentity, P->G * sizeof(int2)));
+  CTM_HIPC(hipMemcpy(P->didentity, ident.data(), P->G * sizeof(int2), hipMemcpyHostToDevice));
+#undef CTM_HIPC
+  reset_stats(P);
+  *out = P;
+  return CTM_OK;
+}
+
+void ctm_plan_destroy(ctm_plan* plan) { delete plan; }
+
+ctm_status ctm_plan_grids(const ctm_plan* P, int* G) {
+  if (!P || !G) return fail(CTM_ERR_INVALID, "NULL argument");
+  *G = P->G;
+  return CTM_OK;
+}
+
+ctm_status ctm_plan_grid_info(const ctm_plan* P, int g, int* levels, double* coef,
+                              long long* offset, long long* npoints) {
+  if (!P) return fail(CTM_ERR_INVALID, "plan is NULL");
+  if (g < 0 || g >= P->G) return fail(CTM_ERR_INVALID, "grid index out of range");
+  const GridHost& gh = P->grids[g];
+  if (levels)
+    for (int i = 0; i < P->d; ++i) levels[i] = gh.lev[i];
+  if (coef) *coef = gh.coef;
+  if (offset) *offset = gh.off;
+  if (npoints) *npoints = gh.npts;
+  return CTM_OK;
+}
+
+ctm_status ctm_plan_state_len(const ctm_plan* P, long long* len) {
+  if (!P || !len) return fail(CTM_ERR_INVALID, "NULL argument");
+  *len = P->slen;
+  return CTM_OK;
+}
+
+ctm_status ctm_plan_workspace_bytes(const ctm_plan* P, size_t* bytes) {
+  if (!P || !bytes) return fail(CTM_ERR_INVALID, "NULL argument");
+  *bytes = make_layout(P, nullptr).bytes;
+  return CTM_OK;
+}
+
+ctm_status ctm_initial_state(ctm_plan* P, double* u0, ctm_stream s) {
+  if (!P || !u0) return fail(CTM_ERR_INVALID, "NULL argument");
+  CTM_HIP(launch_initial_state(P->dgrids, P->G, P->maxpts, P->n, (int)P->icw.size(), P->dicw,
+                               P->dicf, u0, (hipStream_t)s));
+  return CTM_OK;
+}
+
+ctm_status ctm_apply(ctm_plan* P, int level, const double* x, double* y, ctm_stream s) {
+  if (!P || !x || !y) return fail(CTM_ERR_INVALID, "NULL argument");
+  if (level < 0 || level > 16) return fail(CTM_ERR_INVALID, "level out of range");
+  if (x == y) return fail(CTM_ERR_INVALID, "x and y must not overlap");
+  CTM_HIP(launch_apply(P->opc, P->shape, P->dgrids, P->G, P->dtab, P->prob.amp, level_dt(P, level),
+                       P->tabmax, x, y, (hipStream_t)s));
+  return CTM_OK;
+}
+
+ctm_status ctm_propagate(ctm_plan* P, int level, long long nsteps, const double* x, double* y,
+                         int per_grid, ctm_stream s) {
+  if (!P || !x || !y) return fail(CTM_ERR_INVALID, "NULL argument");
+  if (level < 0 || level > 16 || nsteps < 0 || nsteps > (1LL << 30))
+    return fail(CTM_ERR_INVALID, "level or nsteps out of range");
+  hipStream_t hs = (hipStream_t)s;
+  reset_stats(P);
+  ctm_status st = reset_device_stats(P, hs);
+  if (st != CTM_OK) return st;
+  if (nsteps == 0) {
+    if (x != y) CTM_HIP(hipMemcpyAsync(y, x, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    return CTM_OK;
+  }
+  if (!per_grid) {
+    ChainArgs a = base_args(P, level, (int)nsteps);
+    a.start = vref(const_cast<double*>(x), 0, 0);
+    a.fin = vref(y, 0, 0);
+    return run_chain(P, a, P->dsingle, P->G, hs);
+  }
+  for (int g = 0; g < P->G; ++g) {
+    for (long long nn = 0; nn < nsteps; ++nn) {
+      ChainArgs a = base_args(P, level, 1, true);
+      a.start = vref(const_cast<double*>(nn == 0 ? x : y), 0, 0);
+      a.fin = vref(y, 0, 0);
+      if ((st = run_chain(P, a, P->didentity + g, 1, hs, true)) != CTM_OK) return st;
+    }
+  }
+  return CTM_OK;
+}
+
+ctm_status ctm_solve(ctm_plan* P, void* ws, size_t ws_bytes, const double* u0, double* u_final,
+                     ctm_stream s) {
+  if (!P || !ws || !u_final) return fail(CTM_ERR_INVALID, "NULL argument");
+  Layout lay = make_layout(P, static_cast<char*>(ws));
+  if (ws_bytes < lay.bytes) return fail(CTM_ERR_NOMEM, "workspace smaller than ctm_plan_workspace_bytes");
+  hipStream_t hs = (hipStream_t)s;
+  reset_stats(P);
+  ctm_status st = reset_device_stats(P, hs);
+  if (st != CTM_OK) return st;
+  if (u0) {
+    CTM_HIP(hipMemcpyAsync(lay.X, u0, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  } else {
+    CTM_HIP(launch_initial_state(P->dgrids, P->G, P->maxpts, P->n, (int)P->icw.size(), P->dicw,
+                                 P->dicf, lay.X, hs));
+  }
+  ctm_status result = CTM_OK;
+  for (int b = 0; b < P->prob.nrecomb; ++b) {
+    if (b > 0) CTM_HIP(launch_project(P->dgrids, P->doffsets, P->G, P->slen, lay.Y, lay.X, hs));
+    st = mgrit_block(P, lay, hs);
+    P->stats.blocks += 1;
+    if (st == CTM_ERR_NOCONV) {
+      result = st;
+    } else if (st != CTM_OK) {
+      return st;
+    }
+  }
+  CTM_HIP(hipMemcpyAsync(u_final, lay.Y, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  if ((st = collect_device_stats(P, hs)) != CTM_OK) return st;
+  if (result != CTM_OK) return result;
+  return status_from_flags(P->stats.status_flags);
+}
+
+ctm_status ctm_gather(ctm_plan* P, const double* u, const double* pts, long long npts, double* out,
+                      ctm_stream s) {
+  if (!P || !u || (!pts && npts > 0) || (!out && npts > 0)) return fail(CTM_ERR_INVALID, "NULL argument");
+  if (npts < 0) return fail(CTM_ERR_INVALID, "npts must be >= 0");
+  CTM_HIP(launch_gather(P->dgrids, P->G, u, pts, npts, out, (hipStream_t)s));
+  return CTM_OK;
+}
+
+ctm_status ctm_combine_project(ctm_plan* P, const double* u, double* out, ctm_stream s) {
+  if (!P || !u || !out) return fail(CTM_ERR_INVALID, "NULL argument");
+  if (u == out) return fail(CTM_ERR_INVALID, "u and out must not overlap");
+  CTM_HIP(launch_project(P->dgrids, P->doffsets, P->G, P->slen, u, out, (hipStream_t)s));
+  return CTM_OK;
+}
+
+ctm_status ctm_get_stats(const ctm_plan* P, ctm_stats* st) {
+  if (!P || !st) return fail(CTM_ERR_INVALID, "NULL argument");
+  // counters live on the device; the caller has synchronised its stream
+  unsigned long long c[CNT_N];
+  int flags = 0;
+  CTM_HIP(hipMemcpy(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost));
+  CTM_HIP(hipMemcpy(&flags, P->dsync + 1, sizeof(int), hipMemcpyDeviceToHost));
+  *st = P->stats;
+  st->krylov_iterations = (long long)c[CNT_KRYLOV];
+  st->krylov_max = (long long)c[CNT_KRYLOV_MAX];
+  st->refine_sweeps = (long long)c[CNT_REFINE];
+  st->refine_max = (long long)c[CNT_REFINE_MAX];
+  st->phi_solves = (long long)c[CNT_SOLVES];
+  st->status_flags = flags;
+  return CTM_OK;
+}
+
+}  // extern "C"

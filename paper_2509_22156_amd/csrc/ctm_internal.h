@@ -1,0 +1,129 @@
+// Internal structures shared by the host driver and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ctm.h"
+
+namespace ctm {
+
+constexpr int MAXD = CTM_MAXD;
+
+// Operator classes of the stencil kernels.
+//  HEAT: constant coefficients per axis (CTM_OP_HEAT).
+//  SEP:  coefficients that depend on the coordinate of their own axis only,
+//        read from 1-D tables (CTM_OP_OU, CTM_OP_CME).
+//  VAR:  conservative variable-coefficient diffusion with
+//        a = 1 + amp prod_k sin(2 pi x_k) at face midpoints (CTM_OP_VARCOEF).
+enum OpClass { OPC_HEAT = 0, OPC_SEP = 1, OPC_VAR = 2 };
+enum SolverKind { SOLV_CG = 0, SOLV_BICG = 1 };
+
+// Geometry of one component grid (device copy, read once per work-group).
+struct GridDev {
+  int npts;            // unknowns
+  int d;
+  int tabsz;           // doubles in this grid's coefficient table block
+  int pad_;
+  long long off;       // offset of the grid in a packed vector
+  long long tab0;      // start of this grid's table block in the table arrays
+  int n[MAXD];         // unknowns per axis (axis d-1 fastest)
+  int stride[MAXD];    // point-index stride of axis i
+  int boff[MAXD];      // bit offset of coordinate j_i in the packed coordinate word
+  int bmask[MAXD];     // (1 << bits_i) - 1
+  int tab[MAXD];       // offset of axis i inside the grid's table block
+  int lev[MAXD];       // level l_i
+  double ih2[MAXD];    // 1 / h_i^2
+  double lo[MAXD];     // box lower corner
+  double h[MAXD];      // mesh width
+  int j0;              // node index of the first unknown (1 Dirichlet, 0 lattice)
+  int pad3_;
+  double coef;         // combination coefficient (-1)^w binom(d-1, w)
+};
+
+// A family of packed vectors indexed by time: vector index = a * q + b
+// (+ j for per-step roles); element (idx, grid g, point p) lives at
+// base[idx * slen + g.off + p]. base == nullptr disables the role.
+struct VecRef {
+  double* base;
+  long long a, b;
+};
+
+// Arguments of one launch of the chain kernel. A task (g, q) takes grid g,
+// loads the start vector of index start.a*q + start.b, applies `nsteps`
+// implicit steps v <- Phi(v) + forcing_j and stores according to the roles.
+struct ChainArgs {
+  const GridDev* grids;
+  const int2* tasks;        // (grid, q)
+  const double* tab64;      // coefficient tables (FP64; FP32 copies are made in LDS)
+  double amp;               // VAR amplitude
+  double dt;                // step size of this level
+  long long slen;           // length of a packed vector
+  int nsteps;
+  int maxit;                // Krylov iterations per solve / per refinement sweep
+  int refine_maxit;
+  int pad_;
+  double tol;               // FP64 path Krylov tolerance, or mixed refinement tolerance
+  double inner_tol;         // mixed path FP32 Krylov tolerance
+  VecRef start;             // start vector (base == nullptr: zero)
+  VecRef start_wb;          // optional write-back of the start vector
+  VecRef forcing;           // optional addend after step j: index a*q + b + j
+  VecRef inter;             // optional store after step j < nsteps: index a*q + b + j
+  VecRef fin;               // final store (index a*q + b)
+  VecRef target;            // optional: residual mode, fin = v - target[a*q + b]
+  double* res2;             // residual mode: per-task ||fin||_2^2 (optional)
+  unsigned long long* counters;  // statistics (see CNT_*)
+  int* status;              // OR of (1 << ctm_status)
+};
+
+enum {
+  CNT_KRYLOV = 0,
+  CNT_KRYLOV_MAX = 1,
+  CNT_REFINE = 2,
+  CNT_REFINE_MAX = 3,
+  CNT_SOLVES = 4,
+  CNT_N = 8
+};
+
+// Launch configurations of the on-chip solver: W waves per work-group, K
+// points per lane, capacity 64 * W * K unknowns.
+struct ShapeCfg {
+  int W, K;
+};
+constexpr ShapeCfg kShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 4}, {4, 4}, {4, 8}, {8, 8}, {16, 8}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
+                        int ntasks, size_t smem, int tabmax, hipStream_t s);
+
+// Dynamic LDS bytes of the chain kernel for a shape and table size.
+inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed) {
+  const ShapeCfg c = kShapes[shape];
+  size_t cap = 64u * c.W * c.K;
+  size_t vec = cap * sizeof(double);
+  size_t tabs = (size_t)tabmax * sizeof(double) + (mixed ? (size_t)tabmax * sizeof(float) : 0);
+  size_t red = 2u * 64u * sizeof(double);
+  return vec + ((tabs + 15) & ~size_t(15)) + red;
+}
+
+// Auxiliary kernels (aux_kernels.hip).
+hipError_t launch_initial_state(const GridDev* grids, int G, int maxpts, int nlev, int terms,
+                                const double* icw, const double* icf, double* out, hipStream_t s);
+hipError_t launch_apply(int opc, int shape, const GridDev* grids, int G, const double* tab64,
+                        double amp, double dt, int tabmax, const double* x, double* y,
+                        hipStream_t s);
+hipError_t launch_gather(const GridDev* grids, int G, const double* u, const double* pts,
+                         long long npts, double* out, hipStream_t s);
+hipError_t launch_project(const GridDev* grids, const long long* offsets, int G, long long slen,
+                          const double* u, double* out, hipStream_t s);
+hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, double* out,
+                              hipStream_t s);
+hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
+                               const double* norm2, double* out, hipStream_t s);
+// dst[(ad q + bd) slen + e] = x[(ax q + bx) slen + e] (+ y[(ay q + by) slen + e]),
+// q = 0..nvec-1, e = 0..slen-1; y.base may be null.
+hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
+                          hipStream_t s);
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+
+}  // namespace ctm

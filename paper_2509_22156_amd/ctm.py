@@ -1,0 +1,265 @@
+"""Python binding of the C ABI in include/ctm.h (argument marshalling only).
+
+Device buffers are torch tensors on the current HIP device (float64); the
+stream is torch's current stream. Every computation runs in the HIP
+library; if libctm.so is missing this module raises at import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libctm.so")
+
+MAXD = 8
+MAX_HISTORY = 256
+
+OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE = range(7)
+_OPS = {"heat": 0, "varcoef": 1, "ou": 2, "cme": 3}
+_KRYLOV = {"auto": 0, "cg": 1, "bicgstab": 2}
+_PREC = {"fp64": 0, "mixed": 1}
+_RELAX = {"F": 0, "FCF": 1}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int), ("level_n", ctypes.c_int), ("level_min", ctypes.c_int),
+        ("lo", ctypes.c_double * MAXD), ("hi", ctypes.c_double * MAXD),
+        ("op", ctypes.c_int), ("amp", ctypes.c_double),
+        ("theta", ctypes.c_double * MAXD), ("sigma", ctypes.c_double),
+        ("k", ctypes.c_double * MAXD), ("gamma", ctypes.c_double * MAXD),
+        ("t0", ctypes.c_double), ("t1", ctypes.c_double),
+        ("nsteps", ctypes.c_longlong), ("nrecomb", ctypes.c_int),
+        ("mgrit_levels", ctypes.c_int), ("mgrit_cf", ctypes.c_int), ("relax", ctypes.c_int),
+        ("mgrit_tol", ctypes.c_double), ("mgrit_maxit", ctypes.c_int),
+        ("krylov", ctypes.c_int), ("krylov_tol", ctypes.c_double), ("krylov_maxit", ctypes.c_int),
+        ("prec", ctypes.c_int), ("refine_tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+        ("refine_maxit", ctypes.c_int), ("ic_terms", ctypes.c_int),
+        ("ic_weight", ctypes.POINTER(ctypes.c_double)),
+        ("ic_factor", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("blocks", ctypes.c_int), ("mgrit_iterations", ctypes.c_int),
+        ("history_len", ctypes.c_int),
+        ("mgrit_residual", ctypes.c_double * MAX_HISTORY),
+        ("phi_solves", ctypes.c_longlong), ("krylov_iterations", ctypes.c_longlong),
+        ("krylov_max", ctypes.c_longlong), ("refine_sweeps", ctypes.c_longlong),
+        ("refine_max", ctypes.c_longlong), ("status_flags", ctypes.c_int),
+    ]
+
+
+class CtmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ctm status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2509_22156_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i, ll, dbl, sz = ctypes.c_int, ctypes.c_longlong, ctypes.c_double, ctypes.c_size_t
+    sigs = {
+        "ctm_problem_defaults": [ctypes.POINTER(Problem)],
+        "ctm_plan_create": [ctypes.POINTER(Problem), ctypes.POINTER(P)],
+        "ctm_plan_grids": [P, ctypes.POINTER(i)],
+        "ctm_plan_grid_info": [P, i, ctypes.POINTER(i), ctypes.POINTER(dbl), ctypes.POINTER(ll),
+                               ctypes.POINTER(ll)],
+        "ctm_plan_state_len": [P, ctypes.POINTER(ll)],
+        "ctm_plan_workspace_bytes": [P, ctypes.POINTER(sz)],
+        "ctm_initial_state": [P, P, P],
+        "ctm_apply": [P, i, P, P, P],
+        "ctm_propagate": [P, i, ll, P, P, i, P],
+        "ctm_solve": [P, P, sz, P, P, P],
+        "ctm_gather": [P, P, P, ll, P, P],
+        "ctm_combine_project": [P, P, P, P],
+        "ctm_get_stats": [P, ctypes.POINTER(Stats)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ctm_plan_destroy.argtypes = [P]
+    lib.ctm_plan_destroy.restype = None
+    lib.ctm_status_string.argtypes = [ctypes.c_int]
+    lib.ctm_status_string.restype = ctypes.c_char_p
+    lib.ctm_last_error.argtypes = []
+    lib.ctm_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(st: int):
+    if st != OK:
+        raise CtmError(st, _lib.ctm_last_error().decode())
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def problem_struct(prob: dict):
+    """ctm_problem from a problem dictionary (see workloads); returns the
+    struct and the numpy arrays it points to (keep them alive)."""
+    s = Problem()
+    _check(_lib.ctm_problem_defaults(ctypes.byref(s)))
+    d = int(prob["d"])
+    s.d, s.level_n, s.level_min = d, int(prob["n"]), int(prob.get("L0", 1))
+    for i in range(d):
+        s.lo[i] = float(prob["lo"][i])
+        s.hi[i] = float(prob["hi"][i])
+    s.op = _OPS[prob["op"]]
+    s.amp = float(prob.get("amp", 0.0))
+    for i in range(d):
+        s.theta[i] = float(prob.get("theta", [0.0] * d)[i])
+        s.k[i] = float(prob.get("k", [0.0] * d)[i])
+        s.gamma[i] = float(prob.get("gamma", [0.0] * d)[i])
+    s.sigma = float(prob.get("sigma", 0.0))
+    s.t0, s.t1 = float(prob["t0"]), float(prob["t1"])
+    s.nsteps = int(prob["nsteps"])
+    s.nrecomb = int(prob.get("nrecomb", 1))
+    s.mgrit_levels = int(prob.get("mgrit_levels", 2))
+    s.mgrit_cf = int(prob.get("cf", 2))
+    s.relax = _RELAX[prob.get("relax", "FCF")]
+    s.mgrit_tol = float(prob.get("mgrit_tol", 1e-8))
+    s.mgrit_maxit = int(prob.get("mgrit_maxit", 100))
+    s.krylov = _KRYLOV[prob.get("krylov", "auto")]
+    s.krylov_tol = float(prob.get("krylov_tol", 1e-8))
+    s.krylov_maxit = int(prob.get("krylov_maxit", 10000))
+    s.prec = _PREC[prob.get("prec", "fp64")]
+    s.refine_tol = float(prob.get("refine_tol", 1e-8))
+    s.inner_tol = float(prob.get("inner_tol", 1e-5))
+    s.refine_maxit = int(prob.get("refine_maxit", 10))
+    w = np.ascontiguousarray(prob["ic_w"], dtype=np.float64)
+    f = np.ascontiguousarray(prob["ic_f"], dtype=np.float64)
+    s.ic_terms = int(w.shape[0])
+    s.ic_weight = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    s.ic_factor = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return s, (w, f)
+
+
+class Plan:
+    """A plan for one problem: the component grids, their tables on the
+    device, and the entry points of ctm.h."""
+
+    def __init__(self, prob: dict):
+        self.prob = prob
+        s, keep = problem_struct(prob)
+        h = ctypes.c_void_p()
+        _check(_lib.ctm_plan_create(ctypes.byref(s), ctypes.byref(h)))
+        self._h = h
+        G = ctypes.c_int()
+        _check(_lib.ctm_plan_grids(h, ctypes.byref(G)))
+        self.G = G.value
+        n = ctypes.c_longlong()
+        _check(_lib.ctm_plan_state_len(h, ctypes.byref(n)))
+        self.slen = n.value
+        b = ctypes.c_size_t()
+        _check(_lib.ctm_plan_workspace_bytes(h, ctypes.byref(b)))
+        self.workspace_bytes = b.value
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.ctm_plan_destroy(h)
+            self._h = None
+
+    def grid_info(self, g: int):
+        lev = (ctypes.c_int * MAXD)()
+        coef = ctypes.c_double()
+        off = ctypes.c_longlong()
+        npts = ctypes.c_longlong()
+        _check(_lib.ctm_plan_grid_info(self._h, g, lev, ctypes.byref(coef), ctypes.byref(off),
+                                       ctypes.byref(npts)))
+        return tuple(lev[: self.prob["d"]]), coef.value, off.value, npts.value
+
+    def _vec(self, out=None):
+        if out is None:
+            out = torch.empty(self.slen, dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() >= self.slen
+        return out
+
+    def initial_state(self, out=None):
+        out = self._vec(out)
+        _check(_lib.ctm_initial_state(self._h, _ptr(out), _stream()))
+        return out
+
+    def apply(self, x, level: int = 0, out=None):
+        out = self._vec(out)
+        _check(_lib.ctm_apply(self._h, level, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def propagate(self, x, nsteps: int, level: int = 0, per_grid: bool = False, out=None):
+        out = self._vec(out)
+        _check(_lib.ctm_propagate(self._h, level, nsteps, _ptr(x), _ptr(out), int(per_grid),
+                                  _stream()))
+        return out
+
+    def workspace(self):
+        if self._ws is None or self._ws.numel() < self.workspace_bytes:
+            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def solve(self, u0=None, out=None, check: bool = True):
+        """The whole method; returns the packed component states at t1.
+        With check=False returns (state, status) instead of raising."""
+        out = self._vec(out)
+        ws = self.workspace()
+        st = _lib.ctm_solve(self._h, _ptr(ws), ws.numel(), _ptr(u0), _ptr(out), _stream())
+        if check:
+            _check(st)
+            return out
+        return out, st
+
+    def gather(self, u, pts, out=None):
+        pts = pts.contiguous()
+        assert pts.dtype == torch.float64 and pts.is_cuda and pts.shape[1] == self.prob["d"]
+        if out is None:
+            out = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+        _check(_lib.ctm_gather(self._h, _ptr(u), _ptr(pts), pts.shape[0], _ptr(out), _stream()))
+        return out
+
+    def combine_project(self, u, out=None):
+        out = self._vec(out)
+        _check(_lib.ctm_combine_project(self._h, _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(_lib.ctm_get_stats(self._h, ctypes.byref(st)))
+        return dict(blocks=st.blocks, mgrit_iterations=st.mgrit_iterations,
+                    mgrit_residual=list(st.mgrit_residual[: st.history_len]),
+                    phi_solves=st.phi_solves, krylov_iterations=st.krylov_iterations,
+                    krylov_max=st.krylov_max, refine_sweeps=st.refine_sweeps,
+                    refine_max=st.refine_max, status_flags=st.status_flags)
+
+
+def exported_symbols():
+    """Names of the entry points declared in include/ctm.h."""
+    return ["ctm_problem_defaults", "ctm_plan_create", "ctm_plan_destroy", "ctm_plan_grids",
+            "ctm_plan_grid_info", "ctm_plan_state_len", "ctm_plan_workspace_bytes",
+            "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_gather",
+            "ctm_combine_project", "ctm_get_stats", "ctm_status_string", "ctm_last_error"]
