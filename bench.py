@@ -1,0 +1,267 @@
+"""Benchmark of the batched mixed-precision MGRIT + combination solve on one
+MI355X.
+
+A step is one pass of the whole hot path over the workload: sampling of the
+initial value on every component grid, MGRIT over the time interval on all
+grids (FP32 Krylov inside FP64-refined implicit steps), and the FP64
+combination gather at 1e5 seeded points. The workload is the 3-D heat
+equation at sparse-grid level 9 (109 component grids, 73,915 unknowns per
+time level, 256 backward-Euler steps on [0, 0.05], two-level MGRIT with
+c = 8).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBPS = 8000.0
+GATHER_POINTS = 100_000
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload_problem(name: str, prec: str):
+    from workloads import make
+    p = make(name, prec=prec)
+    if prec == "mixed":
+        # FP64-refined implicit steps and MGRIT tolerance chosen so that the
+        # result meets the oracle to 1e-8 relative L2
+        p.update(refine_tol=1e-11, inner_tol=1e-5, refine_maxit=12, mgrit_tol=1e-10,
+                 krylov_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64)
+    else:
+        p.update(krylov_tol=1e-13, mgrit_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64)
+    return p
+
+
+def flops_per_iteration(d: int, krylov: str) -> int:
+    # per unknown: CG = one (2d+1)-point apply (2(2d+1) flops) + 2 dots + 3 axpys;
+    # BiCGStab = two applies + 4 dots + 6 axpys
+    if krylov == "bicgstab":
+        return 2 * 2 * (2 * d + 1) + 20
+    return 2 * (2 * d + 1) + 10
+
+
+def cpu_oracle(prob, pts):
+    """The oracle as it stands on this host: time-sequential backward Euler
+    with sparse LU on every grid, then the combination at the points."""
+    from oracle import combine, solve
+    t0 = time.perf_counter()
+    states = solve.component_states(prob)
+    vals = combine.combine_at(prob, solve.grid_list(prob), states, pts)
+    return time.perf_counter() - t0, solve.packed(states), vals
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="heat3d")
+    ap.add_argument("--no-extras", action="store_true", help="skip the comparator runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(per-GPU sharding by component grid is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2509_22156_amd import ctm
+    from workloads import targets
+
+    torch.cuda.set_device(0)
+    prob = workload_problem(args.workload, "mixed")
+    t0 = time.perf_counter()
+    plan = ctm.Plan(prob)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    pts_np = targets(prob, GATHER_POINTS, seed=0)
+    pts = torch.from_numpy(pts_np).cuda()
+    u = torch.empty(plan.slen, dtype=torch.float64, device="cuda")
+    vals = torch.empty(GATHER_POINTS, dtype=torch.float64, device="cuda")
+    plan.workspace()
+    N = prob["nsteps"]
+    dof_steps = plan.slen * N
+    log(f"workload {args.workload}: G={plan.G} dof/level={plan.slen} N={N} "
+        f"ws={plan.workspace_bytes / 2**20:.1f} MiB")
+
+    def step():
+        plan.solve(out=u)
+        plan.gather(u, pts, out=vals)
+
+    plan.set_timing(False)
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    plan.set_timing(True)
+    agg = dict(chain_ms=0.0, chain_launches=0, krylov_work=0, chain_bytes=0.0,
+               mgrit_iterations=0, krylov_iterations=0, phi_solves=0, refine_sweeps=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        st = plan.stats()
+        for k in agg:
+            agg[k] += st[k]
+        log(f"step {i + 1}/{args.steps}: mgrit it={st['mgrit_iterations']} "
+            f"res={st['mgrit_residual'][-1]:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.set_timing(False)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = dof_steps / (elapsed / args.steps)
+
+    d = prob["d"]
+    fpi = flops_per_iteration(d, prob["krylov"])
+    chain_s = agg["chain_ms"] / 1e3
+    achieved_tflops = agg["krylov_work"] * fpi / chain_s / 1e12 if chain_s > 0 else None
+    launches = max(agg["chain_launches"], 1)
+    roofline = {
+        "kernel": "chain_kernel (batched implicit-step CG, FP32 inner / FP64 refinement)",
+        "bound": "alu",
+        "achieved": achieved_tflops,
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": (achieved_tflops / PEAK_FP32_TFLOPS) if achieved_tflops else None,
+        "traffic": None,
+        "avg_launch_ms": agg["chain_ms"] / launches,
+        "launches": agg["chain_launches"],
+        "algorithmic_flops_per_launch": agg["krylov_work"] * fpi / launches,
+        "algorithmic_hbm_GBps": agg["chain_bytes"] / chain_s / 1e9 if chain_s > 0 else None,
+        "hbm_frac": (agg["chain_bytes"] / chain_s / 1e9 / PEAK_HBM_GBPS) if chain_s > 0 else None,
+    }
+    u_mixed = u.cpu().numpy()
+    vals_mixed = vals.cpu().numpy()
+    it_per_step = agg["mgrit_iterations"] / args.steps
+    log(f"mixed MGRIT: {ms_per_step:.2f} ms/step, {value:.3e} DoF*steps/s, "
+        f"chain {agg['chain_ms'] / args.steps:.2f} ms/step in {launches // args.steps} launches")
+
+    result = {
+        "metric": "DoF*timesteps/s (mixed FP32/FP64 batched MGRIT + combination)",
+        "value": value,
+        "unit": "DoF*timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: heat equation d={d}, sparse-grid level {prob['n']}, "
+                        f"{plan.G} component grids, {plan.slen} DoF per time level, {N} "
+                        f"backward-Euler steps on [0,{prob['t1']}], {prob['mgrit_levels']}-level "
+                        f"MGRIT c={prob['cf']} FCF, CG, mixed precision, gather at "
+                        f"{GATHER_POINTS} points",
+            "grids": plan.G, "dof_per_level": plan.slen, "nsteps": N,
+            "mgrit_iterations_per_step": it_per_step,
+            "phi_solves_per_step": agg["phi_solves"] / args.steps,
+            "krylov_iterations_per_step": agg["krylov_iterations"] / args.steps,
+            "plan_ms": plan_ms,
+        },
+        "roofline": roofline,
+    }
+
+    oracle_u = oracle_vals = None
+    if not args.no_cpu:
+        log("cpu baseline: oracle on the host")
+        t_cpu, oracle_u, oracle_vals = cpu_oracle(prob, pts_np)
+        result["cpu_baseline"] = {
+            "value": dof_steps / t_cpu,
+            "unit": "DoF*timesteps/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"whole workload ({plan.G} grids x {N} steps, sparse LU, single thread) "
+                      f"+ combination at {GATHER_POINTS} points; {t_cpu:.2f} s",
+            "cpu": _cpu_model(),
+        }
+        result["err_vs_oracle"] = {
+            "mixed_state_rel_l2": _rel(u_mixed, oracle_u),
+            "mixed_gather_rel_l2": _rel(vals_mixed, oracle_vals),
+        }
+        log(f"cpu {t_cpu:.2f} s; mixed err {result['err_vs_oracle']}")
+
+    if not args.no_extras:
+        result["comparators"] = _comparators(args, ctm, torch, oracle_u, dof_steps)
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _timed(torch, fn, reps=1):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def _comparators(args, ctm, torch, oracle_u, dof_steps):
+    """FP64 MGRIT, batched time-sequential stepping (mixed and FP64) and the
+    plain per-grid FP64 schedule on the same workload, outside the timed
+    region, each with its error against the oracle."""
+    out = {}
+    runs = [
+        ("fp64_mgrit", workload_problem(args.workload, "fp64"), "solve"),
+        ("mixed_sequential_batched", dict(workload_problem(args.workload, "mixed"),
+                                          mgrit_levels=1), "solve"),
+        ("fp64_sequential_batched", dict(workload_problem(args.workload, "fp64"),
+                                         mgrit_levels=1), "solve"),
+        ("fp64_per_grid_plain", workload_problem(args.workload, "fp64"), "per_grid"),
+    ]
+    for name, prob, kind in runs:
+        plan = ctm.Plan(prob)
+        u0 = plan.initial_state()
+        if kind == "solve":
+            sec, u = _timed(torch, lambda: plan.solve())
+            st = plan.stats()
+        else:
+            sec, u = _timed(torch, lambda: plan.propagate(u0, prob["nsteps"], per_grid=True))
+            st = plan.stats()
+        entry = {"seconds": sec, "value": dof_steps / sec,
+                 "mgrit_iterations": st["mgrit_iterations"],
+                 "krylov_iterations": st["krylov_iterations"]}
+        if oracle_u is not None:
+            entry["state_rel_l2_vs_oracle"] = _rel(u.cpu().numpy(), oracle_u)
+        out[name] = entry
+        log(f"{name}: {sec * 1e3:.1f} ms ({dof_steps / sec:.3e} DoF*steps/s) {entry}")
+    return out
+
+
+if __name__ == "__main__":
+    sys.exit(main())

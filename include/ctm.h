@@ -119,6 +119,11 @@ typedef struct {
   long long refine_sweeps;            /* refinement sweeps summed (mixed path) */
   long long refine_max;               /* largest sweep count of one solve */
   int status_flags;                   /* OR of (1 << ctm_status) met inside kernels */
+  long long krylov_work;              /* sum over solves of Krylov iterations x unknowns */
+  long long chain_launches;           /* launches of the implicit-step kernel */
+  double chain_ms;                    /* their summed duration (only with ctm_set_timing on) */
+  double chain_bytes;                 /* algorithmic HBM bytes those launches move: the
+                                         vectors each task must read and write once */
 } ctm_stats;
 
 /* Fill *p with the paper's solver defaults (Section 4.1): two-level MGRIT,
@@ -184,7 +189,14 @@ ctm_status ctm_gather(ctm_plan* plan, const double* u, const double* pts, long l
  * every grid. u and out must not overlap. Async. */
 ctm_status ctm_combine_project(ctm_plan* plan, const double* u, double* out, ctm_stream s);
 
-/* Statistics of the last ctm_solve / ctm_propagate (reset by each). */
+/* Enable (on != 0) or disable timing of the implicit-step kernel: every
+ * launch made by ctm_solve / ctm_propagate is then bracketed by two HIP
+ * events on the caller's stream and ctm_get_stats reports the summed
+ * duration (chain_ms). Off by default; the plan owns the events. */
+ctm_status ctm_set_timing(ctm_plan* plan, int on);
+
+/* Statistics of the last ctm_solve / ctm_propagate (reset by each). Call
+ * after synchronising the stream the work ran on. */
 ctm_status ctm_get_stats(const ctm_plan* plan, ctm_stats* st);
 
 const char* ctm_status_string(ctm_status st);

@@ -381,6 +381,7 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
       atomicAdd(&a.counters[CNT_REFINE], (unsigned long long)rf_sum);
       atomicMax(&a.counters[CNT_REFINE_MAX], (unsigned long long)rf_max);
       atomicAdd(&a.counters[CNT_SOLVES], (unsigned long long)a.nsteps);
+      atomicAdd(&a.counters[CNT_WORK], (unsigned long long)kr_sum * (unsigned long long)g.npts);
     }
     if (flag && a.status) atomicOr(a.status, flag);
   }

@@ -98,6 +98,9 @@ struct ctm_plan {
   int2* didentity = nullptr;  // (g, 0) in canonical order
   std::map<long long, int2*> interval_tasks;  // M -> (g, q) tasks
   ctm_stats stats;
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // pairs (start, stop) per timed launch
+  size_t events_used = 0;
 
   ~ctm_plan() {
     hipFree(dgrids);
@@ -112,6 +115,7 @@ struct ctm_plan {
     hipFree(didentity);
     if (hsync) hipHostFree(hsync);
     for (auto& kv : interval_tasks) hipFree(kv.second);
+    for (auto e : events) hipEventDestroy(e);
   }
 };
 
@@ -270,20 +274,66 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
 
 VecRef vref(double* base, long long a, long long b) { return VecRef{base, a, b}; }
 
+// Vectors one task must read or write once: start, optional write-back,
+// per-step forcing and intermediate stores, final store and residual target.
+double chain_vectors_per_task(const ChainArgs& a) {
+  double v = 0;
+  if (a.start.base) v += 1;
+  if (a.start_wb.base) v += 1;
+  if (a.forcing.base) v += a.nsteps;
+  if (a.inter.base) v += a.nsteps - 1;
+  if (a.fin.base) v += 1;
+  if (a.target.base) v += 1;
+  return v;
+}
+
 ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const int2* tasks, long long ntasks,
-                     hipStream_t s, bool fp64_only = false) {
+                     hipStream_t s, bool fp64_only = false, long long task_points = -1) {
   ChainArgs c = a;
   c.tasks = tasks;
   const bool mixed = P->mixed && !fp64_only;
   const size_t smem = chain_smem_bytes(P->shape, P->tabmax, mixed);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (P->timing) {
+    while (P->events.size() < P->events_used + 2) {
+      hipEvent_t ev;
+      CTM_HIP(hipEventCreate(&ev));
+      P->events.push_back(ev);
+    }
+    e0 = P->events[P->events_used];
+    e1 = P->events[P->events_used + 1];
+    P->events_used += 2;
+    CTM_HIP(hipEventRecord(e0, s));
+  }
   hipError_t e = launch_chain(P->opc, P->solver, mixed, P->shape, c, (int)ntasks, smem,
                               P->tabmax, s);
   if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("chain launch: ") + hipGetErrorString(e));
+  if (P->timing) CTM_HIP(hipEventRecord(e1, s));
+  // algorithmic bytes: every vector of every task once (tasks cover all grids
+  // for `ntasks / G` intervals unless a single grid is given)
+  const double pts = task_points >= 0 ? (double)task_points
+                                      : (double)P->slen * ((double)ntasks / (double)P->G);
+  P->stats.chain_bytes += 8.0 * pts * chain_vectors_per_task(c);
+  P->stats.chain_launches += 1;
+  return CTM_OK;
+}
+
+// Sum of the timed launch durations (after the stream has been synchronised).
+ctm_status accumulate_timing(ctm_plan* P) {
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < P->events_used; i += 2) {
+    float t = 0.0f;
+    CTM_HIP(hipEventElapsedTime(&t, P->events[i], P->events[i + 1]));
+    ms += t;
+  }
+  P->stats.chain_ms += ms;
+  P->events_used = 0;
   return CTM_OK;
 }
 
 void reset_stats(ctm_plan* P) {
   std::memset(&P->stats, 0, sizeof(P->stats));
+  P->events_used = 0;
 }
 
 ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
@@ -303,7 +353,8 @@ ctm_status collect_device_stats(ctm_plan* P, hipStream_t s) {
   P->stats.refine_max = (long long)c[CNT_REFINE_MAX];
   P->stats.phi_solves = (long long)c[CNT_SOLVES];
   P->stats.status_flags = *reinterpret_cast<int*>(P->hsync + 1);
-  return CTM_OK;
+  P->stats.krylov_work = (long long)c[CNT_WORK];
+  return accumulate_timing(P);
 }
 
 ctm_status status_from_flags(int flags) {
@@ -768,7 +819,8 @@ ctm_status ctm_propagate(ctm_plan* P, int level, long long nsteps, const double*
       ChainArgs a = base_args(P, level, 1, true);
       a.start = vref(const_cast<double*>(nn == 0 ? x : y), 0, 0);
       a.fin = vref(y, 0, 0);
-      if ((st = run_chain(P, a, P->didentity + g, 1, hs, true)) != CTM_OK) return st;
+      if ((st = run_chain(P, a, P->didentity + g, 1, hs, true, P->grids[g].npts)) != CTM_OK)
+        return st;
     }
   }
   return CTM_OK;
@@ -821,8 +873,20 @@ ctm_status ctm_combine_project(ctm_plan* P, const double* u, double* out, ctm_st
   return CTM_OK;
 }
 
-ctm_status ctm_get_stats(const ctm_plan* P, ctm_stats* st) {
-  if (!P || !st) return fail(CTM_ERR_INVALID, "NULL argument");
+ctm_status ctm_set_timing(ctm_plan* P, int on) {
+  if (!P) return fail(CTM_ERR_INVALID, "plan is NULL");
+  P->timing = (on != 0);
+  P->events_used = 0;
+  return CTM_OK;
+}
+
+ctm_status ctm_get_stats(const ctm_plan* Pc, ctm_stats* st) {
+  if (!Pc || !st) return fail(CTM_ERR_INVALID, "NULL argument");
+  ctm_plan* P = const_cast<ctm_plan*>(Pc);
+  if (P->events_used) {
+    ctm_status s2 = accumulate_timing(P);
+    if (s2 != CTM_OK) return s2;
+  }
   // counters live on the device; the caller has synchronised its stream
   unsigned long long c[CNT_N];
   int flags = 0;
@@ -835,6 +899,7 @@ ctm_status ctm_get_stats(const ctm_plan* P, ctm_stats* st) {
   st->refine_max = (long long)c[CNT_REFINE_MAX];
   st->phi_solves = (long long)c[CNT_SOLVES];
   st->status_flags = flags;
+  st->krylov_work = (long long)c[CNT_WORK];
   return CTM_OK;
 }
 

@@ -82,6 +82,7 @@ enum {
   CNT_REFINE = 2,
   CNT_REFINE_MAX = 3,
   CNT_SOLVES = 4,
+  CNT_WORK = 5,
   CNT_N = 8
 };
 

@@ -52,6 +52,8 @@ class Stats(ctypes.Structure):
         ("phi_solves", ctypes.c_longlong), ("krylov_iterations", ctypes.c_longlong),
         ("krylov_max", ctypes.c_longlong), ("refine_sweeps", ctypes.c_longlong),
         ("refine_max", ctypes.c_longlong), ("status_flags", ctypes.c_int),
+        ("krylov_work", ctypes.c_longlong), ("chain_launches", ctypes.c_longlong),
+        ("chain_ms", ctypes.c_double), ("chain_bytes", ctypes.c_double),
     ]
 
 
@@ -83,6 +85,7 @@ def _load():
         "ctm_gather": [P, P, P, ll, P, P],
         "ctm_combine_project": [P, P, P, P],
         "ctm_get_stats": [P, ctypes.POINTER(Stats)],
+        "ctm_set_timing": [P, i],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -254,7 +257,12 @@ class Plan:
                     mgrit_residual=list(st.mgrit_residual[: st.history_len]),
                     phi_solves=st.phi_solves, krylov_iterations=st.krylov_iterations,
                     krylov_max=st.krylov_max, refine_sweeps=st.refine_sweeps,
-                    refine_max=st.refine_max, status_flags=st.status_flags)
+                    refine_max=st.refine_max, status_flags=st.status_flags,
+                    krylov_work=st.krylov_work, chain_launches=st.chain_launches,
+                    chain_ms=st.chain_ms, chain_bytes=st.chain_bytes)
+
+    def set_timing(self, on: bool = True):
+        _check(_lib.ctm_set_timing(self._h, int(on)))
 
 
 def exported_symbols():
@@ -262,4 +270,5 @@ def exported_symbols():
     return ["ctm_problem_defaults", "ctm_plan_create", "ctm_plan_destroy", "ctm_plan_grids",
             "ctm_plan_grid_info", "ctm_plan_state_len", "ctm_plan_workspace_bytes",
             "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_gather",
-            "ctm_combine_project", "ctm_get_stats", "ctm_status_string", "ctm_last_error"]
+            "ctm_combine_project", "ctm_get_stats", "ctm_set_timing", "ctm_status_string",
+            "ctm_last_error"]
