@@ -1,7 +1,7 @@
 // Auxiliary kernels: initial value sampling, standalone stencil apply,
 // combination gather / combine-then-project, norms and vector updates of
 // the MGRIT driver, and the dispatch of the chain kernel instantiations.
-#include "device_common.hpp"
+#include "line_layout.hpp"
 
 namespace ctm {
 
@@ -68,17 +68,16 @@ hipError_t launch_initial_state(const GridDev* grids, int G, int maxpts, int nle
 }
 
 // ---------------------------------------------------------- stencil apply
-// y = (I + dt L_l) x on every grid, one work-group per grid, FP64; the same
-// device stencil the Krylov solvers use.
+// y = (I + dt L_l) x on every grid, one work-group per grid, FP64, in the
+// same line layout and with the same device stencil the solvers use.
 template <int OPC, int W, int K>
 __global__ void __launch_bounds__(64 * W)
     apply_kernel(const GridDev* __restrict__ grids, const double* __restrict__ tab64, double amp,
-                 double dt, const double* __restrict__ x, double* __restrict__ y) {
+                 double dt, const double* __restrict__ x, double* __restrict__ y, int vcap) {
   constexpr int BS = 64 * W;
-  constexpr int CAP = BS * K;
   extern __shared__ __align__(16) unsigned char smem[];
   double* xl = reinterpret_cast<double*>(smem);
-  double* tl = xl + CAP;
+  double* tl = xl + vcap;
   __shared__ GridDev gs;
   {
     const int* src = reinterpret_cast<const int*>(grids + blockIdx.x);
@@ -88,42 +87,45 @@ __global__ void __launch_bounds__(64 * W)
   __syncthreads();
   const GridDev& g = gs;
   load_tables<OPC, double, BS>(g, tab64, dt, tl);
-  Pts<K> P;
-  setup_points<BS, K>(g, P);
+  __syncthreads();
+  Lane<K> L;
+  setup_lane<K>(g, L);
+  LineOp<OPC, double, K> O;
+  lineop_setup<OPC, double, K>(g, L, dt, amp, tl, O);
   double xs[K], ys[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    xs[k] = (P.p[k] >= 0) ? x[g.off + P.p[k]] : 0.0;
-    if (P.p[k] >= 0) xl[P.p[k]] = xs[k];
-  }
+  for (int k = 0; k < K; ++k)
+    xs[k] = (k < L.nval) ? x[g.off + L.cbase + (long long)k * L.cstep] : 0.0;
+  lds_put<double, K>(L, xl, xs);
   __syncthreads();
-  Stencil<OPC, double, K> S;
-  stencil_setup<OPC, double, K>(g, P, dt, amp, tl, S);
-  stencil_apply<OPC, double, K>(g, P, S, tl, xl, xs, ys);
+  line_apply<OPC, double, K>(g, L, O, xl, xs, ys);
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (P.p[k] >= 0) y[g.off + P.p[k]] = ys[k];
+    if (k < L.nval) y[g.off + L.cbase + (long long)k * L.cstep] = ys[k];
 }
 
 template <int OPC>
 static hipError_t launch_apply_t(int shape, const GridDev* grids, int G, const double* tab64,
                                  double amp, double dt, int tabmax, const double* x, double* y,
                                  hipStream_t s) {
-  const size_t smem = (size_t)(64 * kShapes[shape].W * kShapes[shape].K + tabmax) * sizeof(double);
+  const int vcap = 64 * kShapes[shape].W * kShapes[shape].K;
+  const size_t smem = (size_t)(vcap + tabmax) * sizeof(double);
 #define CTM_ACASE(IDX, W, K)                                                                   \
   case IDX:                                                                                    \
     hipLaunchKernelGGL((apply_kernel<OPC, W, K>), dim3(G), dim3(64 * W), smem, s, grids, tab64, \
-                       amp, dt, x, y);                                                         \
+                       amp, dt, x, y, vcap);                                                   \
     break;
   switch (shape) {
-    CTM_ACASE(0, 1, 1)
-    CTM_ACASE(1, 1, 2)
-    CTM_ACASE(2, 1, 4)
-    CTM_ACASE(3, 2, 4)
-    CTM_ACASE(4, 4, 4)
-    CTM_ACASE(5, 4, 8)
-    CTM_ACASE(6, 8, 8)
-    CTM_ACASE(7, 16, 8)
+    CTM_ACASE(0, 1, 4)
+    CTM_ACASE(1, 2, 4)
+    CTM_ACASE(2, 4, 4)
+    CTM_ACASE(3, 8, 4)
+    CTM_ACASE(4, 16, 4)
+    CTM_ACASE(5, 1, 8)
+    CTM_ACASE(6, 2, 8)
+    CTM_ACASE(7, 4, 8)
+    CTM_ACASE(8, 8, 8)
+    CTM_ACASE(9, 16, 8)
     default:
       return hipErrorInvalidValue;
   }

@@ -1,18 +1,20 @@
 // The batched implicit-step kernel ("chain"): one work-group per task
 // (component grid g, time interval q). A task loads its start vector into
-// registers and applies `nsteps` backward-Euler steps v <- Phi(v) + f_j, each
-// solved matrix-free by CG or BiCGStab with all vectors held on chip
-// (registers for the thread's own points, one LDS copy of the vector the
-// stencil reads). This single kernel carries every time-stepping phase:
-// MGRIT F-, C- and FC-relaxation, the C-point residual, the sequential
-// coarse-level solve and plain time-sequential stepping; they differ only
+// registers and applies `nsteps` backward-Euler steps v <- Phi(v) + f_j
+// (Section 2, time propagation), each solved matrix-free by preconditioned
+// CG or BiCGStab (Section 4.1) with every vector held on chip: the lane's
+// own unknowns in registers, one LDS copy of the vector the stencil reads.
+// This one kernel carries every time-stepping phase of MGRIT (F-, C- and
+// FC-relaxation, the C-point residual, the sequential coarse-level solve;
+// Section 2.3.1) and plain time-sequential stepping; the phases differ only
 // in which vectors are read and written (see ChainArgs).
 //
 // Precision: FP64, or mixed: FP64 iterative refinement of each implicit
-// step (FP64 residual b - A x), with the correction solved by FP32 Krylov.
+// step (FP64 residual b - A x) around an FP32 preconditioned Krylov solve of
+// the correction.
 #pragma once
 
-#include "device_common.hpp"
+#include "line_layout.hpp"
 
 namespace ctm {
 
@@ -24,104 +26,134 @@ __device__ __forceinline__ bool finite_val(T v) {
   return v == v && v - v == (T)0;
 }
 
-// Unpreconditioned CG (Section 4.1, symmetric operators) on the work-group.
-// x holds the initial guess; stops when ||b - A x||_2^2 <= tol2 * bb on the
-// recursively updated residual. Returns the iteration count; *flag gets
-// FLAG_NOCONV / FLAG_NONFINITE on failure.
-template <int OPC, typename T, int W, int K>
-__device__ __forceinline__ int krylov_cg(const GridDev& g, const Pts<K>& P,
-                                         const Stencil<OPC, T, K>& S, const T* tab, T* xl,
-                                         RedRing& ring, T (&x)[K], const T (&b)[K], T bb,
-                                         T tol2, int maxit, int* flag) {
-  T r[K], p[K], q[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (P.p[k] >= 0) xl[P.p[k]] = x[k];
+template <int OPC, typename T, int K>
+struct Solver {
+  const GridDev& g;
+  const Lane<K>& L;
+  const LineOp<OPC, T, K>& O;
+  const LinePre<T, K>& M;
+  T* xl;  // LDS vector (precision T)
+};
+
+// y = A x (x written to LDS first; one barrier).
+template <int OPC, typename T, int K>
+__device__ __forceinline__ void sapply(const Solver<OPC, T, K>& S, const T (&x)[K], T (&y)[K]) {
+  lds_put<T, K>(S.L, S.xl, x);
   __syncthreads();
-  stencil_apply<OPC, T, K>(g, P, S, tab, xl, x, q);
-  T s1[1] = {(T)0};
+  line_apply<OPC, T, K>(S.g, S.L, S.O, S.xl, x, y);
+}
+
+// Preconditioned CG in the single-reduction form of Chronopoulos and Gear:
+// per iteration one preconditioner solve, one stencil apply and one fused
+// reduction of (r,z), (Az,z), (r,r). x holds the initial guess (x_zero:
+// it is zero and the first apply is skipped). Stops when
+// ||b - A x||_2^2 <= tol2 * bb on the recursively updated residual.
+template <int OPC, typename T, int W, int K>
+__device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
+                                          const T (&b)[K], bool x_zero, T bb, T tol2, int maxit,
+                                          int* flag) {
+  T r[K], z[K], w[K], p[K], s[K];
+  if (x_zero) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = b[k];
+  } else {
+    sapply<OPC, T, K>(S, x, w);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = b[k] - w[k];
+    __syncthreads();  // every wave has read x from LDS before z overwrites it
+  }
+  linepre_apply<T, K>(S.L, S.M, r, z);
+  sapply<OPC, T, K>(S, z, w);
+  T red[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    r[k] = b[k] - q[k];
-    p[k] = r[k];
-    s1[0] += r[k] * r[k];
+    red[0] += r[k] * z[k];
+    red[1] += w[k] * z[k];
+    red[2] += r[k] * r[k];
   }
-  block_sum<W, 1, T>(s1, ring);
-  T rr = s1[0];
-  if (!finite_val(rr)) {
+  block_sum<W, 3, T>(red, ring);
+  if (!finite_val(red[2]) || !finite_val(red[1])) {
     *flag |= FLAG_NONFINITE;
     return 0;
   }
-  if (rr <= tol2 * bb) return 0;
+  if (red[2] <= tol2 * bb) return 0;
+  T gamma = red[0];
+  T alpha = gamma / red[1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    p[k] = z[k];
+    s[k] = w[k];
+  }
   for (int it = 1; it <= maxit; ++it) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (P.p[k] >= 0) xl[P.p[k]] = p[k];
-    __syncthreads();
-    stencil_apply<OPC, T, K>(g, P, S, tab, xl, p, q);
-    T s2[1] = {(T)0};
-#pragma unroll
-    for (int k = 0; k < K; ++k) s2[0] += p[k] * q[k];
-    block_sum<W, 1, T>(s2, ring);
-    const T alpha = rr / s2[0];
-    T s3[1] = {(T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       x[k] += alpha * p[k];
-      r[k] -= alpha * q[k];
-      s3[0] += r[k] * r[k];
+      r[k] -= alpha * s[k];
     }
-    block_sum<W, 1, T>(s3, ring);
-    const T rn = s3[0];
-    if (!finite_val(rn)) {
+    linepre_apply<T, K>(S.L, S.M, r, z);
+    sapply<OPC, T, K>(S, z, w);
+    T rd[3] = {(T)0, (T)0, (T)0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      rd[0] += r[k] * z[k];
+      rd[1] += w[k] * z[k];
+      rd[2] += r[k] * r[k];
+    }
+    block_sum<W, 3, T>(rd, ring);
+    if (!finite_val(rd[2]) || !finite_val(rd[1])) {
       *flag |= FLAG_NONFINITE;
       return it;
     }
-    if (rn <= tol2 * bb) return it;
-    const T beta = rn / rr;
-    rr = rn;
+    if (rd[2] <= tol2 * bb) return it;
+    const T beta = rd[0] / gamma;
+    const T den = rd[1] - beta * rd[0] / alpha;
+    if (den == (T)0 || !finite_val(den)) {
+      *flag |= FLAG_BREAKDOWN;
+      return it;
+    }
+    alpha = rd[0] / den;
+    gamma = rd[0];
 #pragma unroll
-    for (int k = 0; k < K; ++k) p[k] = r[k] + beta * p[k];
+    for (int k = 0; k < K; ++k) {
+      p[k] = z[k] + beta * p[k];
+      s[k] = w[k] + beta * s[k];
+    }
   }
   *flag |= FLAG_NOCONV;
   return maxit;
 }
 
-// Unpreconditioned BiCGStab (van der Vorst; Section 4.1, non-symmetric
-// operators), shadow residual r^ = r_0.
+// Right-preconditioned BiCGStab (van der Vorst), shadow residual r^ = r_0.
 template <int OPC, typename T, int W, int K>
-__device__ __forceinline__ int krylov_bicgstab(const GridDev& g, const Pts<K>& P,
-                                               const Stencil<OPC, T, K>& S, const T* tab, T* xl,
-                                               RedRing& ring, T (&x)[K], const T (&b)[K],
-                                               T bb, T tol2, int maxit, int* flag) {
-  T r[K], rh[K], p[K], v[K], s[K], t[K];
+__device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedRing& ring,
+                                                T (&x)[K], const T (&b)[K], bool x_zero, T bb,
+                                                T tol2, int maxit, int* flag) {
+  T r[K], rh[K], p[K], v[K], s[K], t[K], h[K];
+  if (x_zero) {
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (P.p[k] >= 0) xl[P.p[k]] = x[k];
-  __syncthreads();
-  stencil_apply<OPC, T, K>(g, P, S, tab, xl, x, v);
+    for (int k = 0; k < K; ++k) r[k] = b[k];
+  } else {
+    sapply<OPC, T, K>(S, x, v);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = b[k] - v[k];
+  }
   T s1[1] = {(T)0};
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    r[k] = b[k] - v[k];
     rh[k] = r[k];
     p[k] = r[k];
     s1[0] += r[k] * r[k];
   }
   block_sum<W, 1, T>(s1, ring);
-  T rr = s1[0];
-  if (!finite_val(rr)) {
+  if (!finite_val(s1[0])) {
     *flag |= FLAG_NONFINITE;
     return 0;
   }
-  if (rr <= tol2 * bb) return 0;
-  T rho = rr;
+  if (s1[0] <= tol2 * bb) return 0;
+  T rho = s1[0];
   for (int it = 1; it <= maxit; ++it) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (P.p[k] >= 0) xl[P.p[k]] = p[k];
-    __syncthreads();
-    stencil_apply<OPC, T, K>(g, P, S, tab, xl, p, v);
+    linepre_apply<T, K>(S.L, S.M, p, h);
+    sapply<OPC, T, K>(S, h, v);
     T s2[1] = {(T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) s2[0] += rh[k] * v[k];
@@ -132,12 +164,12 @@ __device__ __forceinline__ int krylov_bicgstab(const GridDev& g, const Pts<K>& P
     }
     const T alpha = rho / s2[0];
 #pragma unroll
-    for (int k = 0; k < K; ++k) s[k] = r[k] - alpha * v[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (P.p[k] >= 0) xl[P.p[k]] = s[k];
-    __syncthreads();
-    stencil_apply<OPC, T, K>(g, P, S, tab, xl, s, t);
+    for (int k = 0; k < K; ++k) {
+      x[k] += alpha * h[k];
+      s[k] = r[k] - alpha * v[k];
+    }
+    linepre_apply<T, K>(S.L, S.M, s, h);
+    sapply<OPC, T, K>(S, h, t);
     T s3[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -146,11 +178,7 @@ __device__ __forceinline__ int krylov_bicgstab(const GridDev& g, const Pts<K>& P
       s3[2] += s[k] * s[k];
     }
     block_sum<W, 3, T>(s3, ring);
-    if (s3[2] <= tol2 * bb) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) x[k] += alpha * p[k];
-      return it;
-    }
+    if (s3[2] <= tol2 * bb) return it;
     if (s3[1] == (T)0 || !finite_val(s3[1])) {
       *flag |= finite_val(s3[1]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
       return it;
@@ -159,7 +187,7 @@ __device__ __forceinline__ int krylov_bicgstab(const GridDev& g, const Pts<K>& P
     T s4[2] = {(T)0, (T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      x[k] += alpha * p[k] + omega * s[k];
+      x[k] += omega * h[k];
       r[k] = s[k] - omega * t[k];
       s4[0] += r[k] * r[k];
       s4[1] += rh[k] * r[k];
@@ -184,14 +212,13 @@ __device__ __forceinline__ int krylov_bicgstab(const GridDev& g, const Pts<K>& P
 }
 
 template <int OPC, int SOLVER, typename T, int W, int K>
-__device__ __forceinline__ int krylov(const GridDev& g, const Pts<K>& P,
-                                      const Stencil<OPC, T, K>& S, const T* tab, T* xl,
-                                      RedRing& ring, T (&x)[K], const T (&b)[K], T bb, T tol2,
-                                      int maxit, int* flag) {
+__device__ __forceinline__ int krylov(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
+                                      const T (&b)[K], bool x_zero, T bb, T tol2, int maxit,
+                                      int* flag) {
   if constexpr (SOLVER == SOLV_CG)
-    return krylov_cg<OPC, T, W, K>(g, P, S, tab, xl, ring, x, b, bb, tol2, maxit, flag);
+    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, bb, tol2, maxit, flag);
   else
-    return krylov_bicgstab<OPC, T, W, K>(g, P, S, tab, xl, ring, x, b, bb, tol2, maxit, flag);
+    return krylov_pbicgstab<OPC, T, W, K>(S, ring, x, b, x_zero, bb, tol2, maxit, flag);
 }
 
 __device__ __forceinline__ double* vec_at(const VecRef& r, long long idx, long long slen,
@@ -199,18 +226,100 @@ __device__ __forceinline__ double* vec_at(const VecRef& r, long long idx, long l
   return r.base + idx * slen + off;
 }
 
+template <int K>
+__device__ __forceinline__ void gload(const Lane<K>& L, const double* src, double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = (k < L.nval) ? src[L.cbase + (long long)k * L.cstep] : 0.0;
+}
+template <int K>
+__device__ __forceinline__ void gstore(const Lane<K>& L, double* dst, const double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (k < L.nval) dst[L.cbase + (long long)k * L.cstep] = v[k];
+}
+
+// One implicit step in FP64: x <- (I + dt L)^-1 v.
+template <int OPC, int SOLVER, int W, int K>
+__device__ __forceinline__ void step_fp64(const Solver<OPC, double, K>& S, RedRing& ring,
+                                          const double (&v)[K], double bb, double tol2,
+                                          int maxit, double (&x)[K], int* flag,
+                                          long long& kr_sum, long long& kr_max) {
+  const int it = krylov<OPC, SOLVER, double, W, K>(S, ring, x, v, false, bb, tol2, maxit, flag);
+  kr_sum += it;
+  kr_max = it > kr_max ? it : kr_max;
+}
+
+// One implicit step by FP64 iterative refinement around FP32 Krylov solves.
+template <int OPC, int SOLVER, int W, int K>
+__device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
+                                           const Solver<OPC, float, K>& S32, RedRing& ring,
+                                           const double (&v)[K], double bb, double tol2,
+                                           float itol2, int maxit, int refine_maxit,
+                                           double (&x)[K], int* flag, long long& kr_sum,
+                                           long long& kr_max, long long& rf_sum,
+                                           long long& rf_max) {
+  bool conv = false;
+  int sweeps = 0, its = 0;
+  for (; sweeps <= refine_maxit; ++sweeps) {
+    double rq[K];
+    sapply<OPC, double, K>(S64, x, rq);
+    double rr[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      rq[k] = v[k] - rq[k];
+      rr[0] += rq[k] * rq[k];
+    }
+    block_sum<W, 1, double>(rr, ring);
+    if (!finite_val(rr[0])) {
+      *flag |= FLAG_NONFINITE;
+      break;
+    }
+    if (rr[0] <= tol2 * bb) {
+      conv = true;
+      break;
+    }
+    if (sweeps == refine_maxit) break;
+    const double nr = sqrt(rr[0]);
+    const double inv = 1.0 / nr;
+    float r32[K], d32[K];
+    float bb32 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      r32[k] = (float)(rq[k] * inv);
+      d32[k] = 0.0f;
+      bb32 += r32[k] * r32[k];
+    }
+    float bbs[1] = {bb32};
+    block_sum<W, 1, float>(bbs, ring);
+    int iflag = 0;
+    const int it =
+        krylov<OPC, SOLVER, float, W, K>(S32, ring, d32, r32, true, bbs[0], itol2, maxit, &iflag);
+    its += it;
+    if (iflag & FLAG_NONFINITE) {
+      *flag |= FLAG_NONFINITE;
+      break;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] += nr * (double)d32[k];
+  }
+  if (!conv) *flag |= FLAG_NOCONV;
+  kr_sum += its;
+  kr_max = its > kr_max ? its : kr_max;
+  rf_sum += sweeps;
+  rf_max = sweeps > rf_max ? sweeps : rf_max;
+}
+
 template <int OPC, int SOLVER, bool MIXED, int W, int K>
-__global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
+__global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax, int vcap) {
   constexpr int BS = 64 * W;
-  constexpr int CAP = BS * K;
   extern __shared__ __align__(16) unsigned char smem[];
   double* xl64 = reinterpret_cast<double*>(smem);
   float* xl32 = reinterpret_cast<float*>(smem);
-  double* tl64 = reinterpret_cast<double*>(smem + CAP * sizeof(double));
+  double* tl64 = reinterpret_cast<double*>(smem + (size_t)vcap * sizeof(double));
   float* tl32 = reinterpret_cast<float*>(tl64 + tabmax);
   const size_t tab_bytes =
       (size_t)tabmax * sizeof(double) + (MIXED ? (size_t)tabmax * sizeof(float) : 0);
-  double* red = reinterpret_cast<double*>(smem + CAP * sizeof(double) +
+  double* red = reinterpret_cast<double*>(smem + (size_t)vcap * sizeof(double) +
                                           ((tab_bytes + 15) & ~size_t(15)));
   __shared__ GridDev gs;
 
@@ -227,34 +336,40 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
   if constexpr (MIXED) load_tables<OPC, float, BS>(g, a.tab64, a.dt, tl32);
   __syncthreads();
 
-  Pts<K> P;
-  setup_points<BS, K>(g, P);
-  Stencil<OPC, double, K> S64;
-  stencil_setup<OPC, double, K>(g, P, a.dt, a.amp, tl64, S64);
-  Stencil<OPC, float, K> S32;
-  if constexpr (MIXED) stencil_setup<OPC, float, K>(g, P, a.dt, a.amp, tl32, S32);
+  Lane<K> L;
+  setup_lane<K>(g, L);
+  LineOp<OPC, double, K> O64;
+  lineop_setup<OPC, double, K>(g, L, a.dt, a.amp, tl64, O64);
 
   const long long off = g.off;
   double v[K];
   if (a.start.base) {
-    const double* src = vec_at(a.start, a.start.a * q + a.start.b, a.slen, off);
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = (P.p[k] >= 0) ? src[P.p[k]] : 0.0;
+    gload<K>(L, vec_at(a.start, a.start.a * q + a.start.b, a.slen, off), v);
   } else {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = 0.0;
   }
-  if (a.start_wb.base) {
-    double* dst = vec_at(a.start_wb, a.start_wb.a * q + a.start_wb.b, a.slen, off);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (P.p[k] >= 0) dst[P.p[k]] = v[k];
-  }
+  if (a.start_wb.base)
+    gstore<K>(L, vec_at(a.start_wb, a.start_wb.a * q + a.start_wb.b, a.slen, off), v);
 
   RedRing ring{red, 0};
   int flag = 0;
   long long kr_sum = 0, kr_max = 0, rf_sum = 0, rf_max = 0;
   const double tol2 = a.tol * a.tol;
+
+  // preconditioner and FP32 operator (mixed) are built once per chain
+  LinePre<double, K> M64;
+  LineOp<OPC, float, K> O32;
+  LinePre<float, K> M32;
+  if constexpr (MIXED) {
+    lineop_setup<OPC, float, K>(g, L, a.dt, a.amp, tl32, O32);
+    linepre_setup<OPC, float, K>(L, O32, M32);
+  } else {
+    linepre_setup<OPC, double, K>(L, O64, M64);
+  }
+  const Solver<OPC, double, K> S64{g, L, O64, M64, xl64};
+  const Solver<OPC, float, K> S32{g, L, O32, M32, xl32};
+  const float itol2 = (float)(a.inner_tol * a.inner_tol);
 
   for (int j = 1; j <= a.nsteps; ++j) {
     double bbv[1] = {0.0};
@@ -263,114 +378,46 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
     block_sum<W, 1, double>(bbv, ring);
     const double bb = bbv[0];
     double x[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = (bb == 0.0) ? 0.0 : v[k];
     if (!finite_val(bb)) {
       flag |= FLAG_NONFINITE;
-#pragma unroll
-      for (int k = 0; k < K; ++k) x[k] = v[k];
-    } else if (bb == 0.0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) x[k] = 0.0;
-    } else if constexpr (!MIXED) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) x[k] = v[k];
-      const int it = krylov<OPC, SOLVER, double, W, K>(g, P, S64, tl64, xl64, ring, x, v,
-                                                       bb, tol2, a.maxit, &flag);
-      kr_sum += it;
-      kr_max = it > kr_max ? it : kr_max;
-    } else {
-      // FP64 iterative refinement around an FP32 Krylov correction solve
-#pragma unroll
-      for (int k = 0; k < K; ++k) x[k] = v[k];
-      const float itol2 = (float)(a.inner_tol * a.inner_tol);
-      bool conv = false;
-      int sweeps = 0, its = 0;
-      for (; sweeps <= a.refine_maxit; ++sweeps) {
-        double rq[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-          if (P.p[k] >= 0) xl64[P.p[k]] = x[k];
-        __syncthreads();
-        stencil_apply<OPC, double, K>(g, P, S64, tl64, xl64, x, rq);
-        double rr[1] = {0.0};
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          rq[k] = v[k] - rq[k];
-          rr[0] += rq[k] * rq[k];
-        }
-        block_sum<W, 1, double>(rr, ring);
-        if (!finite_val(rr[0])) {
-          flag |= FLAG_NONFINITE;
-          break;
-        }
-        if (rr[0] <= tol2 * bb) {
-          conv = true;
-          break;
-        }
-        if (sweeps == a.refine_maxit) break;
-        const double nr = sqrt(rr[0]);
-        const double inv = 1.0 / nr;
-        float r32[K], d32[K];
-        float bb32 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          r32[k] = (float)(rq[k] * inv);
-          d32[k] = 0.0f;
-          bb32 += r32[k] * r32[k];
-        }
-        float bbs[1] = {bb32};
-        block_sum<W, 1, float>(bbs, ring);
-        int iflag = 0;
-        const int it = krylov<OPC, SOLVER, float, W, K>(g, P, S32, tl32, xl32, ring, d32,
-                                                        r32, bbs[0], itol2, a.maxit, &iflag);
-        its += it;
-        if (iflag & FLAG_NONFINITE) {
-          flag |= FLAG_NONFINITE;
-          break;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) x[k] += nr * (double)d32[k];
-      }
-      if (!conv) flag |= FLAG_NOCONV;
-      kr_sum += its;
-      kr_max = its > kr_max ? its : kr_max;
-      rf_sum += sweeps;
-      rf_max = sweeps > rf_max ? sweeps : rf_max;
+    } else if (bb != 0.0) {
+      if constexpr (MIXED)
+        step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, bb, tol2, itol2, a.maxit,
+                                      a.refine_maxit, x, &flag, kr_sum, kr_max, rf_sum, rf_max);
+      else
+        step_fp64<OPC, SOLVER, W, K>(S64, ring, v, bb, tol2, a.maxit, x, &flag, kr_sum, kr_max);
     }
     if (a.forcing.base) {
-      const double* f = vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off);
+      double f[K];
+      gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[k] = x[k] + ((P.p[k] >= 0) ? f[P.p[k]] : 0.0);
+      for (int k = 0; k < K; ++k) v[k] = x[k] + f[k];
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) v[k] = x[k];
     }
-    if (a.inter.base && j < a.nsteps) {
-      double* dst = vec_at(a.inter, a.inter.a * q + a.inter.b + j, a.slen, off);
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (P.p[k] >= 0) dst[P.p[k]] = v[k];
-    }
+    if (a.inter.base && j < a.nsteps)
+      gstore<K>(L, vec_at(a.inter, a.inter.a * q + a.inter.b + j, a.slen, off), v);
   }
 
   if (a.fin.base) {
     double* dst = vec_at(a.fin, a.fin.a * q + a.fin.b, a.slen, off);
     if (a.target.base) {
-      const double* tg = vec_at(a.target, a.target.a * q + a.target.b, a.slen, off);
+      double tg[K];
+      gload<K>(L, vec_at(a.target, a.target.a * q + a.target.b, a.slen, off), tg);
       double rr[1] = {0.0};
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (P.p[k] >= 0) {
-          const double r = v[k] - tg[P.p[k]];
-          dst[P.p[k]] = r;
-          rr[0] += r * r;
-        }
+        v[k] = (k < L.nval) ? v[k] - tg[k] : 0.0;
+        rr[0] += v[k] * v[k];
       }
+      gstore<K>(L, dst, v);
       block_sum<W, 1, double>(rr, ring);
       if (threadIdx.x == 0 && a.res2) a.res2[blockIdx.x] = rr[0];
     } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (P.p[k] >= 0) dst[P.p[k]] = v[k];
+      gstore<K>(L, dst, v);
     }
   }
 
@@ -391,24 +438,27 @@ template <int OPC, int SOLVER>
 hipError_t launch_chain_t(bool mixed, int shape, const ChainArgs& a, int ntasks, size_t smem,
                           int tabmax, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
+  const int vcap = 64 * kShapes[shape].W * kShapes[shape].K;
 #define CTM_CASE(IDX, W, K)                                                                   \
   case IDX:                                                                                   \
     if (mixed)                                                                                \
       hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, W, K>), dim3(ntasks), dim3(64 * W), \
-                         smem, s, a, tabmax);                                                 \
+                         smem, s, a, tabmax, vcap);                                           \
     else                                                                                      \
       hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, W, K>), dim3(ntasks),              \
-                         dim3(64 * W), smem, s, a, tabmax);                                   \
+                         dim3(64 * W), smem, s, a, tabmax, vcap);                             \
     break;
   switch (shape) {
-    CTM_CASE(0, 1, 1)
-    CTM_CASE(1, 1, 2)
-    CTM_CASE(2, 1, 4)
-    CTM_CASE(3, 2, 4)
-    CTM_CASE(4, 4, 4)
-    CTM_CASE(5, 4, 8)
-    CTM_CASE(6, 8, 8)
-    CTM_CASE(7, 16, 8)
+    CTM_CASE(0, 1, 4)
+    CTM_CASE(1, 2, 4)
+    CTM_CASE(2, 4, 4)
+    CTM_CASE(3, 8, 4)
+    CTM_CASE(4, 16, 4)
+    CTM_CASE(5, 1, 8)
+    CTM_CASE(6, 2, 8)
+    CTM_CASE(7, 4, 8)
+    CTM_CASE(8, 8, 8)
+    CTM_CASE(9, 16, 8)
     default:
       return hipErrorInvalidValue;
   }

@@ -225,13 +225,33 @@ ctm_status validate(const ctm_problem* p) {
   return CTM_OK;
 }
 
-int pick_shape(int maxpts) {
-  if (const char* env = std::getenv("CTM_SHAPE")) {
-    const int s = std::atoi(env);
-    if (s >= 0 && s < kNumShapes && 64 * kShapes[s].W * kShapes[s].K >= maxpts) return s;
+// Lanes a grid needs in the line layout with K unknowns per lane.
+int lanes_needed(const GridDev& gd, int K) {
+  int lc = (gd.ns + K - 1) / K;
+  int p = 1;
+  while (p < lc) p <<= 1;
+  return gd.nlines * p;
+}
+
+// Smallest K whose chunks keep every line inside one wave, then the
+// smallest work-group that holds the largest grid.
+int pick_shape(const std::vector<GridDev>& gds) {
+  int maxns = 0;
+  for (auto& gd : gds) maxns = std::max(maxns, gd.ns);
+  const int env = std::getenv("CTM_SHAPE") ? std::atoi(std::getenv("CTM_SHAPE")) : -1;
+  auto fits = [&](int s) {
+    const int K = kShapes[s].K, W = kShapes[s].W;
+    if (maxns > 64 * K) return false;
+    for (auto& gd : gds)
+      if (lanes_needed(gd, K) > 64 * W) return false;
+    return true;
+  };
+  if (env >= 0 && env < kNumShapes && fits(env)) return env;
+  for (int K : {4, 8}) {
+    if (maxns > 64 * K) continue;
+    for (int s = 0; s < kNumShapes; ++s)
+      if (kShapes[s].K == K && fits(s)) return s;
   }
-  for (int s = 0; s < kNumShapes; ++s)
-    if (64 * kShapes[s].W * kShapes[s].K >= maxpts) return s;
   return -1;
 }
 
@@ -660,10 +680,9 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   P->G = (int)P->grids.size();
   P->slen = off;
   for (auto& gh : P->grids) P->maxpts = (int)std::max<long long>(P->maxpts, gh.npts);
-  P->shape = pick_shape(P->maxpts);
-  if (P->shape < 0) {
+  if (P->maxpts > (1 << 20)) {
     delete P;
-    return fail(CTM_ERR_INVALID, "a component grid exceeds 8192 unknowns (on-chip solver limit)");
+    return fail(CTM_ERR_INVALID, "a component grid exceeds the on-chip solver");
   }
 
   const double dt0 = (prob->t1 - prob->t0) / (double)prob->nsteps;
@@ -681,6 +700,7 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
       gd.lev[i] = gh.lev[i];
       gd.n[i] = P->lattice ? (1 << gh.lev[i]) : ((1 << gh.lev[i]) - 1);
       gd.stride[i] = (int)stride;
+      gd.cstride[i] = (int)stride;
       stride *= gd.n[i];
       gd.boff[i] = bits;
       gd.bmask[i] = (1 << gh.lev[i]) - 1;
@@ -691,11 +711,49 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     }
     build_tables(P, gh, gd);
     P->tabmax = std::max(P->tabmax, gd.tabsz);
+    // stiff axis: strongest coupling (largest off-diagonal magnitude of L
+    // along the axis); ties go to the longer axis, then the lower index
+    double best = -1.0;
+    int sax = 0;
+    for (int i = 0; i < d; ++i) {
+      double strength = 0.0;
+      if (P->opc == OPC_SEP) {
+        const double* t = P->htab.data() + gd.tab0 + gd.tab[i];
+        for (int j = 0; j < gd.n[i]; ++j)
+          strength = std::max(strength, std::fabs(t[j]) + std::fabs(t[2 * gd.n[i] + j]));
+      } else {
+        strength = gd.ih2[i];
+      }
+      if (gd.n[i] == 1) strength = 0.0;  // nothing to couple along this axis
+      if (strength > best * (1 + 1e-12) ||
+          (std::fabs(strength - best) <= 1e-12 * best && gd.n[i] > gd.n[sax])) {
+        best = strength;
+        sax = i;
+      }
+    }
+    gd.sax = sax;
+    gd.ns = gd.n[sax];
+    gd.nlines = gd.npts / gd.ns;
+    int m = 0;
+    for (int i = 0; i < d; ++i)
+      if (i != sax) gd.oax[m++] = i;
+    int ls = 1;
+    for (int mm = d - 2; mm >= 0; --mm) {
+      gd.lstride[mm] = ls;
+      ls *= gd.n[gd.oax[mm]];
+    }
     // cost estimate for longest-first scheduling: unknowns * sqrt(condition)
     double lam = 0.0;
     for (int i = 0; i < d; ++i) lam += 4.0 * gd.ih2[i];
     gh.cost = (double)gh.npts * std::sqrt(1.0 + dt0 * lam);
     P->hdev.push_back(gd);
+  }
+  P->shape = pick_shape(P->hdev);
+  if (P->shape < 0) {
+    delete P;
+    return fail(CTM_ERR_INVALID,
+                "a component grid exceeds the on-chip solver (line longer than 512 unknowns "
+                "or more than 1024 lanes)");
   }
   if (P->htab.empty()) P->htab.push_back(0.0);
   P->order.resize(P->G);

@@ -39,6 +39,16 @@ struct GridDev {
   int j0;              // node index of the first unknown (1 Dirichlet, 0 lattice)
   int pad3_;
   double coef;         // combination coefficient (-1)^w binom(d-1, w)
+  // line layout of the on-chip solver: the stiffest axis `sax` is made the
+  // fastest; internal point p = line * ns + j_sax, lines enumerate the other
+  // axes oax[0..d-2] with oax[d-2] fastest
+  int sax;             // stiff axis (canonical index)
+  int ns;              // unknowns along the stiff axis
+  int nlines;          // npts / ns
+  int pad4_;
+  int oax[MAXD];       // non-stiff axes, canonical indices, increasing
+  int lstride[MAXD];   // line-index stride of oax[m]
+  int cstride[MAXD];   // canonical point stride of canonical axis i (= stride[i])
 };
 
 // A family of packed vectors indexed by time: vector index = a * q + b
@@ -87,11 +97,13 @@ enum {
 };
 
 // Launch configurations of the on-chip solver: W waves per work-group, K
-// points per lane, capacity 64 * W * K unknowns.
+// consecutive stiff-axis unknowns per lane. A line of ns unknowns takes
+// Lc = pow2ceil(ceil(ns / K)) <= 64 lanes of one wave.
 struct ShapeCfg {
   int W, K;
 };
-constexpr ShapeCfg kShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 4}, {4, 4}, {4, 8}, {8, 8}, {16, 8}};
+constexpr ShapeCfg kShapes[] = {{1, 4}, {2, 4}, {4, 4}, {8, 4}, {16, 4},
+                                {1, 8}, {2, 8}, {4, 8}, {8, 8}, {16, 8}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
@@ -101,7 +113,7 @@ hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainA
 inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed) {
   const ShapeCfg c = kShapes[shape];
   size_t cap = 64u * c.W * c.K;
-  size_t vec = cap * sizeof(double);
+  size_t vec = cap * sizeof(double);  // upper bound of npts
   size_t tabs = (size_t)tabmax * sizeof(double) + (mixed ? (size_t)tabmax * sizeof(float) : 0);
   size_t red = 2u * 64u * sizeof(double);
   return vec + ((tabs + 15) & ~size_t(15)) + red;

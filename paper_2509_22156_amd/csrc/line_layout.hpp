@@ -1,0 +1,398 @@
+// Line layout of the on-chip solver and its line-block preconditioner.
+//
+// Each grid is traversed along its stiffest axis s (largest coupling, i.e.
+// finest mesh width): a "line" is the set of ns unknowns with fixed
+// coordinates on the other axes. A line is split into chunks of K
+// consecutive unknowns; chunk c of a line lives in lane c of a segment of
+// Lc = pow2ceil(ceil(ns / K)) consecutive lanes of one wave, so neighbours
+// along s are in the lane's own registers or in the adjacent lane
+// (cross-lane shuffle), and only the other axes go through LDS.
+//
+// Preconditioner: M = the part of A = I + dt L that couples unknowns along
+// s (block Jacobi with whole lines as blocks, i.e. a non-overlapping
+// decomposition into line subdomains with exact subdomain solves; the
+// paper's own spatial solver is a Krylov method preconditioned by domain
+// decomposition with exact local solves, Section 2.1.2). M^-1 is applied
+// exactly: Thomas elimination of each chunk's first K-1 unknowns in
+// registers, a tridiagonal interface system with one unknown per lane (the
+// chunk's last unknown) solved by parallel cyclic reduction over the
+// lanes of the line, and back-substitution. All matrix-only factors are
+// computed once per chain (per step size).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace ctm {
+
+// ------------------------------------------------------------- shuffles
+template <typename T>
+__device__ __forceinline__ T shfl_up_seg(T v, int delta, int width) {
+  return __shfl_up(v, (unsigned)delta, width);
+}
+template <typename T>
+__device__ __forceinline__ T shfl_down_seg(T v, int delta, int width) {
+  return __shfl_down(v, (unsigned)delta, width);
+}
+
+__device__ __forceinline__ int pow2ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Position of this lane in the line layout of grid g.
+template <int K>
+struct Lane {
+  int line;        // line index (>= nlines: idle lane)
+  int c;           // chunk index inside the line
+  int Lc;          // lanes per line
+  int j0;          // stiff coordinate of the chunk's first unknown (c * K)
+  int nval;        // unknowns of the chunk inside the line (0..K)
+  int pbase;       // internal point index of the chunk's first unknown
+  long long cbase; // canonical index of the chunk's first unknown
+  int cstep;       // canonical stride along the stiff axis
+  bool nxt;        // the next chunk of the line holds unknowns
+  unsigned nb;     // bit 2m: lower neighbour line along oax[m]; bit 2m+1: upper
+  int jo[MAXD];    // coordinates on the non-stiff axes oax[m]
+};
+
+template <int K>
+__device__ __forceinline__ void setup_lane(const GridDev& g, Lane<K>& L) {
+  const int Lc = pow2ceil((g.ns + K - 1) / K);
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  L.Lc = Lc;
+  L.c = lane & (Lc - 1);
+  L.line = (t >> 6) * (64 / Lc) + lane / Lc;
+  L.j0 = L.c * K;
+  const bool live = L.line < g.nlines;
+  int nv = g.ns - L.j0;
+  nv = nv < 0 ? 0 : (nv > K ? K : nv);
+  L.nval = live ? nv : 0;
+  L.pbase = L.line * g.ns + L.j0;
+  L.nxt = live && (L.j0 + K < g.ns);
+  L.cstep = g.cstride[g.sax];
+  long long cb = 0;
+  unsigned nb = 0;
+  int rem = live ? L.line : 0;
+#pragma unroll
+  for (int m = 0; m < MAXD - 1; ++m) {
+    L.jo[m] = 0;
+    if (m < g.d - 1) {
+      const int ax = g.oax[m];
+      const int j = (rem / g.lstride[m]) % g.n[ax];
+      L.jo[m] = j;
+      cb += (long long)j * g.cstride[ax];
+      nb |= (unsigned)(j > 0) << (2 * m);
+      nb |= (unsigned)(j < g.n[ax] - 1) << (2 * m + 1);
+    }
+  }
+  L.cbase = cb + (long long)L.j0 * L.cstep;
+  L.nb = live ? nb : 0u;
+}
+
+// ---------------------------------------------------------- operators
+// Coefficients of A = I + dt L in the line layout, precision T:
+//  diag[k]        diagonal of the chunk's unknown k
+//  slo[k], sup[k] couplings to the stiff-axis neighbours j-1, j+1
+//  olo[m], oup[m] couplings to the neighbour lines along oax[m] (per lane;
+//                 VAR adds a per-unknown part qlo/qup[m] * snj[k])
+template <int OPC, typename T, int K>
+struct LineOp {
+  T diag[OPC == OPC_HEAT ? 1 : K];
+  T slo[OPC == OPC_HEAT ? 1 : K];
+  T sup[OPC == OPC_HEAT ? 1 : K];
+  T olo[MAXD - 1], oup[MAXD - 1];
+  T qlo[OPC == OPC_VAR ? MAXD - 1 : 1], qup[OPC == OPC_VAR ? MAXD - 1 : 1];
+  T snj[OPC == OPC_VAR ? K : 1];
+};
+
+// tab: this grid's tables in LDS (SEP: per axis Lo, D, Up of L scaled by
+// dt; VAR: per axis node sines then face sines).
+template <int OPC, typename T, int K>
+__device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L, double dt,
+                                             double amp, const T* tab, LineOp<OPC, T, K>& O) {
+  const int s = g.sax;
+  const double cs = dt * g.ih2[s];
+  if constexpr (OPC == OPC_HEAT) {
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i) sum += (i < g.d) ? 2.0 * dt * g.ih2[i] : 0.0;
+    O.diag[0] = (T)(1.0 + sum);
+    O.slo[0] = (T)(-cs);
+    O.sup[0] = (T)(-cs);
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m) {
+      const double cm = (m < g.d - 1) ? dt * g.ih2[g.oax[m]] : 0.0;
+      O.olo[m] = (T)(-cm);
+      O.oup[m] = (T)(-cm);
+    }
+  } else if constexpr (OPC == OPC_SEP) {
+    T dl = (T)1;
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m) {
+      O.olo[m] = (T)0;
+      O.oup[m] = (T)0;
+      if (m < g.d - 1) {
+        const int ax = g.oax[m];
+        const T* t = tab + g.tab[ax];
+        const int j = L.jo[m];
+        O.olo[m] = t[j];
+        dl += t[g.n[ax] + j];
+        O.oup[m] = t[2 * g.n[ax] + j];
+      }
+    }
+    const T* t = tab + g.tab[s];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = L.j0 + k;
+      const bool v = k < L.nval;
+      O.diag[k] = v ? dl + t[g.n[s] + j] : (T)1;
+      O.slo[k] = v ? t[j] : (T)0;
+      O.sup[k] = v ? t[2 * g.n[s] + j] : (T)0;
+    }
+  } else {
+    // a = 1 + amp * (face sine) * (product of node sines of the other axes)
+    T sn[MAXD - 1];
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m)
+      sn[m] = (m < g.d - 1) ? tab[g.tab[g.oax[m]] + L.jo[m]] : (T)1;
+    T pre[MAXD - 1], suf[MAXD - 1];
+    T run = (T)1;
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m) {
+      pre[m] = run;
+      run *= sn[m];
+    }
+    const T es = run;  // product over all non-stiff axes
+    run = (T)1;
+#pragma unroll
+    for (int m = MAXD - 2; m >= 0; --m) {
+      suf[m] = run;
+      run *= sn[m];
+    }
+    T diag_lane = (T)1;  // per-lane part of the diagonal: 1 + sum_m c_m (2 + ...)
+    const T A = (T)amp;
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m) {
+      O.olo[m] = (T)0;
+      O.oup[m] = (T)0;
+      O.qlo[m] = (T)0;
+      O.qup[m] = (T)0;
+      if (m < g.d - 1) {
+        const int ax = g.oax[m];
+        const T cm = (T)(dt * g.ih2[ax]);
+        const T* sm = tab + g.tab[ax] + g.n[ax];
+        const T pm = pre[m] * suf[m];
+        O.olo[m] = -cm;
+        O.oup[m] = -cm;
+        O.qlo[m] = -cm * A * sm[L.jo[m]] * pm;
+        O.qup[m] = -cm * A * sm[L.jo[m] + 1] * pm;
+      }
+    }
+    const T* sns = tab + g.tab[s];
+    const T* sms = tab + g.tab[s] + g.n[s];
+    const T csT = (T)cs;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = L.j0 + k;
+      const bool v = k < L.nval;
+      const T snv = v ? sns[j] : (T)0;
+      O.snj[k] = snv;
+      const T adn = (T)1 + A * (v ? sms[j] : (T)0) * es;
+      const T aup = (T)1 + A * (v ? sms[j + 1] : (T)0) * es;
+      T dg = diag_lane + csT * (adn + aup);
+#pragma unroll
+      for (int m = 0; m < MAXD - 1; ++m)
+        if (m < g.d - 1) dg -= (O.olo[m] + O.qlo[m] * snv) + (O.oup[m] + O.qup[m] * snv);
+      O.diag[k] = v ? dg : (T)1;
+      O.slo[k] = v ? -csT * adn : (T)0;
+      O.sup[k] = v ? -csT * aup : (T)0;
+    }
+  }
+}
+
+template <int OPC, typename T, int K>
+__device__ __forceinline__ T op_diag(const LineOp<OPC, T, K>& O, int k) {
+  if constexpr (OPC == OPC_HEAT) return O.diag[0];
+  else return O.diag[k];
+}
+template <int OPC, typename T, int K>
+__device__ __forceinline__ T op_slo(const LineOp<OPC, T, K>& O, int k) {
+  if constexpr (OPC == OPC_HEAT) return O.slo[0];
+  else return O.slo[k];
+}
+template <int OPC, typename T, int K>
+__device__ __forceinline__ T op_sup(const LineOp<OPC, T, K>& O, int k) {
+  if constexpr (OPC == OPC_HEAT) return O.sup[0];
+  else return O.sup[k];
+}
+
+// Write the chunk to LDS (internal layout); a barrier must follow before
+// line_apply reads it.
+template <typename T, int K>
+__device__ __forceinline__ void lds_put(const Lane<K>& L, T* xl, const T (&x)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (k < L.nval) xl[L.pbase + k] = x[k];
+}
+
+// y = A x on the chunk; xl holds x of the whole grid (after a barrier).
+template <int OPC, typename T, int K>
+__device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
+                                           const LineOp<OPC, T, K>& O, const T* xl,
+                                           const T (&x)[K], T (&y)[K]) {
+  const T xleft = shfl_up_seg(x[K - 1], 1, L.Lc);
+  const T xright = shfl_down_seg(x[0], 1, L.Lc);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const T xm = (k > 0) ? x[k - 1] : (L.c > 0 ? xleft : (T)0);
+    const T xp = (k < K - 1) ? ((k + 1 < L.nval) ? x[k + 1] : (T)0) : (L.nxt ? xright : (T)0);
+    T acc = op_diag(O, k) * x[k] + op_slo(O, k) * xm + op_sup(O, k) * xp;
+    const int p = L.pbase + k;
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m) {
+      if (m < g.d - 1) {
+        const int off = g.lstride[m] * g.ns;
+        const bool lo = (L.nb >> (2 * m)) & 1u;
+        const bool hi = (L.nb >> (2 * m + 1)) & 1u;
+        T xlo = xl[lo ? p - off : p];
+        T xhi = xl[hi ? p + off : p];
+        xlo = lo ? xlo : (T)0;
+        xhi = hi ? xhi : (T)0;
+        T clo = O.olo[m], chi = O.oup[m];
+        if constexpr (OPC == OPC_VAR) {
+          clo += O.qlo[m] * O.snj[k];
+          chi += O.qup[m] * O.snj[k];
+        }
+        acc += clo * xlo + chi * xhi;
+      }
+    }
+    y[k] = (k < L.nval) ? acc : (T)0;
+  }
+}
+
+// ------------------------------------------------------ preconditioner
+constexpr int kMaxPcr = 6;  // log2(64)
+
+template <typename T, int K>
+struct LinePre {
+  T m[K];            // Thomas multipliers of the chunk interior (k = 1..K-2)
+  T id[K];           // reciprocal pivots (k = 0..K-2)
+  T cu[K];           // upper couplings inside the interior (k = 0..K-3)
+  T phi[K], psi[K];  // interior responses to the previous / own interface unknown
+  T aL, cL;          // couplings of the chunk's last unknown
+  T pa[kMaxPcr], pc[kMaxPcr];  // cyclic-reduction factors per step
+  T pinv;            // reciprocal of the reduced diagonal
+  int steps;         // log2(Lc)
+};
+
+template <int OPC, typename T, int K>
+__device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC, T, K>& O,
+                                              LinePre<T, K>& M) {
+  static_assert(K >= 2, "chunks hold at least two unknowns");
+  T a[K], b[K], c[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool v = k < L.nval;
+    const int j = L.j0 + k;
+    a[k] = (v && j > 0) ? op_slo(O, k) : (T)0;
+    c[k] = (v && k + 1 < L.nval) ? op_sup(O, k) : (T)0;
+    b[k] = v ? op_diag(O, k) : (T)1;
+  }
+  M.m[0] = (T)0;
+  M.id[0] = (T)1 / b[0];
+#pragma unroll
+  for (int k = 1; k < K - 1; ++k) {
+    M.m[k] = a[k] * M.id[k - 1];
+    M.id[k] = (T)1 / (b[k] - M.m[k] * c[k - 1]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) M.cu[k] = (k < K - 2) ? c[k] : (T)0;
+  // phi = T_I^-1 (a_0 e_0), psi = T_I^-1 (c_{K-2} e_{K-2})
+  T f[K];
+  f[0] = a[0];
+#pragma unroll
+  for (int k = 1; k < K - 1; ++k) f[k] = -M.m[k] * f[k - 1];
+  M.phi[K - 2] = f[K - 2] * M.id[K - 2];
+#pragma unroll
+  for (int k = K - 3; k >= 0; --k) M.phi[k] = (f[k] - M.cu[k] * M.phi[k + 1]) * M.id[k];
+  M.psi[K - 2] = c[K - 2] * M.id[K - 2];
+#pragma unroll
+  for (int k = K - 3; k >= 0; --k) M.psi[k] = -M.cu[k] * M.psi[k + 1] * M.id[k];
+  M.phi[K - 1] = (T)0;
+  M.psi[K - 1] = (T)0;
+  // interface equation of the chunk's last unknown u_c:
+  //   A u_{c-1} + B u_c + C u_{c+1} = R
+  // its coupling to the next chunk: the stiff-axis neighbour j0+K exists
+  // iff this chunk is full and the next one holds unknowns
+  const T phi0n = shfl_down_seg(M.phi[0], 1, L.Lc);
+  const T psi0n = shfl_down_seg(M.psi[0], 1, L.Lc);
+  const bool has_next = L.nxt;
+  M.aL = (L.nval == K && K - 1 + L.j0 > 0) ? a[K - 1] : (T)0;
+  M.cL = has_next ? op_sup(O, K - 1) : (T)0;
+  T A = -M.aL * M.phi[K - 2];
+  T B = b[K - 1] - M.aL * M.psi[K - 2] - M.cL * phi0n;
+  T C = -M.cL * psi0n;
+  // cyclic reduction factors over the Lc lanes of the line
+  M.steps = 0;
+#pragma unroll
+  for (int r = 0; r < kMaxPcr; ++r) {
+    M.pa[r] = (T)0;
+    M.pc[r] = (T)0;
+    const int s = 1 << r;
+    if (s < L.Lc) {
+      M.steps = r + 1;
+      const T Am = shfl_up_seg(A, s, L.Lc), Bm = shfl_up_seg(B, s, L.Lc),
+              Cm = shfl_up_seg(C, s, L.Lc);
+      const T Ap = shfl_down_seg(A, s, L.Lc), Bp = shfl_down_seg(B, s, L.Lc),
+              Cp = shfl_down_seg(C, s, L.Lc);
+      const bool vm = L.c >= s, vp = L.c + s < L.Lc;
+      const T al = vm ? -A / Bm : (T)0;
+      const T ga = vp ? -C / Bp : (T)0;
+      M.pa[r] = al;
+      M.pc[r] = ga;
+      const T An = vm ? al * Am : (T)0;
+      const T Cn = vp ? ga * Cp : (T)0;
+      B = B + (vm ? al * Cm : (T)0) + (vp ? ga * Ap : (T)0);
+      A = An;
+      C = Cn;
+    }
+  }
+  M.pinv = (T)1 / B;
+}
+
+// z = M^-1 r for the chunk (padding entries of r must be zero).
+template <typename T, int K>
+__device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LinePre<T, K>& M,
+                                              const T (&r)[K], T (&z)[K]) {
+  T y[K];
+  y[0] = r[0];
+#pragma unroll
+  for (int k = 1; k < K - 1; ++k) y[k] = r[k] - M.m[k] * y[k - 1];
+  y[K - 2] = y[K - 2] * M.id[K - 2];
+#pragma unroll
+  for (int k = K - 3; k >= 0; --k) y[k] = (y[k] - M.cu[k] * y[k + 1]) * M.id[k];
+  const T y0n = shfl_down_seg(y[0], 1, L.Lc);
+  T R = r[K - 1] - M.aL * y[K - 2] - M.cL * y0n;
+#pragma unroll
+  for (int st = 0; st < kMaxPcr; ++st) {
+    if (st < M.steps) {
+      const int s = 1 << st;
+      const T Rm = shfl_up_seg(R, s, L.Lc);
+      const T Rp = shfl_down_seg(R, s, L.Lc);
+      R = R + M.pa[st] * Rm + M.pc[st] * Rp;
+    }
+  }
+  const T u = R * M.pinv;
+  T um = shfl_up_seg(u, 1, L.Lc);
+  um = (L.c > 0) ? um : (T)0;
+#pragma unroll
+  for (int k = 0; k < K - 1; ++k) z[k] = y[k] - M.phi[k] * um - M.psi[k] * u;
+  z[K - 1] = u;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (k >= L.nval) z[k] = (T)0;
+}
+
+}  // namespace ctm
