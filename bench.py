@@ -112,6 +112,7 @@ def main(argv=None):
     plan.set_timing(True)
     agg = dict(chain_ms=0.0, chain_launches=0, krylov_work=0, chain_bytes=0.0,
                mgrit_iterations=0, krylov_iterations=0, phi_solves=0, refine_sweeps=0)
+    shapes = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -119,6 +120,12 @@ def main(argv=None):
         st = plan.stats()
         for k in agg:
             agg[k] += st[k]
+        for sh in st["shapes"]:
+            key = (sh["W"], sh["K"])
+            acc = shapes.setdefault(key, dict(ms=0.0, launches=0, work=0))
+            acc["ms"] += sh["ms"]
+            acc["launches"] += sh["launches"]
+            acc["work"] += sh["work"]
         log(f"step {i + 1}/{args.steps}: mgrit it={st['mgrit_iterations']} "
             f"res={st['mgrit_residual'][-1]:.2e}")
     torch.cuda.synchronize()
@@ -130,19 +137,26 @@ def main(argv=None):
     d = prob["d"]
     fpi = flops_per_iteration(d, prob["krylov"])
     chain_s = agg["chain_ms"] / 1e3
-    achieved_tflops = agg["krylov_work"] * fpi / chain_s / 1e12 if chain_s > 0 else None
+    # dominant kernel: the size class of the implicit-step kernel with the
+    # most device time; its algorithmic FP32 flops over its own timed launches
+    (dw, dk), dom = max(shapes.items(), key=lambda kv: kv[1]["ms"])
+    dom_s = dom["ms"] / 1e3
+    achieved_tflops = dom["work"] * fpi / dom_s / 1e12 if dom_s > 0 else None
     launches = max(agg["chain_launches"], 1)
     roofline = {
-        "kernel": "chain_kernel (batched implicit-step CG, FP32 inner / FP64 refinement)",
+        "kernel": f"chain_kernel<heat, CG, mixed, W={dw}, K={dk}> (batched implicit steps, "
+                  "FP32 preconditioned CG inside FP64 refinement)",
         "bound": "alu",
         "achieved": achieved_tflops,
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": (achieved_tflops / PEAK_FP32_TFLOPS) if achieved_tflops else None,
         "traffic": None,
-        "avg_launch_ms": agg["chain_ms"] / launches,
-        "launches": agg["chain_launches"],
-        "algorithmic_flops_per_launch": agg["krylov_work"] * fpi / launches,
+        "avg_launch_ms": dom["ms"] / max(dom["launches"], 1),
+        "launches": dom["launches"],
+        "algorithmic_flops_per_launch": dom["work"] * fpi / max(dom["launches"], 1),
+        "all_classes": {f"W{w}K{k}": v for (w, k), v in sorted(shapes.items())},
+        "phase_ms_per_step": agg["chain_ms"] / args.steps,
         "algorithmic_hbm_GBps": agg["chain_bytes"] / chain_s / 1e9 if chain_s > 0 else None,
         "hbm_frac": (agg["chain_bytes"] / chain_s / 1e9 / PEAK_HBM_GBPS) if chain_s > 0 else None,
     }

@@ -124,6 +124,12 @@ typedef struct {
   double chain_ms;                    /* their summed duration (only with ctm_set_timing on) */
   double chain_bytes;                 /* algorithmic HBM bytes those launches move: the
                                          vectors each task must read and write once */
+  /* per launch shape (size class) of the implicit-step kernel: waves per
+     work-group, unknowns per lane, timed duration, launches, Krylov work */
+  int shape_w[16], shape_k[16];
+  double shape_ms[16];
+  long long shape_launches[16];
+  long long shape_work[16];
 } ctm_stats;
 
 /* Fill *p with the paper's solver defaults (Section 4.1): two-level MGRIT,

@@ -50,7 +50,7 @@ __device__ __forceinline__ void sapply(const Solver<OPC, T, K>& S, const T (&x)[
 // ||b - A x||_2^2 <= tol2 * bb on the recursively updated residual.
 template <int OPC, typename T, int W, int K>
 __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
-                                          const T (&b)[K], bool x_zero, T bb, T tol2, int maxit,
+                                          const T (&b)[K], bool x_zero, T tol2, int maxit,
                                           int* flag) {
   T r[K], z[K], w[K], p[K], s[K];
   if (x_zero) {
@@ -64,15 +64,18 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
   }
   linepre_apply<T, K>(S.L, S.M, r, z);
   sapply<OPC, T, K>(S, z, w);
-  T red[3] = {(T)0, (T)0, (T)0};
+  // (r,z), (Az,z), (r,r) and, unless x = 0 (then b = r), (b,b)
+  T red[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     red[0] += r[k] * z[k];
     red[1] += w[k] * z[k];
     red[2] += r[k] * r[k];
+    red[3] += b[k] * b[k];
   }
-  block_sum<W, 3, T>(red, ring);
-  if (!finite_val(red[2]) || !finite_val(red[1])) {
+  block_sum<W, 4, T>(red, ring);
+  const T bb = x_zero ? red[2] : red[3];
+  if (!finite_val(red[2]) || !finite_val(red[1]) || !finite_val(bb)) {
     *flag |= FLAG_NONFINITE;
     return 0;
   }
@@ -126,8 +129,8 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
 // Right-preconditioned BiCGStab (van der Vorst), shadow residual r^ = r_0.
 template <int OPC, typename T, int W, int K>
 __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedRing& ring,
-                                                T (&x)[K], const T (&b)[K], bool x_zero, T bb,
-                                                T tol2, int maxit, int* flag) {
+                                                T (&x)[K], const T (&b)[K], bool x_zero, T tol2,
+                                                int maxit, int* flag) {
   T r[K], rh[K], p[K], v[K], s[K], t[K], h[K];
   if (x_zero) {
 #pragma unroll
@@ -137,15 +140,17 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = b[k] - v[k];
   }
-  T s1[1] = {(T)0};
+  T s1[2] = {(T)0, (T)0};
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     rh[k] = r[k];
     p[k] = r[k];
     s1[0] += r[k] * r[k];
+    s1[1] += b[k] * b[k];
   }
-  block_sum<W, 1, T>(s1, ring);
-  if (!finite_val(s1[0])) {
+  block_sum<W, 2, T>(s1, ring);
+  const T bb = x_zero ? s1[0] : s1[1];
+  if (!finite_val(s1[0]) || !finite_val(bb)) {
     *flag |= FLAG_NONFINITE;
     return 0;
   }
@@ -213,12 +218,12 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
 
 template <int OPC, int SOLVER, typename T, int W, int K>
 __device__ __forceinline__ int krylov(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
-                                      const T (&b)[K], bool x_zero, T bb, T tol2, int maxit,
+                                      const T (&b)[K], bool x_zero, T tol2, int maxit,
                                       int* flag) {
   if constexpr (SOLVER == SOLV_CG)
-    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, bb, tol2, maxit, flag);
+    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, tol2, maxit, flag);
   else
-    return krylov_pbicgstab<OPC, T, W, K>(S, ring, x, b, x_zero, bb, tol2, maxit, flag);
+    return krylov_pbicgstab<OPC, T, W, K>(S, ring, x, b, x_zero, tol2, maxit, flag);
 }
 
 __device__ __forceinline__ double* vec_at(const VecRef& r, long long idx, long long slen,
@@ -241,10 +246,10 @@ __device__ __forceinline__ void gstore(const Lane<K>& L, double* dst, const doub
 // One implicit step in FP64: x <- (I + dt L)^-1 v.
 template <int OPC, int SOLVER, int W, int K>
 __device__ __forceinline__ void step_fp64(const Solver<OPC, double, K>& S, RedRing& ring,
-                                          const double (&v)[K], double bb, double tol2,
-                                          int maxit, double (&x)[K], int* flag,
-                                          long long& kr_sum, long long& kr_max) {
-  const int it = krylov<OPC, SOLVER, double, W, K>(S, ring, x, v, false, bb, tol2, maxit, flag);
+                                          const double (&v)[K], double tol2, int maxit,
+                                          double (&x)[K], int* flag, long long& kr_sum,
+                                          long long& kr_max) {
+  const int it = krylov<OPC, SOLVER, double, W, K>(S, ring, x, v, false, tol2, maxit, flag);
   kr_sum += it;
   kr_max = it > kr_max ? it : kr_max;
 }
@@ -253,24 +258,32 @@ __device__ __forceinline__ void step_fp64(const Solver<OPC, double, K>& S, RedRi
 template <int OPC, int SOLVER, int W, int K>
 __device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
                                            const Solver<OPC, float, K>& S32, RedRing& ring,
-                                           const double (&v)[K], double bb, double tol2,
-                                           float itol2, int maxit, int refine_maxit,
-                                           double (&x)[K], int* flag, long long& kr_sum,
-                                           long long& kr_max, long long& rf_sum,
-                                           long long& rf_max) {
+                                           const double (&v)[K], double tol2, float itol2,
+                                           int maxit, int refine_maxit, double (&x)[K],
+                                           int* flag, long long& kr_sum, long long& kr_max,
+                                           long long& rf_sum, long long& rf_max) {
   bool conv = false;
   int sweeps = 0, its = 0;
+  double bb = 0.0;
   for (; sweeps <= refine_maxit; ++sweeps) {
     double rq[K];
     sapply<OPC, double, K>(S64, x, rq);
-    double rr[1] = {0.0};
+    double rr[2] = {0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       rq[k] = v[k] - rq[k];
       rr[0] += rq[k] * rq[k];
+      rr[1] += v[k] * v[k];
     }
-    block_sum<W, 1, double>(rr, ring);
-    if (!finite_val(rr[0])) {
+    if (sweeps == 0) {
+      block_sum<W, 2, double>(rr, ring);
+      bb = rr[1];
+    } else {
+      double r1[1] = {rr[0]};
+      block_sum<W, 1, double>(r1, ring);
+      rr[0] = r1[0];
+    }
+    if (!finite_val(rr[0]) || !finite_val(bb)) {
       *flag |= FLAG_NONFINITE;
       break;
     }
@@ -282,18 +295,14 @@ __device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
     const double nr = sqrt(rr[0]);
     const double inv = 1.0 / nr;
     float r32[K], d32[K];
-    float bb32 = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       r32[k] = (float)(rq[k] * inv);
       d32[k] = 0.0f;
-      bb32 += r32[k] * r32[k];
     }
-    float bbs[1] = {bb32};
-    block_sum<W, 1, float>(bbs, ring);
     int iflag = 0;
     const int it =
-        krylov<OPC, SOLVER, float, W, K>(S32, ring, d32, r32, true, bbs[0], itol2, maxit, &iflag);
+        krylov<OPC, SOLVER, float, W, K>(S32, ring, d32, r32, true, itol2, maxit, &iflag);
     its += it;
     if (iflag & FLAG_NONFINITE) {
       *flag |= FLAG_NONFINITE;
@@ -372,23 +381,14 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax, 
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
 
   for (int j = 1; j <= a.nsteps; ++j) {
-    double bbv[1] = {0.0};
-#pragma unroll
-    for (int k = 0; k < K; ++k) bbv[0] += v[k] * v[k];
-    block_sum<W, 1, double>(bbv, ring);
-    const double bb = bbv[0];
     double x[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) x[k] = (bb == 0.0) ? 0.0 : v[k];
-    if (!finite_val(bb)) {
-      flag |= FLAG_NONFINITE;
-    } else if (bb != 0.0) {
-      if constexpr (MIXED)
-        step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, bb, tol2, itol2, a.maxit,
-                                      a.refine_maxit, x, &flag, kr_sum, kr_max, rf_sum, rf_max);
-      else
-        step_fp64<OPC, SOLVER, W, K>(S64, ring, v, bb, tol2, a.maxit, x, &flag, kr_sum, kr_max);
-    }
+    for (int k = 0; k < K; ++k) x[k] = v[k];
+    if constexpr (MIXED)
+      step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit, x,
+                                    &flag, kr_sum, kr_max, rf_sum, rf_max);
+    else
+      step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, x, &flag, kr_sum, kr_max);
     if (a.forcing.base) {
       double f[K];
       gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);

@@ -67,6 +67,18 @@ long long binom(int n, int k) {
 
 }  // namespace
 
+// Tasks (g, q) of one launch phase, grouped by the launch shape (size
+// class) of their grid; inside a class, grids by decreasing cost.
+struct TaskSet {
+  int2* d = nullptr;
+  long long total = 0;
+  struct Range {
+    int shape;
+    long long offset, count;
+  };
+  std::vector<Range> ranges;
+};
+
 struct ctm_plan {
   ctm_problem prob;
   std::vector<double> icw, icf;
@@ -94,12 +106,15 @@ struct ctm_plan {
   double* dsync = nullptr;    // [0] residual max, [1] status word (int in low bytes)
   double* dnorm2 = nullptr;   // [G]
   double* hsync = nullptr;    // pinned mirror of dsync
-  int2* dsingle = nullptr;    // (g, 0) in cost order
   int2* didentity = nullptr;  // (g, 0) in canonical order
-  std::map<long long, int2*> interval_tasks;  // M -> (g, q) tasks
+  std::vector<int> gshape;    // launch shape of each grid (size class)
+  std::map<long long, TaskSet> tsets;  // M -> (g, q) tasks grouped by shape
+  hipStream_t cstreams[kNumShapes] = {};  // one stream per size class
+  std::vector<hipEvent_t> sync_events;    // fork/join events
   ctm_stats stats;
   bool timing = false;
   std::vector<hipEvent_t> events;  // pairs (start, stop) per timed launch
+  std::vector<int> event_shape;    // shape of each timed pair
   size_t events_used = 0;
 
   ~ctm_plan() {
@@ -111,11 +126,13 @@ struct ctm_plan {
     hipFree(dcounters);
     hipFree(dsync);
     hipFree(dnorm2);
-    hipFree(dsingle);
     hipFree(didentity);
     if (hsync) hipHostFree(hsync);
-    for (auto& kv : interval_tasks) hipFree(kv.second);
+    for (auto& kv : tsets) hipFree(kv.second.d);
     for (auto e : events) hipEventDestroy(e);
+    for (auto e : sync_events) hipEventDestroy(e);
+    for (auto s : cstreams)
+      if (s) hipStreamDestroy(s);
   }
 };
 
@@ -233,12 +250,11 @@ int lanes_needed(const GridDev& gd, int K) {
   return gd.nlines * p;
 }
 
-// Smallest K whose chunks keep every line inside one wave, then the
-// smallest work-group that holds the largest grid.
+// Smallest K whose chunks keep every line of the grids inside one wave,
+// then the smallest work-group that holds them all (or -1).
 int pick_shape(const std::vector<GridDev>& gds) {
   int maxns = 0;
   for (auto& gd : gds) maxns = std::max(maxns, gd.ns);
-  const int env = std::getenv("CTM_SHAPE") ? std::atoi(std::getenv("CTM_SHAPE")) : -1;
   auto fits = [&](int s) {
     const int K = kShapes[s].K, W = kShapes[s].W;
     if (maxns > 64 * K) return false;
@@ -246,7 +262,6 @@ int pick_shape(const std::vector<GridDev>& gds) {
       if (lanes_needed(gd, K) > 64 * W) return false;
     return true;
   };
-  if (env >= 0 && env < kNumShapes && fits(env)) return env;
   for (int K : {4, 8}) {
     if (maxns > 64 * K) continue;
     for (int s = 0; s < kNumShapes; ++s)
@@ -255,21 +270,51 @@ int pick_shape(const std::vector<GridDev>& gds) {
   return -1;
 }
 
-ctm_status tasks_for(ctm_plan* P, long long M, int2** out) {
-  auto it = P->interval_tasks.find(M);
-  if (it != P->interval_tasks.end()) {
-    *out = it->second;
+// Size class of one grid: K = 4 while its lines fit a wave (fewer registers,
+// higher occupancy), else 8; then the fewest waves that hold it. The
+// environment variable CTM_SHAPE forces one shape for every grid it fits.
+int grid_shape(const GridDev& gd) {
+  const char* env = std::getenv("CTM_SHAPE");
+  if (env) {
+    const int s = std::atoi(env);
+    if (s >= 0 && s < kNumShapes &&
+        lanes_needed(gd, kShapes[s].K) <= 64 * kShapes[s].W && gd.ns <= 64 * kShapes[s].K)
+      return s;
+  }
+  // lanes above which a grid moves to K = 8 (fewer, fuller waves)
+  int k8_lanes = 256;
+  if (const char* e2 = std::getenv("CTM_K8_LANES")) k8_lanes = std::atoi(e2);
+  std::vector<GridDev> one{gd};
+  const int s4 = pick_shape(one);
+  if (s4 >= 0 && kShapes[s4].K == 4 && lanes_needed(gd, 4) > k8_lanes && gd.ns <= 512) {
+    for (int s = 0; s < kNumShapes; ++s)
+      if (kShapes[s].K == 8 && lanes_needed(gd, 8) <= 64 * kShapes[s].W) return s;
+  }
+  return s4;
+}
+
+ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
+  auto it = P->tsets.find(M);
+  if (it != P->tsets.end()) {
+    *out = &it->second;
     return CTM_OK;
   }
+  TaskSet ts;
   std::vector<int2> t;
   t.reserve((size_t)P->G * M);
-  for (int g : P->order)
-    for (long long q = 0; q < M; ++q) t.push_back(make_int2(g, (int)q));
-  int2* d = nullptr;
-  CTM_HIP(hipMalloc(&d, t.size() * sizeof(int2)));
-  CTM_HIP(hipMemcpy(d, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice));
-  P->interval_tasks[M] = d;
-  *out = d;
+  for (int s = 0; s < kNumShapes; ++s) {
+    const long long start = (long long)t.size();
+    for (int g : P->order)
+      if (P->gshape[g] == s)
+        for (long long q = 0; q < M; ++q) t.push_back(make_int2(g, (int)q));
+    const long long cnt = (long long)t.size() - start;
+    if (cnt) ts.ranges.push_back({s, start, cnt});
+  }
+  ts.total = (long long)t.size();
+  CTM_HIP(hipMalloc(&ts.d, t.size() * sizeof(int2)));
+  CTM_HIP(hipMemcpy(ts.d, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice));
+  P->tsets[M] = ts;
+  *out = &P->tsets[M];
   return CTM_OK;
 }
 
@@ -287,7 +332,6 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
   const bool mixed = P->mixed && !fp64_only;
   a.tol = mixed ? P->prob.refine_tol : P->prob.krylov_tol;
   a.inner_tol = P->prob.inner_tol;
-  a.counters = P->dcounters;
   a.status = reinterpret_cast<int*>(P->dsync + 1);
   return a;
 }
@@ -307,35 +351,82 @@ double chain_vectors_per_task(const ChainArgs& a) {
   return v;
 }
 
-ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const int2* tasks, long long ntasks,
-                     hipStream_t s, bool fp64_only = false, long long task_points = -1) {
+hipEvent_t take_event(ctm_plan* P, size_t& used, std::vector<hipEvent_t>& pool, bool timed) {
+  while (pool.size() <= used) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, timed ? hipEventDefault : hipEventDisableTiming) !=
+        hipSuccess)
+      return nullptr;
+    pool.push_back(ev);
+  }
+  return pool[used++];
+}
+
+// One launch of the chain kernel for the tasks [offset, offset + count) of a
+// task array, all of one shape, on stream s.
+ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int shape,
+                        long long offset, long long count, hipStream_t s, bool mixed) {
   ChainArgs c = a;
-  c.tasks = tasks;
-  const bool mixed = P->mixed && !fp64_only;
-  const size_t smem = chain_smem_bytes(P->shape, P->tabmax, mixed);
+  c.tasks = tasks + offset;
+  if (a.res2) c.res2 = a.res2 + offset;
+  c.counters = P->dcounters + (size_t)shape * CNT_N;
+  const size_t smem = chain_smem_bytes(shape, P->tabmax, mixed);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (P->timing) {
-    while (P->events.size() < P->events_used + 2) {
-      hipEvent_t ev;
-      CTM_HIP(hipEventCreate(&ev));
-      P->events.push_back(ev);
-    }
-    e0 = P->events[P->events_used];
-    e1 = P->events[P->events_used + 1];
-    P->events_used += 2;
+    e0 = take_event(P, P->events_used, P->events, true);
+    e1 = take_event(P, P->events_used, P->events, true);
+    if (!e0 || !e1) return fail(CTM_ERR_HIP, "event creation failed");
+    P->event_shape.resize(P->events.size());
+    P->event_shape[P->events_used - 2] = shape;
     CTM_HIP(hipEventRecord(e0, s));
   }
-  hipError_t e = launch_chain(P->opc, P->solver, mixed, P->shape, c, (int)ntasks, smem,
-                              P->tabmax, s);
+  hipError_t e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tabmax, s);
   if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("chain launch: ") + hipGetErrorString(e));
   if (P->timing) CTM_HIP(hipEventRecord(e1, s));
-  // algorithmic bytes: every vector of every task once (tasks cover all grids
-  // for `ntasks / G` intervals unless a single grid is given)
-  const double pts = task_points >= 0 ? (double)task_points
-                                      : (double)P->slen * ((double)ntasks / (double)P->G);
-  P->stats.chain_bytes += 8.0 * pts * chain_vectors_per_task(c);
   P->stats.chain_launches += 1;
   return CTM_OK;
+}
+
+// Launch a phase: one kernel per size class; with several classes they run
+// concurrently on the plan's class streams, forked from and joined back
+// into the caller's stream.
+ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStream_t s,
+                     bool fp64_only = false) {
+  const bool mixed = P->mixed && !fp64_only;
+  // algorithmic bytes: every vector of every task once
+  const double per_grid_sets = (double)ts.total / (double)P->G;
+  P->stats.chain_bytes += 8.0 * (double)P->slen * per_grid_sets * chain_vectors_per_task(a);
+  if (ts.ranges.size() == 1) {
+    const auto& r = ts.ranges[0];
+    return launch_range(P, a, ts.d, r.shape, r.offset, r.count, s, mixed);
+  }
+  size_t used = 0;
+  hipEvent_t fork = take_event(P, used, P->sync_events, false);
+  if (!fork) return fail(CTM_ERR_HIP, "event creation failed");
+  CTM_HIP(hipEventRecord(fork, s));
+  std::vector<hipEvent_t> joins;
+  for (const auto& r : ts.ranges) {
+    hipStream_t cs = P->cstreams[r.shape];
+    if (!cs) {
+      CTM_HIP(hipStreamCreateWithFlags(&P->cstreams[r.shape], hipStreamNonBlocking));
+      cs = P->cstreams[r.shape];
+    }
+    CTM_HIP(hipStreamWaitEvent(cs, fork, 0));
+    ctm_status st = launch_range(P, a, ts.d, r.shape, r.offset, r.count, cs, mixed);
+    if (st != CTM_OK) return st;
+    hipEvent_t j = take_event(P, used, P->sync_events, false);
+    if (!j) return fail(CTM_ERR_HIP, "event creation failed");
+    CTM_HIP(hipEventRecord(j, cs));
+    joins.push_back(j);
+  }
+  for (hipEvent_t j : joins) CTM_HIP(hipStreamWaitEvent(s, j, 0));
+  return CTM_OK;
+}
+
+// The plain reference schedule: one grid, one launch.
+ctm_status run_chain_grid(ctm_plan* P, const ChainArgs& a, int g, hipStream_t s) {
+  P->stats.chain_bytes += 8.0 * (double)P->grids[g].npts * chain_vectors_per_task(a);
+  return launch_range(P, a, P->didentity, P->gshape[g], g, 1, s, false);
 }
 
 // Sum of the timed launch durations (after the stream has been synchronised).
@@ -345,6 +436,9 @@ ctm_status accumulate_timing(ctm_plan* P) {
     float t = 0.0f;
     CTM_HIP(hipEventElapsedTime(&t, P->events[i], P->events[i + 1]));
     ms += t;
+    const int sh = P->event_shape[i];
+    P->stats.shape_ms[sh] += t;
+    P->stats.shape_launches[sh] += 1;
   }
   P->stats.chain_ms += ms;
   P->events_used = 0;
@@ -357,23 +451,37 @@ void reset_stats(ctm_plan* P) {
 }
 
 ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
-  CTM_HIP(hipMemsetAsync(P->dcounters, 0, CNT_N * sizeof(unsigned long long), s));
+  CTM_HIP(hipMemsetAsync(P->dcounters, 0, kNumShapes * CNT_N * sizeof(unsigned long long), s));
   CTM_HIP(hipMemsetAsync(P->dsync, 0, 2 * sizeof(double), s));
   return CTM_OK;
 }
 
+// Fold the per-class device counters into the statistics.
+void fold_counters(const ctm_plan* P, const unsigned long long* c, ctm_stats* st) {
+  st->krylov_iterations = st->krylov_max = st->refine_sweeps = st->refine_max = 0;
+  st->phi_solves = st->krylov_work = 0;
+  for (int s = 0; s < kNumShapes; ++s) {
+    const unsigned long long* k = c + (size_t)s * CNT_N;
+    st->krylov_iterations += (long long)k[CNT_KRYLOV];
+    st->krylov_max = std::max(st->krylov_max, (long long)k[CNT_KRYLOV_MAX]);
+    st->refine_sweeps += (long long)k[CNT_REFINE];
+    st->refine_max = std::max(st->refine_max, (long long)k[CNT_REFINE_MAX]);
+    st->phi_solves += (long long)k[CNT_SOLVES];
+    st->krylov_work += (long long)k[CNT_WORK];
+    st->shape_work[s] = (long long)k[CNT_WORK];
+    st->shape_w[s] = kShapes[s].W;
+    st->shape_k[s] = kShapes[s].K;
+  }
+  (void)P;
+}
+
 ctm_status collect_device_stats(ctm_plan* P, hipStream_t s) {
-  unsigned long long c[CNT_N];
+  unsigned long long c[kNumShapes * CNT_N];
   CTM_HIP(hipMemcpyAsync(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost, s));
   CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   CTM_HIP(hipStreamSynchronize(s));
-  P->stats.krylov_iterations = (long long)c[CNT_KRYLOV];
-  P->stats.krylov_max = (long long)c[CNT_KRYLOV_MAX];
-  P->stats.refine_sweeps = (long long)c[CNT_REFINE];
-  P->stats.refine_max = (long long)c[CNT_REFINE_MAX];
-  P->stats.phi_solves = (long long)c[CNT_SOLVES];
+  fold_counters(P, c, &P->stats);
   P->stats.status_flags = *reinterpret_cast<int*>(P->hsync + 1);
-  P->stats.krylov_work = (long long)c[CNT_WORK];
   return accumulate_timing(P);
 }
 
@@ -460,12 +568,13 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     a.inter = vref(E, 0, 0);
     a.fin = vref(E, 0, lay.N[l]);
     CTM_HIP(launch_fill_zero(E, P->slen, s));  // e_0 = g_0 = 0
-    return run_chain(P, a, P->dsingle, P->G, s);
+    TaskSet* single = nullptr;
+    if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
+    return run_chain(P, a, *single, s);
   }
   const long long M = lay.N[l] / c;
-  int2* tasks = nullptr;
+  TaskSet* tasks = nullptr;
   if ((st = tasks_for(P, M, &tasks)) != CTM_OK) return st;
-  const long long nt = (long long)P->G * M;
   CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s));
   double* csrc;
   long long ca;
@@ -477,7 +586,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     fc.forcing = vref(G, c, 0);
     fc.inter = vref(E, c, 0);
     fc.fin = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fc, tasks, nt, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
     ChainArgs fr = base_args(P, l, (int)c);
     fr.start = vref(Cn, 1, 0);
     fr.start_wb = vref(E, c, 0);
@@ -485,7 +594,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fr, tasks, nt, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
     csrc = Cn;
     ca = 1;
   } else {
@@ -495,7 +604,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(E, c, c);
-    if ((st = run_chain(P, fr, tasks, nt, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
     csrc = E;
     ca = c;
   }
@@ -509,7 +618,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
   fi.forcing = vref(G, c, 0);
   fi.inter = vref(E, c, 0);
   fi.fin = vref(E, c, c - 1);
-  return run_chain(P, fi, tasks, nt, s);
+  return run_chain(P, fi, *tasks, s);
 }
 
 // MGRIT on one block: X (start) -> Y (state at the block end).
@@ -520,13 +629,15 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     ChainArgs a = base_args(P, 0, (int)lay.N[0]);
     a.start = vref(lay.X, 0, 0);
     a.fin = vref(lay.Y, 0, 0);
-    return run_chain(P, a, P->dsingle, P->G, s);
+    TaskSet* single = nullptr;
+    if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
+    return run_chain(P, a, *single, s);
   }
   const long long c = lay.c;
   const long long M0 = lay.N[0] / c;
-  int2* tasks = nullptr;
+  TaskSet* tasks = nullptr;
   if ((st = tasks_for(P, M0, &tasks)) != CTM_OK) return st;
-  const long long nt = (long long)P->G * M0;
+  const long long nt = tasks->total;
   const bool fcf = (p.relax == CTM_RELAX_FCF);
   // initial guess: the start state at every C-point
   CTM_HIP(launch_vec_add(vref(lay.U, 1, 0), vref(lay.X, 0, 0), vref(nullptr, 0, 0), (int)(M0 + 1),
@@ -542,7 +653,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
       ChainArgs fc = base_args(P, 0, (int)c);
       fc.start = vref(U, 1, 0);
       fc.fin = vref(Un, 1, 1);
-      if ((st = run_chain(P, fc, tasks, nt, s)) != CTM_OK) return st;
+      if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
       C = Un;
     } else {
       C = U;
@@ -552,8 +663,8 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     fr.fin = vref(lay.R[1], 1, 1);
     fr.target = vref(C, 1, 1);
     fr.res2 = lay.res2;
-    if ((st = run_chain(P, fr, tasks, nt, s)) != CTM_OK) return st;
-    CTM_HIP(launch_residual_max(tasks, (int)nt, lay.res2, P->dnorm2, P->dsync, s));
+    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
+    CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, P->dsync, s));
     CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     CTM_HIP(hipStreamSynchronize(s));
     const double res = P->hsync[0];
@@ -749,6 +860,8 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     P->hdev.push_back(gd);
   }
   P->shape = pick_shape(P->hdev);
+  P->gshape.resize(P->G);
+  for (int g = 0; g < P->G; ++g) P->gshape[g] = grid_shape(P->hdev[g]);
   if (P->shape < 0) {
     delete P;
     return fail(CTM_ERR_INVALID,
@@ -783,19 +896,14 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   CTM_HIPC(hipMemcpy(P->dicw, P->icw.data(), P->icw.size() * sizeof(double), hipMemcpyHostToDevice));
   CTM_HIPC(hipMalloc(&P->dicf, P->icf.size() * sizeof(double)));
   CTM_HIPC(hipMemcpy(P->dicf, P->icf.data(), P->icf.size() * sizeof(double), hipMemcpyHostToDevice));
-  CTM_HIPC(hipMalloc(&P->dcounters, CNT_N * sizeof(unsigned long long)));
-  CTM_HIPC(hipMemset(P->dcounters, 0, CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMalloc(&P->dcounters, kNumShapes * CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMemset(P->dcounters, 0, kNumShapes * CNT_N * sizeof(unsigned long long)));
   CTM_HIPC(hipMalloc(&P->dsync, 2 * sizeof(double)));
   CTM_HIPC(hipMemset(P->dsync, 0, 2 * sizeof(double)));
   CTM_HIPC(hipMalloc(&P->dnorm2, P->G * sizeof(double)));
   CTM_HIPC(hipHostMalloc(&P->hsync, 2 * sizeof(double), hipHostMallocDefault));
-  std::vector<int2> single(P->G), ident(P->G);
-  for (int g = 0; g < P->G; ++g) {
-    single[g] = make_int2(P->order[g], 0);
-    ident[g] = make_int2(g, 0);
-  }
-  CTM_HIPC(hipMalloc(&P->dsingle, P->G * sizeof(int2)));
-  CTM_HIPC(hipMemcpy(P->dsingle, single.data(), P->G * sizeof(int2), hipMemcpyHostToDevice));
+  std::vector<int2> ident(P->G);
+  for (int g = 0; g < P->G; ++g) ident[g] = make_int2(g, 0);
   CTM_HIPC(hipMalloc(&P->didentity, P->G * sizeof(int2)));
   CTM_HIPC(hipMemcpy(P->didentity, ident.data(), P->G * sizeof(int2), hipMemcpyHostToDevice));
 #undef CTM_HIPC
@@ -870,15 +978,16 @@ ctm_status ctm_propagate(ctm_plan* P, int level, long long nsteps, const double*
     ChainArgs a = base_args(P, level, (int)nsteps);
     a.start = vref(const_cast<double*>(x), 0, 0);
     a.fin = vref(y, 0, 0);
-    return run_chain(P, a, P->dsingle, P->G, hs);
+    TaskSet* single = nullptr;
+    if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
+    return run_chain(P, a, *single, hs);
   }
   for (int g = 0; g < P->G; ++g) {
     for (long long nn = 0; nn < nsteps; ++nn) {
       ChainArgs a = base_args(P, level, 1, true);
       a.start = vref(const_cast<double*>(nn == 0 ? x : y), 0, 0);
       a.fin = vref(y, 0, 0);
-      if ((st = run_chain(P, a, P->didentity + g, 1, hs, true, P->grids[g].npts)) != CTM_OK)
-        return st;
+      if ((st = run_chain_grid(P, a, g, hs)) != CTM_OK) return st;
     }
   }
   return CTM_OK;
@@ -946,18 +1055,13 @@ ctm_status ctm_get_stats(const ctm_plan* Pc, ctm_stats* st) {
     if (s2 != CTM_OK) return s2;
   }
   // counters live on the device; the caller has synchronised its stream
-  unsigned long long c[CNT_N];
+  unsigned long long c[kNumShapes * CNT_N];
   int flags = 0;
   CTM_HIP(hipMemcpy(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost));
   CTM_HIP(hipMemcpy(&flags, P->dsync + 1, sizeof(int), hipMemcpyDeviceToHost));
   *st = P->stats;
-  st->krylov_iterations = (long long)c[CNT_KRYLOV];
-  st->krylov_max = (long long)c[CNT_KRYLOV_MAX];
-  st->refine_sweeps = (long long)c[CNT_REFINE];
-  st->refine_max = (long long)c[CNT_REFINE_MAX];
-  st->phi_solves = (long long)c[CNT_SOLVES];
+  fold_counters(P, c, st);
   st->status_flags = flags;
-  st->krylov_work = (long long)c[CNT_WORK];
   return CTM_OK;
 }
 

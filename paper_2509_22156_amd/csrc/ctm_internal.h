@@ -105,6 +105,7 @@ struct ShapeCfg {
 constexpr ShapeCfg kShapes[] = {{1, 4}, {2, 4}, {4, 4}, {8, 4}, {16, 4},
                                 {1, 8}, {2, 8}, {4, 8}, {8, 8}, {16, 8}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+static_assert(kNumShapes <= 16, "ctm_stats keeps 16 shape slots");
 
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
                         int ntasks, size_t smem, int tabmax, hipStream_t s);

@@ -34,15 +34,35 @@ __device__ __forceinline__ double readlane(double v, int l) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum over the 64 lanes of a wave; every lane gets the same value (the four
-// row sums are read from fixed lanes and added in a fixed order).
+// DPP move with a row mask: rows outside `ROWMASK` receive 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ unsigned dpp32m(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xF, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dppm(float v) {
+  return __builtin_bit_cast(float, dpp32m<CTRL, ROWMASK>(__builtin_bit_cast(unsigned, v)));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dppm(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const unsigned lo = dpp32m<CTRL, ROWMASK>((unsigned)u);
+  const unsigned hi = dpp32m<CTRL, ROWMASK>((unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave; every lane gets the same value. Row sums
+// by quad permutes and row rotations, then the row broadcasts add row 0 into
+// row 1, row 2 into row 3 and rows 0-1 into row 3; lane 63 holds the total.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp<0x124>(v);  // row_ror:4
   v += dpp<0x128>(v);  // row_ror:8
-  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+  v += dppm<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dppm<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return readlane(v, 63);
 }
 
 // Two LDS slot arrays for cross-wave sums, used strictly alternately: the
@@ -52,7 +72,7 @@ struct RedRing {
   int phase;
 };
 
-// Sum of NV (<= 3) values over the work-group of W (<= 16) waves; every
+// Sum of NV (<= 4) values over the work-group of W (<= 16) waves; every
 // thread gets the same result (partials added in wave order).
 template <int W, int NV, typename T>
 __device__ __forceinline__ void block_sum(T (&v)[NV], RedRing& ring) {

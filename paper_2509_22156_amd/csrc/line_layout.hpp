@@ -25,13 +25,36 @@
 namespace ctm {
 
 // ------------------------------------------------------------- shuffles
+// Lane exchanges inside a line segment of Lc lanes (Lc a power of two,
+// segments aligned). Shifts by one lane use the wave-wide DPP shifts; shifts
+// by 2..8 inside segments of at most 16 lanes stay within a DPP row; longer
+// shifts go through ds_bpermute. Lanes whose source lies outside their
+// segment receive an unspecified value and must be masked by the caller.
 template <typename T>
-__device__ __forceinline__ T shfl_up_seg(T v, int delta, int width) {
-  return __shfl_up(v, (unsigned)delta, width);
+__device__ __forceinline__ T from_minus(T v, int s, int Lc) {
+  if (s == 1) return dpp<0x138>(v);  // wave_shr:1
+  if (Lc <= 16) {
+    switch (s) {
+      case 2: return dpp<0x112>(v);  // row_shr:2
+      case 4: return dpp<0x114>(v);
+      case 8: return dpp<0x118>(v);
+      default: break;
+    }
+  }
+  return __shfl_up(v, (unsigned)s, Lc);
 }
 template <typename T>
-__device__ __forceinline__ T shfl_down_seg(T v, int delta, int width) {
-  return __shfl_down(v, (unsigned)delta, width);
+__device__ __forceinline__ T from_plus(T v, int s, int Lc) {
+  if (s == 1) return dpp<0x130>(v);  // wave_shl:1
+  if (Lc <= 16) {
+    switch (s) {
+      case 2: return dpp<0x102>(v);  // row_shl:2
+      case 4: return dpp<0x104>(v);
+      case 8: return dpp<0x108>(v);
+      default: break;
+    }
+  }
+  return __shfl_down(v, (unsigned)s, Lc);
 }
 
 __device__ __forceinline__ int pow2ceil(int v) {
@@ -48,7 +71,8 @@ struct Lane {
   int Lc;          // lanes per line
   int j0;          // stiff coordinate of the chunk's first unknown (c * K)
   int nval;        // unknowns of the chunk inside the line (0..K)
-  int pbase;       // internal point index of the chunk's first unknown
+  int pbase;       // LDS index of the chunk's first unknown (line * pitch + c * K)
+  int pitch;       // LDS slots per line (Lc * K, a multiple of K)
   long long cbase; // canonical index of the chunk's first unknown
   int cstep;       // canonical stride along the stiff axis
   bool nxt;        // the next chunk of the line holds unknowns
@@ -69,7 +93,8 @@ __device__ __forceinline__ void setup_lane(const GridDev& g, Lane<K>& L) {
   int nv = g.ns - L.j0;
   nv = nv < 0 ? 0 : (nv > K ? K : nv);
   L.nval = live ? nv : 0;
-  L.pbase = L.line * g.ns + L.j0;
+  L.pitch = Lc * K;
+  L.pbase = L.line * L.pitch + L.j0;
   L.nxt = live && (L.j0 + K < g.ns);
   L.cstep = g.cstride[g.sax];
   long long cb = 0;
@@ -228,13 +253,42 @@ __device__ __forceinline__ T op_sup(const LineOp<OPC, T, K>& O, int k) {
   else return O.sup[k];
 }
 
-// Write the chunk to LDS (internal layout); a barrier must follow before
-// line_apply reads it.
+// Write the chunk to LDS (K aligned slots per lane, padding included); a
+// barrier must follow before line_apply reads it.
 template <typename T, int K>
 __device__ __forceinline__ void lds_put(const Lane<K>& L, T* xl, const T (&x)[K]) {
+  if constexpr (sizeof(T) == 8) {
+    double2* p = reinterpret_cast<double2*>(xl + L.pbase);
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (k < L.nval) xl[L.pbase + k] = x[k];
+    for (int k = 0; k < K / 2; ++k) p[k] = make_double2(x[2 * k], x[2 * k + 1]);
+  } else {
+    float4* p = reinterpret_cast<float4*>(xl + L.pbase);
+#pragma unroll
+    for (int k = 0; k < K / 4; ++k) p[k] = make_float4(x[4 * k], x[4 * k + 1], x[4 * k + 2], x[4 * k + 3]);
+  }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void lds_get(const T* src, T (&v)[K]) {
+  if constexpr (sizeof(T) == 8) {
+    const double2* p = reinterpret_cast<const double2*>(src);
+#pragma unroll
+    for (int k = 0; k < K / 2; ++k) {
+      const double2 t = p[k];
+      v[2 * k] = t.x;
+      v[2 * k + 1] = t.y;
+    }
+  } else {
+    const float4* p = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int k = 0; k < K / 4; ++k) {
+      const float4 t = p[k];
+      v[4 * k] = t.x;
+      v[4 * k + 1] = t.y;
+      v[4 * k + 2] = t.z;
+      v[4 * k + 3] = t.w;
+    }
+  }
 }
 
 // y = A x on the chunk; xl holds x of the whole grid (after a barrier).
@@ -242,34 +296,37 @@ template <int OPC, typename T, int K>
 __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
                                            const LineOp<OPC, T, K>& O, const T* xl,
                                            const T (&x)[K], T (&y)[K]) {
-  const T xleft = shfl_up_seg(x[K - 1], 1, L.Lc);
-  const T xright = shfl_down_seg(x[0], 1, L.Lc);
+  const T xleft = from_minus(x[K - 1], 1, L.Lc);
+  const T xright = from_plus(x[0], 1, L.Lc);
+  T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const T xm = (k > 0) ? x[k - 1] : (L.c > 0 ? xleft : (T)0);
     const T xp = (k < K - 1) ? ((k + 1 < L.nval) ? x[k + 1] : (T)0) : (L.nxt ? xright : (T)0);
-    T acc = op_diag(O, k) * x[k] + op_slo(O, k) * xm + op_sup(O, k) * xp;
-    const int p = L.pbase + k;
+    acc[k] = op_diag(O, k) * x[k] + op_slo(O, k) * xm + op_sup(O, k) * xp;
+  }
 #pragma unroll
-    for (int m = 0; m < MAXD - 1; ++m) {
-      if (m < g.d - 1) {
-        const int off = g.lstride[m] * g.ns;
-        const bool lo = (L.nb >> (2 * m)) & 1u;
-        const bool hi = (L.nb >> (2 * m + 1)) & 1u;
-        T xlo = xl[lo ? p - off : p];
-        T xhi = xl[hi ? p + off : p];
-        xlo = lo ? xlo : (T)0;
-        xhi = hi ? xhi : (T)0;
+  for (int m = 0; m < MAXD - 1; ++m) {
+    if (m < g.d - 1) {
+      const int off = g.lstride[m] * L.pitch;
+      const bool lo = (L.nb >> (2 * m)) & 1u;
+      const bool hi = (L.nb >> (2 * m + 1)) & 1u;
+      T vlo[K], vhi[K];
+      lds_get<T, K>(xl + (lo ? L.pbase - off : L.pbase), vlo);
+      lds_get<T, K>(xl + (hi ? L.pbase + off : L.pbase), vhi);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
         T clo = O.olo[m], chi = O.oup[m];
         if constexpr (OPC == OPC_VAR) {
           clo += O.qlo[m] * O.snj[k];
           chi += O.qup[m] * O.snj[k];
         }
-        acc += clo * xlo + chi * xhi;
+        acc[k] += (lo ? clo * vlo[k] : (T)0) + (hi ? chi * vhi[k] : (T)0);
       }
     }
-    y[k] = (k < L.nval) ? acc : (T)0;
   }
+#pragma unroll
+  for (int k = 0; k < K; ++k) y[k] = (k < L.nval) ? acc[k] : (T)0;
 }
 
 // ------------------------------------------------------ preconditioner
@@ -326,8 +383,8 @@ __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC
   //   A u_{c-1} + B u_c + C u_{c+1} = R
   // its coupling to the next chunk: the stiff-axis neighbour j0+K exists
   // iff this chunk is full and the next one holds unknowns
-  const T phi0n = shfl_down_seg(M.phi[0], 1, L.Lc);
-  const T psi0n = shfl_down_seg(M.psi[0], 1, L.Lc);
+  const T phi0n = from_plus(M.phi[0], 1, L.Lc);
+  const T psi0n = from_plus(M.psi[0], 1, L.Lc);
   const bool has_next = L.nxt;
   M.aL = (L.nval == K && K - 1 + L.j0 > 0) ? a[K - 1] : (T)0;
   M.cL = has_next ? op_sup(O, K - 1) : (T)0;
@@ -343,10 +400,10 @@ __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC
     const int s = 1 << r;
     if (s < L.Lc) {
       M.steps = r + 1;
-      const T Am = shfl_up_seg(A, s, L.Lc), Bm = shfl_up_seg(B, s, L.Lc),
-              Cm = shfl_up_seg(C, s, L.Lc);
-      const T Ap = shfl_down_seg(A, s, L.Lc), Bp = shfl_down_seg(B, s, L.Lc),
-              Cp = shfl_down_seg(C, s, L.Lc);
+      const T Am = from_minus(A, s, L.Lc), Bm = from_minus(B, s, L.Lc),
+              Cm = from_minus(C, s, L.Lc);
+      const T Ap = from_plus(A, s, L.Lc), Bp = from_plus(B, s, L.Lc),
+              Cp = from_plus(C, s, L.Lc);
       const bool vm = L.c >= s, vp = L.c + s < L.Lc;
       const T al = vm ? -A / Bm : (T)0;
       const T ga = vp ? -C / Bp : (T)0;
@@ -373,19 +430,19 @@ __device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LinePre<T,
   y[K - 2] = y[K - 2] * M.id[K - 2];
 #pragma unroll
   for (int k = K - 3; k >= 0; --k) y[k] = (y[k] - M.cu[k] * y[k + 1]) * M.id[k];
-  const T y0n = shfl_down_seg(y[0], 1, L.Lc);
+  const T y0n = from_plus(y[0], 1, L.Lc);
   T R = r[K - 1] - M.aL * y[K - 2] - M.cL * y0n;
 #pragma unroll
   for (int st = 0; st < kMaxPcr; ++st) {
     if (st < M.steps) {
       const int s = 1 << st;
-      const T Rm = shfl_up_seg(R, s, L.Lc);
-      const T Rp = shfl_down_seg(R, s, L.Lc);
+      const T Rm = from_minus(R, s, L.Lc);
+      const T Rp = from_plus(R, s, L.Lc);
       R = R + M.pa[st] * Rm + M.pc[st] * Rp;
     }
   }
   const T u = R * M.pinv;
-  T um = shfl_up_seg(u, 1, L.Lc);
+  T um = from_minus(u, 1, L.Lc);
   um = (L.c > 0) ? um : (T)0;
 #pragma unroll
   for (int k = 0; k < K - 1; ++k) z[k] = y[k] - M.phi[k] * um - M.psi[k] * u;

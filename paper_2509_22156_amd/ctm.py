@@ -54,6 +54,9 @@ class Stats(ctypes.Structure):
         ("refine_max", ctypes.c_longlong), ("status_flags", ctypes.c_int),
         ("krylov_work", ctypes.c_longlong), ("chain_launches", ctypes.c_longlong),
         ("chain_ms", ctypes.c_double), ("chain_bytes", ctypes.c_double),
+        ("shape_w", ctypes.c_int * 16), ("shape_k", ctypes.c_int * 16),
+        ("shape_ms", ctypes.c_double * 16), ("shape_launches", ctypes.c_longlong * 16),
+        ("shape_work", ctypes.c_longlong * 16),
     ]
 
 
@@ -259,7 +262,10 @@ class Plan:
                     krylov_max=st.krylov_max, refine_sweeps=st.refine_sweeps,
                     refine_max=st.refine_max, status_flags=st.status_flags,
                     krylov_work=st.krylov_work, chain_launches=st.chain_launches,
-                    chain_ms=st.chain_ms, chain_bytes=st.chain_bytes)
+                    chain_ms=st.chain_ms, chain_bytes=st.chain_bytes,
+                    shapes=[dict(W=st.shape_w[i], K=st.shape_k[i], ms=st.shape_ms[i],
+                                 launches=st.shape_launches[i], work=st.shape_work[i])
+                            for i in range(16) if st.shape_launches[i] or st.shape_work[i]])
 
     def set_timing(self, on: bool = True):
         _check(_lib.ctm_set_timing(self._h, int(on)))
