@@ -74,6 +74,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="heat3d")
     ap.add_argument("--no-extras", action="store_true", help="skip the comparator runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a plain 256 MiB device copy (hardware-counter calibration)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -215,6 +217,12 @@ def main(argv=None):
 
     if not args.no_extras:
         result["comparators"] = _comparators(args, ctm, torch, oracle_u, dof_steps)
+    if args.copy_calibration:
+        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
 
     print(json.dumps(result), flush=True)
     return 0

@@ -38,8 +38,10 @@ struct Solver {
 // y = A x (x written to LDS first; one barrier).
 template <int OPC, typename T, int K>
 __device__ __forceinline__ void sapply(const Solver<OPC, T, K>& S, const T (&x)[K], T (&y)[K]) {
-  lds_put<T, K>(S.L, S.xl, x);
-  __syncthreads();
+  if (S.g.d > 1) {  // one-dimensional grids need no neighbour lines
+    lds_put<T, K>(S.L, S.xl, x);
+    __syncthreads();
+  }
   line_apply<OPC, T, K>(S.g, S.L, S.O, S.xl, x, y);
 }
 

@@ -71,8 +71,8 @@ struct Lane {
   int Lc;          // lanes per line
   int j0;          // stiff coordinate of the chunk's first unknown (c * K)
   int nval;        // unknowns of the chunk inside the line (0..K)
-  int pbase;       // LDS index of the chunk's first unknown (line * pitch + c * K)
-  int pitch;       // LDS slots per line (Lc * K, a multiple of K)
+  int tid;         // thread index: LDS slot of unknown k is k * nl + tid
+  int nl;          // threads per work-group
   long long cbase; // canonical index of the chunk's first unknown
   int cstep;       // canonical stride along the stiff axis
   bool nxt;        // the next chunk of the line holds unknowns
@@ -93,8 +93,8 @@ __device__ __forceinline__ void setup_lane(const GridDev& g, Lane<K>& L) {
   int nv = g.ns - L.j0;
   nv = nv < 0 ? 0 : (nv > K ? K : nv);
   L.nval = live ? nv : 0;
-  L.pitch = Lc * K;
-  L.pbase = L.line * L.pitch + L.j0;
+  L.tid = t;
+  L.nl = blockDim.x;
   L.nxt = live && (L.j0 + K < g.ns);
   L.cstep = g.cstride[g.sax];
   long long cb = 0;
@@ -253,42 +253,15 @@ __device__ __forceinline__ T op_sup(const LineOp<OPC, T, K>& O, int k) {
   else return O.sup[k];
 }
 
-// Write the chunk to LDS (K aligned slots per lane, padding included); a
-// barrier must follow before line_apply reads it.
+// Write the chunk to LDS, transposed: unknown k of thread t goes to slot
+// k * nl + t, so that every LDS access of a wave touches consecutive
+// addresses (no bank conflicts). A barrier must follow before line_apply.
+// Thread t holds chunk c of line `line` with t = line * Lc + c, so the
+// neighbouring line along oax[m] lives in thread t +- lstride[m] * Lc.
 template <typename T, int K>
 __device__ __forceinline__ void lds_put(const Lane<K>& L, T* xl, const T (&x)[K]) {
-  if constexpr (sizeof(T) == 8) {
-    double2* p = reinterpret_cast<double2*>(xl + L.pbase);
 #pragma unroll
-    for (int k = 0; k < K / 2; ++k) p[k] = make_double2(x[2 * k], x[2 * k + 1]);
-  } else {
-    float4* p = reinterpret_cast<float4*>(xl + L.pbase);
-#pragma unroll
-    for (int k = 0; k < K / 4; ++k) p[k] = make_float4(x[4 * k], x[4 * k + 1], x[4 * k + 2], x[4 * k + 3]);
-  }
-}
-
-template <typename T, int K>
-__device__ __forceinline__ void lds_get(const T* src, T (&v)[K]) {
-  if constexpr (sizeof(T) == 8) {
-    const double2* p = reinterpret_cast<const double2*>(src);
-#pragma unroll
-    for (int k = 0; k < K / 2; ++k) {
-      const double2 t = p[k];
-      v[2 * k] = t.x;
-      v[2 * k + 1] = t.y;
-    }
-  } else {
-    const float4* p = reinterpret_cast<const float4*>(src);
-#pragma unroll
-    for (int k = 0; k < K / 4; ++k) {
-      const float4 t = p[k];
-      v[4 * k] = t.x;
-      v[4 * k + 1] = t.y;
-      v[4 * k + 2] = t.z;
-      v[4 * k + 3] = t.w;
-    }
-  }
+  for (int k = 0; k < K; ++k) xl[k * L.nl + L.tid] = x[k];
 }
 
 // y = A x on the chunk; xl holds x of the whole grid (after a barrier).
@@ -308,12 +281,11 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
 #pragma unroll
   for (int m = 0; m < MAXD - 1; ++m) {
     if (m < g.d - 1) {
-      const int off = g.lstride[m] * L.pitch;
+      const int off = g.lstride[m] * L.Lc;
       const bool lo = (L.nb >> (2 * m)) & 1u;
       const bool hi = (L.nb >> (2 * m + 1)) & 1u;
-      T vlo[K], vhi[K];
-      lds_get<T, K>(xl + (lo ? L.pbase - off : L.pbase), vlo);
-      lds_get<T, K>(xl + (hi ? L.pbase + off : L.pbase), vhi);
+      const T* plo = xl + (lo ? L.tid - off : L.tid);
+      const T* phi = xl + (hi ? L.tid + off : L.tid);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         T clo = O.olo[m], chi = O.oup[m];
@@ -321,7 +293,9 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
           clo += O.qlo[m] * O.snj[k];
           chi += O.qup[m] * O.snj[k];
         }
-        acc[k] += (lo ? clo * vlo[k] : (T)0) + (hi ? chi * vhi[k] : (T)0);
+        const T vlo = plo[k * L.nl];
+        const T vhi = phi[k * L.nl];
+        acc[k] += (lo ? clo * vlo : (T)0) + (hi ? chi * vhi : (T)0);
       }
     }
   }
