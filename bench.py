@@ -56,6 +56,25 @@ def flops_per_iteration(d: int, krylov: str) -> int:
     return 2 * (2 * d + 1) + 10
 
 
+def measured_traffic(cls_key: str):
+    """Calibrated HBM bytes per launch of a chain-kernel size class from the
+    committed hardware-counter runs, or None once the kernel sources differ
+    from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "chain_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["source_sha256"] or cls_key not in rec["classes"]:
+        return None
+    return rec["classes"][cls_key]["bytes_per_launch"]
+
+
 def cpu_oracle(prob, pts):
     """The oracle as it stands on this host: time-sequential backward Euler
     with sparse LU on every grid, then the combination at the points."""
@@ -124,10 +143,11 @@ def main(argv=None):
             agg[k] += st[k]
         for sh in st["shapes"]:
             key = (sh["W"], sh["K"])
-            acc = shapes.setdefault(key, dict(ms=0.0, launches=0, work=0))
+            acc = shapes.setdefault(key, dict(ms=0.0, launches=0, work=0, bytes=0.0))
             acc["ms"] += sh["ms"]
             acc["launches"] += sh["launches"]
             acc["work"] += sh["work"]
+            acc["bytes"] += sh["bytes"]
         log(f"step {i + 1}/{args.steps}: mgrit it={st['mgrit_iterations']} "
             f"res={st['mgrit_residual'][-1]:.2e}")
     torch.cuda.synchronize()
@@ -153,10 +173,12 @@ def main(argv=None):
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": (achieved_tflops / PEAK_FP32_TFLOPS) if achieved_tflops else None,
-        "traffic": None,
+        "traffic": measured_traffic(f"W{dw}K{dk}"),
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "avg_launch_ms": dom["ms"] / max(dom["launches"], 1),
         "launches": dom["launches"],
         "algorithmic_flops_per_launch": dom["work"] * fpi / max(dom["launches"], 1),
+        "algorithmic_bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
         "all_classes": {f"W{w}K{k}": v for (w, k), v in sorted(shapes.items())},
         "phase_ms_per_step": agg["chain_ms"] / args.steps,
         "algorithmic_hbm_GBps": agg["chain_bytes"] / chain_s / 1e9 if chain_s > 0 else None,

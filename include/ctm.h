@@ -130,6 +130,7 @@ typedef struct {
   double shape_ms[16];
   long long shape_launches[16];
   long long shape_work[16];
+  double shape_bytes[16];             /* algorithmic HBM bytes of that class's launches */
 } ctm_stats;
 
 /* Fill *p with the paper's solver defaults (Section 4.1): two-level MGRIT,

@@ -75,6 +75,7 @@ struct TaskSet {
   struct Range {
     int shape;
     long long offset, count;
+    double points;  // unknowns summed over the range's tasks
   };
   std::vector<Range> ranges;
 };
@@ -304,11 +305,14 @@ ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
   t.reserve((size_t)P->G * M);
   for (int s = 0; s < kNumShapes; ++s) {
     const long long start = (long long)t.size();
+    double pts = 0.0;
     for (int g : P->order)
-      if (P->gshape[g] == s)
+      if (P->gshape[g] == s) {
         for (long long q = 0; q < M; ++q) t.push_back(make_int2(g, (int)q));
+        pts += (double)P->grids[g].npts * (double)M;
+      }
     const long long cnt = (long long)t.size() - start;
-    if (cnt) ts.ranges.push_back({s, start, cnt});
+    if (cnt) ts.ranges.push_back({s, start, cnt, pts});
   }
   ts.total = (long long)t.size();
   CTM_HIP(hipMalloc(&ts.d, t.size() * sizeof(int2)));
@@ -365,12 +369,15 @@ hipEvent_t take_event(ctm_plan* P, size_t& used, std::vector<hipEvent_t>& pool, 
 // One launch of the chain kernel for the tasks [offset, offset + count) of a
 // task array, all of one shape, on stream s.
 ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int shape,
-                        long long offset, long long count, hipStream_t s, bool mixed) {
+                        long long offset, long long count, double points, hipStream_t s,
+                        bool mixed) {
   ChainArgs c = a;
   c.tasks = tasks + offset;
   if (a.res2) c.res2 = a.res2 + offset;
   c.counters = P->dcounters + (size_t)shape * CNT_N;
   const size_t smem = chain_smem_bytes(shape, P->tabmax, mixed);
+  // algorithmic bytes: every vector role of every task once
+  P->stats.shape_bytes[shape] += 8.0 * points * chain_vectors_per_task(a);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (P->timing) {
     e0 = take_event(P, P->events_used, P->events, true);
@@ -398,7 +405,7 @@ ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStre
   P->stats.chain_bytes += 8.0 * (double)P->slen * per_grid_sets * chain_vectors_per_task(a);
   if (ts.ranges.size() == 1) {
     const auto& r = ts.ranges[0];
-    return launch_range(P, a, ts.d, r.shape, r.offset, r.count, s, mixed);
+    return launch_range(P, a, ts.d, r.shape, r.offset, r.count, r.points, s, mixed);
   }
   size_t used = 0;
   hipEvent_t fork = take_event(P, used, P->sync_events, false);
@@ -412,7 +419,7 @@ ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStre
       cs = P->cstreams[r.shape];
     }
     CTM_HIP(hipStreamWaitEvent(cs, fork, 0));
-    ctm_status st = launch_range(P, a, ts.d, r.shape, r.offset, r.count, cs, mixed);
+    ctm_status st = launch_range(P, a, ts.d, r.shape, r.offset, r.count, r.points, cs, mixed);
     if (st != CTM_OK) return st;
     hipEvent_t j = take_event(P, used, P->sync_events, false);
     if (!j) return fail(CTM_ERR_HIP, "event creation failed");
@@ -426,7 +433,8 @@ ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStre
 // The plain reference schedule: one grid, one launch.
 ctm_status run_chain_grid(ctm_plan* P, const ChainArgs& a, int g, hipStream_t s) {
   P->stats.chain_bytes += 8.0 * (double)P->grids[g].npts * chain_vectors_per_task(a);
-  return launch_range(P, a, P->didentity, P->gshape[g], g, 1, s, false);
+  return launch_range(P, a, P->didentity, P->gshape[g], g, 1, (double)P->grids[g].npts, s,
+                      false);
 }
 
 // Sum of the timed launch durations (after the stream has been synchronised).

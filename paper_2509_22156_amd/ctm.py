@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
         ("chain_ms", ctypes.c_double), ("chain_bytes", ctypes.c_double),
         ("shape_w", ctypes.c_int * 16), ("shape_k", ctypes.c_int * 16),
         ("shape_ms", ctypes.c_double * 16), ("shape_launches", ctypes.c_longlong * 16),
-        ("shape_work", ctypes.c_longlong * 16),
+        ("shape_work", ctypes.c_longlong * 16), ("shape_bytes", ctypes.c_double * 16),
     ]
 
 
@@ -264,7 +264,8 @@ class Plan:
                     krylov_work=st.krylov_work, chain_launches=st.chain_launches,
                     chain_ms=st.chain_ms, chain_bytes=st.chain_bytes,
                     shapes=[dict(W=st.shape_w[i], K=st.shape_k[i], ms=st.shape_ms[i],
-                                 launches=st.shape_launches[i], work=st.shape_work[i])
+                                 launches=st.shape_launches[i], work=st.shape_work[i],
+                                 bytes=st.shape_bytes[i])
                             for i in range(16) if st.shape_launches[i] or st.shape_work[i]])
 
     def set_timing(self, on: bool = True):
