@@ -36,15 +36,18 @@ def log(msg):
 
 
 def workload_problem(name: str, prec: str):
+    """The workload with tolerances chosen for the metric's accuracy target:
+    the final state within 1e-8 relative L2 of the FP64 oracle (measured and
+    reported as err_vs_oracle; both precisions land near 1e-9)."""
     from workloads import make
     p = make(name, prec=prec)
     if prec == "mixed":
-        # FP64-refined implicit steps and MGRIT tolerance chosen so that the
-        # result meets the oracle to 1e-8 relative L2
-        p.update(refine_tol=1e-11, inner_tol=1e-5, refine_maxit=12, mgrit_tol=1e-10,
+        # FP64-refined implicit steps to 1e-10 relative residual, FP32 inner
+        # solves to 1e-6, MGRIT C-point residual to 1e-9
+        p.update(refine_tol=1e-10, inner_tol=1e-6, refine_maxit=12, mgrit_tol=1e-9,
                  krylov_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64)
     else:
-        p.update(krylov_tol=1e-13, mgrit_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64)
+        p.update(krylov_tol=1e-10, mgrit_tol=1e-9, krylov_maxit=20000, mgrit_maxit=64)
     return p
 
 
