@@ -36,18 +36,12 @@ def log(msg):
 
 
 def workload_problem(name: str, prec: str):
-    """The workload with tolerances chosen for the metric's accuracy target:
-    the final state within 1e-8 relative L2 of the FP64 oracle (measured and
-    reported as err_vs_oracle; both precisions land near 1e-9)."""
-    from workloads import make
+    """The workload with the solver tolerances of the measurement (final
+    state within 1e-8 relative L2 of the FP64 oracle, reported as
+    err_vs_oracle)."""
+    from workloads import make, metric_settings
     p = make(name, prec=prec)
-    if prec == "mixed":
-        # FP64-refined implicit steps to 1e-10 relative residual, FP32 inner
-        # solves to 1e-6, MGRIT C-point residual to 1e-9
-        p.update(refine_tol=1e-10, inner_tol=1e-6, refine_maxit=12, mgrit_tol=1e-9,
-                 krylov_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64)
-    else:
-        p.update(krylov_tol=1e-10, mgrit_tol=1e-9, krylov_maxit=20000, mgrit_maxit=64)
+    p.update(metric_settings(prec))
     return p
 
 

@@ -106,6 +106,17 @@ typedef struct {
   const double* ic_weight; /* host [ic_terms] */
   const double* ic_factor; /* host [ic_terms][d][2^n + 1]: factor r on axis i at the finest
                               1-D node x = lo_i + J (hi_i - lo_i) / 2^n, J = 0..2^n */
+  double coarse_tol;  /* relative residual target of the implicit steps on MGRIT levels >= 1,
+                         both precisions; the mixed path's FP32 inner tolerance there is
+                         max(inner_tol, coarse_tol / 4). 0 = use the level-0 tolerances.
+                         The coarse propagator only steers the correction (Section 2.3.1), so
+                         the converged result does not depend on it: a loose value trades
+                         MGRIT iterations for cheaper coarse solves. */
+  int warm_start;     /* nonzero (the default): keep the whole level-0 trajectory of the block
+                         in the workspace (N / nrecomb packed vectors more) and start every
+                         fine implicit solve of a relaxation from the previous iteration's
+                         value at the same time point instead of from the state one step
+                         earlier; 0: keep C-points only. The fixed point is the same. */
 } ctm_problem;
 
 typedef struct {

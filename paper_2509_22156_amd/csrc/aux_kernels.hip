@@ -73,12 +73,14 @@ hipError_t launch_initial_state(const GridDev* grids, int G, int maxpts, int nle
 template <int OPC, int W, int K>
 __global__ void __launch_bounds__(64 * W)
     apply_kernel(const GridDev* __restrict__ grids, const double* __restrict__ tab64, double amp,
-                 double dt, const double* __restrict__ x, double* __restrict__ y, int vcap) {
+                 double dt, const double* __restrict__ x, double* __restrict__ y) {
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
+  const ChainSmem lay = chain_smem_layout(W, K, 0, false);
   double* xl = reinterpret_cast<double*>(smem);
-  double* tl = xl + vcap;
+  double* tl = reinterpret_cast<double*>(smem + lay.tab);
   __shared__ GridDev gs;
+  lds_zero_ghosts<double, K>(xl);
   {
     const int* src = reinterpret_cast<const int*>(grids + blockIdx.x);
     int* dst = reinterpret_cast<int*>(&gs);
@@ -108,12 +110,12 @@ template <int OPC>
 static hipError_t launch_apply_t(int shape, const GridDev* grids, int G, const double* tab64,
                                  double amp, double dt, int tabmax, const double* x, double* y,
                                  hipStream_t s) {
-  const int vcap = 64 * kShapes[shape].W * kShapes[shape].K;
-  const size_t smem = (size_t)(vcap + tabmax) * sizeof(double);
+  const size_t smem = chain_smem_layout(kShapes[shape].W, kShapes[shape].K, 0, false).tab +
+                      (size_t)tabmax * sizeof(double);
 #define CTM_ACASE(IDX, W, K)                                                                   \
   case IDX:                                                                                    \
     hipLaunchKernelGGL((apply_kernel<OPC, W, K>), dim3(G), dim3(64 * W), smem, s, grids, tab64, \
-                       amp, dt, x, y, vcap);                                                   \
+                       amp, dt, x, y);                                                   \
     break;
   switch (shape) {
     CTM_ACASE(0, 1, 4)

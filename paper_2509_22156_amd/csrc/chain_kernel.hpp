@@ -321,18 +321,18 @@ __device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
 }
 
 template <int OPC, int SOLVER, bool MIXED, int W, int K>
-__global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax, int vcap) {
+__global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
+  const ChainSmem lay = chain_smem_layout(W, K, tabmax, MIXED);
   double* xl64 = reinterpret_cast<double*>(smem);
-  float* xl32 = reinterpret_cast<float*>(smem);
-  double* tl64 = reinterpret_cast<double*>(smem + (size_t)vcap * sizeof(double));
+  float* xl32 = reinterpret_cast<float*>(smem + lay.x32);
+  double* tl64 = reinterpret_cast<double*>(smem + lay.tab);
   float* tl32 = reinterpret_cast<float*>(tl64 + tabmax);
-  const size_t tab_bytes =
-      (size_t)tabmax * sizeof(double) + (MIXED ? (size_t)tabmax * sizeof(float) : 0);
-  double* red = reinterpret_cast<double*>(smem + (size_t)vcap * sizeof(double) +
-                                          ((tab_bytes + 15) & ~size_t(15)));
+  double* red = reinterpret_cast<double*>(smem + lay.red);
   __shared__ GridDev gs;
+  lds_zero_ghosts<double, K>(xl64);
+  if constexpr (MIXED) lds_zero_ghosts<float, K>(xl32);
 
   const int2 task = a.tasks[blockIdx.x];
   const int q = task.y;
@@ -383,9 +383,17 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax, 
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
 
   for (int j = 1; j <= a.nsteps; ++j) {
+    // initial guess: the given one (a previous iterate at this time point),
+    // else the state one step earlier
     double x[K];
+    const bool last = (j == a.nsteps);
+    const VecRef gr = last ? a.guess_fin : a.guess;
+    if (gr.base) {
+      gload<K>(L, vec_at(gr, gr.a * q + gr.b + (last ? 0 : j), a.slen, off), x);
+    } else {
 #pragma unroll
-    for (int k = 0; k < K; ++k) x[k] = v[k];
+      for (int k = 0; k < K; ++k) x[k] = v[k];
+    }
     if constexpr (MIXED)
       step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit, x,
                                     &flag, kr_sum, kr_max, rf_sum, rf_max);
@@ -440,15 +448,14 @@ template <int OPC, int SOLVER>
 hipError_t launch_chain_t(bool mixed, int shape, const ChainArgs& a, int ntasks, size_t smem,
                           int tabmax, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-  const int vcap = 64 * kShapes[shape].W * kShapes[shape].K;
 #define CTM_CASE(IDX, W, K)                                                                   \
   case IDX:                                                                                   \
     if (mixed)                                                                                \
       hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, W, K>), dim3(ntasks), dim3(64 * W), \
-                         smem, s, a, tabmax, vcap);                                           \
+                         smem, s, a, tabmax);                                           \
     else                                                                                      \
       hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, W, K>), dim3(ntasks),              \
-                         dim3(64 * W), smem, s, a, tabmax, vcap);                             \
+                         dim3(64 * W), smem, s, a, tabmax);                             \
     break;
   switch (shape) {
     CTM_CASE(0, 1, 4)

@@ -235,6 +235,8 @@ ctm_status validate(const ctm_problem* p) {
   if (p->prec == CTM_PREC_MIXED &&
       (!(p->refine_tol > 0) || !(p->inner_tol > 0) || p->refine_maxit < 1))
     return fail(CTM_ERR_INVALID, "mixed precision needs refine_tol, inner_tol > 0, refine_maxit >= 1");
+  if (!(p->coarse_tol >= 0) || !(p->coarse_tol < 1))
+    return fail(CTM_ERR_INVALID, "coarse_tol must be in [0, 1)");
   const bool sym = (p->op == CTM_OP_HEAT || p->op == CTM_OP_VARCOEF);
   if (p->krylov == CTM_KRYLOV_CG && !sym)
     return fail(CTM_ERR_INVALID, "CG needs a symmetric operator (heat or varcoef)");
@@ -340,10 +342,23 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
   return a;
 }
 
+// Arguments of a chain on MGRIT level l >= 1: the coarse tolerance, when set,
+// replaces the level-0 one (the inner FP32 target follows it).
+ChainArgs coarse_args(ctm_plan* P, int level, int nsteps) {
+  ChainArgs a = base_args(P, level, nsteps);
+  const double ct = P->prob.coarse_tol;
+  if (ct > 0) {
+    a.tol = ct;
+    a.inner_tol = std::max(P->prob.inner_tol, 0.25 * ct);
+  }
+  return a;
+}
+
 VecRef vref(double* base, long long a, long long b) { return VecRef{base, a, b}; }
 
 // Vectors one task must read or write once: start, optional write-back,
-// per-step forcing and intermediate stores, final store and residual target.
+// per-step forcing, initial guesses and intermediate stores, final store and
+// residual target.
 double chain_vectors_per_task(const ChainArgs& a) {
   double v = 0;
   if (a.start.base) v += 1;
@@ -352,6 +367,8 @@ double chain_vectors_per_task(const ChainArgs& a) {
   if (a.inter.base) v += a.nsteps - 1;
   if (a.fin.base) v += 1;
   if (a.target.base) v += 1;
+  if (a.guess.base) v += a.nsteps - 1;
+  if (a.guess_fin.base) v += 1;
   return v;
 }
 
@@ -513,6 +530,7 @@ struct Layout {
   std::vector<long long> N;  // N[l], steps on level l
   double* U = nullptr;
   double* Un = nullptr;
+  double* Tr = nullptr;  // level-0 trajectory (warm starts), index c * q + j
   std::vector<double*> R, E, Cn;
   double* X = nullptr;
   double* Y = nullptr;
@@ -545,6 +563,7 @@ Layout make_layout(const ctm_plan* P, char* base) {
     const long long M0 = lay.N[0] / lay.c;
     lay.U = take(M0 + 1);
     if (fcf) lay.Un = take(M0 + 1);
+    if (p.warm_start) lay.Tr = take(lay.N[0]);
     for (int l = 1; l < lay.L; ++l) {
       lay.R[l] = take(lay.N[l] + 1);
       lay.E[l] = take(lay.N[l] + 1);
@@ -570,7 +589,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
   double* E = lay.E[l];
   ctm_status st;
   if (l == lay.L - 1) {
-    ChainArgs a = base_args(P, l, (int)lay.N[l]);
+    ChainArgs a = coarse_args(P, l, (int)lay.N[l]);
     a.start = vref(nullptr, 0, 0);
     a.forcing = vref(G, 0, 0);
     a.inter = vref(E, 0, 0);
@@ -589,13 +608,13 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
   if (P->prob.relax == CTM_RELAX_FCF) {
     double* Cn = lay.Cn[l];
     CTM_HIP(launch_fill_zero(Cn, P->slen, s));
-    ChainArgs fc = base_args(P, l, (int)c);
+    ChainArgs fc = coarse_args(P, l, (int)c);
     fc.start = vref(E, c, 0);
     fc.forcing = vref(G, c, 0);
     fc.inter = vref(E, c, 0);
     fc.fin = vref(Cn, 1, 1);
     if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
-    ChainArgs fr = base_args(P, l, (int)c);
+    ChainArgs fr = coarse_args(P, l, (int)c);
     fr.start = vref(Cn, 1, 0);
     fr.start_wb = vref(E, c, 0);
     fr.forcing = vref(G, c, 0);
@@ -606,7 +625,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     csrc = Cn;
     ca = 1;
   } else {
-    ChainArgs fr = base_args(P, l, (int)c);
+    ChainArgs fr = coarse_args(P, l, (int)c);
     fr.start = vref(E, c, 0);
     fr.forcing = vref(G, c, 0);
     fr.inter = vref(E, c, 0);
@@ -621,7 +640,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
   // correction at the C-points, then F-relaxation (ideal interpolation)
   CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0), (int)(M + 1),
                          P->slen, s));
-  ChainArgs fi = base_args(P, l, (int)(c - 1));
+  ChainArgs fi = coarse_args(P, l, (int)(c - 1));
   fi.start = vref(E, c, 0);
   fi.forcing = vref(G, c, 0);
   fi.inter = vref(E, c, 0);
@@ -655,13 +674,26 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   CTM_HIP(launch_grid_norms2(P->dgrids, P->G, lay.X, P->dnorm2, s));
   double* U = lay.U;
   double* Un = lay.Un;
+  // warm starts: every relaxation stores its F-points in the trajectory, and
+  // once it holds values, each fine solve starts from the value at its own
+  // time point (the last step of an interval from the current C-point)
+  double* Tr = lay.Tr;
+  bool traj = false;
   for (int it = 1; it <= p.mgrit_maxit; ++it) {
     double* C;
     if (fcf) {
       ChainArgs fc = base_args(P, 0, (int)c);
       fc.start = vref(U, 1, 0);
       fc.fin = vref(Un, 1, 1);
+      if (Tr) {
+        fc.inter = vref(Tr, c, 0);
+        if (traj) {
+          fc.guess = vref(Tr, c, 0);
+          fc.guess_fin = vref(U, 1, 1);
+        }
+      }
       if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
+      traj = (Tr != nullptr);
       C = Un;
     } else {
       C = U;
@@ -671,7 +703,15 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     fr.fin = vref(lay.R[1], 1, 1);
     fr.target = vref(C, 1, 1);
     fr.res2 = lay.res2;
+    if (Tr) {
+      fr.inter = vref(Tr, c, 0);
+      if (traj) {
+        fr.guess = vref(Tr, c, 0);
+        fr.guess_fin = vref(C, 1, 1);
+      }
+    }
     if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
+    traj = (Tr != nullptr);
     CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, P->dsync, s));
     CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     CTM_HIP(hipStreamSynchronize(s));
@@ -744,6 +784,7 @@ ctm_status ctm_problem_defaults(ctm_problem* p) {
   p->refine_tol = 1e-8;
   p->inner_tol = 1e-5;
   p->refine_maxit = 10;
+  p->warm_start = 1;
   return CTM_OK;
 }
 
@@ -813,7 +854,6 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     gd.off = gh.off;
     gd.j0 = P->lattice ? 0 : 1;
     gd.coef = gh.coef;
-    int bits = 0;
     long long stride = 1;
     for (int i = d - 1; i >= 0; --i) {
       gd.lev[i] = gh.lev[i];
@@ -821,9 +861,6 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
       gd.stride[i] = (int)stride;
       gd.cstride[i] = (int)stride;
       stride *= gd.n[i];
-      gd.boff[i] = bits;
-      gd.bmask[i] = (1 << gh.lev[i]) - 1;
-      bits += gh.lev[i];
       gd.lo[i] = prob->lo[i];
       gd.h[i] = (prob->hi[i] - prob->lo[i]) / (double)(1LL << gh.lev[i]);
       gd.ih2[i] = 1.0 / (gd.h[i] * gd.h[i]);

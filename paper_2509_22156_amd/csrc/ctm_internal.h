@@ -29,8 +29,6 @@ struct GridDev {
   long long tab0;      // start of this grid's table block in the table arrays
   int n[MAXD];         // unknowns per axis (axis d-1 fastest)
   int stride[MAXD];    // point-index stride of axis i
-  int boff[MAXD];      // bit offset of coordinate j_i in the packed coordinate word
-  int bmask[MAXD];     // (1 << bits_i) - 1
   int tab[MAXD];       // offset of axis i inside the grid's table block
   int lev[MAXD];       // level l_i
   double ih2[MAXD];    // 1 / h_i^2
@@ -81,6 +79,8 @@ struct ChainArgs {
   VecRef inter;             // optional store after step j < nsteps: index a*q + b + j
   VecRef fin;               // final store (index a*q + b)
   VecRef target;            // optional: residual mode, fin = v - target[a*q + b]
+  VecRef guess;             // optional initial guess of step j < nsteps: index a*q + b + j
+  VecRef guess_fin;         // optional initial guess of step nsteps: index a*q + b
   double* res2;             // residual mode: per-task ||fin||_2^2 (optional)
   unsigned long long* counters;  // statistics (see CNT_*)
   int* status;              // OR of (1 << ctm_status)
@@ -110,14 +110,28 @@ static_assert(kNumShapes <= 16, "ctm_stats keeps 16 shape slots");
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
                         int ntasks, size_t smem, int tabmax, hipStream_t s);
 
-// Dynamic LDS bytes of the chain kernel for a shape and table size.
+// LDS copy of a vector the stencil reads: K rows (one per chunk position k)
+// of pitch 64 W + kLdsGhost; thread t owns column t, and the columns from
+// 64 W on hold zeros that lanes without a neighbour line read instead.
+constexpr int kLdsGhost = 2;
+__host__ __device__ constexpr int lds_pitch(int W) { return 64 * W + kLdsGhost; }
+
+// Dynamic LDS of the chain kernel: FP64 vector, FP32 vector (mixed), the
+// coefficient tables (FP64, then FP32 if mixed), two reduction slots.
+struct ChainSmem {
+  size_t x32, tab, red, total;  // byte offsets and total
+};
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+__host__ __device__ constexpr ChainSmem chain_smem_layout(int W, int K, int tabmax, bool mixed) {
+  const size_t elems = (size_t)K * lds_pitch(W);
+  const size_t x32 = align16(elems * sizeof(double));
+  const size_t tab = x32 + (mixed ? align16(elems * sizeof(float)) : 0);
+  const size_t red = tab + align16((size_t)tabmax * sizeof(double) +
+                                   (mixed ? (size_t)tabmax * sizeof(float) : 0));
+  return ChainSmem{x32, tab, red, red + 2u * 64u * sizeof(double)};
+}
 inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed) {
-  const ShapeCfg c = kShapes[shape];
-  size_t cap = 64u * c.W * c.K;
-  size_t vec = cap * sizeof(double);  // upper bound of npts
-  size_t tabs = (size_t)tabmax * sizeof(double) + (mixed ? (size_t)tabmax * sizeof(float) : 0);
-  size_t red = 2u * 64u * sizeof(double);
-  return vec + ((tabs + 15) & ~size_t(15)) + red;
+  return chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, mixed).total;
 }
 
 // Auxiliary kernels (aux_kernels.hip).

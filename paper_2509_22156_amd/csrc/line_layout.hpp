@@ -71,8 +71,8 @@ struct Lane {
   int Lc;          // lanes per line
   int j0;          // stiff coordinate of the chunk's first unknown (c * K)
   int nval;        // unknowns of the chunk inside the line (0..K)
-  int tid;         // thread index: LDS slot of unknown k is k * nl + tid
-  int nl;          // threads per work-group
+  int tid;         // thread index: LDS slot of unknown k is k * pitch + tid
+  int pitch;       // LDS row pitch: threads per work-group + kLdsGhost
   long long cbase; // canonical index of the chunk's first unknown
   int cstep;       // canonical stride along the stiff axis
   bool nxt;        // the next chunk of the line holds unknowns
@@ -94,7 +94,7 @@ __device__ __forceinline__ void setup_lane(const GridDev& g, Lane<K>& L) {
   nv = nv < 0 ? 0 : (nv > K ? K : nv);
   L.nval = live ? nv : 0;
   L.tid = t;
-  L.nl = blockDim.x;
+  L.pitch = blockDim.x + kLdsGhost;
   L.nxt = live && (L.j0 + K < g.ns);
   L.cstep = g.cstride[g.sax];
   long long cb = 0;
@@ -254,17 +254,28 @@ __device__ __forceinline__ T op_sup(const LineOp<OPC, T, K>& O, int k) {
 }
 
 // Write the chunk to LDS, transposed: unknown k of thread t goes to slot
-// k * nl + t, so that every LDS access of a wave touches consecutive
+// k * pitch + t, so that every LDS access of a wave touches consecutive
 // addresses (no bank conflicts). A barrier must follow before line_apply.
 // Thread t holds chunk c of line `line` with t = line * Lc + c, so the
 // neighbouring line along oax[m] lives in thread t +- lstride[m] * Lc.
 template <typename T, int K>
 __device__ __forceinline__ void lds_put(const Lane<K>& L, T* xl, const T (&x)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) xl[k * L.nl + L.tid] = x[k];
+  for (int k = 0; k < K; ++k) xl[k * L.pitch + L.tid] = x[k];
+}
+
+// Zero the ghost columns (column blockDim.x + i of every row); done once per
+// kernel before the first barrier, never overwritten by lds_put.
+template <typename T, int K>
+__device__ __forceinline__ void lds_zero_ghosts(T* xl) {
+  const int t = threadIdx.x;
+  if (t < K * kLdsGhost)
+    xl[(t / kLdsGhost) * ((int)blockDim.x + kLdsGhost) + (int)blockDim.x + t % kLdsGhost] = (T)0;
 }
 
 // y = A x on the chunk; xl holds x of the whole grid (after a barrier).
+// Padding entries of x (k >= nval) must be zero, and so are those of y. A
+// missing neighbour line is read from the zero ghost column.
 template <int OPC, typename T, int K>
 __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
                                            const LineOp<OPC, T, K>& O, const T* xl,
@@ -275,17 +286,16 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const T xm = (k > 0) ? x[k - 1] : (L.c > 0 ? xleft : (T)0);
-    const T xp = (k < K - 1) ? ((k + 1 < L.nval) ? x[k + 1] : (T)0) : (L.nxt ? xright : (T)0);
+    const T xp = (k < K - 1) ? x[k + 1] : (L.nxt ? xright : (T)0);
     acc[k] = op_diag(O, k) * x[k] + op_slo(O, k) * xm + op_sup(O, k) * xp;
   }
+  const int ghost = L.pitch - kLdsGhost;
 #pragma unroll
   for (int m = 0; m < MAXD - 1; ++m) {
     if (m < g.d - 1) {
       const int off = g.lstride[m] * L.Lc;
-      const bool lo = (L.nb >> (2 * m)) & 1u;
-      const bool hi = (L.nb >> (2 * m + 1)) & 1u;
-      const T* plo = xl + (lo ? L.tid - off : L.tid);
-      const T* phi = xl + (hi ? L.tid + off : L.tid);
+      const T* plo = xl + (((L.nb >> (2 * m)) & 1u) ? L.tid - off : ghost);
+      const T* phi = xl + (((L.nb >> (2 * m + 1)) & 1u) ? L.tid + off : ghost);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         T clo = O.olo[m], chi = O.oup[m];
@@ -293,9 +303,8 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
           clo += O.qlo[m] * O.snj[k];
           chi += O.qup[m] * O.snj[k];
         }
-        const T vlo = plo[k * L.nl];
-        const T vhi = phi[k * L.nl];
-        acc[k] += (lo ? clo * vlo : (T)0) + (hi ? chi * vhi : (T)0);
+        acc[k] += clo * plo[k * L.pitch];
+        acc[k] += chi * phi[k * L.pitch];
       }
     }
   }

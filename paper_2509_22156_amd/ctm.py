@@ -41,6 +41,7 @@ class Problem(ctypes.Structure):
         ("refine_maxit", ctypes.c_int), ("ic_terms", ctypes.c_int),
         ("ic_weight", ctypes.POINTER(ctypes.c_double)),
         ("ic_factor", ctypes.POINTER(ctypes.c_double)),
+        ("coarse_tol", ctypes.c_double), ("warm_start", ctypes.c_int),
     ]
 
 
@@ -157,6 +158,8 @@ def problem_struct(prob: dict):
     s.refine_tol = float(prob.get("refine_tol", 1e-8))
     s.inner_tol = float(prob.get("inner_tol", 1e-5))
     s.refine_maxit = int(prob.get("refine_maxit", 10))
+    s.coarse_tol = float(prob.get("coarse_tol", 0.0))
+    s.warm_start = int(prob.get("warm_start", 1))
     w = np.ascontiguousarray(prob["ic_w"], dtype=np.float64)
     f = np.ascontiguousarray(prob["ic_f"], dtype=np.float64)
     s.ic_terms = int(w.shape[0])

@@ -76,6 +76,8 @@ def _create(prob):
     (lambda s: setattr(s, "mgrit_tol", -1.0), "mgrit_tol"),
     (lambda s: setattr(s, "ic_terms", 0), "initial value"),
     (lambda s: setattr(s, "t1", -1.0), "t1"),
+    (lambda s: setattr(s, "coarse_tol", -1e-3), "coarse_tol"),
+    (lambda s: setattr(s, "coarse_tol", 1.0), "coarse_tol"),
 ])
 def test_invalid_problems_rejected_on_host(mutate, msg):
     s, keep = _create(make("heat2d"))

@@ -174,6 +174,21 @@ def retabulate(p: dict, seed: int = 0) -> dict:
     return p
 
 
+def metric_settings(prec: str) -> dict:
+    """Solver tolerances of the throughput measurement: the final state
+    within 1e-8 relative L2 of the FP64 oracle. Mixed: FP64-refined implicit
+    steps to 1e-10 relative residual around FP32 inner solves to 1e-6; FP64:
+    Krylov to 1e-10. Both: MGRIT C-point residual to 1e-9, and the implicit
+    steps of the coarse MGRIT levels to 1e-3 (they only steer the
+    correction, the fixed point is the fine-level one)."""
+    if prec == "mixed":
+        return dict(prec="mixed", refine_tol=1e-10, inner_tol=1e-6, refine_maxit=12,
+                    mgrit_tol=1e-9, krylov_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64,
+                    coarse_tol=1e-3)
+    return dict(prec="fp64", krylov_tol=1e-10, mgrit_tol=1e-9, krylov_maxit=20000,
+                mgrit_maxit=64, coarse_tol=1e-3)
+
+
 def targets(p: dict, m: int, seed: int = 0) -> np.ndarray:
     """m seeded evaluation points in Omega, shape (m, d), float64.
     Lattice problems get integer lattice states 0..hi-1."""
