@@ -73,12 +73,14 @@ hipError_t launch_initial_state(const GridDev* grids, int G, int maxpts, int nle
 template <int OPC, int W, int K>
 __global__ void __launch_bounds__(64 * W)
     apply_kernel(const GridDev* __restrict__ grids, const double* __restrict__ tab64, double amp,
-                 double dt, const double* __restrict__ x, double* __restrict__ y) {
+                 double dt, const double* __restrict__ x, double* __restrict__ y,
+                 int tabmax) {
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
-  const ChainSmem lay = chain_smem_layout(W, K, 0, false);
+  const ChainSmem lay = chain_smem_layout(W, K, tabmax, false, OPC == OPC_HEAT);
   double* xl = reinterpret_cast<double*>(smem);
   double* tl = reinterpret_cast<double*>(smem + lay.tab);
+  HeatTab<double, K>* ht = reinterpret_cast<HeatTab<double, K>*>(smem + lay.heat);
   __shared__ GridDev gs;
   lds_zero_ghosts<double, K>(xl);
   {
@@ -93,7 +95,8 @@ __global__ void __launch_bounds__(64 * W)
   Lane<K> L;
   setup_lane<K>(g, L);
   LineOp<OPC, double, K> O;
-  lineop_setup<OPC, double, K>(g, L, dt, amp, tl, O);
+  lineop_setup<OPC, double, K>(g, L, dt, amp, tl, ht, O);
+  __syncthreads();  // constant-coefficient table written
   double xs[K], ys[K];
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -110,12 +113,12 @@ template <int OPC>
 static hipError_t launch_apply_t(int shape, const GridDev* grids, int G, const double* tab64,
                                  double amp, double dt, int tabmax, const double* x, double* y,
                                  hipStream_t s) {
-  const size_t smem = chain_smem_layout(kShapes[shape].W, kShapes[shape].K, 0, false).tab +
-                      (size_t)tabmax * sizeof(double);
+  const size_t smem =
+      chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, false, OPC == OPC_HEAT).total;
 #define CTM_ACASE(IDX, W, K)                                                                   \
   case IDX:                                                                                    \
     hipLaunchKernelGGL((apply_kernel<OPC, W, K>), dim3(G), dim3(64 * W), smem, s, grids, tab64, \
-                       amp, dt, x, y);                                                   \
+                       amp, dt, x, y, tabmax);                                                   \
     break;
   switch (shape) {
     CTM_ACASE(0, 1, 4)

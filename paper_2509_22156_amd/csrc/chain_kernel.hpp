@@ -31,7 +31,7 @@ struct Solver {
   const GridDev& g;
   const Lane<K>& L;
   const LineOp<OPC, T, K>& O;
-  const LinePre<T, K>& M;
+  const PreOf<OPC, T, K>& M;
   T* xl;  // LDS vector (precision T)
 };
 
@@ -50,10 +50,12 @@ __device__ __forceinline__ void sapply(const Solver<OPC, T, K>& S, const T (&x)[
 // reduction of (r,z), (Az,z), (r,r). x holds the initial guess (x_zero:
 // it is zero and the first apply is skipped). Stops when
 // ||b - A x||_2^2 <= tol2 * bb on the recursively updated residual.
+// check_first (a guess that may already be converged): test the initial
+// residual on its own reduction before the first preconditioner solve.
 template <int OPC, typename T, int W, int K>
 __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
-                                          const T (&b)[K], bool x_zero, T tol2, int maxit,
-                                          int* flag) {
+                                          const T (&b)[K], bool x_zero, bool check_first,
+                                          T tol2, int maxit, int* flag) {
   T r[K], z[K], w[K], p[K], s[K];
   if (x_zero) {
 #pragma unroll
@@ -63,6 +65,20 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = b[k] - w[k];
     __syncthreads();  // every wave has read x from LDS before z overwrites it
+  }
+  if (check_first && !x_zero) {
+    T s2[2] = {(T)0, (T)0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      s2[0] += r[k] * r[k];
+      s2[1] += b[k] * b[k];
+    }
+    block_sum<W, 2, T>(s2, ring);
+    if (!finite_val(s2[0]) || !finite_val(s2[1])) {
+      *flag |= FLAG_NONFINITE;
+      return 0;
+    }
+    if (s2[0] <= tol2 * s2[1]) return 0;
   }
   linepre_apply<T, K>(S.L, S.M, r, z);
   sapply<OPC, T, K>(S, z, w);
@@ -221,9 +237,9 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
 template <int OPC, int SOLVER, typename T, int W, int K>
 __device__ __forceinline__ int krylov(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
                                       const T (&b)[K], bool x_zero, T tol2, int maxit,
-                                      int* flag) {
+                                      int* flag, bool check_first = false) {
   if constexpr (SOLVER == SOLV_CG)
-    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, tol2, maxit, flag);
+    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, check_first, tol2, maxit, flag);
   else
     return krylov_pbicgstab<OPC, T, W, K>(S, ring, x, b, x_zero, tol2, maxit, flag);
 }
@@ -245,13 +261,15 @@ __device__ __forceinline__ void gstore(const Lane<K>& L, double* dst, const doub
     if (k < L.nval) dst[L.cbase + (long long)k * L.cstep] = v[k];
 }
 
-// One implicit step in FP64: x <- (I + dt L)^-1 v.
+// One implicit step in FP64: x <- (I + dt L)^-1 v (x: the initial guess;
+// warm: a guess that may already meet the tolerance).
 template <int OPC, int SOLVER, int W, int K>
 __device__ __forceinline__ void step_fp64(const Solver<OPC, double, K>& S, RedRing& ring,
                                           const double (&v)[K], double tol2, int maxit,
-                                          double (&x)[K], int* flag, long long& kr_sum,
-                                          long long& kr_max) {
-  const int it = krylov<OPC, SOLVER, double, W, K>(S, ring, x, v, false, tol2, maxit, flag);
+                                          bool warm, double (&x)[K], int* flag,
+                                          long long& kr_sum, long long& kr_max) {
+  const int it =
+      krylov<OPC, SOLVER, double, W, K>(S, ring, x, v, false, tol2, maxit, flag, warm);
   kr_sum += it;
   kr_max = it > kr_max ? it : kr_max;
 }
@@ -324,11 +342,14 @@ template <int OPC, int SOLVER, bool MIXED, int W, int K>
 __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
-  const ChainSmem lay = chain_smem_layout(W, K, tabmax, MIXED);
+  const ChainSmem lay = chain_smem_layout(W, K, tabmax, MIXED, OPC == OPC_HEAT);
   double* xl64 = reinterpret_cast<double*>(smem);
   float* xl32 = reinterpret_cast<float*>(smem + lay.x32);
   double* tl64 = reinterpret_cast<double*>(smem + lay.tab);
   float* tl32 = reinterpret_cast<float*>(tl64 + tabmax);
+  HeatTab<double, K>* ht64 = reinterpret_cast<HeatTab<double, K>*>(smem + lay.heat);
+  HeatTab<float, K>* ht32 = reinterpret_cast<HeatTab<float, K>*>(
+      smem + lay.heat + align16(sizeof(HeatTab<double, K>)));
   double* red = reinterpret_cast<double*>(smem + lay.red);
   __shared__ GridDev gs;
   lds_zero_ghosts<double, K>(xl64);
@@ -350,7 +371,7 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
   Lane<K> L;
   setup_lane<K>(g, L);
   LineOp<OPC, double, K> O64;
-  lineop_setup<OPC, double, K>(g, L, a.dt, a.amp, tl64, O64);
+  lineop_setup<OPC, double, K>(g, L, a.dt, a.amp, tl64, ht64, O64);
 
   const long long off = g.off;
   double v[K];
@@ -369,15 +390,16 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
   const double tol2 = a.tol * a.tol;
 
   // preconditioner and FP32 operator (mixed) are built once per chain
-  LinePre<double, K> M64;
+  PreOf<OPC, double, K> M64;
   LineOp<OPC, float, K> O32;
-  LinePre<float, K> M32;
+  PreOf<OPC, float, K> M32;
   if constexpr (MIXED) {
-    lineop_setup<OPC, float, K>(g, L, a.dt, a.amp, tl32, O32);
+    lineop_setup<OPC, float, K>(g, L, a.dt, a.amp, tl32, ht32, O32);
     linepre_setup<OPC, float, K>(L, O32, M32);
   } else {
     linepre_setup<OPC, double, K>(L, O64, M64);
   }
+  if constexpr (OPC == OPC_HEAT && MIXED) __syncthreads();  // FP64 weights visible
   const Solver<OPC, double, K> S64{g, L, O64, M64, xl64};
   const Solver<OPC, float, K> S32{g, L, O32, M32, xl32};
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
@@ -398,7 +420,8 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
       step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit, x,
                                     &flag, kr_sum, kr_max, rf_sum, rf_max);
     else
-      step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, x, &flag, kr_sum, kr_max);
+      step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, gr.base != nullptr, x, &flag,
+                                   kr_sum, kr_max);
     if (a.forcing.base) {
       double f[K];
       gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);

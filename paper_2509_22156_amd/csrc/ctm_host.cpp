@@ -110,7 +110,10 @@ struct ctm_plan {
   int2* didentity = nullptr;  // (g, 0) in canonical order
   std::vector<int> gshape;    // launch shape of each grid (size class)
   std::map<long long, TaskSet> tsets;  // M -> (g, q) tasks grouped by shape
-  hipStream_t cstreams[kNumShapes] = {};  // one stream per size class
+  // side streams for concurrent size classes: with the caller's stream they
+  // make four, the number of hardware queues HIP gives a process by default
+  static constexpr int kSideStreams = 3;
+  hipStream_t cstreams[kSideStreams] = {};
   std::vector<hipEvent_t> sync_events;    // fork/join events
   ctm_stats stats;
   bool timing = false;
@@ -392,7 +395,7 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   c.tasks = tasks + offset;
   if (a.res2) c.res2 = a.res2 + offset;
   c.counters = P->dcounters + (size_t)shape * CNT_N;
-  const size_t smem = chain_smem_bytes(shape, P->tabmax, mixed);
+  const size_t smem = chain_smem_bytes(shape, P->tabmax, mixed, P->opc == OPC_HEAT);
   // algorithmic bytes: every vector role of every task once
   P->stats.shape_bytes[shape] += 8.0 * points * chain_vectors_per_task(a);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -424,26 +427,51 @@ ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStre
     const auto& r = ts.ranges[0];
     return launch_range(P, a, ts.d, r.shape, r.offset, r.count, r.points, s, mixed);
   }
+  // classes in decreasing order of work (unknowns x tasks), each onto the
+  // lane (caller's stream or a side stream) with the least work so far
+  constexpr int nlanes = ctm_plan::kSideStreams + 1;
+  std::vector<int> order(ts.ranges.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return ts.ranges[x].points > ts.ranges[y].points;
+  });
+  double load[nlanes] = {};
+  int lane_of[kNumShapes];
+  for (int i : order) {
+    int best = 0;
+    for (int l = 1; l < nlanes; ++l)
+      if (load[l] < load[best]) best = l;
+    lane_of[i] = best;
+    load[best] += ts.ranges[i].points;
+  }
   size_t used = 0;
   hipEvent_t fork = take_event(P, used, P->sync_events, false);
   if (!fork) return fail(CTM_ERR_HIP, "event creation failed");
   CTM_HIP(hipEventRecord(fork, s));
-  std::vector<hipEvent_t> joins;
-  for (const auto& r : ts.ranges) {
-    hipStream_t cs = P->cstreams[r.shape];
-    if (!cs) {
-      CTM_HIP(hipStreamCreateWithFlags(&P->cstreams[r.shape], hipStreamNonBlocking));
-      cs = P->cstreams[r.shape];
+  bool forked[nlanes] = {};
+  for (int i : order) {
+    const auto& r = ts.ranges[i];
+    const int l = lane_of[i];
+    hipStream_t cs = s;
+    if (l > 0) {
+      if (!P->cstreams[l - 1])
+        CTM_HIP(hipStreamCreateWithFlags(&P->cstreams[l - 1], hipStreamNonBlocking));
+      cs = P->cstreams[l - 1];
+      if (!forked[l]) {
+        CTM_HIP(hipStreamWaitEvent(cs, fork, 0));
+        forked[l] = true;
+      }
     }
-    CTM_HIP(hipStreamWaitEvent(cs, fork, 0));
     ctm_status st = launch_range(P, a, ts.d, r.shape, r.offset, r.count, r.points, cs, mixed);
     if (st != CTM_OK) return st;
+  }
+  for (int l = 1; l < nlanes; ++l) {
+    if (!forked[l]) continue;
     hipEvent_t j = take_event(P, used, P->sync_events, false);
     if (!j) return fail(CTM_ERR_HIP, "event creation failed");
-    CTM_HIP(hipEventRecord(j, cs));
-    joins.push_back(j);
+    CTM_HIP(hipEventRecord(j, P->cstreams[l - 1]));
+    CTM_HIP(hipStreamWaitEvent(s, j, 0));
   }
-  for (hipEvent_t j : joins) CTM_HIP(hipStreamWaitEvent(s, j, 0));
   return CTM_OK;
 }
 

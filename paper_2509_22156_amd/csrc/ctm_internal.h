@@ -116,22 +116,47 @@ hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainA
 constexpr int kLdsGhost = 2;
 __host__ __device__ constexpr int lds_pitch(int W) { return 64 * W + kLdsGhost; }
 
+// Constant-coefficient operator (OPC_HEAT), one table per work-group and
+// precision in LDS: the stencil weights, and the line preconditioner's
+// factors, which are the same for every line of the grid: the elimination
+// factors of a chunk's interior (shared by all chunks; a chunk scales the
+// responses phiU/psiU by its own couplings) and the cyclic-reduction factors
+// of each lane position c of a line.
+constexpr int kMaxPcr = 6;  // log2(64): cyclic-reduction steps over <= 64 lanes
+template <typename T, int K>
+struct HeatTab {
+  T diag, s;            // diagonal of A, coupling along the stiff axis
+  T o[MAXD - 1];        // coupling to the neighbour lines along oax[m]
+  T m[K], id[K], cu[K]; // Thomas multipliers, reciprocal pivots, upper couplings
+  T phiU[K], psiU[K];   // interior responses to the previous / own interface unknown
+  T pa[kMaxPcr][64], pc[kMaxPcr][64], pinv[64];  // per lane position c
+};
+
 // Dynamic LDS of the chain kernel: FP64 vector, FP32 vector (mixed), the
-// coefficient tables (FP64, then FP32 if mixed), two reduction slots.
+// coefficient tables (FP64, then FP32 if mixed), the constant-coefficient
+// tables (heat; FP64, then FP32 if mixed), two reduction slots.
 struct ChainSmem {
-  size_t x32, tab, red, total;  // byte offsets and total
+  size_t x32, tab, heat, red, total;  // byte offsets and total
 };
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
-__host__ __device__ constexpr ChainSmem chain_smem_layout(int W, int K, int tabmax, bool mixed) {
+__host__ __device__ constexpr size_t heat_tab_bytes(int K, bool mixed) {
+  return K == 4 ? align16(sizeof(HeatTab<double, 4>)) +
+                      (mixed ? align16(sizeof(HeatTab<float, 4>)) : 0)
+                : align16(sizeof(HeatTab<double, 8>)) +
+                      (mixed ? align16(sizeof(HeatTab<float, 8>)) : 0);
+}
+__host__ __device__ constexpr ChainSmem chain_smem_layout(int W, int K, int tabmax, bool mixed,
+                                                          bool heat) {
   const size_t elems = (size_t)K * lds_pitch(W);
   const size_t x32 = align16(elems * sizeof(double));
   const size_t tab = x32 + (mixed ? align16(elems * sizeof(float)) : 0);
-  const size_t red = tab + align16((size_t)tabmax * sizeof(double) +
-                                   (mixed ? (size_t)tabmax * sizeof(float) : 0));
-  return ChainSmem{x32, tab, red, red + 2u * 64u * sizeof(double)};
+  const size_t hb = tab + align16((size_t)tabmax * sizeof(double) +
+                                  (mixed ? (size_t)tabmax * sizeof(float) : 0));
+  const size_t red = hb + (heat ? heat_tab_bytes(K, mixed) : 0);
+  return ChainSmem{x32, tab, hb, red, red + 2u * 64u * sizeof(double)};
 }
-inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed) {
-  return chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, mixed).total;
+inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed, bool heat) {
+  return chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, mixed, heat).total;
 }
 
 // Auxiliary kernels (aux_kernels.hip).

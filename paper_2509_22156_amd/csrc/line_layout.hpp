@@ -20,6 +20,8 @@
 // computed once per chain (per step size).
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace ctm {
@@ -124,33 +126,41 @@ __device__ __forceinline__ void setup_lane(const GridDev& g, Lane<K>& L) {
 //                 VAR adds a per-unknown part qlo/qup[m] * snj[k])
 template <int OPC, typename T, int K>
 struct LineOp {
-  T diag[OPC == OPC_HEAT ? 1 : K];
-  T slo[OPC == OPC_HEAT ? 1 : K];
-  T sup[OPC == OPC_HEAT ? 1 : K];
+  T diag[K];
+  T slo[K];
+  T sup[K];
   T olo[MAXD - 1], oup[MAXD - 1];
   T qlo[OPC == OPC_VAR ? MAXD - 1 : 1], qup[OPC == OPC_VAR ? MAXD - 1 : 1];
   T snj[OPC == OPC_VAR ? K : 1];
 };
+// HEAT: the weights are the same for every lane; they live in the
+// work-group's LDS table (read with broadcast loads), not in registers.
+template <typename T, int K>
+struct LineOp<OPC_HEAT, T, K> {
+  HeatTab<T, K>* h;
+};
 
 // tab: this grid's tables in LDS (SEP: per axis Lo, D, Up of L scaled by
-// dt; VAR: per axis node sines then face sines).
+// dt; VAR: per axis node sines then face sines). ht: the work-group's
+// constant-coefficient table (HEAT only; thread 0 fills its weights, and a
+// barrier must follow before they are read).
 template <int OPC, typename T, int K>
 __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L, double dt,
-                                             double amp, const T* tab, LineOp<OPC, T, K>& O) {
+                                             double amp, const T* tab, HeatTab<T, K>* ht,
+                                             LineOp<OPC, T, K>& O) {
   const int s = g.sax;
   const double cs = dt * g.ih2[s];
   if constexpr (OPC == OPC_HEAT) {
-    double sum = 0.0;
+    O.h = ht;
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
 #pragma unroll
-    for (int i = 0; i < MAXD; ++i) sum += (i < g.d) ? 2.0 * dt * g.ih2[i] : 0.0;
-    O.diag[0] = (T)(1.0 + sum);
-    O.slo[0] = (T)(-cs);
-    O.sup[0] = (T)(-cs);
+      for (int i = 0; i < MAXD; ++i) sum += (i < g.d) ? 2.0 * dt * g.ih2[i] : 0.0;
+      ht->diag = (T)(1.0 + sum);
+      ht->s = (T)(-cs);
 #pragma unroll
-    for (int m = 0; m < MAXD - 1; ++m) {
-      const double cm = (m < g.d - 1) ? dt * g.ih2[g.oax[m]] : 0.0;
-      O.olo[m] = (T)(-cm);
-      O.oup[m] = (T)(-cm);
+      for (int m = 0; m < MAXD - 1; ++m)
+        ht->o[m] = (T)(-((m < g.d - 1) ? dt * g.ih2[g.oax[m]] : 0.0));
     }
   } else if constexpr (OPC == OPC_SEP) {
     T dl = (T)1;
@@ -239,18 +249,28 @@ __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L,
 
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_diag(const LineOp<OPC, T, K>& O, int k) {
-  if constexpr (OPC == OPC_HEAT) return O.diag[0];
+  if constexpr (OPC == OPC_HEAT) return O.h->diag;
   else return O.diag[k];
 }
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_slo(const LineOp<OPC, T, K>& O, int k) {
-  if constexpr (OPC == OPC_HEAT) return O.slo[0];
+  if constexpr (OPC == OPC_HEAT) return O.h->s;
   else return O.slo[k];
 }
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_sup(const LineOp<OPC, T, K>& O, int k) {
-  if constexpr (OPC == OPC_HEAT) return O.sup[0];
+  if constexpr (OPC == OPC_HEAT) return O.h->s;
   else return O.sup[k];
+}
+template <int OPC, typename T, int K>
+__device__ __forceinline__ T op_olo(const LineOp<OPC, T, K>& O, int m) {
+  if constexpr (OPC == OPC_HEAT) return O.h->o[m];
+  else return O.olo[m];
+}
+template <int OPC, typename T, int K>
+__device__ __forceinline__ T op_oup(const LineOp<OPC, T, K>& O, int m) {
+  if constexpr (OPC == OPC_HEAT) return O.h->o[m];
+  else return O.oup[m];
 }
 
 // Write the chunk to LDS, transposed: unknown k of thread t goes to slot
@@ -298,7 +318,7 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
       const T* phi = xl + (((L.nb >> (2 * m + 1)) & 1u) ? L.tid + off : ghost);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        T clo = O.olo[m], chi = O.oup[m];
+        T clo = op_olo(O, m), chi = op_oup(O, m);
         if constexpr (OPC == OPC_VAR) {
           clo += O.qlo[m] * O.snj[k];
           chi += O.qup[m] * O.snj[k];
@@ -313,8 +333,6 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
 }
 
 // ------------------------------------------------------ preconditioner
-constexpr int kMaxPcr = 6;  // log2(64)
-
 template <typename T, int K>
 struct LinePre {
   T m[K];            // Thomas multipliers of the chunk interior (k = 1..K-2)
@@ -429,6 +447,159 @@ __device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LinePre<T,
   um = (L.c > 0) ? um : (T)0;
 #pragma unroll
   for (int k = 0; k < K - 1; ++k) z[k] = y[k] - M.phi[k] * um - M.psi[k] * u;
+  z[K - 1] = u;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (k >= L.nval) z[k] = (T)0;
+}
+
+
+// ------------------------------------- preconditioner, constant coefficients
+// HEAT: the chunk-interior factors are the same for all chunks of all lines
+// (full chunks, and the last chunk of a line, which holds K - 1 unknowns
+// when ns = 2^l - 1; a line of one chunk has ns < K unknowns in every lane)
+// and the cyclic-reduction factors depend on the lane position c only, so
+// they live in the work-group's HeatTab. A lane keeps four scalars: a0
+// scales phiU (zero in the first chunk of a line), ps selects psiU (one in
+// a full chunk), aL and cL are the couplings of its interface unknown.
+template <typename T, int K>
+struct LinePreH {
+  const HeatTab<T, K>* h;
+  T a0, ps, aL, cL;
+  int steps;  // log2(Lc)
+};
+
+template <int OPC, typename T, int K>
+using PreOf = typename std::conditional<OPC == OPC_HEAT, LinePreH<T, K>, LinePre<T, K>>::type;
+
+// Builds the table's factors. Every thread of the work-group calls it after
+// lineop_setup; it contains the barriers that publish the table.
+template <int OPC, typename T, int K>
+__device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC_HEAT, T, K>& O,
+                                              LinePreH<T, K>& M) {
+  static_assert(OPC == OPC_HEAT, "constant-coefficient preconditioner");
+  static_assert(K >= 2, "chunks hold at least two unknowns");
+  HeatTab<T, K>* h = O.h;
+  __syncthreads();  // weights visible
+  if (threadIdx.x == 0) {
+    // interior of a representative chunk: a full one, or the one chunk of
+    // the line (thread 0 holds it) when Lc = 1
+    const T dg = h->diag, sc = h->s;
+    const int nrep = (L.Lc == 1) ? L.nval : K;
+    T a[K], b[K], c[K], mm[K], id[K], cu[K], f[K], ph[K], ps[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a[k] = (k > 0 && k < nrep) ? sc : (T)0;
+      c[k] = (k + 1 < nrep) ? sc : (T)0;
+      b[k] = (k < nrep) ? dg : (T)1;
+    }
+    mm[0] = (T)0;
+    id[0] = (T)1 / b[0];
+#pragma unroll
+    for (int k = 1; k < K - 1; ++k) {
+      mm[k] = a[k] * id[k - 1];
+      id[k] = (T)1 / (b[k] - mm[k] * c[k - 1]);
+    }
+    mm[K - 1] = (T)0;
+    id[K - 1] = (T)1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) cu[k] = (k < K - 2) ? c[k] : (T)0;
+    // phiU = T_I^-1 e_0, psiU = T_I^-1 (s e_{K-2})
+    f[0] = (T)1;
+#pragma unroll
+    for (int k = 1; k < K - 1; ++k) f[k] = -mm[k] * f[k - 1];
+    ph[K - 2] = f[K - 2] * id[K - 2];
+#pragma unroll
+    for (int k = K - 3; k >= 0; --k) ph[k] = (f[k] - cu[k] * ph[k + 1]) * id[k];
+    ps[K - 2] = sc * id[K - 2];
+#pragma unroll
+    for (int k = K - 3; k >= 0; --k) ps[k] = -cu[k] * ps[k + 1] * id[k];
+    ph[K - 1] = (T)0;
+    ps[K - 1] = (T)0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      h->m[k] = mm[k];
+      h->id[k] = id[k];
+      h->cu[k] = cu[k];
+      h->phiU[k] = ph[k];
+      h->psiU[k] = ps[k];
+    }
+  }
+  __syncthreads();  // interior factors visible
+  const T sc = h->s;
+  M.h = h;
+  M.a0 = (L.nval > 0 && L.c > 0) ? sc : (T)0;
+  M.ps = (L.nval == K) ? (T)1 : (T)0;
+  M.aL = (L.nval == K) ? sc : (T)0;
+  M.cL = L.nxt ? sc : (T)0;
+  M.steps = 0;
+  while ((1 << M.steps) < L.Lc) ++M.steps;
+  if (threadIdx.x < 64) {
+    // wave 0 holds line 0 in lanes 0..Lc-1: its interface system gives the
+    // cyclic-reduction factors of every lane position
+    const T bK = (K - 1 < L.nval) ? h->diag : (T)1;
+    const T phi0n = from_plus(M.a0 * h->phiU[0], 1, L.Lc);
+    const T psi0n = from_plus(M.ps * h->psiU[0], 1, L.Lc);
+    T A = -M.aL * M.a0 * h->phiU[K - 2];
+    T B = bK - M.aL * M.ps * h->psiU[K - 2] - M.cL * phi0n;
+    T C = -M.cL * psi0n;
+    const bool store = (L.line == 0);
+#pragma unroll
+    for (int r = 0; r < kMaxPcr; ++r) {
+      const int s = 1 << r;
+      if (s < L.Lc) {
+        const T Am = from_minus(A, s, L.Lc), Bm = from_minus(B, s, L.Lc),
+                Cm = from_minus(C, s, L.Lc);
+        const T Ap = from_plus(A, s, L.Lc), Bp = from_plus(B, s, L.Lc),
+                Cp = from_plus(C, s, L.Lc);
+        const bool vm = L.c >= s, vp = L.c + s < L.Lc;
+        const T al = vm ? -A / Bm : (T)0;
+        const T ga = vp ? -C / Bp : (T)0;
+        if (store) {
+          h->pa[r][L.c] = al;
+          h->pc[r][L.c] = ga;
+        }
+        const T An = vm ? al * Am : (T)0;
+        const T Cn = vp ? ga * Cp : (T)0;
+        B = B + (vm ? al * Cm : (T)0) + (vp ? ga * Ap : (T)0);
+        A = An;
+        C = Cn;
+      }
+    }
+    if (store) h->pinv[L.c] = (T)1 / B;
+  }
+  __syncthreads();  // reduction factors visible
+}
+
+// z = M^-1 r for the chunk (padding entries of r must be zero).
+template <typename T, int K>
+__device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LinePreH<T, K>& M,
+                                              const T (&r)[K], T (&z)[K]) {
+  const HeatTab<T, K>* h = M.h;
+  T y[K];
+  y[0] = r[0];
+#pragma unroll
+  for (int k = 1; k < K - 1; ++k) y[k] = r[k] - h->m[k] * y[k - 1];
+  y[K - 2] = y[K - 2] * h->id[K - 2];
+#pragma unroll
+  for (int k = K - 3; k >= 0; --k) y[k] = (y[k] - h->cu[k] * y[k + 1]) * h->id[k];
+  const T y0n = from_plus(y[0], 1, L.Lc);
+  T R = r[K - 1] - M.aL * y[K - 2] - M.cL * y0n;
+#pragma unroll
+  for (int st = 0; st < kMaxPcr; ++st) {
+    if (st < M.steps) {
+      const int s = 1 << st;
+      const T Rm = from_minus(R, s, L.Lc);
+      const T Rp = from_plus(R, s, L.Lc);
+      R = R + h->pa[st][L.c] * Rm + h->pc[st][L.c] * Rp;
+    }
+  }
+  const T u = R * h->pinv[L.c];
+  T um = from_minus(u, 1, L.Lc);
+  um = (L.c > 0) ? um : (T)0;
+  const T ua = M.a0 * um, up = M.ps * u;
+#pragma unroll
+  for (int k = 0; k < K - 1; ++k) z[k] = y[k] - h->phiU[k] * ua - h->psiU[k] * up;
   z[K - 1] = u;
 #pragma unroll
   for (int k = 0; k < K; ++k)
