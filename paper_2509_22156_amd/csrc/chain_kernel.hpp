@@ -338,6 +338,26 @@ __device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
   rf_max = sweeps > rf_max ? sweeps : rf_max;
 }
 
+// One implicit step as a single FP32 solve from zero (mixed path, loose
+// coarse-level tolerance): x <- (I + dt L)^-1 v to relative tolerance itol.
+template <int OPC, int SOLVER, int W, int K>
+__device__ __forceinline__ void step_single32(const Solver<OPC, float, K>& S32, RedRing& ring,
+                                              const double (&v)[K], float itol2, int maxit,
+                                              double (&x)[K], int* flag, long long& kr_sum,
+                                              long long& kr_max) {
+  float b32[K], d32[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    b32[k] = (float)v[k];
+    d32[k] = 0.0f;
+  }
+  const int it = krylov<OPC, SOLVER, float, W, K>(S32, ring, d32, b32, true, itol2, maxit, flag);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] = (double)d32[k];
+  kr_sum += it;
+  kr_max = it > kr_max ? it : kr_max;
+}
+
 template <int OPC, int SOLVER, bool MIXED, int W, int K>
 __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
   constexpr int BS = 64 * W;
@@ -405,6 +425,12 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
 
   for (int j = 1; j <= a.nsteps; ++j) {
+    // heat (few registers in use): the forcing of this step is loaded
+    // before the solve, so that its latency hides behind it
+    constexpr bool kEarly = (OPC == OPC_HEAT);
+    double f[K];
+    if (kEarly && a.forcing.base)
+      gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
     // initial guess: the given one (a previous iterate at this time point),
     // else the state one step earlier
     double x[K];
@@ -416,15 +442,19 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
 #pragma unroll
       for (int k = 0; k < K; ++k) x[k] = v[k];
     }
-    if constexpr (MIXED)
-      step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit, x,
-                                    &flag, kr_sum, kr_max, rf_sum, rf_max);
-    else
+    if constexpr (MIXED) {
+      if (a.single32)
+        step_single32<OPC, SOLVER, W, K>(S32, ring, v, itol2, a.maxit, x, &flag, kr_sum, kr_max);
+      else
+        step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit,
+                                      x, &flag, kr_sum, kr_max, rf_sum, rf_max);
+    } else {
       step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, gr.base != nullptr, x, &flag,
                                    kr_sum, kr_max);
+    }
     if (a.forcing.base) {
-      double f[K];
-      gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
+      if (!kEarly)
+        gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
 #pragma unroll
       for (int k = 0; k < K; ++k) v[k] = x[k] + f[k];
     } else {

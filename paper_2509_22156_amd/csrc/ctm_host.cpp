@@ -346,13 +346,19 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
 }
 
 // Arguments of a chain on MGRIT level l >= 1: the coarse tolerance, when set,
-// replaces the level-0 one (the inner FP32 target follows it).
+// replaces the level-0 one. In the mixed path a tolerance that FP32 reaches
+// by itself (>= 1e-5) makes each coarse step a single FP32 solve; otherwise
+// the inner FP32 target follows it.
 ChainArgs coarse_args(ctm_plan* P, int level, int nsteps) {
   ChainArgs a = base_args(P, level, nsteps);
   const double ct = P->prob.coarse_tol;
   if (ct > 0) {
     a.tol = ct;
     a.inner_tol = std::max(P->prob.inner_tol, 0.25 * ct);
+    if (P->mixed && ct >= 1e-5) {
+      a.single32 = 1;
+      a.inner_tol = ct;
+    }
   }
   return a;
 }

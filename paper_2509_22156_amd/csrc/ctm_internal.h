@@ -70,7 +70,8 @@ struct ChainArgs {
   int nsteps;
   int maxit;                // Krylov iterations per solve / per refinement sweep
   int refine_maxit;
-  int pad_;
+  int single32;             // mixed path: each step is one FP32 solve to inner_tol (no
+                            // FP64 refinement); for loose coarse-level tolerances
   double tol;               // FP64 path Krylov tolerance, or mixed refinement tolerance
   double inner_tol;         // mixed path FP32 Krylov tolerance
   VecRef start;             // start vector (base == nullptr: zero)
