@@ -189,7 +189,7 @@ ctm_status ctm_propagate(ctm_plan* plan, int level, long long nsteps, const doub
 /* The whole method (Algorithm 3): for each of the s recombination blocks,
  * MGRIT (or time-sequential stepping when mgrit_levels = 1) on every grid
  * from the block's start state, then combine-and-project onto every grid
- * before the next block (Section 2.2.2). u0 (packed, may be NULL = the
+ * (ctm_recombine) before the next block (Section 2.2.2). u0 (packed, may be NULL = the
  * problem's sampled initial value) is the start state; u_final receives the
  * packed component states at t1. ws must hold ctm_plan_workspace_bytes.
  * Synchronises s. Statistics are available through ctm_get_stats. */
@@ -204,8 +204,31 @@ ctm_status ctm_gather(ctm_plan* plan, const double* u, const double* pts, long l
 
 /* Combine, then project onto every component grid (Section 2.2.2,
  * combine-then-project operator): out[packed] = u^(c) at the unknowns of
- * every grid. u and out must not overlap. Async. */
+ * every grid, by direct interpolation (every unknown sums the interpolants
+ * of all grids; cost grows with the number of grids). u and out must not
+ * overlap. Async. */
 ctm_status ctm_combine_project(ctm_plan* plan, const double* u, double* out, ctm_stream s);
+
+/* Change of basis of every component grid (Section 2.2.2, hierarchization
+ * H_l and de-hierarchization H_l^-1): inverse = 0 maps nodal values to the
+ * surpluses of the piecewise linear hierarchical basis (per axis, the value
+ * at a node of level k minus the mean of its two parents at distance
+ * 2^-k; zero at the Dirichlet boundary and at the lattice node hi),
+ * inverse != 0 maps back. in and out are packed device vectors and may be
+ * the same. Async. */
+ctm_status ctm_hierarchize(ctm_plan* plan, const double* in, double* out, int inverse,
+                           ctm_stream s);
+
+/* Combine-then-project through the hierarchical basis, Q = H^-1 Qbar H
+ * (Section 2.2.2, recombination operator Qbar): hierarchize every grid, sum
+ * the surpluses of each basis function over the grids that contain it with
+ * the combination coefficients, give every grid the sums of its own basis
+ * functions, de-hierarchize. Equals ctm_combine_project up to rounding, at a
+ * cost linear in the state length; ctm_solve uses it between recombination
+ * blocks. u and out may be the same vector. The first call builds the
+ * plan's node map (device memory owned by the plan, about 16 bytes per
+ * unknown). Async. */
+ctm_status ctm_recombine(ctm_plan* plan, const double* u, double* out, ctm_stream s);
 
 /* Enable (on != 0) or disable timing of the implicit-step kernel: every
  * launch made by ctm_solve / ctm_propagate is then bracketed by two HIP

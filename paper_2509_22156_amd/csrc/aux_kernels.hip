@@ -264,6 +264,96 @@ hipError_t launch_project(const GridDev* grids, const long long* offsets, int G,
   return hipGetLastError();
 }
 
+// ----------------------------------------------------- hierarchical basis
+// 1-D passes along each axis of the grid: a node J at level k (an odd
+// multiple of 2^(l-k)) has the parents J -/+ 2^(l-k); its surplus is its
+// value minus their mean (zero at the Dirichlet boundary and at the lattice
+// node hi). Forward: levels finest first; inverse: coarsest first. Nodes of
+// one level only read coarser ones, so a level is one parallel pass.
+template <bool INV>
+__global__ void __launch_bounds__(256)
+    hier_kernel(const GridDev* __restrict__ grids, int lattice, const double* in,
+                double* out) {
+  extern __shared__ double buf[];
+  __shared__ GridDev gs;
+  {
+    const int* src = reinterpret_cast<const int*>(grids + blockIdx.x);
+    int* dst = reinterpret_cast<int*>(&gs);
+    for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += 256) dst[t] = src[t];
+  }
+  __syncthreads();
+  const GridDev& g = gs;
+  const int npts = g.npts;
+  for (int p = threadIdx.x; p < npts; p += 256) buf[p] = in[g.off + p];
+  __syncthreads();
+  const int j0 = lattice ? 0 : 1;
+  for (int i = 0; i < g.d; ++i) {
+    const int li = g.lev[i], ni = g.n[i], sti = g.stride[i];
+    for (int step = 0; step < li; ++step) {
+      const int k = INV ? 1 + step : li - step;
+      const int st = 1 << (li - k);
+      for (int p = threadIdx.x; p < npts; p += 256) {
+        const int J = (p / sti) % ni + j0;
+        if ((J & (2 * st - 1)) != st) continue;
+        const int jl = J - st - j0, jr = J + st - j0;  // parents as unknown indices
+        const double vl = (jl >= 0) ? buf[p - st * sti] : 0.0;
+        const double vr = (jr < ni) ? buf[p + st * sti] : 0.0;
+        const double m = 0.5 * (vl + vr);
+        buf[p] = INV ? buf[p] + m : buf[p] - m;
+      }
+      __syncthreads();
+    }
+  }
+  for (int p = threadIdx.x; p < npts; p += 256) out[g.off + p] = buf[p];
+}
+
+hipError_t launch_hierarchize(const GridDev* grids, int G, int maxpts, bool lattice,
+                              bool inverse, const double* in, double* out, hipStream_t s) {
+  if (G <= 0) return hipSuccess;
+  const size_t smem = (size_t)maxpts * sizeof(double);
+  if (inverse)
+    hipLaunchKernelGGL(hier_kernel<true>, dim3(G), dim3(256), smem, s, grids, (int)lattice, in,
+                       out);
+  else
+    hipLaunchKernelGGL(hier_kernel<false>, dim3(G), dim3(256), smem, s, grids, (int)lattice, in,
+                       out);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+    hier_combine_kernel(const int* __restrict__ off, const int* __restrict__ idx,
+                        const double* __restrict__ coef, int nodes,
+                        const double* __restrict__ uh, double* __restrict__ sg) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= nodes) return;
+  double acc = 0.0;
+  for (int e = off[s]; e < off[s + 1]; ++e) acc += coef[e] * uh[idx[e]];
+  sg[s] = acc;
+}
+
+hipError_t launch_hier_combine(const int* off, const int* idx, const double* coef, int nodes,
+                               const double* uh, double* sg, hipStream_t s) {
+  if (nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hier_combine_kernel, dim3((nodes + 255) / 256), dim3(256), 0, s, off, idx,
+                     coef, nodes, uh, sg);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+    hier_scatter_kernel(const int* __restrict__ node, long long slen,
+                        const double* __restrict__ sg, double* __restrict__ out) {
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p < slen) out[p] = sg[node[p]];
+}
+
+hipError_t launch_hier_scatter(const int* node, long long slen, const double* sg, double* out,
+                               hipStream_t s) {
+  if (slen <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hier_scatter_kernel, dim3((unsigned)((slen + 255) / 256)), dim3(256), 0, s,
+                     node, slen, sg, out);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------- reductions
 __global__ void __launch_bounds__(256)
     grid_norms2_kernel(const GridDev* __restrict__ grids, const double* __restrict__ u,

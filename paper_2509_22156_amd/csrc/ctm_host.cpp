@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <string>
@@ -114,6 +115,14 @@ struct ctm_plan {
   // make four, the number of hardware queues HIP gives a process by default
   static constexpr int kSideStreams = 3;
   hipStream_t cstreams[kSideStreams] = {};
+  // hierarchical basis (built on first use): node id of every unknown; per
+  // node, the unknowns of all grids that share its basis function
+  int hnodes = 0;
+  int* dhnode = nullptr;    // [slen]
+  int* dhoff = nullptr;     // [hnodes + 1]
+  int* dhidx = nullptr;     // [slen], grouped by node, canonical order inside a node
+  double* dhcoef = nullptr; // [slen] combination coefficient of the entry's grid
+  double* dhsg = nullptr;   // [hnodes] combined surpluses
   std::vector<hipEvent_t> sync_events;    // fork/join events
   ctm_stats stats;
   bool timing = false;
@@ -131,6 +140,11 @@ struct ctm_plan {
     hipFree(dsync);
     hipFree(dnorm2);
     hipFree(didentity);
+    hipFree(dhnode);
+    hipFree(dhoff);
+    hipFree(dhidx);
+    hipFree(dhcoef);
+    hipFree(dhsg);
     if (hsync) hipHostFree(hsync);
     for (auto& kv : tsets) hipFree(kv.second.d);
     for (auto e : events) hipEventDestroy(e);
@@ -682,6 +696,76 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
   return run_chain(P, fi, *tasks, s);
 }
 
+// Node map of the hierarchical basis: every unknown named by its node on
+// the finest grid (per axis J * 2^(n - l_i)); unknowns of different grids at
+// the same node share one hierarchical basis function (Section 2.2.2).
+ctm_status ensure_hier(ctm_plan* P) {
+  if (P->dhnode) return CTM_OK;
+  const long long N = P->slen;
+  if (N >= (1LL << 31)) return fail(CTM_ERR_INVALID, "state too long for the node map");
+  const int d = P->d;
+  std::vector<uint32_t> J((size_t)N * d);
+  std::vector<double> cof((size_t)N);
+  for (const auto& g : P->hdev) {
+    for (int p = 0; p < g.npts; ++p) {
+      int rem = p;
+      for (int i = d - 1; i >= 0; --i) {
+        const int j = rem % g.n[i];
+        rem /= g.n[i];
+        J[(size_t)(g.off + p) * d + i] = (uint32_t)(j + g.j0) << (P->n - g.lev[i]);
+      }
+      cof[(size_t)(g.off + p)] = g.coef;
+    }
+  }
+  std::vector<int> ord((size_t)N);
+  for (long long p = 0; p < N; ++p) ord[(size_t)p] = (int)p;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    const uint32_t* x = &J[(size_t)a * d];
+    const uint32_t* y = &J[(size_t)b * d];
+    for (int i = 0; i < d; ++i)
+      if (x[i] != y[i]) return x[i] < y[i];
+    return false;
+  });
+  std::vector<int> node((size_t)N), off;
+  std::vector<double> coef((size_t)N);
+  for (size_t e = 0; e < ord.size(); ++e) {
+    const bool fresh = (e == 0) || std::memcmp(&J[(size_t)ord[e] * d], &J[(size_t)ord[e - 1] * d],
+                                               d * sizeof(uint32_t)) != 0;
+    if (fresh) off.push_back((int)e);
+    node[(size_t)ord[e]] = (int)off.size() - 1;
+    coef[e] = cof[(size_t)ord[e]];
+  }
+  off.push_back((int)N);
+  const int nodes = (int)off.size() - 1;
+  auto alloc = [&](void** ptr, size_t bytes, const void* src) -> ctm_status {
+    if (hipMalloc(ptr, bytes) != hipSuccess) return fail(CTM_ERR_NOMEM, "device allocation failed");
+    if (src && hipMemcpy(*ptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(CTM_ERR_HIP, "hipMemcpy failed");
+    return CTM_OK;
+  };
+  ctm_status st;
+  if ((st = alloc((void**)&P->dhoff, off.size() * sizeof(int), off.data())) != CTM_OK ||
+      (st = alloc((void**)&P->dhidx, ord.size() * sizeof(int), ord.data())) != CTM_OK ||
+      (st = alloc((void**)&P->dhcoef, coef.size() * sizeof(double), coef.data())) != CTM_OK ||
+      (st = alloc((void**)&P->dhsg, (size_t)nodes * sizeof(double), nullptr)) != CTM_OK ||
+      (st = alloc((void**)&P->dhnode, node.size() * sizeof(int), node.data())) != CTM_OK)
+    return st;
+  P->hnodes = nodes;
+  return CTM_OK;
+}
+
+// Combine-then-project through the hierarchical basis, Q = H^-1 Qbar H
+// (Section 2.2.2); u and out may be the same vector.
+ctm_status recombine(ctm_plan* P, const double* u, double* out, hipStream_t s) {
+  ctm_status st = ensure_hier(P);
+  if (st != CTM_OK) return st;
+  CTM_HIP(launch_hierarchize(P->dgrids, P->G, P->maxpts, P->lattice, false, u, out, s));
+  CTM_HIP(launch_hier_combine(P->dhoff, P->dhidx, P->dhcoef, P->hnodes, out, P->dhsg, s));
+  CTM_HIP(launch_hier_scatter(P->dhnode, P->slen, P->dhsg, out, s));
+  CTM_HIP(launch_hierarchize(P->dgrids, P->G, P->maxpts, P->lattice, true, out, out, s));
+  return CTM_OK;
+}
+
 // MGRIT on one block: X (start) -> Y (state at the block end).
 ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   const ctm_problem& p = P->prob;
@@ -1089,7 +1173,7 @@ ctm_status ctm_solve(ctm_plan* P, void* ws, size_t ws_bytes, const double* u0, d
   }
   ctm_status result = CTM_OK;
   for (int b = 0; b < P->prob.nrecomb; ++b) {
-    if (b > 0) CTM_HIP(launch_project(P->dgrids, P->doffsets, P->G, P->slen, lay.Y, lay.X, hs));
+    if (b > 0 && (st = recombine(P, lay.Y, lay.X, hs)) != CTM_OK) return st;
     st = mgrit_block(P, lay, hs);
     P->stats.blocks += 1;
     if (st == CTM_ERR_NOCONV) {
@@ -1117,6 +1201,19 @@ ctm_status ctm_combine_project(ctm_plan* P, const double* u, double* out, ctm_st
   if (u == out) return fail(CTM_ERR_INVALID, "u and out must not overlap");
   CTM_HIP(launch_project(P->dgrids, P->doffsets, P->G, P->slen, u, out, (hipStream_t)s));
   return CTM_OK;
+}
+
+ctm_status ctm_hierarchize(ctm_plan* P, const double* in, double* out, int inverse,
+                           ctm_stream s) {
+  if (!P || !in || !out) return fail(CTM_ERR_INVALID, "NULL argument");
+  CTM_HIP(launch_hierarchize(P->dgrids, P->G, P->maxpts, P->lattice, inverse != 0, in, out,
+                             (hipStream_t)s));
+  return CTM_OK;
+}
+
+ctm_status ctm_recombine(ctm_plan* P, const double* u, double* out, ctm_stream s) {
+  if (!P || !u || !out) return fail(CTM_ERR_INVALID, "NULL argument");
+  return recombine(P, u, out, (hipStream_t)s);
 }
 
 ctm_status ctm_set_timing(ctm_plan* P, int on) {

@@ -170,6 +170,16 @@ hipError_t launch_gather(const GridDev* grids, int G, const double* u, const dou
                          long long npts, double* out, hipStream_t s);
 hipError_t launch_project(const GridDev* grids, const long long* offsets, int G, long long slen,
                           const double* u, double* out, hipStream_t s);
+// Hierarchical basis (Section 2.2.2): per-grid (de)hierarchization (one
+// work-group per grid, the grid staged in LDS; in may equal out), the
+// combination of surpluses per basis function, sg[s] = sum over the entries
+// e of node s of coef[e] * uh[idx[e]], and the scatter out[p] = sg[node[p]].
+hipError_t launch_hierarchize(const GridDev* grids, int G, int maxpts, bool lattice,
+                              bool inverse, const double* in, double* out, hipStream_t s);
+hipError_t launch_hier_combine(const int* off, const int* idx, const double* coef, int nodes,
+                               const double* uh, double* sg, hipStream_t s);
+hipError_t launch_hier_scatter(const int* node, long long slen, const double* sg, double* out,
+                               hipStream_t s);
 hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, double* out,
                               hipStream_t s);
 hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,

@@ -88,6 +88,8 @@ def _load():
         "ctm_solve": [P, P, sz, P, P, P],
         "ctm_gather": [P, P, P, ll, P, P],
         "ctm_combine_project": [P, P, P, P],
+        "ctm_hierarchize": [P, P, P, i, P],
+        "ctm_recombine": [P, P, P, P],
         "ctm_get_stats": [P, ctypes.POINTER(Stats)],
         "ctm_set_timing": [P, i],
     }
@@ -256,6 +258,16 @@ class Plan:
         _check(_lib.ctm_combine_project(self._h, _ptr(u), _ptr(out), _stream()))
         return out
 
+    def hierarchize(self, u, out=None, inverse=False):
+        out = self._vec(out)
+        _check(_lib.ctm_hierarchize(self._h, _ptr(u), _ptr(out), int(bool(inverse)), _stream()))
+        return out
+
+    def recombine(self, u, out=None):
+        out = self._vec(out)
+        _check(_lib.ctm_recombine(self._h, _ptr(u), _ptr(out), _stream()))
+        return out
+
     def stats(self) -> dict:
         st = Stats()
         _check(_lib.ctm_get_stats(self._h, ctypes.byref(st)))
@@ -280,5 +292,5 @@ def exported_symbols():
     return ["ctm_problem_defaults", "ctm_plan_create", "ctm_plan_destroy", "ctm_plan_grids",
             "ctm_plan_grid_info", "ctm_plan_state_len", "ctm_plan_workspace_bytes",
             "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_gather",
-            "ctm_combine_project", "ctm_get_stats", "ctm_set_timing", "ctm_status_string",
+            "ctm_combine_project", "ctm_hierarchize", "ctm_recombine", "ctm_get_stats", "ctm_set_timing", "ctm_status_string",
             "ctm_last_error"]

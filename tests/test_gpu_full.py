@@ -74,3 +74,20 @@ def test_full_size_solve(name, kw, tol, stride):
     ref_g = combine.combine_at(p, gl, split(p, u), pts)
     scale = sum(abs(c) for (_, _, c) in gl) * np.abs(u).max()
     assert np.abs(got - ref_g).max() <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("name", ["heat2d", "heat3d", "ou4d", "cme5d", "varcoef6d"])
+def test_full_size_recombine(name):
+    # combine-then-project through the hierarchical basis at full size
+    from workloads import random_vectors
+    p = make(name, prec="fp64")
+    plan = ctm.Plan(p)
+    _say(f"full recombine {name}: G={plan.G} unknowns={plan.slen}")
+    x = random_vectors(plan.slen, 1, seed=21)[0]
+    got = plan.recombine(torch.from_numpy(x).cuda()).cpu().numpy()
+    gl = solve.grid_list(p)
+    ref = np.concatenate(combine.recombine_hier(p, gl, split(p, x)))
+    scale = sum(abs(c) for (_, _, c) in gl) * np.abs(x).max()
+    err = np.abs(got - ref).max() / scale
+    _say(f"  max error / (sum|c| max|x|) = {err:.2e}")
+    assert err <= 1e-14

@@ -196,6 +196,47 @@ def test_gather_and_project(name):
     assert np.abs(proj - ref_p).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("name", ALL)
+def test_hierarchize_matches_oracle(name):
+    p = _fp64(_small(name))
+    _say(f"hierarchize {name}")
+    plan = ctm.Plan(p)
+    x = random_vectors(plan.slen, 1, seed=12)[0]
+    xt = torch.from_numpy(x).cuda()
+    gl = solve.grid_list(p)
+    states = split(p, x)
+    h = plan.hierarchize(xt).cpu().numpy()
+    ref = np.concatenate([combine.hierarchize(p, l, u) for (l, _, _), u in zip(gl, states)])
+    assert np.abs(h - ref).max() <= 1e-14 * np.abs(ref).max() * 8
+    back = plan.hierarchize(torch.from_numpy(ref).cuda(), inverse=True).cpu().numpy()
+    assert np.abs(back - x).max() <= 1e-13 * np.abs(x).max()
+    # in place
+    y = xt.clone()
+    plan.hierarchize(y, out=y)
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-14 * np.abs(ref).max() * 8
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_recombine_matches_oracle_and_direct(name):
+    p = _fp64(_small(name))
+    _say(f"recombine {name}")
+    plan = ctm.Plan(p)
+    x = random_vectors(plan.slen, 1, seed=13)[0]
+    xt = torch.from_numpy(x).cuda()
+    gl = solve.grid_list(p)
+    states = split(p, x)
+    got = plan.recombine(xt).cpu().numpy()
+    ref = np.concatenate(combine.recombine_hier(p, gl, states))
+    scale = sum(abs(c) for (_, _, c) in gl) * np.abs(x).max()
+    assert np.abs(got - ref).max() <= 1e-14 * scale
+    direct = plan.combine_project(xt).cpu().numpy()
+    assert np.abs(got - direct).max() <= 1e-13 * scale
+    # twice in a row, the second in place
+    y = xt.clone()
+    plan.recombine(y, out=y)
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-14 * scale
+
+
 def test_recombination_blocks():
     p = _fp64(_small("heat3d", nsteps=64, nrecomb=2))
     _say("solve s=2")

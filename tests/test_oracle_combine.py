@@ -82,3 +82,68 @@ def test_interpolant_between_nodes_and_boundary():
     q = make("cme5d", d=1)
     got = combine.interpolate(q, (1,), np.array([3.0, 5.0]), np.array([[0.0], [16.0], [48.0], [63.0]]))
     assert np.allclose(got, [3.0, 4.0, 2.5, 5.0 / 32], atol=1e-15)
+
+
+# ------------------------------------------------------- hierarchical basis
+def _level_of(J, li):
+    # level at which node index J (0 < J < 2^li) first appears
+    tz = (J & -J).bit_length() - 1
+    return li - tz
+
+
+@pytest.mark.parametrize("l", [(5,), (3, 4), (2, 3, 4), (4, 1, 2)])
+def test_hierarchical_surplus_closed_form(l):
+    # f = prod (x_i - lo_i)(hi_i - x_i) has f_i'' = -2 on every axis, so the
+    # 1-D surplus f(x) - (f(x-h) + f(x+h))/2 at a level-k node is h_k^2 and
+    # the tensor surplus is the product over axes
+    p = make("heat3d", d=len(l), n=max(l) + 1)
+    p["lo"] = [-0.5, 0.25, 1.0][: len(l)]
+    p["hi"] = [1.5, 2.25, 1.75][: len(l)]
+    lo, hi = np.asarray(p["lo"]), np.asarray(p["hi"])
+    X = grids.coordinates(p, l)
+    u = np.prod((X - lo) * (hi - X), axis=1)
+    uh = combine.hierarchize(p, l, u)
+    J = [np.arange(1, 2 ** li) for li in l]
+    mesh = np.meshgrid(*J, indexing="ij")
+    want = np.ones(mesh[0].size)
+    for i, li in enumerate(l):
+        k = np.array([_level_of(int(j), li) for j in mesh[i].reshape(-1)])
+        want *= ((hi[i] - lo[i]) * 2.0 ** (-k)) ** 2
+    assert np.abs(uh - want).max() <= 1e-14 * np.abs(want).max() * 16
+
+
+def test_hierarchical_lattice_linear_has_level0_only():
+    # on a lattice axis the interpolant is 0 at hi; (hi - x) is reproduced by
+    # the level-0 function alone: one coefficient hi - lo at the origin
+    p = make("cme5d", d=2, n=4, hi=[16.0, 16.0])
+    for l in [(4, 2), (1, 3), (3, 3)]:
+        X = grids.coordinates(p, l)
+        u = np.prod(16.0 - X, axis=1)
+        uh = combine.hierarchize(p, l, u)
+        assert abs(uh[0] - 256.0) <= 1e-12
+        assert np.abs(uh[1:]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("name,d,n", [("heat3d", 3, 5), ("cme5d", 3, 4), ("ou4d", 2, 6)])
+def test_hierarchize_roundtrip(name, d, n):
+    p = make(name, d=d, n=n)
+    rng = np.random.default_rng(4)
+    for (l, _, _) in index_set.combination_grids(d, n, 1)[:6]:
+        u = rng.standard_normal(int(np.prod(grids.shape(p, l))))
+        back = combine.dehierarchize(p, l, combine.hierarchize(p, l, u))
+        assert np.abs(back - u).max() <= 1e-13
+
+
+@pytest.mark.parametrize("name,d,n", [("heat3d", 3, 5), ("cme5d", 3, 4), ("heat2d", 2, 6),
+                                      ("varcoef6d", 4, 4)])
+def test_recombine_hier_equals_direct_projection(name, d, n):
+    # Q = H^-1 Qbar H equals combine-then-take-node-values (Section 2.2.2)
+    p = make(name, d=d, n=n)
+    gl = index_set.combination_grids(d, n, 1)
+    rng = np.random.default_rng(5)
+    states = [rng.standard_normal(int(np.prod(grids.shape(p, l)))) for (l, _, _) in gl]
+    a = combine.recombine_hier(p, gl, states)
+    b = combine.project(p, gl, states)
+    scale = sum(abs(c) for (_, _, c) in gl)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= 1e-13 * scale
