@@ -74,6 +74,14 @@ typedef enum {
                          deaths -h at rate gamma_i x/h (Section 4.3) */
 } ctm_op_kind;
 
+/* Manufactured-solution problems (Section 4.2): CTM_MMS_HEAT is the heat
+ * equation on [0,1]^d whose exact solution is
+ *   u*(x, t) = sqrt(|x|^2 + t^2) e^-t prod_i sin(pi x_i);
+ * each implicit step solves (I + dt L) u_n = u_{n-1} + dt f(., t_n) with
+ * f = d/dt u* - Laplace(u*) evaluated at the unknowns (Section 2: forcing
+ * g_n = Phi dt f_n), and the initial value is u*(., t0) (ic_* ignored). */
+typedef enum { CTM_MMS_NONE = 0, CTM_MMS_HEAT = 1 } ctm_manufactured;
+
 typedef enum { CTM_PREC_FP64 = 0, CTM_PREC_MIXED = 1 } ctm_precision;
 typedef enum { CTM_KRYLOV_AUTO = 0, CTM_KRYLOV_CG = 1, CTM_KRYLOV_BICGSTAB = 2 } ctm_krylov;
 typedef enum { CTM_RELAX_F = 0, CTM_RELAX_FCF = 1 } ctm_relax;
@@ -117,6 +125,8 @@ typedef struct {
                          fine implicit solve of a relaxation from the previous iteration's
                          value at the same time point instead of from the state one step
                          earlier; 0: keep C-points only. The fixed point is the same. */
+  ctm_manufactured manufactured; /* CTM_MMS_HEAT: forcing and initial value of the
+                         manufactured heat problem (needs op = CTM_OP_HEAT on [0,1]^d) */
 } ctm_problem;
 
 typedef struct {

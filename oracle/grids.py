@@ -58,7 +58,11 @@ def coordinates(prob, l) -> np.ndarray:
 
 def initial_value(prob, l) -> np.ndarray:
     """u0 sampled at the unknowns of Omega_l: sum_r w_r prod_i f_{r,i}(x_i),
-    each factor read from the finest 1-D table at J * 2^{n - l_i}."""
+    each factor read from the finest 1-D table at J * 2^{n - l_i}; for the
+    manufactured heat problem, u*(x, t0)."""
+    if prob.get("manufactured") == "heat":
+        from . import manufactured
+        return manufactured.u_star(coordinates(prob, l), prob["t0"])
     n = prob["n"]
     w = np.asarray(prob["ic_w"], dtype=np.float64)
     f = np.asarray(prob["ic_f"], dtype=np.float64)

@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import combine, grids, index_set, propagate
+from . import combine, grids, index_set, manufactured, propagate
 
 
 def grid_list(prob):
@@ -45,14 +45,21 @@ def component_states(prob, grids_sel=None):
         raise ValueError("grid subsets need s = 1")
     states = {g: grids.initial_value(prob, gl[g][0]) for g in sel}
     phis = {g: propagate.Propagator(prob, gl[g][0], dt) for g in sel}
+    forced = manufactured.is_manufactured(prob)
     for k in range(1, s + 1):
         if k > 1:
             proj = combine.project(prob, gl, [states[g] for g in range(len(gl))])
             states = {g: proj[g] for g in sel}
         for g in sel:
             u = states[g]
-            for _ in range(N // s):
-                u = phis[g](u)
+            X = grids.coordinates(prob, gl[g][0]) if forced else None
+            for i in range(N // s):
+                if forced:
+                    # u_n = Phi (u_{n-1} + dt f(t_n)), t_n = t0 + n dt
+                    tn = prob["t0"] + ((k - 1) * (N // s) + i + 1) * dt
+                    u = phis[g](u + dt * manufactured.forcing(X, tn))
+                else:
+                    u = phis[g](u)
             states[g] = u
     return [states[g] for g in sel]
 

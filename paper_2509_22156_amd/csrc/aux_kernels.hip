@@ -2,6 +2,7 @@
 // combination gather / combine-then-project, norms and vector updates of
 // the MGRIT driver, and the dispatch of the chain kernel instantiations.
 #include "line_layout.hpp"
+#include "manufactured.hpp"
 
 namespace ctm {
 
@@ -64,6 +65,28 @@ hipError_t launch_initial_state(const GridDev* grids, int G, int maxpts, int nle
   dim3 grid((maxpts + 255) / 256, G);
   hipLaunchKernelGGL(initial_state_kernel, grid, dim3(256), 0, s, grids, nlev, terms, icw, icf,
                      out);
+  return hipGetLastError();
+}
+
+__global__ void mms_initial_kernel(const GridDev* __restrict__ grids, double t,
+                                   double* __restrict__ out) {
+  const GridDev& g = grids[blockIdx.y];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.npts) return;
+  double x[MAXD];
+  int rem = p;
+  for (int i = g.d - 1; i >= 0; --i) {
+    const int j = rem % g.n[i];
+    rem /= g.n[i];
+    x[i] = g.lo[i] + (double)(j + g.j0) * g.h[i];
+  }
+  out[g.off + p] = mms_exact(x, g.d, t);
+}
+
+hipError_t launch_mms_initial(const GridDev* grids, int G, int maxpts, double t, double* out,
+                              hipStream_t s) {
+  dim3 grid((maxpts + 255) / 256, G);
+  hipLaunchKernelGGL(mms_initial_kernel, grid, dim3(256), 0, s, grids, t, out);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 #pragma once
 
 #include "line_layout.hpp"
+#include "manufactured.hpp"
 
 namespace ctm {
 
@@ -441,6 +442,15 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) x[k] = v[k];
+    }
+    // manufactured heat problem: the step solves (I + dt L) x = v + dt f(t_j)
+    if constexpr (OPC == OPC_HEAT) {
+      if (a.fkind) {
+        double fj[K];
+        mms_forcing<K>(g, L, a.ft0 + (double)q * a.ftq + (double)j * a.dt, fj);
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += a.dt * fj[k];
+      }
     }
     if constexpr (MIXED) {
       if (a.single32)

@@ -117,6 +117,7 @@ struct ctm_plan {
   hipStream_t cstreams[kSideStreams] = {};
   // hierarchical basis (built on first use): node id of every unknown; per
   // node, the unknowns of all grids that share its basis function
+  double block_t0 = 0.0;     // start time of the recombination block being solved
   int hnodes = 0;
   int* dhnode = nullptr;    // [slen]
   int* dhoff = nullptr;     // [hnodes + 1]
@@ -254,11 +255,23 @@ ctm_status validate(const ctm_problem* p) {
     return fail(CTM_ERR_INVALID, "mixed precision needs refine_tol, inner_tol > 0, refine_maxit >= 1");
   if (!(p->coarse_tol >= 0) || !(p->coarse_tol < 1))
     return fail(CTM_ERR_INVALID, "coarse_tol must be in [0, 1)");
+  if (p->manufactured != CTM_MMS_NONE) {
+    if (p->manufactured != CTM_MMS_HEAT || p->op != CTM_OP_HEAT)
+      return fail(CTM_ERR_INVALID, "manufactured: only the heat problem (op = heat)");
+    for (int i = 0; i < p->d; ++i)
+      if (p->lo[i] != 0.0 || p->hi[i] != 1.0)
+        return fail(CTM_ERR_INVALID, "manufactured heat problem lives on [0,1]^d");
+  }
   const bool sym = (p->op == CTM_OP_HEAT || p->op == CTM_OP_VARCOEF);
   if (p->krylov == CTM_KRYLOV_CG && !sym)
     return fail(CTM_ERR_INVALID, "CG needs a symmetric operator (heat or varcoef)");
-  if (p->ic_terms < 1 || p->ic_terms > CTM_MAX_IC_TERMS || !p->ic_weight || !p->ic_factor)
+  if (p->manufactured == CTM_MMS_NONE &&
+      (p->ic_terms < 1 || p->ic_terms > CTM_MAX_IC_TERMS || !p->ic_weight || !p->ic_factor))
     return fail(CTM_ERR_INVALID, "initial value needs 1..16 terms with weight and factor arrays");
+  if (p->manufactured != CTM_MMS_NONE &&
+      (p->ic_terms < 0 || p->ic_terms > CTM_MAX_IC_TERMS ||
+       (p->ic_terms > 0 && (!p->ic_weight || !p->ic_factor))))
+    return fail(CTM_ERR_INVALID, "initial value arrays inconsistent with ic_terms");
   return CTM_OK;
 }
 
@@ -356,6 +369,13 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
   a.tol = mixed ? P->prob.refine_tol : P->prob.krylov_tol;
   a.inner_tol = P->prob.inner_tol;
   a.status = reinterpret_cast<int*>(P->dsync + 1);
+  // the forcing enters the level-0 steps only (coarse levels solve for
+  // corrections, whose right-hand sides are residuals)
+  if (level == 0 && P->prob.manufactured == CTM_MMS_HEAT) {
+    a.fkind = 1;
+    a.ft0 = P->block_t0;
+    a.ftq = 0.0;
+  }
   return a;
 }
 
@@ -801,6 +821,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     double* C;
     if (fcf) {
       ChainArgs fc = base_args(P, 0, (int)c);
+      fc.ftq = (double)c * fc.dt;  // task q starts at fine step c q
       fc.start = vref(U, 1, 0);
       fc.fin = vref(Un, 1, 1);
       if (Tr) {
@@ -817,6 +838,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
       C = U;
     }
     ChainArgs fr = base_args(P, 0, (int)c);
+    fr.ftq = (double)c * fr.dt;
     fr.start = vref(C, 1, 0);
     fr.fin = vref(lay.R[1], 1, 1);
     fr.target = vref(C, 1, 1);
@@ -914,11 +936,17 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   ctm_plan* P = new (std::nothrow) ctm_plan();
   if (!P) return fail(CTM_ERR_NOMEM, "host allocation failed");
   P->prob = *prob;
+  P->block_t0 = prob->t0;
   P->d = prob->d;
   P->n = prob->level_n;
   const int F = (1 << P->n) + 1;
-  P->icw.assign(prob->ic_weight, prob->ic_weight + prob->ic_terms);
-  P->icf.assign(prob->ic_factor, prob->ic_factor + (size_t)prob->ic_terms * P->d * F);
+  if (prob->ic_terms > 0) {
+    P->icw.assign(prob->ic_weight, prob->ic_weight + prob->ic_terms);
+    P->icf.assign(prob->ic_factor, prob->ic_factor + (size_t)prob->ic_terms * P->d * F);
+  } else {  // manufactured problem without tables: one zero term keeps the buffers valid
+    P->icw.assign(1, 0.0);
+    P->icf.assign((size_t)P->d * F, 0.0);
+  }
   P->prob.ic_weight = nullptr;
   P->prob.ic_factor = nullptr;
   P->lattice = (prob->op == CTM_OP_CME);
@@ -1108,10 +1136,17 @@ ctm_status ctm_plan_workspace_bytes(const ctm_plan* P, size_t* bytes) {
   return CTM_OK;
 }
 
+// The problem's initial value on every grid.
+hipError_t initial_state(ctm_plan* P, double* u0, hipStream_t s) {
+  if (P->prob.manufactured == CTM_MMS_HEAT)
+    return launch_mms_initial(P->dgrids, P->G, P->maxpts, P->prob.t0, u0, s);
+  return launch_initial_state(P->dgrids, P->G, P->maxpts, P->n, (int)P->icw.size(), P->dicw,
+                              P->dicf, u0, s);
+}
+
 ctm_status ctm_initial_state(ctm_plan* P, double* u0, ctm_stream s) {
   if (!P || !u0) return fail(CTM_ERR_INVALID, "NULL argument");
-  CTM_HIP(launch_initial_state(P->dgrids, P->G, P->maxpts, P->n, (int)P->icw.size(), P->dicw,
-                               P->dicf, u0, (hipStream_t)s));
+  CTM_HIP(initial_state(P, u0, (hipStream_t)s));
   return CTM_OK;
 }
 
@@ -1168,12 +1203,14 @@ ctm_status ctm_solve(ctm_plan* P, void* ws, size_t ws_bytes, const double* u0, d
   if (u0) {
     CTM_HIP(hipMemcpyAsync(lay.X, u0, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
   } else {
-    CTM_HIP(launch_initial_state(P->dgrids, P->G, P->maxpts, P->n, (int)P->icw.size(), P->dicw,
-                                 P->dicf, lay.X, hs));
+    CTM_HIP(initial_state(P, lay.X, hs));
   }
   ctm_status result = CTM_OK;
+  const double dt0 = (P->prob.t1 - P->prob.t0) / (double)P->prob.nsteps;
+  const long long Nb = P->prob.nsteps / P->prob.nrecomb;
   for (int b = 0; b < P->prob.nrecomb; ++b) {
     if (b > 0 && (st = recombine(P, lay.Y, lay.X, hs)) != CTM_OK) return st;
+    P->block_t0 = P->prob.t0 + (double)(b * Nb) * dt0;
     st = mgrit_block(P, lay, hs);
     P->stats.blocks += 1;
     if (st == CTM_ERR_NOCONV) {
@@ -1182,6 +1219,7 @@ ctm_status ctm_solve(ctm_plan* P, void* ws, size_t ws_bytes, const double* u0, d
       return st;
     }
   }
+  P->block_t0 = P->prob.t0;
   CTM_HIP(hipMemcpyAsync(u_final, lay.Y, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
   if ((st = collect_device_stats(P, hs)) != CTM_OK) return st;
   if (result != CTM_OK) return result;

@@ -72,6 +72,9 @@ struct ChainArgs {
   int refine_maxit;
   int single32;             // mixed path: each step is one FP32 solve to inner_tol (no
                             // FP64 refinement); for loose coarse-level tolerances
+  int fkind;                // forcing: 0 none, 1 manufactured heat problem (heat only)
+  int pad_;
+  double ft0, ftq;          // time of step j of task q: ft0 + q ftq + j dt
   double tol;               // FP64 path Krylov tolerance, or mixed refinement tolerance
   double inner_tol;         // mixed path FP32 Krylov tolerance
   VecRef start;             // start vector (base == nullptr: zero)
@@ -163,6 +166,9 @@ inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed, bool heat) {
 // Auxiliary kernels (aux_kernels.hip).
 hipError_t launch_initial_state(const GridDev* grids, int G, int maxpts, int nlev, int terms,
                                 const double* icw, const double* icf, double* out, hipStream_t s);
+// u*(x, t) of the manufactured heat problem at every unknown.
+hipError_t launch_mms_initial(const GridDev* grids, int G, int maxpts, double t, double* out,
+                              hipStream_t s);
 hipError_t launch_apply(int opc, int shape, const GridDev* grids, int G, const double* tab64,
                         double amp, double dt, int tabmax, const double* x, double* y,
                         hipStream_t s);

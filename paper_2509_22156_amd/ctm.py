@@ -42,6 +42,7 @@ class Problem(ctypes.Structure):
         ("ic_weight", ctypes.POINTER(ctypes.c_double)),
         ("ic_factor", ctypes.POINTER(ctypes.c_double)),
         ("coarse_tol", ctypes.c_double), ("warm_start", ctypes.c_int),
+        ("manufactured", ctypes.c_int),
     ]
 
 
@@ -162,6 +163,7 @@ def problem_struct(prob: dict):
     s.refine_maxit = int(prob.get("refine_maxit", 10))
     s.coarse_tol = float(prob.get("coarse_tol", 0.0))
     s.warm_start = int(prob.get("warm_start", 1))
+    s.manufactured = 1 if prob.get("manufactured") == "heat" else 0
     w = np.ascontiguousarray(prob["ic_w"], dtype=np.float64)
     f = np.ascontiguousarray(prob["ic_f"], dtype=np.float64)
     s.ic_terms = int(w.shape[0])

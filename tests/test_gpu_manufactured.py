@@ -1,0 +1,74 @@
+"""GPU parity of the manufactured heat problem (Section 4.2): forcing
+g_n = Phi dt f(t_n) in every level-0 implicit step, initial value u*(., t0),
+against the CPU oracle on the same problem."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2509_22156_amd import ctm  # noqa: E402
+from workloads import make  # noqa: E402
+
+from helpers import oracle_initial, oracle_propagate, rel_l2, solve  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _fp64(**kw):
+    p = make("heat_mms", **kw)
+    p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100)
+    return p
+
+
+def test_manufactured_initial_state():
+    p = _fp64(d=3, n=5)
+    plan = ctm.Plan(p)
+    got = plan.initial_state().cpu().numpy()
+    ref = oracle_initial(p)
+    assert np.abs(got - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max()) * 8
+
+
+def test_manufactured_propagate():
+    p = _fp64(d=3, n=5, nsteps=16, t1=0.5)
+    plan = ctm.Plan(p)
+    u0 = plan.initial_state()
+    got = plan.propagate(u0, 6).cpu().numpy()
+    ref = np.concatenate(oracle_propagate(p, u0.cpu().numpy(), 6))
+    assert rel_l2(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("kw", [dict(d=2, n=6, mgrit_levels=1),
+                                dict(d=2, n=6),
+                                dict(d=3, n=5, cf=4),
+                                dict(d=3, n=5, mgrit_levels=3, cf=2),
+                                dict(d=4, n=4, nrecomb=2),
+                                dict(d=3, n=5, relax="F")])
+def test_manufactured_solve_fp64(kw):
+    kw = dict(kw)
+    base = {k: kw.pop(k) for k in ("d", "n") if k in kw}
+    p = _fp64(nsteps=32, t1=0.5, **base)
+    p.update(kw)
+    _say(f"manufactured fp64 {base} {kw}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    assert st["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(u, ref) <= 1e-11, (rel_l2(u, ref), st["mgrit_iterations"])
+
+
+def test_manufactured_solve_mixed():
+    p = make("heat_mms", d=3, n=6, nsteps=32, t1=0.5)
+    p.update(prec="mixed", refine_tol=1e-12, inner_tol=1e-5, mgrit_tol=1e-11, krylov_tol=1e-13,
+             mgrit_maxit=100, coarse_tol=1e-3)
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(u, ref) <= 1e-8

@@ -128,10 +128,28 @@ def varcoef6d(seed: int = 0, prec: str = "mixed") -> dict:
     return _sin_product(p, [[1] * 6], [1.0])
 
 
+def heat_mms(seed: int = 0, prec: str = "fp64", d: int = 3, n: int = 6, nsteps: int = 64,
+             t1: float = 1.0) -> dict:
+    """Heat equation on [0,1]^d with the manufactured solution of Section 4.2
+    (forcing and initial value derived from it; nothing is drawn, the seed
+    is accepted for a uniform interface). Two-level MGRIT with c = 2 and
+    FCF-relaxation, CG, as in the paper's solver setting (Section 4.1)."""
+    p = _base(d, n, 0.0, 1.0, "heat", t1, nsteps, 2, 2, "cg", prec)
+    p["manufactured"] = "heat"
+    p["ic_w"] = [0.0]
+    p["ic_f"] = np.zeros((1, d, 2 ** n + 1))
+    return p
+
+
 def make(name: str, seed: int = 0, **overrides) -> dict:
     """Problem dictionary of a named workload with optional field overrides.
     Overriding n or the box re-tabulates nothing: pass a fresh ic via
     overrides or use `retabulate`."""
+    if name == "heat_mms":
+        kw = {k: overrides.pop(k) for k in ("prec", "d", "n", "nsteps", "t1") if k in overrides}
+        p = heat_mms(seed, **kw)
+        p.update(overrides)
+        return p
     fn = {"heat2d": heat2d, "heat3d": heat3d, "ou4d": ou4d, "cme5d": cme5d,
           "varcoef6d": varcoef6d}[name]
     kw = {}
