@@ -82,6 +82,43 @@ def cpu_oracle(prob, pts):
     return time.perf_counter() - t0, solve.packed(states), vals
 
 
+# (d, n) cases of the manufactured heat family: two sparse-grid levels per d
+MMS_CASES = [(2, 7), (2, 9), (3, 7), (3, 9), (4, 6), (4, 8), (5, 6), (5, 8), (6, 5), (6, 7)]
+
+
+def mms_sweep(ctm, torch):
+    """Section 4.2 family: heat equation on [0,1]^d with the manufactured
+    solution, T = 1, N = 64 steps, two-level MGRIT with c = 2 and FCF,
+    MGRIT tolerance 1e-8, mixed precision. Reports the MGRIT iterations (the
+    paper observes them independent of d, L and the grid), the solve time
+    and the error of the combination against u*(., T) at seeded points."""
+    import numpy as np
+    from workloads import make
+    for d, n in MMS_CASES:
+        p = make("heat_mms", d=d, n=n, nsteps=64, t1=1.0)
+        p.update(prec="mixed", refine_tol=1e-10, inner_tol=1e-6, refine_maxit=12,
+                 mgrit_tol=1e-8, krylov_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64,
+                 coarse_tol=1e-3)
+        plan = ctm.Plan(p)
+        u = plan.solve()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        u = plan.solve()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        st = plan.stats()
+        rng = np.random.default_rng(3)
+        pts = rng.uniform(0.05, 0.95, size=(2000, d))
+        got = plan.gather(u, torch.from_numpy(pts).cuda()).cpu().numpy()
+        r = np.sqrt(np.sum(pts * pts, axis=1) + 1.0)
+        exact = r * np.exp(-1.0) * np.prod(np.sin(np.pi * pts), axis=1)
+        print(json.dumps(dict(case="heat_mms", d=d, n=n, grids=plan.G, dof_per_level=plan.slen,
+                              nsteps=64, mgrit_iterations=st["mgrit_iterations"], ms=round(ms, 2),
+                              krylov_iterations=st["krylov_iterations"],
+                              max_error_vs_exact=float(np.abs(got - exact).max()))), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +127,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="heat3d")
     ap.add_argument("--no-extras", action="store_true", help="skip the comparator runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--mms-sweep", action="store_true",
+                    help="instead of the metric: the manufactured heat family of Section 4.2 "
+                         "over d = 2..6 and two levels each (one JSON line per case)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 256 MiB device copy (hardware-counter calibration)")
     args = ap.parse_args(argv)
@@ -105,6 +145,8 @@ def main(argv=None):
     from workloads import targets
 
     torch.cuda.set_device(0)
+    if args.mms_sweep:
+        return mms_sweep(ctm, torch)
     prob = workload_problem(args.workload, "mixed")
     t0 = time.perf_counter()
     plan = ctm.Plan(prob)

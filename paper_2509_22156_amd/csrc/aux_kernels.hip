@@ -405,7 +405,8 @@ hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, doub
 __global__ void __launch_bounds__(256)
     residual_max_kernel(const int2* __restrict__ tasks, int ntasks,
                         const double* __restrict__ res2, const double* __restrict__ norm2,
-                        double* __restrict__ out) {
+                        double* __restrict__ mg, int it, double tol,
+                        const int* __restrict__ status) {
   __shared__ double part[256];
   double m = 0.0;
   for (int t = threadIdx.x; t < ntasks; t += 256) {
@@ -422,18 +423,29 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = part[0];
+  if (threadIdx.x == 0) {
+    if (mg[0] == 0.0) {
+      const double res = part[0];
+      mg[2 * it] = res;
+      const bool nonfinite = (res != res) || ((*status >> CTM_ERR_NONFINITE) & 1);
+      if (res <= tol || nonfinite) mg[0] = (double)it;
+    }
+    mg[2 * it + 1] = mg[0];
+  }
 }
 
 hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
-                               const double* norm2, double* out, hipStream_t s) {
+                               const double* norm2, double* mg, int it, double tol,
+                               const int* status, hipStream_t s) {
   hipLaunchKernelGGL(residual_max_kernel, dim3(1), dim3(256), 0, s, tasks, ntasks, res2, norm2,
-                     out);
+                     mg, it, tol, status);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ vector ops
-__global__ void vec_add_kernel(VecRef dst, VecRef x, VecRef y, long long slen) {
+__global__ void vec_add_kernel(VecRef dst, VecRef x, VecRef y, long long slen,
+                               const double* skip) {
+  if (skip && *skip != 0.0) return;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= slen) return;
   const long long q = blockIdx.y;
@@ -443,24 +455,25 @@ __global__ void vec_add_kernel(VecRef dst, VecRef x, VecRef y, long long slen) {
 }
 
 hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
-                          hipStream_t s) {
+                          hipStream_t s, const double* skip) {
   if (nvec <= 0 || slen <= 0) return hipSuccess;
   hipLaunchKernelGGL(vec_add_kernel, dim3((unsigned)((slen + 255) / 256), nvec), dim3(256), 0, s,
-                     dst, x, y, slen);
+                     dst, x, y, slen, skip);
   return hipGetLastError();
 }
 
-__global__ void fill_zero_kernel(double* p, long long n) {
+__global__ void fill_zero_kernel(double* p, long long n, const double* skip) {
+  if (skip && *skip != 0.0) return;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x)
     p[e] = 0.0;
 }
 
-hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s, const double* skip) {
   if (n <= 0) return hipSuccess;
   long long blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, skip);
   return hipGetLastError();
 }
 

@@ -359,7 +359,10 @@ __device__ __forceinline__ void step_single32(const Solver<OPC, float, K>& S32, 
   kr_max = it > kr_max ? it : kr_max;
 }
 
-template <int OPC, int SOLVER, bool MIXED, int W, int K>
+// FORCED (heat only): the steps add the manufactured-problem forcing; a
+// separate instantiation, so that the forcing's transcendental functions do
+// not raise the register budget of the unforced kernels.
+template <int OPC, int SOLVER, bool MIXED, bool FORCED, int W, int K>
 __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -373,6 +376,7 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
       smem + lay.heat + align16(sizeof(HeatTab<double, K>)));
   double* red = reinterpret_cast<double*>(smem + lay.red);
   __shared__ GridDev gs;
+  if (a.skip && *a.skip != 0.0) return;  // whole work-group: queued past convergence
   lds_zero_ghosts<double, K>(xl64);
   if constexpr (MIXED) lds_zero_ghosts<float, K>(xl32);
 
@@ -444,13 +448,11 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
       for (int k = 0; k < K; ++k) x[k] = v[k];
     }
     // manufactured heat problem: the step solves (I + dt L) x = v + dt f(t_j)
-    if constexpr (OPC == OPC_HEAT) {
-      if (a.fkind) {
-        double fj[K];
-        mms_forcing<K>(g, L, a.ft0 + (double)q * a.ftq + (double)j * a.dt, fj);
+    if constexpr (FORCED) {
+      double fj[K];
+      mms_forcing<K>(g, L, a.ft0 + (double)q * a.ftq + (double)j * a.dt, fj);
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += a.dt * fj[k];
-      }
+      for (int k = 0; k < K; ++k) v[k] += a.dt * fj[k];
     }
     if constexpr (MIXED) {
       if (a.single32)
@@ -511,14 +513,25 @@ template <int OPC, int SOLVER>
 hipError_t launch_chain_t(bool mixed, int shape, const ChainArgs& a, int ntasks, size_t smem,
                           int tabmax, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-#define CTM_CASE(IDX, W, K)                                                                   \
-  case IDX:                                                                                   \
-    if (mixed)                                                                                \
-      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, W, K>), dim3(ntasks), dim3(64 * W), \
-                         smem, s, a, tabmax);                                           \
-    else                                                                                      \
-      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, W, K>), dim3(ntasks),              \
-                         dim3(64 * W), smem, s, a, tabmax);                             \
+  // the manufactured forcing exists for the heat operator only
+  const bool forced = (OPC == OPC_HEAT) && a.fkind;
+  constexpr bool kF = (OPC == OPC_HEAT);
+#define CTM_CASE(IDX, W, K)                                                                  \
+  case IDX:                                                                                  \
+    if (forced) {                                                                            \
+      if (mixed)                                                                             \
+        hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, kF, W, K>), dim3(ntasks),        \
+                           dim3(64 * W), smem, s, a, tabmax);                                \
+      else                                                                                   \
+        hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, kF, W, K>), dim3(ntasks),       \
+                           dim3(64 * W), smem, s, a, tabmax);                                \
+    } else if (mixed) {                                                                      \
+      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, false, W, K>), dim3(ntasks),       \
+                         dim3(64 * W), smem, s, a, tabmax);                                  \
+    } else {                                                                                 \
+      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, false, W, K>), dim3(ntasks),      \
+                         dim3(64 * W), smem, s, a, tabmax);                                  \
+    }                                                                                        \
     break;
   switch (shape) {
     CTM_CASE(0, 1, 4)

@@ -118,6 +118,14 @@ struct ctm_plan {
   // hierarchical basis (built on first use): node id of every unknown; per
   // node, the unknowns of all grids that share its basis function
   double block_t0 = 0.0;     // start time of the recombination block being solved
+  // MGRIT convergence on the device: dmg[0] = stopping iteration (0 while
+  // running), dmg[2 it], dmg[2 it + 1] = residual and dmg[0] after iteration
+  // it; hmg its pinned per-iteration mirror; skip = dmg while a block's
+  // iterations are queued (launches past the stopping iteration do nothing)
+  double* dmg = nullptr;
+  double* hmg = nullptr;
+  const double* skip = nullptr;
+  std::vector<hipEvent_t> it_events;
   int hnodes = 0;
   int* dhnode = nullptr;    // [slen]
   int* dhoff = nullptr;     // [hnodes + 1]
@@ -146,6 +154,9 @@ struct ctm_plan {
     hipFree(dhidx);
     hipFree(dhcoef);
     hipFree(dhsg);
+    hipFree(dmg);
+    if (hmg) hipHostFree(hmg);
+    for (auto e : it_events) hipEventDestroy(e);
     if (hsync) hipHostFree(hsync);
     for (auto& kv : tsets) hipFree(kv.second.d);
     for (auto e : events) hipEventDestroy(e);
@@ -369,6 +380,7 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
   a.tol = mixed ? P->prob.refine_tol : P->prob.krylov_tol;
   a.inner_tol = P->prob.inner_tol;
   a.status = reinterpret_cast<int*>(P->dsync + 1);
+  a.skip = P->skip;
   // the forcing enters the level-0 steps only (coarse levels solve for
   // corrections, whose right-hand sides are residuals)
   if (level == 0 && P->prob.manufactured == CTM_MMS_HEAT) {
@@ -662,7 +674,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     a.forcing = vref(G, 0, 0);
     a.inter = vref(E, 0, 0);
     a.fin = vref(E, 0, lay.N[l]);
-    CTM_HIP(launch_fill_zero(E, P->slen, s));  // e_0 = g_0 = 0
+    CTM_HIP(launch_fill_zero(E, P->slen, s, P->skip));  // e_0 = g_0 = 0
     TaskSet* single = nullptr;
     if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
     return run_chain(P, a, *single, s);
@@ -670,12 +682,12 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
   const long long M = lay.N[l] / c;
   TaskSet* tasks = nullptr;
   if ((st = tasks_for(P, M, &tasks)) != CTM_OK) return st;
-  CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s));
+  CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s, P->skip));
   double* csrc;
   long long ca;
   if (P->prob.relax == CTM_RELAX_FCF) {
     double* Cn = lay.Cn[l];
-    CTM_HIP(launch_fill_zero(Cn, P->slen, s));
+    CTM_HIP(launch_fill_zero(Cn, P->slen, s, P->skip));
     ChainArgs fc = coarse_args(P, l, (int)c);
     fc.start = vref(E, c, 0);
     fc.forcing = vref(G, c, 0);
@@ -703,11 +715,11 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     csrc = E;
     ca = c;
   }
-  CTM_HIP(launch_fill_zero(lay.R[l + 1], P->slen, s));  // r_0 = 0
+  CTM_HIP(launch_fill_zero(lay.R[l + 1], P->slen, s, P->skip));  // r_0 = 0
   if ((st = cycle(P, lay, l + 1, s)) != CTM_OK) return st;
   // correction at the C-points, then F-relaxation (ideal interpolation)
   CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0), (int)(M + 1),
-                         P->slen, s));
+                         P->slen, s, P->skip));
   ChainArgs fi = coarse_args(P, l, (int)(c - 1));
   fi.start = vref(E, c, 0);
   fi.forcing = vref(G, c, 0);
@@ -817,7 +829,75 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   // time point (the last step of an interval from the current C-point)
   double* Tr = lay.Tr;
   bool traj = false;
-  for (int it = 1; it <= p.mgrit_maxit; ++it) {
+  // The convergence test runs on the device. Iteration it is queued before
+  // the host waits for the test of iteration it - 1, so the GPU always has
+  // work; once the test stops the block, everything queued after it does
+  // nothing (skip), and the C-points keep the stopping iteration's values.
+  const int maxit = p.mgrit_maxit;
+  CTM_HIP(launch_fill_zero(P->dmg, 2LL * (maxit + 1), s));
+  while ((int)P->it_events.size() <= maxit) {
+    hipEvent_t e = nullptr;
+    CTM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    P->it_events.push_back(e);
+  }
+  std::vector<double*> Cit(maxit + 1, nullptr);  // C-point buffer of each iteration
+  P->skip = P->dmg;
+  struct SkipOff {
+    ctm_plan* P;
+    ~SkipOff() { P->skip = nullptr; }
+  } skip_off{P};
+  int stop = 0;      // stopping iteration found by the host (0: none yet)
+  int queued = 0;
+  // reads the test of iteration k (queued earlier); returns true when the
+  // block has stopped at or before k
+  // launch bookkeeping after the test of each iteration: launches queued
+  // past the stopping iteration do nothing and are taken back out
+  struct Mark {
+    long long launches;
+    double bytes;
+    double shape_bytes[16];
+    size_t events_used;
+  };
+  std::vector<Mark> marks(maxit + 1);
+  auto mark = [&](int k) {
+    Mark& m = marks[k];
+    m.launches = P->stats.chain_launches;
+    m.bytes = P->stats.chain_bytes;
+    std::memcpy(m.shape_bytes, P->stats.shape_bytes, sizeof(m.shape_bytes));
+    m.events_used = P->events_used;
+  };
+  auto rewind = [&](int k) {
+    const Mark& m = marks[k];
+    P->stats.chain_launches = m.launches;
+    P->stats.chain_bytes = m.bytes;
+    std::memcpy(P->stats.shape_bytes, m.shape_bytes, sizeof(m.shape_bytes));
+    P->events_used = m.events_used;
+  };
+  auto observe = [&](int k) -> ctm_status {
+    if (hipEventSynchronize(P->it_events[k]) != hipSuccess)
+      return fail(CTM_ERR_HIP, "hipEventSynchronize failed");
+    const double res = P->hmg[2 * k];
+    const int at = (int)P->hmg[2 * k + 1];
+    if (at == 0 || at == k) {
+      P->stats.mgrit_iterations += 1;
+      if (P->stats.history_len < CTM_MAX_HISTORY)
+        P->stats.mgrit_residual[P->stats.history_len++] = res;
+    }
+    if (at != 0) stop = at;
+    return CTM_OK;
+  };
+  int seen = 0;  // iterations observed so far
+  for (int it = 1; it <= maxit; ++it) {
+    // when the residuals seen so far predict that iteration it - 1 meets the
+    // tolerance (geometric decrease), wait for its test before queueing more
+    if (it >= 2 && seen == it - 2 && seen >= 2) {
+      const double r1 = P->hmg[2 * seen], r0 = P->hmg[2 * (seen - 1)];
+      if (r0 > 0 && r1 * (r1 / r0) <= p.mgrit_tol) {
+        if ((st = observe(it - 1)) != CTM_OK) return st;
+        seen = it - 1;
+        if (stop) break;
+      }
+    }
     double* C;
     if (fcf) {
       ChainArgs fc = base_args(P, 0, (int)c);
@@ -837,6 +917,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     } else {
       C = U;
     }
+    Cit[it] = C;
     ChainArgs fr = base_args(P, 0, (int)c);
     fr.ftq = (double)c * fr.dt;
     fr.start = vref(C, 1, 0);
@@ -852,30 +933,36 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     }
     if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
     traj = (Tr != nullptr);
-    CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, P->dsync, s));
-    CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    CTM_HIP(hipStreamSynchronize(s));
-    const double res = P->hsync[0];
-    const int flags = *reinterpret_cast<int*>(P->hsync + 1);
-    P->stats.mgrit_iterations += 1;
-    if (P->stats.history_len < CTM_MAX_HISTORY) P->stats.mgrit_residual[P->stats.history_len++] = res;
-    if (flags & (1 << CTM_ERR_NONFINITE)) return fail(CTM_ERR_NONFINITE, "non-finite value in MGRIT");
-    if (res <= p.mgrit_tol) {
-      CTM_HIP(hipMemcpyAsync(lay.Y, C + M0 * P->slen, P->slen * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      return CTM_OK;
+    CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, P->dmg, it, p.mgrit_tol,
+                                reinterpret_cast<const int*>(P->dsync + 1), s));
+    CTM_HIP(hipMemcpyAsync(P->hmg + 2 * it, P->dmg + 2 * it, 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    CTM_HIP(hipEventRecord(P->it_events[it], s));
+    mark(it);
+    queued = it;
+    if (it < maxit) {
+      if ((st = cycle(P, lay, 1, s)) != CTM_OK) return st;
+      CTM_HIP(launch_vec_add(vref(C, 1, 0), vref(C, 1, 0), vref(lay.E[1], 1, 0), (int)(M0 + 1),
+                             P->slen, s, P->skip));
+      if (fcf) std::swap(U, Un);
     }
-    if ((st = cycle(P, lay, 1, s)) != CTM_OK) return st;
-    CTM_HIP(launch_vec_add(vref(C, 1, 0), vref(C, 1, 0), vref(lay.E[1], 1, 0), (int)(M0 + 1),
-                           P->slen, s));
-    if (fcf) std::swap(U, Un);
-    if (it == p.mgrit_maxit) {
-      CTM_HIP(hipMemcpyAsync(lay.Y, C + M0 * P->slen, P->slen * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      return fail(CTM_ERR_NOCONV, "MGRIT reached mgrit_maxit");
+    if (it >= 2 && seen < it - 1) {
+      if ((st = observe(it - 1)) != CTM_OK) return st;
+      seen = it - 1;
     }
+    if (stop) break;
   }
-  return CTM_OK;
+  if (!stop && seen < queued && (st = observe(queued)) != CTM_OK) return st;
+  const int last = stop ? stop : queued;
+  if (stop) rewind(stop);
+  CTM_HIP(hipMemcpyAsync(lay.Y, Cit[last] + M0 * P->slen, P->slen * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  if (stop) {
+    const double res = P->hmg[2 * stop];
+    if (!(res <= p.mgrit_tol)) return fail(CTM_ERR_NONFINITE, "non-finite value in MGRIT");
+    return CTM_OK;
+  }
+  return fail(CTM_ERR_NOCONV, "MGRIT reached mgrit_maxit");
 }
 
 }  // namespace
@@ -1093,6 +1180,11 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   CTM_HIPC(hipMemset(P->dsync, 0, 2 * sizeof(double)));
   CTM_HIPC(hipMalloc(&P->dnorm2, P->G * sizeof(double)));
   CTM_HIPC(hipHostMalloc(&P->hsync, 2 * sizeof(double), hipHostMallocDefault));
+  {
+    const size_t nmg = 2 * (size_t)(std::max(1, prob->mgrit_maxit) + 1);
+    CTM_HIPC(hipMalloc(&P->dmg, nmg * sizeof(double)));
+    CTM_HIPC(hipHostMalloc(&P->hmg, nmg * sizeof(double), hipHostMallocDefault));
+  }
   std::vector<int2> ident(P->G);
   for (int g = 0; g < P->G; ++g) ident[g] = make_int2(g, 0);
   CTM_HIPC(hipMalloc(&P->didentity, P->G * sizeof(int2)));

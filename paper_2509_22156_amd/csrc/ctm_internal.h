@@ -88,6 +88,8 @@ struct ChainArgs {
   double* res2;             // residual mode: per-task ||fin||_2^2 (optional)
   unsigned long long* counters;  // statistics (see CNT_*)
   int* status;              // OR of (1 << ctm_status)
+  const double* skip;       // optional: the launch does nothing once *skip != 0 (MGRIT
+                            // work queued past the converged iteration)
 };
 
 enum {
@@ -188,12 +190,20 @@ hipError_t launch_hier_scatter(const int* node, long long slen, const double* sg
                                hipStream_t s);
 hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, double* out,
                               hipStream_t s);
+// MGRIT convergence test of iteration it on the device: res = max over tasks
+// t of sqrt(res2[t] / norm2[grid(t)]) (norm2 = 0 -> 1). Unless mg[0] (the
+// stopping iteration, 0 while running) is set already, mg[2 it] = res and
+// mg[0] = it when res <= tol, res is not a number, or *status has the
+// non-finite bit. Always mg[2 it + 1] = mg[0].
 hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
-                               const double* norm2, double* out, hipStream_t s);
+                               const double* norm2, double* mg, int it, double tol,
+                               const int* status, hipStream_t s);
 // dst[(ad q + bd) slen + e] = x[(ax q + bx) slen + e] (+ y[(ay q + by) slen + e]),
 // q = 0..nvec-1, e = 0..slen-1; y.base may be null.
+// skip (optional): the launch does nothing once *skip != 0.
 hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
-                          hipStream_t s);
-hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+                          hipStream_t s, const double* skip = nullptr);
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s,
+                            const double* skip = nullptr);
 
 }  // namespace ctm

@@ -72,3 +72,17 @@ def test_manufactured_solve_mixed():
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
     assert rel_l2(u, ref) <= 1e-8
+
+
+def test_mgrit_iterations_independent_of_dimension_and_level():
+    # Section 4.2 reports MGRIT iteration counts that do not grow with d,
+    # the level L or the anisotropy of the grids (within a factor of 2)
+    its = {}
+    for d, n in [(2, 5), (2, 7), (3, 5), (3, 7), (4, 5), (5, 5)]:
+        p = make("heat_mms", d=d, n=n, nsteps=32, t1=1.0)
+        p.update(prec="fp64", krylov_tol=1e-10, mgrit_tol=1e-8, mgrit_maxit=64)
+        plan = ctm.Plan(p)
+        plan.solve()
+        its[(d, n)] = plan.stats()["mgrit_iterations"]
+    _say(f"MGRIT iterations {its}")
+    assert max(its.values()) <= 2 * min(its.values()), its
