@@ -69,9 +69,14 @@ typedef enum {
   CTM_OP_VARCOEF = 1, /* L u = -div(a grad u), a = 1 + amp prod_k sin(2 pi x_k), face midpoints */
   CTM_OP_OU = 2,      /* Fokker-Planck of dX = -theta X dt + sigma dW: central diffusion
                          sigma^2/2, donor-cell drift fluxes with face velocity -theta_i x */
-  CTM_OP_CME = 3      /* immigration-death master equation per species on the lattice
+  CTM_OP_CME = 3,     /* immigration-death master equation per species on the lattice
                          embedding: births +h at rate k_i/h (none at the last state),
                          deaths -h at rate gamma_i x/h (Section 4.3) */
+  CTM_OP_DRIFT = 4    /* Fokker-Planck of the linear SDE dX = theta X dt + sigma dW with a
+                         full drift matrix (Section 4.4): L u = sum_i d_i((theta x)_i u)
+                         - 1/2 sum_i H_ii d_ii u, H diagonal; central diffusion and
+                         donor-cell fluxes with the face velocity (theta x)_i taken at the
+                         face (x_i shifted by -/+ h_i/2, the other coordinates at the node) */
 } ctm_op_kind;
 
 /* Manufactured-solution problems (Section 4.2): CTM_MMS_HEAT is the heat
@@ -127,6 +132,9 @@ typedef struct {
                          earlier; 0: keep C-points only. The fixed point is the same. */
   ctm_manufactured manufactured; /* CTM_MMS_HEAT: forcing and initial value of the
                          manufactured heat problem (needs op = CTM_OP_HEAT on [0,1]^d) */
+  double drift[CTM_MAXD * CTM_MAXD]; /* CTM_OP_DRIFT: theta, row-major d x d (row i = the
+                         velocity component along axis i) */
+  double diffusion[CTM_MAXD];        /* CTM_OP_DRIFT: H_ii = (2 sigma D sigma^T)_ii >= 0 */
 } ctm_problem;
 
 typedef struct {

@@ -20,6 +20,13 @@ Operator kinds (u_t + L u = 0 in all workloads):
            Diffusion by central differences; drift in flux form with donor-cell
            (upwind) face fluxes F_{j+1/2} = max(w,0) u_j + min(w,0) u_{j+1},
            w = -theta_i x_{j+1/2}; L is minus the discrete right-hand side.
+  drift    Fokker-Planck operator of the linear SDE dX = theta X dt + sigma dW
+           with a full drift matrix theta (Section 4.4): u_t = -sum_i
+           d_i((theta x)_i u) + (1/2) sum_i H_ii d_ii u with H = 2 sigma D
+           sigma^T diagonal (as in both systems of Section 4.4). Same
+           discretisation as ou: central diffusion, donor-cell face fluxes
+           with the face velocity w = (theta x)_i taken at the face (x_i
+           shifted by -/+ h_i/2, the other coordinates at the node).
   cme      master-equation generator of independent immigration-death
            species (Section 4.3, master equation with propensities k_i and
            gamma_i x_i) on the lattice embedding with node spacing h: births
@@ -32,7 +39,10 @@ heat at amp = 0, is symmetric, and is second-order consistent with
 -div(a grad u) for a smooth u; ou and cme have zero column sums (exactly for
 cme, away from boundary-adjacent columns for ou), the M-matrix sign pattern,
 and the expected consistency order; the cme chain at h = 1 reproduces
-Poisson marginals (tests/test_oracle_propagate.py).
+Poisson marginals (tests/test_oracle_propagate.py); drift equals ou exactly
+for theta = -diag(theta_i), H = sigma^2 I, has zero column sums away from
+the boundary and the M-matrix sign pattern, and is first-order consistent
+with the continuous operator for a full theta.
 """
 from __future__ import annotations
 
@@ -74,6 +84,16 @@ def couplings(prob, l, i: int, X: np.ndarray):
         diag = (np.maximum(w_up, 0.0) - np.minimum(w_dn, 0.0)) / h + 2.0 * D / h ** 2
         upper = np.minimum(w_up, 0.0) / h - D / h ** 2
         lower = -np.maximum(w_dn, 0.0) / h - D / h ** 2
+        return diag, lower, upper
+    if op == "drift":
+        th = np.asarray(prob["drift"], dtype=np.float64)
+        H = float(prob["diffusion"][i])
+        wc = X @ th[i]  # (theta x)_i at the node
+        w_up = wc + th[i, i] * 0.5 * h
+        w_dn = wc - th[i, i] * 0.5 * h
+        diag = (np.maximum(w_up, 0.0) - np.minimum(w_dn, 0.0)) / h + H / h ** 2
+        upper = np.minimum(w_up, 0.0) / h - 0.5 * H / h ** 2
+        lower = -np.maximum(w_dn, 0.0) / h - 0.5 * H / h ** 2
         return diag, lower, upper
     if op == "cme":
         k = prob["k"][i]

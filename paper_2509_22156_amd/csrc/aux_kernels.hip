@@ -11,6 +11,7 @@ hipError_t launch_chain_heat_bicg(bool, int, const ChainArgs&, int, size_t, int,
 hipError_t launch_chain_sep_bicg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
 hipError_t launch_chain_var_cg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
 hipError_t launch_chain_var_bicg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
+hipError_t launch_chain_drift_bicg(bool, int, const ChainArgs&, int, size_t, int, hipStream_t);
 
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
                         int ntasks, size_t smem, int tabmax, hipStream_t s) {
@@ -24,6 +25,8 @@ hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainA
     return launch_chain_var_cg(mixed, shape, a, ntasks, smem, tabmax, s);
   if (opc == OPC_VAR && solver == SOLV_BICG)
     return launch_chain_var_bicg(mixed, shape, a, ntasks, smem, tabmax, s);
+  if (opc == OPC_DRIFT && solver == SOLV_BICG)
+    return launch_chain_drift_bicg(mixed, shape, a, ntasks, smem, tabmax, s);
   return hipErrorInvalidValue;
 }
 
@@ -172,6 +175,8 @@ hipError_t launch_apply(int opc, int shape, const GridDev* grids, int G, const d
       return launch_apply_t<OPC_SEP>(shape, grids, G, tab64, amp, dt, tabmax, x, y, s);
     case OPC_VAR:
       return launch_apply_t<OPC_VAR>(shape, grids, G, tab64, amp, dt, tabmax, x, y, s);
+    case OPC_DRIFT:
+      return launch_apply_t<OPC_DRIFT>(shape, grids, G, tab64, amp, dt, tabmax, x, y, s);
   }
   return hipErrorInvalidValue;
 }

@@ -209,6 +209,8 @@ void build_tables(ctm_plan* P, const GridHost& gh, GridDev& gd) {
         }
       }
       pos += 3 * ni;
+    } else if (P->opc == OPC_DRIFT) {
+      // theta (row-major) and H once per grid, after the loop over axes
     } else if (P->opc == OPC_VAR) {
       for (int j = 0; j < ni; ++j) {
         const double x = gd.lo[i] + (double)(j + gd.j0) * h;
@@ -220,6 +222,12 @@ void build_tables(ctm_plan* P, const GridHost& gh, GridDev& gd) {
       }
       pos += 2 * ni + 1;
     }
+  }
+  if (P->opc == OPC_DRIFT) {
+    const int d = P->d;
+    for (int i = 0; i < d * d; ++i) P->htab.push_back(p.drift[i]);
+    for (int i = 0; i < d; ++i) P->htab.push_back(p.diffusion[i]);
+    pos = d * d + d;
   }
   gd.tabsz = pos;
   (void)gh;
@@ -235,7 +243,7 @@ ctm_status validate(const ctm_problem* p) {
     return fail(CTM_ERR_INVALID, "no component grid with l >= level_min");
   for (int i = 0; i < p->d; ++i)
     if (!(p->hi[i] > p->lo[i])) return fail(CTM_ERR_INVALID, "box must have hi > lo");
-  if (p->op < CTM_OP_HEAT || p->op > CTM_OP_CME) return fail(CTM_ERR_INVALID, "unknown operator");
+  if (p->op < CTM_OP_HEAT || p->op > CTM_OP_DRIFT) return fail(CTM_ERR_INVALID, "unknown operator");
   if (p->op == CTM_OP_CME)
     for (int i = 0; i < p->d; ++i) {
       const double span = p->hi[i] - p->lo[i];
@@ -266,6 +274,13 @@ ctm_status validate(const ctm_problem* p) {
     return fail(CTM_ERR_INVALID, "mixed precision needs refine_tol, inner_tol > 0, refine_maxit >= 1");
   if (!(p->coarse_tol >= 0) || !(p->coarse_tol < 1))
     return fail(CTM_ERR_INVALID, "coarse_tol must be in [0, 1)");
+  if (p->op == CTM_OP_DRIFT) {
+    for (int i = 0; i < p->d; ++i)
+      if (!(p->diffusion[i] >= 0) || !std::isfinite(p->diffusion[i]))
+        return fail(CTM_ERR_INVALID, "drift: diffusion must be finite and >= 0");
+    for (int i = 0; i < p->d * p->d; ++i)
+      if (!std::isfinite(p->drift[i])) return fail(CTM_ERR_INVALID, "drift: theta not finite");
+  }
   if (p->manufactured != CTM_MMS_NONE) {
     if (p->manufactured != CTM_MMS_HEAT || p->op != CTM_OP_HEAT)
       return fail(CTM_ERR_INVALID, "manufactured: only the heat problem (op = heat)");
@@ -1037,7 +1052,10 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   P->prob.ic_weight = nullptr;
   P->prob.ic_factor = nullptr;
   P->lattice = (prob->op == CTM_OP_CME);
-  P->opc = prob->op == CTM_OP_HEAT ? OPC_HEAT : (prob->op == CTM_OP_VARCOEF ? OPC_VAR : OPC_SEP);
+  P->opc = prob->op == CTM_OP_HEAT      ? OPC_HEAT
+           : prob->op == CTM_OP_VARCOEF ? OPC_VAR
+           : prob->op == CTM_OP_DRIFT   ? OPC_DRIFT
+                                        : OPC_SEP;
   const bool sym = (prob->op == CTM_OP_HEAT || prob->op == CTM_OP_VARCOEF);
   P->solver = (prob->krylov == CTM_KRYLOV_BICGSTAB || (prob->krylov == CTM_KRYLOV_AUTO && !sym))
                   ? SOLV_BICG : SOLV_CG;
@@ -1110,6 +1128,13 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
         const double* t = P->htab.data() + gd.tab0 + gd.tab[i];
         for (int j = 0; j < gd.n[i]; ++j)
           strength = std::max(strength, std::fabs(t[j]) + std::fabs(t[2 * gd.n[i] + j]));
+      } else if (P->opc == OPC_DRIFT) {
+        // diffusion plus the largest face velocity over the box
+        double wmax = 0.0;
+        for (int c2 = 0; c2 < d; ++c2)
+          wmax += std::fabs(prob->drift[i * d + c2]) *
+                  std::max(std::fabs(prob->lo[c2]), std::fabs(prob->hi[c2]));
+        strength = prob->diffusion[i] * gd.ih2[i] + wmax / gd.h[i];
       } else {
         strength = gd.ih2[i];
       }

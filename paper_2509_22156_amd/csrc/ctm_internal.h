@@ -16,7 +16,10 @@ constexpr int MAXD = CTM_MAXD;
 //        read from 1-D tables (CTM_OP_OU, CTM_OP_CME).
 //  VAR:  conservative variable-coefficient diffusion with
 //        a = 1 + amp prod_k sin(2 pi x_k) at face midpoints (CTM_OP_VARCOEF).
-enum OpClass { OPC_HEAT = 0, OPC_SEP = 1, OPC_VAR = 2 };
+//  DRIFT: Fokker-Planck operator with a full drift matrix: face velocities
+//        depend on every coordinate; theta and H are read from the table
+//        (CTM_OP_DRIFT).
+enum OpClass { OPC_HEAT = 0, OPC_SEP = 1, OPC_VAR = 2, OPC_DRIFT = 3 };
 enum SolverKind { SOLV_CG = 0, SOLV_BICG = 1 };
 
 // Geometry of one component grid (device copy, read once per work-group).

@@ -139,6 +139,19 @@ template <typename T, int K>
 struct LineOp<OPC_HEAT, T, K> {
   HeatTab<T, K>* h;
 };
+// DRIFT: the face velocity along a non-stiff axis a at unknown k is
+// base[m] + theta[a][s] x_s(k) -/+ theta[a][a] h_a / 2, so a lane keeps
+// base[m] (the contribution of its fixed coordinates) and computes the
+// neighbour couplings in the apply; the stiff-axis and diagonal couplings
+// are kept per unknown.
+template <typename T, int K>
+struct LineOp<OPC_DRIFT, T, K> {
+  T diag[K], slo[K], sup[K];
+  T base[MAXD - 1];  // sum over the non-stiff axes c of theta[oax[m]][c] x_c
+  T xs0;             // stiff coordinate of the chunk's first unknown
+  T dt;
+  const T* tab;      // theta (row-major d x d), then H (d), in LDS
+};
 
 // tab: this grid's tables in LDS (SEP: per axis Lo, D, Up of L scaled by
 // dt; VAR: per axis node sines then face sines). ht: the work-group's
@@ -161,6 +174,55 @@ __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L,
 #pragma unroll
       for (int m = 0; m < MAXD - 1; ++m)
         ht->o[m] = (T)(-((m < g.d - 1) ? dt * g.ih2[g.oax[m]] : 0.0));
+    }
+  } else if constexpr (OPC == OPC_DRIFT) {
+    const int d = g.d;
+    O.tab = tab;
+    O.dt = (T)dt;
+    T xo[MAXD - 1];
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m)
+      xo[m] = (m < d - 1) ? (T)(g.lo[g.oax[m]] + (double)(L.jo[m] + g.j0) * g.h[g.oax[m]])
+                          : (T)0;
+    T bs = (T)0;  // stiff-axis velocity without the stiff coordinate
+#pragma unroll
+    for (int m = 0; m < MAXD - 1; ++m) {
+      O.base[m] = (T)0;
+      if (m < d - 1) {
+        const int a = g.oax[m];
+        T acc = (T)0;
+#pragma unroll
+        for (int mm = 0; mm < MAXD - 1; ++mm)
+          if (mm < d - 1) acc += tab[a * d + g.oax[mm]] * xo[mm];
+        O.base[m] = acc;
+        bs += tab[s * d + a] * xo[m];
+      }
+    }
+    const T hs = (T)g.h[s];
+    O.xs0 = (T)(g.lo[s] + (double)(L.j0 + g.j0) * g.h[s]);
+    const T tss = tab[s * d + s], Hs = tab[d * d + s];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const bool v = k < L.nval;
+      const T xs = O.xs0 + (T)k * hs;
+      const T wc = bs + tss * xs;
+      const T wup = wc + tss * (T)0.5 * hs, wdn = wc - tss * (T)0.5 * hs;
+      T dg = (max(wup, (T)0) - min(wdn, (T)0)) / hs + Hs / (hs * hs);
+      const T up = min(wup, (T)0) / hs - (T)0.5 * Hs / (hs * hs);
+      const T lo = -max(wdn, (T)0) / hs - (T)0.5 * Hs / (hs * hs);
+#pragma unroll
+      for (int m = 0; m < MAXD - 1; ++m) {
+        if (m < d - 1) {
+          const int a = g.oax[m];
+          const T ha = (T)g.h[a], taa = tab[a * d + a];
+          const T w0 = O.base[m] + tab[a * d + s] * xs;
+          const T wu = w0 + taa * (T)0.5 * ha, wd = w0 - taa * (T)0.5 * ha;
+          dg += (max(wu, (T)0) - min(wd, (T)0)) / ha + tab[d * d + a] / (ha * ha);
+        }
+      }
+      O.diag[k] = v ? (T)1 + O.dt * dg : (T)1;
+      O.slo[k] = v ? O.dt * lo : (T)0;
+      O.sup[k] = v ? O.dt * up : (T)0;
     }
   } else if constexpr (OPC == OPC_SEP) {
     T dl = (T)1;
@@ -316,15 +378,32 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
       const int off = g.lstride[m] * L.Lc;
       const T* plo = xl + (((L.nb >> (2 * m)) & 1u) ? L.tid - off : ghost);
       const T* phi = xl + (((L.nb >> (2 * m + 1)) & 1u) ? L.tid + off : ghost);
+      if constexpr (OPC == OPC_DRIFT) {
+        // donor-cell couplings from the face velocities of this unknown
+        const int d = g.d, a = g.oax[m], s = g.sax;
+        const T ha = (T)g.h[a], hs = (T)g.h[s];
+        const T tas = O.tab[a * d + s], half = O.tab[a * d + a] * (T)0.5 * ha;
+        const T ih = O.dt / ha;
+        const T dH = (T)0.5 * O.dt * O.tab[d * d + a] / (ha * ha);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        T clo = op_olo(O, m), chi = op_oup(O, m);
-        if constexpr (OPC == OPC_VAR) {
-          clo += O.qlo[m] * O.snj[k];
-          chi += O.qup[m] * O.snj[k];
+        for (int k = 0; k < K; ++k) {
+          const T w0 = O.base[m] + tas * (O.xs0 + (T)k * hs);
+          const T clo = -ih * max(w0 - half, (T)0) - dH;
+          const T chi = ih * min(w0 + half, (T)0) - dH;
+          acc[k] += clo * plo[k * L.pitch];
+          acc[k] += chi * phi[k * L.pitch];
         }
-        acc[k] += clo * plo[k * L.pitch];
-        acc[k] += chi * phi[k * L.pitch];
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          T clo = op_olo(O, m), chi = op_oup(O, m);
+          if constexpr (OPC == OPC_VAR) {
+            clo += O.qlo[m] * O.snj[k];
+            chi += O.qup[m] * O.snj[k];
+          }
+          acc[k] += clo * plo[k * L.pitch];
+          acc[k] += chi * phi[k * L.pitch];
+        }
       }
     }
   }

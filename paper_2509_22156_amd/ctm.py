@@ -19,7 +19,7 @@ MAXD = 8
 MAX_HISTORY = 256
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE = range(7)
-_OPS = {"heat": 0, "varcoef": 1, "ou": 2, "cme": 3}
+_OPS = {"heat": 0, "varcoef": 1, "ou": 2, "cme": 3, "drift": 4}
 _KRYLOV = {"auto": 0, "cg": 1, "bicgstab": 2}
 _PREC = {"fp64": 0, "mixed": 1}
 _RELAX = {"F": 0, "FCF": 1}
@@ -43,6 +43,7 @@ class Problem(ctypes.Structure):
         ("ic_factor", ctypes.POINTER(ctypes.c_double)),
         ("coarse_tol", ctypes.c_double), ("warm_start", ctypes.c_int),
         ("manufactured", ctypes.c_int),
+        ("drift", ctypes.c_double * (MAXD * MAXD)), ("diffusion", ctypes.c_double * MAXD),
     ]
 
 
@@ -164,6 +165,12 @@ def problem_struct(prob: dict):
     s.coarse_tol = float(prob.get("coarse_tol", 0.0))
     s.warm_start = int(prob.get("warm_start", 1))
     s.manufactured = 1 if prob.get("manufactured") == "heat" else 0
+    if prob["op"] == "drift":
+        th = np.asarray(prob["drift"], dtype=np.float64)
+        for i in range(d):
+            s.diffusion[i] = float(prob["diffusion"][i])
+            for j in range(d):
+                s.drift[i * d + j] = float(th[i, j])
     w = np.ascontiguousarray(prob["ic_w"], dtype=np.float64)
     f = np.ascontiguousarray(prob["ic_f"], dtype=np.float64)
     s.ic_terms = int(w.shape[0])

@@ -38,6 +38,8 @@ CASES = [
     ("cme5d", FP64, 1e-11, None),
     ("cme5d", MIXED, 1e-8, None),
     ("varcoef6d", MIXED, 1e-8, 43),
+    ("fp_osc2d", FP64, 1e-11, None),
+    ("fp_lin4d", MIXED, 1e-8, None),
     # the throughput measurement's own settings, held to its 1e-8 target
     ("heat3d", metric_settings("mixed"), 1e-8, None),
     ("heat3d", metric_settings("fp64"), 1e-8, None),
@@ -91,3 +93,22 @@ def test_full_size_recombine(name):
     err = np.abs(got - ref).max() / scale
     _say(f"  max error / (sum|c| max|x|) = {err:.2e}")
     assert err <= 1e-14
+
+
+def test_oscillator_density_follows_exact_gaussian():
+    # Section 4.4: the combination solution of the 2-D linear oscillator
+    # against its exact Gaussian law at T (mean within 5% of the standard
+    # deviation; first-order upwind in space and backward Euler in time)
+    from oracle import sde
+    p = make("fp_osc2d", prec="fp64")
+    p.update(FP64)
+    plan = ctm.Plan(p)
+    u = plan.solve()
+    g = np.linspace(-9.9, 9.9, 400)
+    X = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
+    dens = plan.gather(u, torch.from_numpy(X).cuda()).cpu().numpy()
+    mean = (X * dens[:, None]).sum(axis=0) / dens.sum()
+    m_ex, c_ex = sde.moments(np.asarray(p["drift"]), np.diag(p["diffusion"]), p["mean0"],
+                             np.diag(p["var0"]), p["t1"])
+    _say(f"  oscillator mean {mean} exact {m_ex}")
+    assert np.abs(mean - m_ex).max() <= 0.05 * np.sqrt(np.diag(c_ex)).max()

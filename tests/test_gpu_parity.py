@@ -34,6 +34,8 @@ def _small(name, **kw):
         "ou4d": dict(n=5, nsteps=64, t1=0.25),
         "cme5d": dict(d=3, n=4, hi=[16.0] * 3, nsteps=32, t1=0.5),
         "varcoef6d": dict(d=4, n=4, nsteps=64, t1=0.02, cf=4),
+        "fp_osc2d": dict(n=9, L0=4, nsteps=32),
+        "fp_lin4d": dict(n=5, nsteps=32),
     }[name]
     base.update(kw)
     return make(name, **base)
@@ -46,7 +48,7 @@ def _fp64(p, **kw):
     return p
 
 
-ALL = ["heat2d", "heat3d", "ou4d", "cme5d", "varcoef6d"]
+ALL = ["heat2d", "heat3d", "ou4d", "cme5d", "varcoef6d", "fp_osc2d", "fp_lin4d"]
 
 
 @pytest.mark.parametrize("name", ALL)
@@ -128,7 +130,7 @@ def test_mgrit_solve_fp64(name, relax):
     assert rel_l2(u, ref) <= 1e-11, (rel_l2(u, ref), st["mgrit_iterations"])
 
 
-@pytest.mark.parametrize("name", ["heat2d", "heat3d", "ou4d", "cme5d"])
+@pytest.mark.parametrize("name", ["heat2d", "heat3d", "ou4d", "cme5d", "fp_lin4d"])
 def test_mgrit_residual_history_matches_oracle(name):
     # the first iterations' C-point residuals are fixed by the algorithm
     # (relaxation, injection, coarse solve, correction); they pin the MGRIT

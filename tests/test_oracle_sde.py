@@ -1,0 +1,97 @@
+"""Pins of the full-drift Fokker-Planck operator and the exact Gaussian law
+of the linear SDE (Section 4.4)."""
+import numpy as np
+import pytest
+
+from oracle import grids, operators, propagate, sde
+from workloads import make
+
+
+def _drift_from_ou(p):
+    q = dict(p)
+    d = p["d"]
+    q["op"] = "drift"
+    q["drift"] = (-np.diag(p["theta"][:d])).tolist()
+    q["diffusion"] = [p["sigma"] ** 2] * d
+    return q
+
+
+@pytest.mark.parametrize("l", [(4, 3), (3, 2, 3)])
+def test_drift_equals_ou_for_diagonal_theta(l):
+    p = make("ou4d", d=len(l), n=5)
+    q = _drift_from_ou(p)
+    A = operators.matrix(p, l).toarray()
+    B = operators.matrix(q, l).toarray()
+    assert np.abs(A - B).max() <= 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("name,l", [("fp_osc2d", (5, 4)), ("fp_lin4d", (3, 2, 3, 2))])
+def test_drift_conservation_and_sign_pattern(name, l):
+    p = make(name)
+    A = operators.matrix(p, l).toarray()
+    off = A - np.diag(np.diag(A))
+    assert (off <= 1e-14).all() and (np.diag(A) >= -1e-14).all()
+    # columns away from the boundary sum to zero (mass is conserved inside)
+    shp = grids.shape(p, l)
+    idx = np.arange(A.shape[0]).reshape(shp)
+    inner = idx[tuple(slice(1, -1) for _ in shp)].reshape(-1)
+    assert np.abs(A[:, inner].sum(axis=0)).max() <= 1e-10 * np.abs(A).max()
+
+
+def test_drift_first_order_consistency():
+    # L f against the continuous operator for a smooth f with a full theta
+    p = make("fp_lin4d", d=4)
+    th = np.asarray(p["drift"])
+    H = np.asarray(p["diffusion"])
+    errs = []
+    for lev in (4, 5):
+        l = (lev,) * 4
+        X = grids.coordinates(p, l)
+        f = np.exp(-np.sum(X ** 2, axis=1) / 4.0)
+        # continuous: div((theta x) f) - 1/2 sum H_ii d_ii f
+        g = -X / 2.0  # grad f / f
+        div = np.trace(th) + np.sum((X @ th.T) * g, axis=1)
+        lap = np.sum(H * (g ** 2 - 0.5), axis=1)
+        cont = f * div - 0.5 * f * lap
+        mask = np.all(np.abs(X) < 3.0, axis=1)
+        errs.append(np.abs(operators.matrix(p, l) @ f - cont)[mask].max())
+    assert errs[1] < 0.65 * errs[0], errs
+
+
+@pytest.mark.parametrize("name", ["fp_osc2d", "fp_lin4d"])
+def test_gaussian_moments_solve_their_odes(name):
+    p = make(name)
+    th = np.asarray(p["drift"])
+    H = np.diag(p["diffusion"])
+    M, C = np.asarray(p["mean0"]), np.diag(p["var0"])
+    t, e = 0.7, 1e-5
+    m0, c0 = sde.moments(th, H, M, C, t)
+    mp, cp = sde.moments(th, H, M, C, t + e)
+    mm, cm = sde.moments(th, H, M, C, t - e)
+    assert np.abs((mp - mm) / (2 * e) - th @ m0).max() <= 1e-7 * max(1, np.abs(m0).max())
+    dc = (cp - cm) / (2 * e)
+    assert np.abs(dc - (th @ c0 + c0 @ th.T + H)).max() <= 1e-6 * max(1, np.abs(c0).max())
+    m, c = sde.moments(th, H, M, C, 0.0)
+    assert np.allclose(m, M) and np.allclose(c, C)
+
+
+def test_discrete_density_moments_approach_exact():
+    # one full grid of the 2-D oscillator: the discrete density's mean at T
+    # approaches the Gaussian law (first order in h and dt: the error about
+    # halves when both halve)
+    p = make("fp_osc2d")
+    th, H = np.asarray(p["drift"]), np.diag(p["diffusion"])
+    T = 0.5
+    m_ex, c_ex = sde.moments(th, H, p["mean0"], np.diag(p["var0"]), T)
+    errs = []
+    for lev, dt in ((6, 0.02), (7, 0.01), (8, 0.005)):
+        l = (lev, lev)
+        q = dict(p, n=lev, nsteps=int(round(T / dt)), t1=T)
+        X = grids.coordinates(q, l)
+        u0 = sde.density(X, np.asarray(p["mean0"]), np.diag(p["var0"]))
+        u = propagate.march(q, l, u0, q["nsteps"], dt)
+        h = 20.0 / 2 ** lev
+        mass = u.sum() * h * h
+        mean = (X * u[:, None]).sum(axis=0) * h * h / mass
+        errs.append(np.abs(mean - m_ex).max())
+    assert errs[2] < 0.7 * errs[1] < 0.49 * errs[0] and errs[2] < 0.05, errs

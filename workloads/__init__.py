@@ -101,6 +101,48 @@ def ou4d(seed: int = 0, prec: str = "mixed") -> dict:
     return p
 
 
+def _gaussian_tables(p, mean, var):
+    d, n = p["d"], p["n"]
+    f = np.empty((1, d, 2 ** n + 1))
+    for i in range(d):
+        x = _finest_nodes(p["lo"][i], p["hi"][i], n)
+        f[0, i] = np.exp(-(x - mean[i]) ** 2 / (2 * var[i])) / math.sqrt(2 * math.pi * var[i])
+    p["ic_w"] = np.ones(1)
+    p["ic_f"] = f
+    return p
+
+
+def fp_osc2d(seed: int = 0, prec: str = "fp64") -> dict:
+    """Fokker-Planck equation of the 2-D linear oscillator of Section 4.4:
+    theta = [[0, 1], [-w0^2, -2 xi w0]] with w0 = 1, xi = 0.05, sigma =
+    (0, 1)^T, D = 0.1 (H = diag(0, 0.2)); N((5, 5), I/9) start on
+    [-10, 10]^2; dt = 0.005 as in the paper, N = 256 steps; level 12 with
+    L0 = 6 (the paper's initial level; three grids fit the on-chip solver);
+    two-level MGRIT with c = 2, BiCGStab. Nothing is drawn."""
+    p = _base(2, 12, -10.0, 10.0, "drift", 256 * 0.005, 256, 2, 2, "bicgstab", prec)
+    p["L0"] = 6
+    p["drift"] = [[0.0, 1.0], [-1.0, -0.1]]
+    p["diffusion"] = [0.0, 0.2]
+    p["mean0"], p["var0"] = [5.0, 5.0], [1.0 / 9.0] * 2
+    return _gaussian_tables(p, p["mean0"], p["var0"])
+
+
+def fp_lin4d(seed: int = 0, prec: str = "mixed") -> dict:
+    """Fokker-Planck equation of the 4-D two-mass system of Section 4.4:
+    k1 = k2 = k3 = 1, c1 = c2 = 0.4, excitation on both velocities with
+    D1 = D2 = 0.2 (H = diag(0, 0.8, 0, 0.8)); N(0, 0.5 I) start on
+    [-6, 6]^4; dt = 20/5000 as in the paper, N = 256 steps; level 8;
+    two-level MGRIT with c = 2, BiCGStab. Nothing is drawn."""
+    p = _base(4, 8, -6.0, 6.0, "drift", 256 * 0.004, 256, 2, 2, "bicgstab", prec)
+    k1 = k2 = k3 = 1.0
+    c1 = c2 = 0.4
+    p["drift"] = [[0.0, 1.0, 0.0, 0.0], [-(k1 + k2), -c1, k2, 0.0],
+                  [0.0, 0.0, 0.0, 1.0], [k2, 0.0, -(k2 + k3), -c2]]
+    p["diffusion"] = [0.0, 0.8, 0.0, 0.8]
+    p["mean0"], p["var0"] = [0.0] * 4, [0.5] * 4
+    return _gaussian_tables(p, p["mean0"], p["var0"])
+
+
 def cme5d(seed: int = 0, prec: str = "mixed") -> dict:
     """Master equation of 5 independent immigration-death species on the
     lattice 0..63 per species; k_i ~ U[5, 20], gamma_i ~ U[0.5, 1.5]; all
@@ -151,7 +193,7 @@ def make(name: str, seed: int = 0, **overrides) -> dict:
         p.update(overrides)
         return p
     fn = {"heat2d": heat2d, "heat3d": heat3d, "ou4d": ou4d, "cme5d": cme5d,
-          "varcoef6d": varcoef6d}[name]
+          "varcoef6d": varcoef6d, "fp_osc2d": fp_osc2d, "fp_lin4d": fp_lin4d}[name]
     kw = {}
     if "prec" in overrides:
         kw["prec"] = overrides["prec"]
@@ -176,6 +218,8 @@ def retabulate(p: dict, seed: int = 0) -> dict:
             return _sin_product(p, [[1] * d], [1.0])
         kv = [(list(m) + [1] * d)[:d] for m in modes]
         return _sin_product(p, kv, list(p["ic_w"]))
+    if p["op"] == "drift":
+        return _gaussian_tables(p, p["mean0"], p["var0"])
     if p["op"] == "ou":
         mu0 = (list(p.get("mu0", [0.0])) + [0.0] * d)[:d]
         var0 = p.get("var0", 0.25)
