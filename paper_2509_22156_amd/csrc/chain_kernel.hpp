@@ -27,6 +27,16 @@ __device__ __forceinline__ bool finite_val(T v) {
   return v == v && v - v == (T)0;
 }
 
+// Quotient of two Krylov scalars. FP32 (the inner solves) uses the hardware
+// reciprocal (about 1 ulp): the recurrences do not need a correctly rounded
+// quotient, and the FP64 refinement around them decides convergence. FP64
+// keeps the IEEE division.
+template <typename T>
+__device__ __forceinline__ T kdiv(T a, T b) {
+  if constexpr (sizeof(T) == 4) return a * __builtin_amdgcn_rcpf(b);
+  else return a / b;
+}
+
 template <int OPC, typename T, int K>
 struct Solver {
   const GridDev& g;
@@ -100,7 +110,7 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
   }
   if (red[2] <= tol2 * bb) return 0;
   T gamma = red[0];
-  T alpha = gamma / red[1];
+  T alpha = kdiv(gamma, red[1]);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     p[k] = z[k];
@@ -127,13 +137,13 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
       return it;
     }
     if (rd[2] <= tol2 * bb) return it;
-    const T beta = rd[0] / gamma;
-    const T den = rd[1] - beta * rd[0] / alpha;
+    const T beta = kdiv(rd[0], gamma);
+    const T den = rd[1] - beta * kdiv(rd[0], alpha);
     if (den == (T)0 || !finite_val(den)) {
       *flag |= FLAG_BREAKDOWN;
       return it;
     }
-    alpha = rd[0] / den;
+    alpha = kdiv(rd[0], den);
     gamma = rd[0];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -186,7 +196,7 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
       *flag |= finite_val(s2[0]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
       return it;
     }
-    const T alpha = rho / s2[0];
+    const T alpha = kdiv(rho, s2[0]);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       x[k] += alpha * h[k];
@@ -207,7 +217,7 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
       *flag |= finite_val(s3[1]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
       return it;
     }
-    const T omega = s3[0] / s3[1];
+    const T omega = kdiv(s3[0], s3[1]);
     T s4[2] = {(T)0, (T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -226,7 +236,7 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
       *flag |= FLAG_BREAKDOWN;
       return it;
     }
-    const T beta = (s4[1] / rho) * (alpha / omega);
+    const T beta = kdiv(s4[1], rho) * kdiv(alpha, omega);
     rho = s4[1];
 #pragma unroll
     for (int k = 0; k < K; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
