@@ -278,6 +278,8 @@ def main(argv=None):
 
     if not args.no_extras:
         result["comparators"] = _comparators(args, ctm, torch, oracle_u, dof_steps)
+        result["streaming"] = _streaming(ctm, torch)
+        log(f"streaming: {result['streaming']}")
     if args.copy_calibration:
         src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -344,6 +346,52 @@ def _comparators(args, ctm, torch, oracle_u, dof_steps):
         out[name] = entry
         log(f"{name}: {sec * 1e3:.1f} ms ({dof_steps / sec:.3e} DoF*steps/s) {entry}")
     return out
+
+
+# HBM bytes per unknown of one streaming Krylov iteration (FP64 vectors in
+# HBM, every sweep counted once; neighbour reads served by the caches)
+STREAM_BYTES_PER_ITERATION = {"cg": 112, "bicgstab": 216}
+
+
+def _streaming(ctm, torch):
+    """The streaming kernel on grids beyond the on-chip solver: the 2-D
+    oscillator of Section 4.4 at the paper's own levels (L = 14, L0 = 6:
+    seven grids of up to 32,193 unknowns), FP64 MGRIT. Its roofline is HBM:
+    algorithmic bytes (sweeps x unknowns x Krylov iterations) over the
+    streaming launches' own event-timed duration."""
+    from workloads import make
+    p = make("fp_osc2d", n=14, L0=6, prec="fp64")
+    p.update(krylov_tol=1e-10, mgrit_tol=1e-9, mgrit_maxit=64, krylov_maxit=20000)
+    plan = ctm.Plan(p)
+    plan.solve()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    plan.solve()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    st = plan.stats()
+    plan.set_timing(False)
+    cls = [sh for sh in st["shapes"] if sh["K"] == 0]
+    if not cls:
+        return None
+    c = cls[0]
+    bpi = STREAM_BYTES_PER_ITERATION[p["krylov"]]
+    achieved = c["work"] * bpi / (c["ms"] / 1e3) / 1e9 if c["ms"] > 0 else None
+    return {
+        "workload": f"fp_osc2d at L = 14, L0 = 6: {plan.G} grids, {plan.slen} DoF per level, "
+                    f"{p['nsteps']} steps, 2-level MGRIT c = 2, BiCGStab, FP64",
+        "seconds": sec,
+        "value": plan.slen * p["nsteps"] / sec,
+        "mgrit_iterations": st["mgrit_iterations"],
+        "roofline": {"kernel": "stream_kernel<drift, BiCGStab> (Krylov vectors in HBM)",
+                     "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBPS if achieved else None,
+                     "bytes_per_unknown_iteration": bpi,
+                     "avg_launch_ms": c["ms"] / max(c["launches"], 1),
+                     "launches": c["launches"]},
+    }
 
 
 if __name__ == "__main__":

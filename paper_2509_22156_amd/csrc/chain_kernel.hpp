@@ -19,9 +19,6 @@
 
 namespace ctm {
 
-enum { FLAG_NOCONV = 1 << CTM_ERR_NOCONV, FLAG_BREAKDOWN = 1 << CTM_ERR_BREAKDOWN,
-       FLAG_NONFINITE = 1 << CTM_ERR_NONFINITE };
-
 template <typename T>
 __device__ __forceinline__ bool finite_val(T v) {
   return v == v && v - v == (T)0;

@@ -118,6 +118,10 @@ struct ctm_plan {
   // hierarchical basis (built on first use): node id of every unknown; per
   // node, the unknowns of all grids that share its basis function
   double block_t0 = 0.0;     // start time of the recombination block being solved
+  // streaming grids: scratch of kStreamVectors vectors of stream_ss doubles
+  // for each of up to stream_tasks tasks
+  long long stream_ss = 0, stream_tasks = 0;
+  double* dstream = nullptr;
   // MGRIT convergence on the device: dmg[0] = stopping iteration (0 while
   // running), dmg[2 it], dmg[2 it + 1] = residual and dmg[0] after iteration
   // it; hmg its pinned per-iteration mirror; skip = dmg while a block's
@@ -154,6 +158,7 @@ struct ctm_plan {
     hipFree(dhidx);
     hipFree(dhcoef);
     hipFree(dhsg);
+    hipFree(dstream);
     hipFree(dmg);
     if (hmg) hipHostFree(hmg);
     for (auto e : it_events) hipEventDestroy(e);
@@ -361,7 +366,7 @@ ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
   TaskSet ts;
   std::vector<int2> t;
   t.reserve((size_t)P->G * M);
-  for (int s = 0; s < kNumShapes; ++s) {
+  for (int s = 0; s <= kStreamShape; ++s) {
     const long long start = (long long)t.size();
     double pts = 0.0;
     for (int g : P->order)
@@ -462,7 +467,8 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   c.tasks = tasks + offset;
   if (a.res2) c.res2 = a.res2 + offset;
   c.counters = P->dcounters + (size_t)shape * CNT_N;
-  const size_t smem = chain_smem_bytes(shape, P->tabmax, mixed, P->opc == OPC_HEAT);
+  const size_t smem =
+      (shape == kStreamShape) ? 0 : chain_smem_bytes(shape, P->tabmax, mixed, P->opc == OPC_HEAT);
   // algorithmic bytes: every vector role of every task once
   P->stats.shape_bytes[shape] += 8.0 * points * chain_vectors_per_task(a);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -474,7 +480,13 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
     P->event_shape[P->events_used - 2] = shape;
     CTM_HIP(hipEventRecord(e0, s));
   }
-  hipError_t e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tabmax, s);
+  hipError_t e;
+  if (shape == kStreamShape) {
+    if (count > P->stream_tasks) return fail(CTM_ERR_INVALID, "streaming launch exceeds its scratch");
+    e = launch_stream(P->opc, P->solver, c, (int)count, P->tabmax, P->dstream, P->stream_ss, s);
+  } else {
+    e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tabmax, s);
+  }
   if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("chain launch: ") + hipGetErrorString(e));
   if (P->timing) CTM_HIP(hipEventRecord(e1, s));
   P->stats.chain_launches += 1;
@@ -503,7 +515,7 @@ ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStre
     return ts.ranges[x].points > ts.ranges[y].points;
   });
   double load[nlanes] = {};
-  int lane_of[kNumShapes];
+  int lane_of[kNumShapes + 1];
   for (int i : order) {
     int best = 0;
     for (int l = 1; l < nlanes; ++l)
@@ -571,7 +583,7 @@ void reset_stats(ctm_plan* P) {
 }
 
 ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
-  CTM_HIP(hipMemsetAsync(P->dcounters, 0, kNumShapes * CNT_N * sizeof(unsigned long long), s));
+  CTM_HIP(hipMemsetAsync(P->dcounters, 0, (kNumShapes + 1) * CNT_N * sizeof(unsigned long long), s));
   CTM_HIP(hipMemsetAsync(P->dsync, 0, 2 * sizeof(double), s));
   return CTM_OK;
 }
@@ -580,7 +592,7 @@ ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
 void fold_counters(const ctm_plan* P, const unsigned long long* c, ctm_stats* st) {
   st->krylov_iterations = st->krylov_max = st->refine_sweeps = st->refine_max = 0;
   st->phi_solves = st->krylov_work = 0;
-  for (int s = 0; s < kNumShapes; ++s) {
+  for (int s = 0; s <= kStreamShape; ++s) {
     const unsigned long long* k = c + (size_t)s * CNT_N;
     st->krylov_iterations += (long long)k[CNT_KRYLOV];
     st->krylov_max = std::max(st->krylov_max, (long long)k[CNT_KRYLOV_MAX]);
@@ -589,14 +601,14 @@ void fold_counters(const ctm_plan* P, const unsigned long long* c, ctm_stats* st
     st->phi_solves += (long long)k[CNT_SOLVES];
     st->krylov_work += (long long)k[CNT_WORK];
     st->shape_work[s] = (long long)k[CNT_WORK];
-    st->shape_w[s] = kShapes[s].W;
-    st->shape_k[s] = kShapes[s].K;
+    st->shape_w[s] = (s == kStreamShape) ? 16 : kShapes[s].W;  // streaming: 1,024 threads
+    st->shape_k[s] = (s == kStreamShape) ? 0 : kShapes[s].K;
   }
   (void)P;
 }
 
 ctm_status collect_device_stats(ctm_plan* P, hipStream_t s) {
-  unsigned long long c[kNumShapes * CNT_N];
+  unsigned long long c[(kNumShapes + 1) * CNT_N];
   CTM_HIP(hipMemcpyAsync(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost, s));
   CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   CTM_HIP(hipStreamSynchronize(s));
@@ -1162,14 +1174,37 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     gh.cost = (double)gh.npts * std::sqrt(1.0 + dt0 * lam);
     P->hdev.push_back(gd);
   }
+  // grids the on-chip shapes cannot hold go to the streaming kernel
   P->shape = pick_shape(P->hdev);
   P->gshape.resize(P->G);
-  for (int g = 0; g < P->G; ++g) P->gshape[g] = grid_shape(P->hdev[g]);
-  if (P->shape < 0) {
-    delete P;
-    return fail(CTM_ERR_INVALID,
-                "a component grid exceeds the on-chip solver (line longer than 512 unknowns "
-                "or more than 1024 lanes)");
+  int nstream = 0, maxstream = 0;
+  for (int g = 0; g < P->G; ++g) {
+    const int sh = grid_shape(P->hdev[g]);
+    P->gshape[g] = sh >= 0 ? sh : kStreamShape;
+    if (sh < 0) {
+      ++nstream;
+      maxstream = std::max(maxstream, P->hdev[g].npts);
+      if (P->hdev[g].ns > 1024) {
+        delete P;
+        return fail(CTM_ERR_INVALID, "a component grid has lines longer than 1024 unknowns");
+      }
+    }
+  }
+  if (nstream) {
+    if (prob->manufactured != CTM_MMS_NONE) {
+      delete P;
+      return fail(CTM_ERR_INVALID, "the manufactured forcing needs every grid on chip");
+    }
+    if ((size_t)P->tabmax * sizeof(double) > 65536) {
+      delete P;
+      return fail(CTM_ERR_INVALID, "coefficient tables of a streaming grid exceed 64 KiB");
+    }
+    // scratch for the largest launch: every streaming grid times the
+    // level-0 intervals of a block (or one task per grid)
+    const long long nb = prob->nsteps / prob->nrecomb;
+    const long long M = (prob->mgrit_levels > 1) ? std::max<long long>(1, nb / prob->mgrit_cf) : 1;
+    P->stream_ss = ((long long)maxstream + 63) / 64 * 64;
+    P->stream_tasks = (long long)nstream * M;
   }
   if (P->htab.empty()) P->htab.push_back(0.0);
   P->order.resize(P->G);
@@ -1199,12 +1234,18 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   CTM_HIPC(hipMemcpy(P->dicw, P->icw.data(), P->icw.size() * sizeof(double), hipMemcpyHostToDevice));
   CTM_HIPC(hipMalloc(&P->dicf, P->icf.size() * sizeof(double)));
   CTM_HIPC(hipMemcpy(P->dicf, P->icf.data(), P->icf.size() * sizeof(double), hipMemcpyHostToDevice));
-  CTM_HIPC(hipMalloc(&P->dcounters, kNumShapes * CNT_N * sizeof(unsigned long long)));
-  CTM_HIPC(hipMemset(P->dcounters, 0, kNumShapes * CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMalloc(&P->dcounters, (kNumShapes + 1) * CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMemset(P->dcounters, 0, (kNumShapes + 1) * CNT_N * sizeof(unsigned long long)));
   CTM_HIPC(hipMalloc(&P->dsync, 2 * sizeof(double)));
   CTM_HIPC(hipMemset(P->dsync, 0, 2 * sizeof(double)));
   CTM_HIPC(hipMalloc(&P->dnorm2, P->G * sizeof(double)));
   CTM_HIPC(hipHostMalloc(&P->hsync, 2 * sizeof(double), hipHostMallocDefault));
+  if (P->stream_tasks) {
+    const size_t bytes =
+        (size_t)P->stream_tasks * kStreamVectors * (size_t)P->stream_ss * sizeof(double);
+    if (hipMalloc(&P->dstream, bytes) != hipSuccess)
+      return cleanup(fail(CTM_ERR_NOMEM, "streaming scratch allocation failed"));
+  }
   {
     const size_t nmg = 2 * (size_t)(std::max(1, prob->mgrit_maxit) + 1);
     CTM_HIPC(hipMalloc(&P->dmg, nmg * sizeof(double)));
@@ -1271,8 +1312,12 @@ ctm_status ctm_apply(ctm_plan* P, int level, const double* x, double* y, ctm_str
   if (!P || !x || !y) return fail(CTM_ERR_INVALID, "NULL argument");
   if (level < 0 || level > 16) return fail(CTM_ERR_INVALID, "level out of range");
   if (x == y) return fail(CTM_ERR_INVALID, "x and y must not overlap");
-  CTM_HIP(launch_apply(P->opc, P->shape, P->dgrids, P->G, P->dtab, P->prob.amp, level_dt(P, level),
-                       P->tabmax, x, y, (hipStream_t)s));
+  if (P->shape < 0)  // some grid streams: the point-wise apply for every grid
+    CTM_HIP(launch_stream_apply(P->opc, P->dgrids, P->G, P->dtab, P->prob.amp,
+                                level_dt(P, level), P->tabmax, x, y, (hipStream_t)s));
+  else
+    CTM_HIP(launch_apply(P->opc, P->shape, P->dgrids, P->G, P->dtab, P->prob.amp,
+                         level_dt(P, level), P->tabmax, x, y, (hipStream_t)s));
   return CTM_OK;
 }
 
@@ -1386,7 +1431,7 @@ ctm_status ctm_get_stats(const ctm_plan* Pc, ctm_stats* st) {
     if (s2 != CTM_OK) return s2;
   }
   // counters live on the device; the caller has synchronised its stream
-  unsigned long long c[kNumShapes * CNT_N];
+  unsigned long long c[(kNumShapes + 1) * CNT_N];
   int flags = 0;
   CTM_HIP(hipMemcpy(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost));
   CTM_HIP(hipMemcpy(&flags, P->dsync + 1, sizeof(int), hipMemcpyDeviceToHost));

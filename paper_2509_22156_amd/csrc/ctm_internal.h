@@ -114,10 +114,21 @@ struct ShapeCfg {
 constexpr ShapeCfg kShapes[] = {{1, 4}, {2, 4}, {4, 4}, {8, 4}, {16, 4},
                                 {1, 8}, {2, 8}, {4, 8}, {8, 8}, {16, 8}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-static_assert(kNumShapes <= 16, "ctm_stats keeps 16 shape slots");
+// Grids beyond the on-chip shapes go to the streaming kernel (vectors in HBM
+// scratch, one 1,024-thread work-group per task); its size class index:
+constexpr int kStreamShape = kNumShapes;
+static_assert(kNumShapes + 1 <= 16, "ctm_stats keeps 16 shape slots");
 
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
                         int ntasks, size_t smem, int tabmax, hipStream_t s);
+// Streaming kernel (stream_ops.hip): task t of the launch uses the scratch
+// doubles [t * SV_N * ss, (t + 1) * SV_N * ss); FP64 whatever the precision.
+constexpr int kStreamVectors = 9;
+hipError_t launch_stream(int opc, int solver, const ChainArgs& a, int ntasks, int tabmax,
+                         double* scratch, long long ss, hipStream_t s);
+hipError_t launch_stream_apply(int opc, const GridDev* grids, int G, const double* tab64,
+                               double amp, double dt, int tabmax, const double* x, double* y,
+                               hipStream_t s);
 
 // LDS copy of a vector the stencil reads: K rows (one per chunk position k)
 // of pitch 64 W + kLdsGhost; thread t owns column t, and the columns from

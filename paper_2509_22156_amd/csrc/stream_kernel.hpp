@@ -1,0 +1,494 @@
+// The streaming implicit-step kernel, for component grids that do not fit
+// the on-chip solver (more than 8,192 unknowns, or lines longer than 512):
+// one work-group of 1,024 threads per task (grid g, interval q), with every
+// Krylov vector of the task in its own slot of an HBM scratch array. Thread
+// t takes the points t, t + 1024, ... of the grid (canonical order, so every
+// sweep is coalesced); a Krylov iteration is a few sweeps over the task's
+// vectors, with block-wide reductions between them. FP64 throughout, CG or
+// right-preconditioned BiCGStab (Section 4.1) with the same line-block
+// preconditioner as the on-chip solver (exact solves of the stiff-axis
+// lines), the same vector roles as the on-chip chain kernel (ChainArgs).
+//
+// The stencil coefficients are evaluated per point and sweep from the grid
+// descriptor and the coefficient tables in LDS; they match the on-chip
+// operators of every class.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace ctm {
+
+constexpr int kStreamThreads = 1024;
+constexpr int kStreamW = kStreamThreads / 64;
+
+// Scratch vectors of one task (each `sstride` doubles); SV_D holds the
+// preconditioned direction in BiCGStab.
+enum { SV_X = 0, SV_B, SV_R, SV_P, SV_Q, SV_RH, SV_S, SV_T, SV_D, SV_N };
+
+// Coefficients of A = I + dt L at point p of grid g: the diagonal, and per
+// axis the couplings to the lower and upper neighbour (zero where that
+// neighbour is not an unknown), plus the point strides.
+template <int OPC>
+struct PointCoef {
+  double diag;
+  double lo[MAXD], up[MAXD];
+  int j[MAXD];
+};
+
+template <int OPC>
+__device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, double dt,
+                                           double amp, int p, PointCoef<OPC>& c) {
+  const int d = g.d;
+  int rem = p;
+#pragma unroll
+  for (int i = MAXD - 1; i >= 0; --i) {
+    c.j[i] = 0;
+    if (i < d) {
+      c.j[i] = rem % g.n[i];
+      rem /= g.n[i];
+    }
+  }
+  double diag = 1.0;
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) {
+    c.lo[i] = c.up[i] = 0.0;
+    if (i >= d) continue;
+    const int j = c.j[i];
+    const int n = g.n[i];
+    double lo = 0.0, up = 0.0;
+    if constexpr (OPC == OPC_HEAT) {
+      const double cc = dt * g.ih2[i];
+      diag += 2.0 * cc;
+      lo = up = -cc;
+    } else if constexpr (OPC == OPC_SEP) {
+      const double* t = tl + g.tab[i];  // Lo, D, Up of L, already times dt
+      lo = t[j];
+      diag += t[n + j];
+      up = t[2 * n + j];
+    } else if constexpr (OPC == OPC_VAR) {
+      // a at the faces: 1 + amp * (face sine) * (node sines of the other axes)
+      double es = 1.0;
+#pragma unroll
+      for (int k = 0; k < MAXD; ++k)
+        if (k < d && k != i) es *= tl[g.tab[k] + c.j[k]];
+      const double* sm = tl + g.tab[i] + n;
+      const double adn = 1.0 + amp * sm[j] * es, aup = 1.0 + amp * sm[j + 1] * es;
+      const double cc = dt * g.ih2[i];
+      diag += cc * (adn + aup);
+      lo = -cc * adn;
+      up = -cc * aup;
+    } else {  // OPC_DRIFT: theta (d x d), then H (d)
+      double w = 0.0;
+#pragma unroll
+      for (int k = 0; k < MAXD; ++k)
+        if (k < d) w += tl[i * d + k] * (g.lo[k] + (double)(c.j[k] + g.j0) * g.h[k]);
+      const double h = g.h[i], half = tl[i * d + i] * 0.5 * h, H = tl[d * d + i];
+      const double wu = w + half, wd = w - half;
+      diag += dt * ((fmax(wu, 0.0) - fmin(wd, 0.0)) / h + H / (h * h));
+      up = dt * (fmin(wu, 0.0) / h - 0.5 * H / (h * h));
+      lo = dt * (-fmax(wd, 0.0) / h - 0.5 * H / (h * h));
+    }
+    c.lo[i] = (j > 0) ? lo : 0.0;
+    c.up[i] = (j < n - 1) ? up : 0.0;
+  }
+  c.diag = diag;
+}
+
+// y = A x at every point of the task; returns this thread's part of
+// sum w[p] y[p] when w is given.
+template <int OPC>
+__device__ __forceinline__ double stream_apply(const GridDev& g, const double* tl, double dt,
+                                               double amp, const double* x, double* y,
+                                               const double* w) {
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < g.npts; p += kStreamThreads) {
+    PointCoef<OPC> c;
+    point_coef<OPC>(g, tl, dt, amp, p, c);
+    double v = c.diag * x[p];
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i) {
+      if (i >= g.d) continue;
+      const int st = g.stride[i];
+      if (c.lo[i] != 0.0) v += c.lo[i] * x[p - st];
+      if (c.up[i] != 0.0) v += c.up[i] * x[p + st];
+    }
+    y[p] = v;
+    if (w) acc += w[p] * v;
+  }
+  return acc;
+}
+
+// z = M^-1 r for the line-block preconditioner M: the part of A that couples
+// unknowns along the stiff axis (one tridiagonal block per line, as in the
+// on-chip solver). Lines are staged through LDS in batches of 1024 / ns'
+// lines (ns' = ns rounded up to a power of two, at most 1024) and each is
+// solved by parallel cyclic reduction over its unknowns. Returns this
+// thread's part of sum w[p] z[p] when w is given. Ends with a barrier.
+template <int OPC>
+__device__ double stream_precond(const GridDev& g, const double* tl, double dt, double amp,
+                                 const double* r, double* z, double* lds, const double* w) {
+  const int s = g.sax, ns = g.ns;
+  int nsp = 1;
+  while (nsp < ns) nsp <<= 1;
+  const int per = kStreamThreads / nsp;  // lines per batch
+  const int t = threadIdx.x, li = t / nsp, i = t % nsp;
+  double* A = lds;
+  double* Bd = lds + kStreamThreads;
+  double* C = lds + 2 * kStreamThreads;
+  double* R = lds + 3 * kStreamThreads;
+  double acc = 0.0;
+  for (int l0 = 0; l0 < g.nlines; l0 += per) {
+    const int line = l0 + li;
+    const bool live = (li < per) && (line < g.nlines) && (i < ns);
+    int p = 0;
+    if (live) {
+      int rem = line;
+      p = i * g.stride[s];
+#pragma unroll
+      for (int m = 0; m < MAXD - 1; ++m)
+        if (m < g.d - 1) {
+          const int ax = g.oax[m];
+          p += ((rem / g.lstride[m]) % g.n[ax]) * g.stride[ax];
+        }
+      (void)rem;
+      PointCoef<OPC> c;
+      point_coef<OPC>(g, tl, dt, amp, p, c);
+      double lo = 0.0, up = 0.0;  // (unrolled select: no dynamic register index)
+#pragma unroll
+      for (int ax = 0; ax < MAXD; ++ax)
+        if (ax == s) {
+          lo = c.lo[ax];
+          up = c.up[ax];
+        }
+      A[t] = lo;
+      Bd[t] = c.diag;
+      C[t] = up;
+      R[t] = r[p];
+    } else {
+      A[t] = 0.0;
+      Bd[t] = 1.0;
+      C[t] = 0.0;
+      R[t] = 0.0;
+    }
+    __syncthreads();
+    for (int st = 1; st < nsp; st <<= 1) {
+      const double ai = A[t], bi = Bd[t], ci = C[t], ri = R[t];
+      double an = 0.0, cn = 0.0, bn = bi, rn = ri;
+      if (i >= st) {
+        const double al = -ai / Bd[t - st];
+        an = al * A[t - st];
+        bn += al * C[t - st];
+        rn += al * R[t - st];
+      }
+      if (i + st < nsp) {
+        const double ga = -ci / Bd[t + st];
+        cn = ga * C[t + st];
+        bn += ga * A[t + st];
+        rn += ga * R[t + st];
+      }
+      __syncthreads();
+      A[t] = an;
+      Bd[t] = bn;
+      C[t] = cn;
+      R[t] = rn;
+      __syncthreads();
+    }
+    if (live) {
+      const double zv = R[t] / Bd[t];
+      z[p] = zv;
+      if (w) acc += w[p] * zv;
+    }
+    __syncthreads();  // the next batch overwrites LDS; z complete for readers
+  }
+  return acc;
+}
+
+// One implicit step: x <- (I + dt L)^-1 b, x holding the initial guess.
+// Preconditioned CG (symmetric operators).
+template <int OPC>
+__device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a, double* sv,
+                         long long ss, double* lds, RedRing& ring, double tol2, int* flag) {
+  double* X = sv + SV_X * ss;
+  double* B = sv + SV_B * ss;
+  double* R = sv + SV_R * ss;
+  double* P = sv + SV_P * ss;
+  double* Q = sv + SV_Q * ss;
+  double* Z = sv + SV_S * ss;
+  const int np = g.npts;
+  stream_apply<OPC>(g, tl, a.dt, a.amp, X, Q, nullptr);
+  double s0[2] = {0.0, 0.0};  // (r, r), (b, b)
+  for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+    const double r = B[p] - Q[p];
+    R[p] = r;
+    s0[0] += r * r;
+    s0[1] += B[p] * B[p];
+  }
+  block_sum<kStreamW, 2, double>(s0, ring);  // also orders R before the preconditioner
+  const double bb = s0[1];
+  if (!(s0[0] == s0[0]) || !(bb == bb)) {
+    *flag |= FLAG_NONFINITE;
+    return 0;
+  }
+  if (s0[0] <= tol2 * bb) return 0;
+  double rz1[1] = {stream_precond<OPC>(g, tl, a.dt, a.amp, R, Z, lds, R)};
+  block_sum<kStreamW, 1, double>(rz1, ring);
+  double rz = rz1[0];
+  for (int p = threadIdx.x; p < np; p += kStreamThreads) P[p] = Z[p];
+  __syncthreads();
+  for (int it = 1; it <= a.maxit; ++it) {
+    double pq[1] = {stream_apply<OPC>(g, tl, a.dt, a.amp, P, Q, P)};
+    block_sum<kStreamW, 1, double>(pq, ring);
+    if (!(pq[0] != 0.0) || !(pq[0] == pq[0])) {
+      *flag |= (pq[0] == pq[0]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
+      return it;
+    }
+    const double alpha = rz / pq[0];
+    double s1[1] = {0.0};
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      X[p] += alpha * P[p];
+      const double r = R[p] - alpha * Q[p];
+      R[p] = r;
+      s1[0] += r * r;
+    }
+    block_sum<kStreamW, 1, double>(s1, ring);
+    if (!(s1[0] == s1[0])) {
+      *flag |= FLAG_NONFINITE;
+      return it;
+    }
+    if (s1[0] <= tol2 * bb) return it;
+    double rzn[1] = {stream_precond<OPC>(g, tl, a.dt, a.amp, R, Z, lds, R)};
+    block_sum<kStreamW, 1, double>(rzn, ring);
+    const double beta = rzn[0] / rz;
+    rz = rzn[0];
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) P[p] = Z[p] + beta * P[p];
+    __syncthreads();  // P complete before the next apply reads neighbours
+  }
+  *flag |= FLAG_NOCONV;
+  return a.maxit;
+}
+
+// Right-preconditioned BiCGStab (van der Vorst): p^ = M^-1 p, v = A p^,
+// s^ = M^-1 s, t = A s^, x += alpha p^ + omega s^ (the first part as soon as
+// alpha is known, so that p^ and s^ share one scratch vector).
+template <int OPC>
+__device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainArgs& a,
+                               double* sv, long long ss, double* lds, RedRing& ring, double tol2,
+                               int* flag) {
+  double* X = sv + SV_X * ss;
+  double* B = sv + SV_B * ss;
+  double* R = sv + SV_R * ss;
+  double* P = sv + SV_P * ss;
+  double* V = sv + SV_Q * ss;
+  double* RH = sv + SV_RH * ss;
+  double* S = sv + SV_S * ss;
+  double* T = sv + SV_T * ss;
+  double* H = sv + SV_D * ss;  // p^, then s^
+  const int np = g.npts;
+  stream_apply<OPC>(g, tl, a.dt, a.amp, X, V, nullptr);
+  double s0[2] = {0.0, 0.0};
+  for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+    const double r = B[p] - V[p];
+    R[p] = r;
+    RH[p] = r;
+    P[p] = r;
+    s0[0] += r * r;
+    s0[1] += B[p] * B[p];
+  }
+  block_sum<kStreamW, 2, double>(s0, ring);
+  const double bb = s0[1];
+  if (!(s0[0] == s0[0]) || !(bb == bb)) {
+    *flag |= FLAG_NONFINITE;
+    return 0;
+  }
+  if (s0[0] <= tol2 * bb) return 0;
+  double rho = s0[0];
+  for (int it = 1; it <= a.maxit; ++it) {
+    stream_precond<OPC>(g, tl, a.dt, a.amp, P, H, lds, nullptr);
+    double s2[1] = {stream_apply<OPC>(g, tl, a.dt, a.amp, H, V, RH)};
+    block_sum<kStreamW, 1, double>(s2, ring);
+    if (!(s2[0] != 0.0) || !(s2[0] == s2[0])) {
+      *flag |= (s2[0] == s2[0]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
+      return it;
+    }
+    const double alpha = rho / s2[0];
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      X[p] += alpha * H[p];
+      S[p] = R[p] - alpha * V[p];
+    }
+    __syncthreads();  // S complete before the preconditioner reads whole lines
+    stream_precond<OPC>(g, tl, a.dt, a.amp, S, H, lds, nullptr);
+    double s3[3] = {0.0, 0.0, 0.0};  // (t, s), (t, t), (s, s)
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      PointCoef<OPC> c;
+      point_coef<OPC>(g, tl, a.dt, a.amp, p, c);
+      double v = c.diag * H[p];
+#pragma unroll
+      for (int i = 0; i < MAXD; ++i) {
+        if (i >= g.d) continue;
+        const int st = g.stride[i];
+        if (c.lo[i] != 0.0) v += c.lo[i] * H[p - st];
+        if (c.up[i] != 0.0) v += c.up[i] * H[p + st];
+      }
+      T[p] = v;
+      s3[0] += v * S[p];
+      s3[1] += v * v;
+      s3[2] += S[p] * S[p];
+    }
+    block_sum<kStreamW, 3, double>(s3, ring);
+    if (s3[2] <= tol2 * bb) return it;  // x already holds x + alpha p^
+    if (!(s3[1] != 0.0) || !(s3[1] == s3[1])) {
+      *flag |= (s3[1] == s3[1]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
+      return it;
+    }
+    const double omega = s3[0] / s3[1];
+    double s4[2] = {0.0, 0.0};  // (r, r), (rh, r)
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      X[p] += omega * H[p];
+      const double r = S[p] - omega * T[p];
+      R[p] = r;
+      s4[0] += r * r;
+      s4[1] += RH[p] * r;
+    }
+    block_sum<kStreamW, 2, double>(s4, ring);
+    if (!(s4[0] == s4[0])) {
+      *flag |= FLAG_NONFINITE;
+      return it;
+    }
+    if (s4[0] <= tol2 * bb) return it;
+    if (s4[1] == 0.0 || omega == 0.0) {
+      *flag |= FLAG_BREAKDOWN;
+      return it;
+    }
+    const double beta = (s4[1] / rho) * (alpha / omega);
+    rho = s4[1];
+    for (int p = threadIdx.x; p < np; p += kStreamThreads)
+      P[p] = R[p] + beta * (P[p] - omega * V[p]);
+    __syncthreads();  // P complete before the preconditioner reads whole lines
+  }
+  *flag |= FLAG_NOCONV;
+  return a.maxit;
+}
+
+// Scratch of task t of the launch: sv = scratch + t * SV_N * ss.
+template <int OPC, int SOLVER>
+__global__ void __launch_bounds__(kStreamThreads)
+    stream_kernel(ChainArgs a, int tabmax, double* scratch, long long ss) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ GridDev gs;
+  __shared__ double red[2 * 64];
+  __shared__ double pcr[4 * kStreamThreads];  // cyclic-reduction staging of the lines
+  if (a.skip && *a.skip != 0.0) return;  // whole work-group: queued past convergence
+  double* tl = reinterpret_cast<double*>(smem);
+  const int2 task = a.tasks[blockIdx.x];
+  const int q = task.y;
+  {
+    const int* src = reinterpret_cast<const int*>(a.grids + task.x);
+    int* dst = reinterpret_cast<int*>(&gs);
+    for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += kStreamThreads)
+      dst[t] = src[t];
+  }
+  __syncthreads();
+  const GridDev& g = gs;
+  load_tables<OPC, double, kStreamThreads>(g, a.tab64, a.dt, tl);
+  __syncthreads();
+  (void)tabmax;
+  double* sv = scratch + (long long)blockIdx.x * SV_N * ss;
+  double* X = sv + SV_X * ss;
+  double* B = sv + SV_B * ss;
+  const int np = g.npts;
+  const long long off = g.off;
+  auto at = [&](const VecRef& r, long long idx) { return r.base + idx * a.slen + off; };
+  const double* st = a.start.base ? at(a.start, a.start.a * q + a.start.b) : nullptr;
+  double* wb = a.start_wb.base ? at(a.start_wb, a.start_wb.a * q + a.start_wb.b) : nullptr;
+  for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+    const double v = st ? st[p] : 0.0;
+    B[p] = v;
+    if (wb) wb[p] = v;
+  }
+  __syncthreads();
+  RedRing ring{red, 0};
+  int flag = 0;
+  long long kr_sum = 0, kr_max = 0;
+  const double tol2 = a.tol * a.tol;
+  for (int j = 1; j <= a.nsteps; ++j) {
+    const bool last = (j == a.nsteps);
+    const VecRef gr = last ? a.guess_fin : a.guess;
+    const double* gx = gr.base ? at(gr, gr.a * q + gr.b + (last ? 0 : j)) : nullptr;
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) X[p] = gx ? gx[p] : B[p];
+    __syncthreads();
+    int it;
+    if constexpr (SOLVER == SOLV_CG)
+      it = stream_cg<OPC>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
+    else
+      it = stream_bicgstab<OPC>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
+    kr_sum += it;
+    kr_max = it > kr_max ? it : kr_max;
+    const double* f = a.forcing.base ? at(a.forcing, a.forcing.a * q + a.forcing.b + j) : nullptr;
+    double* is = (a.inter.base && j < a.nsteps) ? at(a.inter, a.inter.a * q + a.inter.b + j)
+                                                 : nullptr;
+    __syncthreads();  // every thread's X final
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      const double v = X[p] + (f ? f[p] : 0.0);
+      B[p] = v;
+      if (is) is[p] = v;
+    }
+    __syncthreads();
+  }
+  if (a.fin.base) {
+    double* dst = at(a.fin, a.fin.a * q + a.fin.b);
+    const double* tg = a.target.base ? at(a.target, a.target.a * q + a.target.b) : nullptr;
+    double rr[1] = {0.0};
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      const double v = tg ? B[p] - tg[p] : B[p];
+      dst[p] = v;
+      rr[0] += v * v;
+    }
+    if (tg) {
+      block_sum<kStreamW, 1, double>(rr, ring);
+      if (threadIdx.x == 0 && a.res2) a.res2[blockIdx.x] = rr[0];
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (a.counters) {
+      atomicAdd(&a.counters[CNT_KRYLOV], (unsigned long long)kr_sum);
+      atomicMax(&a.counters[CNT_KRYLOV_MAX], (unsigned long long)kr_max);
+      atomicAdd(&a.counters[CNT_SOLVES], (unsigned long long)a.nsteps);
+      atomicAdd(&a.counters[CNT_WORK], (unsigned long long)kr_sum * (unsigned long long)np);
+    }
+    if (flag && a.status) atomicOr(a.status, flag);
+  }
+}
+
+template <int OPC, int SOLVER>
+hipError_t launch_stream_t(const ChainArgs& a, int ntasks, int tabmax, double* scratch,
+                           long long ss, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  const size_t smem = (size_t)tabmax * sizeof(double);
+  hipLaunchKernelGGL((stream_kernel<OPC, SOLVER>), dim3(ntasks), dim3(kStreamThreads), smem, s,
+                     a, tabmax, scratch, ss);
+  return hipGetLastError();
+}
+
+// y = (I + dt L) x on every grid, point-wise (one work-group per grid); the
+// standalone apply for plans with streaming grids.
+template <int OPC>
+__global__ void __launch_bounds__(kStreamThreads)
+    stream_apply_kernel(const GridDev* __restrict__ grids, const double* __restrict__ tab64,
+                        double amp, double dt, const double* __restrict__ x,
+                        double* __restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ GridDev gs;
+  double* tl = reinterpret_cast<double*>(smem);
+  {
+    const int* src = reinterpret_cast<const int*>(grids + blockIdx.x);
+    int* dst = reinterpret_cast<int*>(&gs);
+    for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += kStreamThreads)
+      dst[t] = src[t];
+  }
+  __syncthreads();
+  load_tables<OPC, double, kStreamThreads>(gs, tab64, dt, tl);
+  __syncthreads();
+  stream_apply<OPC>(gs, tl, dt, amp, x + gs.off, y + gs.off, nullptr);
+}
+
+}  // namespace ctm

@@ -103,3 +103,12 @@ def test_cg_rejected_for_nonsymmetric_and_lattice_box():
 def test_status_strings():
     for st in range(7):
         assert ctm.lib().ctm_status_string(st)
+
+
+def test_lines_beyond_streaming_limit_rejected():
+    # lines of 2,047 unknowns exceed the streaming preconditioner's LDS lines
+    s, keep = ctm.problem_struct(make("heat2d", n=12))
+    h = ctypes.c_void_p()
+    assert ctm.lib().ctm_plan_create(ctypes.byref(s), ctypes.byref(h)) == ctm.ERR_INVALID
+    assert "longer than 1024" in ctm.lib().ctm_last_error().decode()
+    assert not h.value
