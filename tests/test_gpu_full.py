@@ -39,6 +39,9 @@ CASES = [
     ("cme5d", MIXED, 1e-8, None),
     ("varcoef6d", MIXED, 1e-8, 43),
     ("fp_osc2d", FP64, 1e-11, None),
+    # the paper's own levels for the oscillator (L = 14, L0 = 6): seven grids
+    # of up to 32,193 unknowns, all on the streaming path
+    ("fp_osc2d-paper", FP64, 1e-11, None),
     ("fp_lin4d", MIXED, 1e-8, None),
     # the throughput measurement's own settings, held to its 1e-8 target
     ("heat3d", metric_settings("mixed"), 1e-8, None),
@@ -50,7 +53,10 @@ CASES = [
                          ids=[f"{c[0]}-{c[1]['prec']}" + ("-metric" if "coarse_tol" in c[1] else "")
                               for c in CASES])
 def test_full_size_solve(name, kw, tol, stride):
-    p = make(name, prec=kw["prec"])
+    if name == "fp_osc2d-paper":
+        p = make("fp_osc2d", n=14, L0=6, prec=kw["prec"])
+    else:
+        p = make(name, prec=kw["prec"])
     p.update(kw)
     _say(f"full {name} {kw['prec']}: d={p['d']} n={p['n']} N={p['nsteps']} "
          f"levels={p['mgrit_levels']} cf={p['cf']}")
