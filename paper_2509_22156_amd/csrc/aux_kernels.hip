@@ -127,9 +127,9 @@ __global__ void __launch_bounds__(64 * W)
 #pragma unroll
   for (int k = 0; k < K; ++k)
     xs[k] = (k < L.nval) ? x[g.off + L.cbase + (long long)k * L.cstep] : 0.0;
-  lds_put<double, K>(L, xl, xs);
+  lds_put<double, K, lds_pitch(W)>(L, xl, xs);
   __syncthreads();
-  line_apply<OPC, double, K>(g, L, O, xl, xs, ys);
+  line_apply<OPC, double, K, lds_pitch(W)>(g, L, O, xl, xs, ys);
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (k < L.nval) y[g.off + L.cbase + (long long)k * L.cstep] = ys[k];

@@ -44,13 +44,13 @@ struct Solver {
 };
 
 // y = A x (x written to LDS first; one barrier).
-template <int OPC, typename T, int K>
+template <int OPC, typename T, int W, int K>
 __device__ __forceinline__ void sapply(const Solver<OPC, T, K>& S, const T (&x)[K], T (&y)[K]) {
   if (S.g.d > 1) {  // one-dimensional grids need no neighbour lines
-    lds_put<T, K>(S.L, S.xl, x);
+    lds_put<T, K, lds_pitch(W)>(S.L, S.xl, x);
     __syncthreads();
   }
-  line_apply<OPC, T, K>(S.g, S.L, S.O, S.xl, x, y);
+  line_apply<OPC, T, K, lds_pitch(W)>(S.g, S.L, S.O, S.xl, x, y);
 }
 
 // Preconditioned CG in the single-reduction form of Chronopoulos and Gear:
@@ -69,7 +69,7 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = b[k];
   } else {
-    sapply<OPC, T, K>(S, x, w);
+    sapply<OPC, T, W, K>(S, x, w);
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = b[k] - w[k];
     __syncthreads();  // every wave has read x from LDS before z overwrites it
@@ -89,7 +89,7 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
     if (s2[0] <= tol2 * s2[1]) return 0;
   }
   linepre_apply<T, K>(S.L, S.M, r, z);
-  sapply<OPC, T, K>(S, z, w);
+  sapply<OPC, T, W, K>(S, z, w);
   // (r,z), (Az,z), (r,r) and, unless x = 0 (then b = r), (b,b)
   T red[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
@@ -120,7 +120,7 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
       r[k] -= alpha * s[k];
     }
     linepre_apply<T, K>(S.L, S.M, r, z);
-    sapply<OPC, T, K>(S, z, w);
+    sapply<OPC, T, W, K>(S, z, w);
     T rd[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -162,7 +162,7 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = b[k];
   } else {
-    sapply<OPC, T, K>(S, x, v);
+    sapply<OPC, T, W, K>(S, x, v);
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = b[k] - v[k];
   }
@@ -184,7 +184,7 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
   T rho = s1[0];
   for (int it = 1; it <= maxit; ++it) {
     linepre_apply<T, K>(S.L, S.M, p, h);
-    sapply<OPC, T, K>(S, h, v);
+    sapply<OPC, T, W, K>(S, h, v);
     T s2[1] = {(T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) s2[0] += rh[k] * v[k];
@@ -200,7 +200,7 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
       s[k] = r[k] - alpha * v[k];
     }
     linepre_apply<T, K>(S.L, S.M, s, h);
-    sapply<OPC, T, K>(S, h, t);
+    sapply<OPC, T, W, K>(S, h, t);
     T s3[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -295,7 +295,7 @@ __device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
   double bb = 0.0;
   for (; sweeps <= refine_maxit; ++sweeps) {
     double rq[K];
-    sapply<OPC, double, K>(S64, x, rq);
+    sapply<OPC, double, W, K>(S64, x, rq);
     double rr[2] = {0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {

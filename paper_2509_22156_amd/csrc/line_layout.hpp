@@ -73,8 +73,7 @@ struct Lane {
   int Lc;          // lanes per line
   int j0;          // stiff coordinate of the chunk's first unknown (c * K)
   int nval;        // unknowns of the chunk inside the line (0..K)
-  int tid;         // thread index: LDS slot of unknown k is k * pitch + tid
-  int pitch;       // LDS row pitch: threads per work-group + kLdsGhost
+  int tid;         // thread index: LDS slot of unknown k is k * lds_pitch(W) + tid
   long long cbase; // canonical index of the chunk's first unknown
   int cstep;       // canonical stride along the stiff axis
   bool nxt;        // the next chunk of the line holds unknowns
@@ -96,7 +95,6 @@ __device__ __forceinline__ void setup_lane(const GridDev& g, Lane<K>& L) {
   nv = nv < 0 ? 0 : (nv > K ? K : nv);
   L.nval = live ? nv : 0;
   L.tid = t;
-  L.pitch = blockDim.x + kLdsGhost;
   L.nxt = live && (L.j0 + K < g.ns);
   L.cstep = g.cstride[g.sax];
   long long cb = 0;
@@ -340,10 +338,10 @@ __device__ __forceinline__ T op_oup(const LineOp<OPC, T, K>& O, int m) {
 // addresses (no bank conflicts). A barrier must follow before line_apply.
 // Thread t holds chunk c of line `line` with t = line * Lc + c, so the
 // neighbouring line along oax[m] lives in thread t +- lstride[m] * Lc.
-template <typename T, int K>
+template <typename T, int K, int PITCH>
 __device__ __forceinline__ void lds_put(const Lane<K>& L, T* xl, const T (&x)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) xl[k * L.pitch + L.tid] = x[k];
+  for (int k = 0; k < K; ++k) xl[k * PITCH + L.tid] = x[k];
 }
 
 // Zero the ghost columns (column blockDim.x + i of every row); done once per
@@ -358,7 +356,7 @@ __device__ __forceinline__ void lds_zero_ghosts(T* xl) {
 // y = A x on the chunk; xl holds x of the whole grid (after a barrier).
 // Padding entries of x (k >= nval) must be zero, and so are those of y. A
 // missing neighbour line is read from the zero ghost column.
-template <int OPC, typename T, int K>
+template <int OPC, typename T, int K, int PITCH>
 __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
                                            const LineOp<OPC, T, K>& O, const T* xl,
                                            const T (&x)[K], T (&y)[K]) {
@@ -371,7 +369,9 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
     const T xp = (k < K - 1) ? x[k + 1] : (L.nxt ? xright : (T)0);
     acc[k] = op_diag(O, k) * x[k] + op_slo(O, k) * xm + op_sup(O, k) * xp;
   }
-  const int ghost = L.pitch - kLdsGhost;
+  // PITCH (the LDS row length) is a compile-time constant, so the K row
+  // offsets of a neighbour read are immediate fields of the LDS loads
+  const int ghost = PITCH - kLdsGhost;
 #pragma unroll
   for (int m = 0; m < MAXD - 1; ++m) {
     if (m < g.d - 1) {
@@ -390,8 +390,8 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
           const T w0 = O.base[m] + tas * (O.xs0 + (T)k * hs);
           const T clo = -ih * max(w0 - half, (T)0) - dH;
           const T chi = ih * min(w0 + half, (T)0) - dH;
-          acc[k] += clo * plo[k * L.pitch];
-          acc[k] += chi * phi[k * L.pitch];
+          acc[k] += clo * plo[k * PITCH];
+          acc[k] += chi * phi[k * PITCH];
         }
       } else {
 #pragma unroll
@@ -401,8 +401,8 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
             clo += O.qlo[m] * O.snj[k];
             chi += O.qup[m] * O.snj[k];
           }
-          acc[k] += clo * plo[k * L.pitch];
-          acc[k] += chi * phi[k * L.pitch];
+          acc[k] += clo * plo[k * PITCH];
+          acc[k] += chi * phi[k * PITCH];
         }
       }
     }
