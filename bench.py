@@ -130,6 +130,12 @@ def main(argv=None):
     ap.add_argument("--mms-sweep", action="store_true",
                     help="instead of the metric: the manufactured heat family of Section 4.2 "
                          "over d = 2..6 and two levels each (one JSON line per case)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the plan's default launch shapes (no autotuning)")
+    ap.add_argument("--save-shapes", default=None,
+                    help="write the tuned launch shape of every grid to this JSON file")
+    ap.add_argument("--load-shapes", default=None,
+                    help="take the launch shapes from this JSON file instead of tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 256 MiB device copy (hardware-counter calibration)")
     args = ap.parse_args(argv)
@@ -151,6 +157,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     plan = ctm.Plan(prob)
     plan_ms = (time.perf_counter() - t0) * 1e3
+    tune = _shapes(args, plan)
     pts_np = targets(prob, GATHER_POINTS, seed=0)
     pts = torch.from_numpy(pts_np).cuda()
     u = torch.empty(plan.slen, dtype=torch.float64, device="cuda")
@@ -253,6 +260,7 @@ def main(argv=None):
             "phi_solves_per_step": agg["phi_solves"] / args.steps,
             "krylov_iterations_per_step": agg["krylov_iterations"] / args.steps,
             "plan_ms": plan_ms,
+            "autotune": tune,
         },
         "roofline": roofline,
     }
@@ -306,6 +314,29 @@ def _cpu_model():
     return None
 
 
+def _shapes(args, plan):
+    """Launch shapes of the timed plan, outside the timed region: autotuned
+    (ctm_autotune, full trial solves, fastest of two), taken from a file, or
+    the defaults."""
+    if args.load_shapes:
+        with open(args.load_shapes) as f:
+            rec = json.load(f)
+        assert rec["workload"] == args.workload and len(rec["shapes"]) == plan.G
+        for g, (w, k) in enumerate(rec["shapes"]):
+            if k:
+                plan.set_grid_shape(g, w, k)
+        return {"source": args.load_shapes}
+    tune = None
+    if not args.no_tune:
+        tune = plan.autotune(trial_iterations=0, repeats=2)
+        log(f"autotune: {tune}")
+    if args.save_shapes:
+        with open(args.save_shapes, "w") as f:
+            json.dump({"workload": args.workload,
+                       "shapes": [plan.grid_shape(g) for g in range(plan.G)]}, f)
+    return tune
+
+
 def _timed(torch, fn, reps=1):
     fn()
     torch.cuda.synchronize()
@@ -319,7 +350,9 @@ def _timed(torch, fn, reps=1):
 def _comparators(args, ctm, torch, oracle_u, dof_steps):
     """FP64 MGRIT, batched time-sequential stepping (mixed and FP64) and the
     plain per-grid FP64 schedule on the same workload, outside the timed
-    region, each with its error against the oracle."""
+    region, each with its error against the oracle. The batched ones are
+    autotuned like the timed plan (unless --no-tune) and timed as the mean
+    of three solves; the plain schedule keeps the default shapes."""
     out = {}
     runs = [
         ("fp64_mgrit", workload_problem(args.workload, "fp64"), "solve"),
@@ -333,7 +366,9 @@ def _comparators(args, ctm, torch, oracle_u, dof_steps):
         plan = ctm.Plan(prob)
         u0 = plan.initial_state()
         if kind == "solve":
-            sec, u = _timed(torch, lambda: plan.solve())
+            if not args.no_tune:
+                plan.autotune(trial_iterations=0, repeats=2)
+            sec, u = _timed(torch, lambda: plan.solve(), reps=3)
             st = plan.stats()
         else:
             sec, u = _timed(torch, lambda: plan.propagate(u0, prob["nsteps"], per_grid=True))

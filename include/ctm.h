@@ -248,6 +248,47 @@ ctm_status ctm_hierarchize(ctm_plan* plan, const double* in, double* out, int in
  * unknown). Async. */
 ctm_status ctm_recombine(ctm_plan* plan, const double* u, double* out, ctm_stream s);
 
+/* Launch shape of grid g in the on-chip solver: *waves = wavefronts per
+ * work-group (one work-group solves one grid's system), *per_lane =
+ * consecutive unknowns of a line held by one lane (4 or 8). A grid beyond
+ * the on-chip shapes reports *waves = 16, *per_lane = 0 (the streaming
+ * solver, 1,024 threads per system). Either pointer may be NULL. */
+ctm_status ctm_plan_grid_shape(const ctm_plan* plan, int g, int* waves, int* per_lane);
+
+/* Give grid g the on-chip launch shape (waves, per_lane). Rejects a shape
+ * that is not one of the solver's ({1,2,4,8,16} x {4,8}), one whose lanes
+ * cannot hold the grid's lines (every line of n_s unknowns needs
+ * 2^ceil(log2(ceil(n_s / per_lane))) <= 64 lanes of one wave), and grids on
+ * the streaming solver. Results do not depend on the shape beyond rounding;
+ * the next solve uses it. */
+ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lane);
+
+typedef struct {
+  int classes;       /* anisotropy classes with more than one candidate shape */
+  int trials;        /* timed trial solves run */
+  int changed;       /* classes whose shape differs from the plan's default */
+  double ms_default; /* trial time with the shapes the plan started with */
+  double ms_tuned;   /* trial time with the chosen shapes */
+  double tune_ms;    /* wall time of the whole tuning */
+} ctm_tune_report;
+
+/* Autotuner of the launch shapes. The on-chip grids fall into anisotropy
+ * classes: equal stiff-axis line length and number of lines, hence the same
+ * candidate shapes (per_lane 4 or 8, each with the fewest waves that hold
+ * the lines). For each class with two candidates, in decreasing order of
+ * its unknowns, the other candidate is tried and kept when it shortens the
+ * trial by more than 2%. A trial is ctm_solve from the problem's initial
+ * value, capped at trial_iterations MGRIT iterations per block when
+ * trial_iterations > 0 (0 = run to convergence); each configuration runs
+ * `repeats` >= 1 times and its fastest run counts. ws (ctm_plan_workspace_bytes)
+ * and u_scratch (a packed vector) are overwritten. Synchronous on s; the
+ * chosen shapes stay with the plan (ctm_plan_grid_shape); statistics are
+ * those of the last trial. report may be NULL. Errors of a trial solve
+ * other than CTM_ERR_NOCONV end the tuning with the default shapes. */
+ctm_status ctm_autotune(ctm_plan* plan, void* ws, size_t ws_bytes, double* u_scratch,
+                        int trial_iterations, int repeats, ctm_tune_report* report,
+                        ctm_stream s);
+
 /* Enable (on != 0) or disable timing of the implicit-step kernel: every
  * launch made by ctm_solve / ctm_propagate is then bracketed by two HIP
  * events on the caller's stream and ctm_get_stats reports the summed

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -334,27 +335,25 @@ int pick_shape(const std::vector<GridDev>& gds) {
   return -1;
 }
 
-// Size class of one grid: K = 4 while its lines fit a wave (fewer registers,
-// higher occupancy), else 8; then the fewest waves that hold it. The
-// environment variable CTM_SHAPE forces one shape for every grid it fits.
+// Shape with K unknowns per lane and the fewest waves that hold the lines
+// of grid gd, or -1.
+int min_waves_shape(const GridDev& gd, int K) {
+  if (gd.ns > 64 * K) return -1;
+  for (int s = 0; s < kNumShapes; ++s)
+    if (kShapes[s].K == K && lanes_needed(gd, K) <= 64 * kShapes[s].W) return s;
+  return -1;
+}
+
+// Default size class of one grid: K = 4 while its lines fit a wave (fewer
+// registers, higher occupancy) and it needs at most 256 lanes, else 8; then
+// the fewest waves that hold it. ctm_autotune revises it per anisotropy class.
 int grid_shape(const GridDev& gd) {
-  const char* env = std::getenv("CTM_SHAPE");
-  if (env) {
-    const int s = std::atoi(env);
-    if (s >= 0 && s < kNumShapes &&
-        lanes_needed(gd, kShapes[s].K) <= 64 * kShapes[s].W && gd.ns <= 64 * kShapes[s].K)
-      return s;
+  const int s4 = min_waves_shape(gd, 4);
+  if (s4 >= 0 && lanes_needed(gd, 4) > 256) {
+    const int s8 = min_waves_shape(gd, 8);
+    if (s8 >= 0) return s8;
   }
-  // lanes above which a grid moves to K = 8 (fewer, fuller waves)
-  int k8_lanes = 256;
-  if (const char* e2 = std::getenv("CTM_K8_LANES")) k8_lanes = std::atoi(e2);
-  std::vector<GridDev> one{gd};
-  const int s4 = pick_shape(one);
-  if (s4 >= 0 && kShapes[s4].K == 4 && lanes_needed(gd, 4) > k8_lanes && gd.ns <= 512) {
-    for (int s = 0; s < kNumShapes; ++s)
-      if (kShapes[s].K == 8 && lanes_needed(gd, 8) <= 64 * kShapes[s].W) return s;
-  }
-  return s4;
+  return s4 >= 0 ? s4 : min_waves_shape(gd, 8);
 }
 
 ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
@@ -383,6 +382,14 @@ ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
   P->tsets[M] = ts;
   *out = &P->tsets[M];
   return CTM_OK;
+}
+
+// Move grid g to size class sh; the cached task lists are rebuilt on next use.
+void set_shape(ctm_plan* P, int g, int sh) {
+  if (P->gshape[g] == sh) return;
+  P->gshape[g] = sh;
+  for (auto& kv : P->tsets) hipFree(kv.second.d);
+  P->tsets.clear();
 }
 
 ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) {
@@ -1414,6 +1421,116 @@ ctm_status ctm_hierarchize(ctm_plan* P, const double* in, double* out, int inver
 ctm_status ctm_recombine(ctm_plan* P, const double* u, double* out, ctm_stream s) {
   if (!P || !u || !out) return fail(CTM_ERR_INVALID, "NULL argument");
   return recombine(P, u, out, (hipStream_t)s);
+}
+
+ctm_status ctm_plan_grid_shape(const ctm_plan* P, int g, int* waves, int* per_lane) {
+  if (!P) return fail(CTM_ERR_INVALID, "plan is NULL");
+  if (g < 0 || g >= P->G) return fail(CTM_ERR_INVALID, "grid index out of range");
+  const int sh = P->gshape[g];
+  if (waves) *waves = (sh == kStreamShape) ? 16 : kShapes[sh].W;
+  if (per_lane) *per_lane = (sh == kStreamShape) ? 0 : kShapes[sh].K;
+  return CTM_OK;
+}
+
+ctm_status ctm_plan_set_grid_shape(ctm_plan* P, int g, int waves, int per_lane) {
+  if (!P) return fail(CTM_ERR_INVALID, "plan is NULL");
+  if (g < 0 || g >= P->G) return fail(CTM_ERR_INVALID, "grid index out of range");
+  if (P->gshape[g] == kStreamShape)
+    return fail(CTM_ERR_INVALID, "the grid is on the streaming solver");
+  int sh = -1;
+  for (int s2 = 0; s2 < kNumShapes; ++s2)
+    if (kShapes[s2].W == waves && kShapes[s2].K == per_lane) sh = s2;
+  if (sh < 0) return fail(CTM_ERR_INVALID, "no such launch shape");
+  const GridDev& gd = P->hdev[g];
+  if (gd.ns > 64 * per_lane || lanes_needed(gd, per_lane) > 64 * waves)
+    return fail(CTM_ERR_INVALID, "the launch shape cannot hold the grid's lines");
+  set_shape(P, g, sh);
+  return CTM_OK;
+}
+
+ctm_status ctm_autotune(ctm_plan* P, void* ws, size_t ws_bytes, double* u_scratch,
+                        int trial_iterations, int repeats, ctm_tune_report* report,
+                        ctm_stream s) {
+  if (!P || !ws || !u_scratch) return fail(CTM_ERR_INVALID, "NULL argument");
+  if (repeats < 1 || trial_iterations < 0)
+    return fail(CTM_ERR_INVALID, "repeats must be >= 1 and trial_iterations >= 0");
+  using clock = std::chrono::steady_clock;
+  const auto t_start = clock::now();
+  hipStream_t hs = (hipStream_t)s;
+  // anisotropy classes: grids with equal line length and line count
+  struct TuneClass {
+    std::vector<int> grids;
+    double points = 0.0;
+    int cand[2] = {-1, -1};
+  };
+  std::map<std::pair<int, int>, TuneClass> by_key;
+  for (int g = 0; g < P->G; ++g) {
+    if (P->gshape[g] == kStreamShape) continue;
+    const GridDev& gd = P->hdev[g];
+    TuneClass& tc = by_key[{gd.ns, gd.nlines}];
+    tc.grids.push_back(g);
+    tc.points += (double)gd.npts;
+    tc.cand[0] = min_waves_shape(gd, 4);
+    tc.cand[1] = min_waves_shape(gd, 8);
+  }
+  std::vector<TuneClass> classes;
+  for (auto& kv : by_key)
+    if (kv.second.cand[0] >= 0 && kv.second.cand[1] >= 0) classes.push_back(kv.second);
+  std::stable_sort(classes.begin(), classes.end(),
+                   [](const TuneClass& a, const TuneClass& b) { return a.points > b.points; });
+  const std::vector<int> initial = P->gshape;
+  const bool timing = P->timing;
+  const int maxit = P->prob.mgrit_maxit;
+  P->timing = false;
+  if (trial_iterations > 0 && P->prob.mgrit_levels > 1)
+    P->prob.mgrit_maxit = std::min(maxit, trial_iterations);
+  ctm_tune_report rep{};
+  rep.classes = (int)classes.size();
+  // fastest of `repeats` trial solves with the current shapes
+  auto trial = [&](double* best) -> ctm_status {
+    *best = 1e300;
+    for (int r = 0; r < repeats; ++r) {
+      if (hipStreamSynchronize(hs) != hipSuccess)
+        return fail(CTM_ERR_HIP, "hipStreamSynchronize failed");
+      const auto t0 = clock::now();
+      ctm_status st = ctm_solve(P, ws, ws_bytes, nullptr, u_scratch, s);
+      if (hipStreamSynchronize(hs) != hipSuccess)
+        return fail(CTM_ERR_HIP, "hipStreamSynchronize failed");
+      const double ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
+      rep.trials += 1;
+      if (st != CTM_OK && st != CTM_ERR_NOCONV) return st;
+      *best = std::min(*best, ms);
+    }
+    return CTM_OK;
+  };
+  double cur = 0.0;
+  ctm_status st = trial(&cur);
+  rep.ms_default = cur;
+  for (size_t i = 0; st == CTM_OK && i < classes.size(); ++i) {
+    const TuneClass& tc = classes[i];
+    const int now = P->gshape[tc.grids[0]];
+    const int alt = (now == tc.cand[0]) ? tc.cand[1] : tc.cand[0];
+    for (int g : tc.grids) set_shape(P, g, alt);
+    double t = 0.0;
+    st = trial(&t);
+    if (st == CTM_OK && t < 0.98 * cur) {
+      cur = t;
+    } else {
+      for (int g : tc.grids) set_shape(P, g, now);
+    }
+  }
+  P->timing = timing;
+  P->prob.mgrit_maxit = maxit;
+  if (st != CTM_OK) {
+    for (int g = 0; g < P->G; ++g) set_shape(P, g, initial[g]);
+    return st;
+  }
+  rep.ms_tuned = cur;
+  for (const TuneClass& tc : classes)
+    if (P->gshape[tc.grids[0]] != initial[tc.grids[0]]) rep.changed += 1;
+  rep.tune_ms = std::chrono::duration<double, std::milli>(clock::now() - t_start).count();
+  if (report) *report = rep;
+  return CTM_OK;
 }
 
 ctm_status ctm_set_timing(ctm_plan* P, int on) {

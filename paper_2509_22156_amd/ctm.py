@@ -63,6 +63,12 @@ class Stats(ctypes.Structure):
     ]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("classes", ctypes.c_int), ("trials", ctypes.c_int), ("changed", ctypes.c_int),
+                ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double),
+                ("tune_ms", ctypes.c_double)]
+
+
 class CtmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"ctm status {status}: {msg}")
@@ -94,6 +100,9 @@ def _load():
         "ctm_recombine": [P, P, P, P],
         "ctm_get_stats": [P, ctypes.POINTER(Stats)],
         "ctm_set_timing": [P, i],
+        "ctm_plan_grid_shape": [P, i, ctypes.POINTER(i), ctypes.POINTER(i)],
+        "ctm_plan_set_grid_shape": [P, i, i, i],
+        "ctm_autotune": [P, P, sz, P, i, i, ctypes.POINTER(TuneReport), P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -292,6 +301,26 @@ class Plan:
                                  bytes=st.shape_bytes[i])
                             for i in range(16) if st.shape_launches[i] or st.shape_work[i]])
 
+    def grid_shape(self, g: int):
+        """(waves per work-group, unknowns per lane) of grid g; (16, 0) for
+        the streaming solver."""
+        w, k = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.ctm_plan_grid_shape(self._h, g, ctypes.byref(w), ctypes.byref(k)))
+        return w.value, k.value
+
+    def set_grid_shape(self, g: int, waves: int, per_lane: int):
+        _check(_lib.ctm_plan_set_grid_shape(self._h, g, waves, per_lane))
+
+    def autotune(self, trial_iterations: int = 0, repeats: int = 2) -> dict:
+        """Choose the launch shape of every anisotropy class by timed trial
+        solves (ctm_autotune); returns its report."""
+        ws = self.workspace()
+        u = self._vec()
+        rep = TuneReport()
+        _check(_lib.ctm_autotune(self._h, _ptr(ws), ws.numel(), _ptr(u), trial_iterations,
+                                 repeats, ctypes.byref(rep), _stream()))
+        return {k: getattr(rep, k) for k, _ in TuneReport._fields_}
+
     def set_timing(self, on: bool = True):
         _check(_lib.ctm_set_timing(self._h, int(on)))
 
@@ -301,5 +330,6 @@ def exported_symbols():
     return ["ctm_problem_defaults", "ctm_plan_create", "ctm_plan_destroy", "ctm_plan_grids",
             "ctm_plan_grid_info", "ctm_plan_state_len", "ctm_plan_workspace_bytes",
             "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_gather",
-            "ctm_combine_project", "ctm_hierarchize", "ctm_recombine", "ctm_get_stats", "ctm_set_timing", "ctm_status_string",
+            "ctm_combine_project", "ctm_hierarchize", "ctm_recombine", "ctm_get_stats", "ctm_set_timing", "ctm_plan_grid_shape",
+            "ctm_plan_set_grid_shape", "ctm_autotune", "ctm_status_string",
             "ctm_last_error"]

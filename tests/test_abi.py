@@ -44,6 +44,7 @@ def test_problem_struct_layout_matches_c(tmp_path):
 int main(void) {{
   printf("size %zu\\n", sizeof(ctm_problem));
   printf("stats %zu\\n", sizeof(ctm_stats));
+  printf("tune %zu\\n", sizeof(ctm_tune_report));
 {body}
   return 0;
 }}
@@ -55,6 +56,7 @@ int main(void) {{
                                                         text=True, check=True).stdout.splitlines())
     assert int(out["size"]) == ctypes.sizeof(ctm.Problem)
     assert int(out["stats"]) == ctypes.sizeof(ctm.Stats)
+    assert int(out["tune"]) == ctypes.sizeof(ctm.TuneReport)
     for f in fields:
         assert int(out[f]) == getattr(ctm.Problem, f).offset, f
 
@@ -112,3 +114,13 @@ def test_lines_beyond_streaming_limit_rejected():
     assert ctm.lib().ctm_plan_create(ctypes.byref(s), ctypes.byref(h)) == ctm.ERR_INVALID
     assert "longer than 1024" in ctm.lib().ctm_last_error().decode()
     assert not h.value
+
+
+def test_shape_entry_points_reject_null_plan():
+    lib = ctm.lib()
+    w, k = ctypes.c_int(), ctypes.c_int()
+    assert lib.ctm_plan_grid_shape(None, 0, ctypes.byref(w), ctypes.byref(k)) == 1
+    assert lib.ctm_plan_set_grid_shape(None, 0, 1, 4) == 1
+    rep = ctm.TuneReport()
+    assert lib.ctm_autotune(None, None, 0, None, 0, 1, ctypes.byref(rep), None) == 1
+    assert "NULL" in lib.ctm_last_error().decode()
