@@ -82,6 +82,52 @@ def cpu_oracle(prob, pts):
     return time.perf_counter() - t0, solve.packed(states), vals
 
 
+def _oracle_grids(prob, sel):
+    from oracle import solve
+    return sel, solve.component_states(prob, sel)
+
+
+def _oracle_combine(prob, states, pts):
+    from oracle import combine, solve
+    return combine.combine_at(prob, solve.grid_list(prob), states, pts)
+
+
+def _oracle_warm(_):
+    from oracle import solve  # noqa: F401  (imports paid before the clock starts)
+    return os.getpid()
+
+
+def cpu_oracle_parallel(prob, pts, workers):
+    """The same oracle spread over `workers` host processes: the grids
+    (longest-first by unknowns), then the points of the combination. Started
+    before the process touches the GPU; the worker start-up is outside the
+    clock."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    from oracle import solve
+    gl = solve.grid_list(prob)
+    sizes = np.diff(solve.offsets(prob))
+    bins = [[] for _ in range(workers)]
+    load = [0] * workers
+    for g in sorted(range(len(gl)), key=lambda g: -sizes[g]):
+        b = load.index(min(load))
+        bins[b].append(g)
+        load[b] += int(sizes[g])
+    bins = [b for b in bins if b]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_oracle_warm, range(4 * workers)))
+        t0 = time.perf_counter()
+        states = [None] * len(gl)
+        for sel, st in ex.map(_oracle_grids, [prob] * len(bins), bins):
+            for g, u in zip(sel, st):
+                states[g] = u
+        chunks = np.array_split(pts, workers)
+        vals = np.concatenate(list(ex.map(_oracle_combine, [prob] * workers,
+                                          [states] * workers, chunks)))
+        t = time.perf_counter() - t0
+    return t, max(len(bins), workers), solve.packed(states), vals
+
+
 # (d, n) cases of the manufactured heat family: two sparse-grid levels per d
 MMS_CASES = [(2, 7), (2, 9), (3, 7), (3, 9), (4, 6), (4, 8), (5, 6), (5, 8), (6, 5), (6, 7)]
 
@@ -146,14 +192,25 @@ def main(argv=None):
               "(per-GPU sharding by component grid is described in DESIGN.md)", file=sys.stderr)
         return 2
 
+    from workloads import targets
+    par = None
+    if not args.mms_sweep:
+        prob = workload_problem(args.workload, "mixed")
+        if not args.no_cpu:
+            # the parallel oracle runs first: its worker processes start
+            # before this process loads the HIP library or touches the GPU
+            workers = max(1, min(16, os.cpu_count() or 1))
+            log(f"cpu baseline: oracle over {workers} host processes")
+            par = cpu_oracle_parallel(prob, targets(prob, GATHER_POINTS, seed=0), workers)
+            log(f"parallel oracle {par[0]:.2f} s on {par[1]} processes")
+
     import torch
     from paper_2509_22156_amd import ctm
-    from workloads import targets
 
-    torch.cuda.set_device(0)
     if args.mms_sweep:
+        torch.cuda.set_device(0)
         return mms_sweep(ctm, torch)
-    prob = workload_problem(args.workload, "mixed")
+    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     plan = ctm.Plan(prob)
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -278,6 +335,16 @@ def main(argv=None):
                       f"+ combination at {GATHER_POINTS} points; {t_cpu:.2f} s",
             "cpu": _cpu_model(),
         }
+        if par is not None:
+            result["cpu_baseline_parallel"] = {
+                "value": dof_steps / par[0],
+                "unit": "DoF*timesteps/s",
+                "cores": par[1],
+                "kind": "oracle",
+                "sample": f"whole workload over {par[1]} host processes: grids longest-first, "
+                          f"then the {GATHER_POINTS} combination points; {par[0]:.2f} s",
+            }
+            assert _rel(par[2], oracle_u) == 0.0
         result["err_vs_oracle"] = {
             "mixed_state_rel_l2": _rel(u_mixed, oracle_u),
             "mixed_gather_rel_l2": _rel(vals_mixed, oracle_vals),

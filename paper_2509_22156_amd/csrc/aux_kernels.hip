@@ -410,8 +410,8 @@ hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, doub
 __global__ void __launch_bounds__(256)
     residual_max_kernel(const int2* __restrict__ tasks, int ntasks,
                         const double* __restrict__ res2, const double* __restrict__ norm2,
-                        double* __restrict__ mg, int it, double tol,
-                        const int* __restrict__ status) {
+                        double* __restrict__ mg, double* __restrict__ host_mg, int it,
+                        double tol, const int* __restrict__ status) {
   __shared__ double part[256];
   double m = 0.0;
   for (int t = threadIdx.x; t < ntasks; t += 256) {
@@ -436,14 +436,18 @@ __global__ void __launch_bounds__(256)
       if (res <= tol || nonfinite) mg[0] = (double)it;
     }
     mg[2 * it + 1] = mg[0];
+    if (host_mg) {  // pinned host mirror, read by the host after this iteration's event
+      host_mg[2 * it] = mg[2 * it];
+      host_mg[2 * it + 1] = mg[2 * it + 1];
+    }
   }
 }
 
 hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
-                               const double* norm2, double* mg, int it, double tol,
-                               const int* status, hipStream_t s) {
+                               const double* norm2, double* mg, double* host_mg, int it,
+                               double tol, const int* status, hipStream_t s) {
   hipLaunchKernelGGL(residual_max_kernel, dim3(1), dim3(256), 0, s, tasks, ntasks, res2, norm2,
-                     mg, it, tol, status);
+                     mg, host_mg, it, tol, status);
   return hipGetLastError();
 }
 
@@ -464,6 +468,28 @@ hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long sl
   if (nvec <= 0 || slen <= 0) return hipSuccess;
   hipLaunchKernelGGL(vec_add_kernel, dim3((unsigned)((slen + 255) / 256), nvec), dim3(256), 0, s,
                      dst, x, y, slen, skip);
+  return hipGetLastError();
+}
+
+__global__ void class_vec_add_kernel(const int2* __restrict__ tasks,
+                                     const GridDev* __restrict__ grids, VecRef dst, VecRef x,
+                                     VecRef y, long long slen, const double* skip) {
+  if (skip && *skip != 0.0) return;
+  const GridDev& g = grids[tasks[blockIdx.x].x];
+  const long long q = blockIdx.y;
+  const long long base = g.off;
+  double* d = dst.base + (dst.a * q + dst.b) * slen + base;
+  const double* xs = x.base + (x.a * q + x.b) * slen + base;
+  const double* ys = y.base ? y.base + (y.a * q + y.b) * slen + base : nullptr;
+  for (int e = threadIdx.x; e < g.npts; e += blockDim.x) d[e] = xs[e] + (ys ? ys[e] : 0.0);
+}
+
+hipError_t launch_class_vec_add(const int2* tasks, int ntasks, const GridDev* grids, VecRef dst,
+                                VecRef x, VecRef y, int nvec, long long slen, hipStream_t s,
+                                const double* skip) {
+  if (ntasks <= 0 || nvec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(class_vec_add_kernel, dim3((unsigned)ntasks, (unsigned)nvec), dim3(256), 0,
+                     s, tasks, grids, dst, x, y, slen, skip);
   return hipGetLastError();
 }
 

@@ -116,6 +116,10 @@ struct ctm_plan {
   // make four, the number of hardware queues HIP gives a process by default
   static constexpr int kSideStreams = 3;
   hipStream_t cstreams[kSideStreams] = {};
+  // lane of each size class: 0 = the caller's stream, l > 0 = cstreams[l - 1].
+  // Fixed per plan, so that consecutive phases of one class need no
+  // cross-stream synchronisation.
+  int lane_of[kNumShapes + 1] = {};
   // hierarchical basis (built on first use): node id of every unknown; per
   // node, the unknowns of all grids that share its basis function
   double block_t0 = 0.0;     // start time of the recombination block being solved
@@ -128,7 +132,8 @@ struct ctm_plan {
   // it; hmg its pinned per-iteration mirror; skip = dmg while a block's
   // iterations are queued (launches past the stopping iteration do nothing)
   double* dmg = nullptr;
-  double* hmg = nullptr;
+  double* hmg = nullptr;      // mapped pinned memory: written by the convergence kernel
+  double* hmg_dev = nullptr;  // its device address
   const double* skip = nullptr;
   std::vector<hipEvent_t> it_events;
   int hnodes = 0;
@@ -384,12 +389,32 @@ ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
   return CTM_OK;
 }
 
+// Lanes of the size classes: in decreasing order of unknowns, each class
+// onto the lane (caller's stream or a side stream) with the fewest so far.
+void assign_lanes(ctm_plan* P) {
+  constexpr int nlanes = ctm_plan::kSideStreams + 1;
+  double pts[kNumShapes + 1] = {};
+  for (int g = 0; g < P->G; ++g) pts[P->gshape[g]] += (double)P->grids[g].npts;
+  int order[kNumShapes + 1];
+  for (int i = 0; i <= kNumShapes; ++i) order[i] = i;
+  std::stable_sort(order, order + kNumShapes + 1, [&](int x, int y) { return pts[x] > pts[y]; });
+  double load[nlanes] = {};
+  for (int i : order) {
+    int best = 0;
+    for (int l = 1; l < nlanes; ++l)
+      if (load[l] < load[best]) best = l;
+    P->lane_of[i] = best;
+    load[best] += pts[i];
+  }
+}
+
 // Move grid g to size class sh; the cached task lists are rebuilt on next use.
 void set_shape(ctm_plan* P, int g, int sh) {
   if (P->gshape[g] == sh) return;
   P->gshape[g] = sh;
   for (auto& kv : P->tsets) hipFree(kv.second.d);
   P->tsets.clear();
+  assign_lanes(P);
 }
 
 ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) {
@@ -500,59 +525,72 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   return CTM_OK;
 }
 
-// Launch a phase: one kernel per size class; with several classes they run
-// concurrently on the plan's class streams, forked from and joined back
-// into the caller's stream.
+// Stream of lane l: the caller's stream s for l = 0 (may be the null
+// stream), else side stream l - 1, created on first use.
+ctm_status lane_stream(ctm_plan* P, int l, hipStream_t s, hipStream_t* out) {
+  if (l > 0 && !P->cstreams[l - 1])
+    CTM_HIP(hipStreamCreateWithFlags(&P->cstreams[l - 1], hipStreamNonBlocking));
+  *out = (l == 0) ? s : P->cstreams[l - 1];
+  return CTM_OK;
+}
+
+// Make stream s wait for all work queued on the side streams.
+ctm_status join_lanes(ctm_plan* P, hipStream_t s) {
+  size_t used = 0;
+  for (int l = 1; l <= ctm_plan::kSideStreams; ++l) {
+    if (!P->cstreams[l - 1]) continue;
+    hipEvent_t j = take_event(P, used, P->sync_events, false);
+    if (!j) return fail(CTM_ERR_HIP, "event creation failed");
+    CTM_HIP(hipEventRecord(j, P->cstreams[l - 1]));
+    CTM_HIP(hipStreamWaitEvent(s, j, 0));
+  }
+  return CTM_OK;
+}
+
+// Launch a phase: one kernel per size class, each on its class's lane (the
+// caller's stream or a side stream), so that the classes run concurrently.
+// fork: the side streams first wait for the work queued on s; without it
+// they continue from their own previous phase (valid when every task of the
+// phase reads only what its own class wrote before, or what was joined and
+// forked earlier). join: s then waits for the side streams.
 ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStream_t s,
-                     bool fp64_only = false) {
+                     bool fp64_only = false, bool fork = true, bool join = true) {
   const bool mixed = P->mixed && !fp64_only;
   // algorithmic bytes: every vector of every task once
   const double per_grid_sets = (double)ts.total / (double)P->G;
   P->stats.chain_bytes += 8.0 * (double)P->slen * per_grid_sets * chain_vectors_per_task(a);
-  if (ts.ranges.size() == 1) {
-    const auto& r = ts.ranges[0];
-    return launch_range(P, a, ts.d, r.shape, r.offset, r.count, r.points, s, mixed);
-  }
-  // classes in decreasing order of work (unknowns x tasks), each onto the
-  // lane (caller's stream or a side stream) with the least work so far
   constexpr int nlanes = ctm_plan::kSideStreams + 1;
+  // launch order: decreasing work (unknowns x tasks)
   std::vector<int> order(ts.ranges.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return ts.ranges[x].points > ts.ranges[y].points;
   });
-  double load[nlanes] = {};
-  int lane_of[kNumShapes + 1];
-  for (int i : order) {
-    int best = 0;
-    for (int l = 1; l < nlanes; ++l)
-      if (load[l] < load[best]) best = l;
-    lane_of[i] = best;
-    load[best] += ts.ranges[i].points;
-  }
   size_t used = 0;
-  hipEvent_t fork = take_event(P, used, P->sync_events, false);
-  if (!fork) return fail(CTM_ERR_HIP, "event creation failed");
-  CTM_HIP(hipEventRecord(fork, s));
-  bool forked[nlanes] = {};
+  // the fork point is recorded before anything of this phase is queued on s
+  hipEvent_t fork_ev = nullptr;
+  bool side = false;
+  for (const auto& r : ts.ranges) side |= (P->lane_of[r.shape] > 0);
+  if (fork && side) {
+    fork_ev = take_event(P, used, P->sync_events, false);
+    if (!fork_ev) return fail(CTM_ERR_HIP, "event creation failed");
+    CTM_HIP(hipEventRecord(fork_ev, s));
+  }
+  bool used_lane[nlanes] = {};
   for (int i : order) {
     const auto& r = ts.ranges[i];
-    const int l = lane_of[i];
-    hipStream_t cs = s;
-    if (l > 0) {
-      if (!P->cstreams[l - 1])
-        CTM_HIP(hipStreamCreateWithFlags(&P->cstreams[l - 1], hipStreamNonBlocking));
-      cs = P->cstreams[l - 1];
-      if (!forked[l]) {
-        CTM_HIP(hipStreamWaitEvent(cs, fork, 0));
-        forked[l] = true;
-      }
-    }
-    ctm_status st = launch_range(P, a, ts.d, r.shape, r.offset, r.count, r.points, cs, mixed);
+    const int l = P->lane_of[r.shape];
+    hipStream_t cs = nullptr;
+    ctm_status st = lane_stream(P, l, s, &cs);
+    if (st != CTM_OK) return st;
+    if (l > 0 && fork && !used_lane[l]) CTM_HIP(hipStreamWaitEvent(cs, fork_ev, 0));
+    used_lane[l] = true;
+    st = launch_range(P, a, ts.d, r.shape, r.offset, r.count, r.points, cs, mixed);
     if (st != CTM_OK) return st;
   }
+  if (!join) return CTM_OK;
   for (int l = 1; l < nlanes; ++l) {
-    if (!forked[l]) continue;
+    if (!used_lane[l]) continue;
     hipEvent_t j = take_event(P, used, P->sync_events, false);
     if (!j) return fail(CTM_ERR_HIP, "event creation failed");
     CTM_HIP(hipEventRecord(j, P->cstreams[l - 1]));
@@ -697,7 +735,11 @@ Layout make_layout(const ctm_plan* P, char* base) {
 
 // One cycle on level l >= 1 for e_0 = g_0, e_n = Phi_l e_{n-1} + g_n from a
 // zero initial guess; writes all points of E[l].
-ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
+// One MGRIT cycle on level l >= 1 for the residual equation. On the last
+// level, e_m for m >= 1 is written and e_0 (= 0, cleared once per block) is
+// left alone; with open_last the coarse chain is not joined back into s
+// (its readers run on the same lanes).
+ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last = false) {
   const long long c = lay.c;
   double* G = lay.R[l];
   double* E = lay.E[l];
@@ -708,10 +750,9 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s) {
     a.forcing = vref(G, 0, 0);
     a.inter = vref(E, 0, 0);
     a.fin = vref(E, 0, lay.N[l]);
-    CTM_HIP(launch_fill_zero(E, P->slen, s, P->skip));  // e_0 = g_0 = 0
     TaskSet* single = nullptr;
     if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
-    return run_chain(P, a, *single, s);
+    return run_chain(P, a, *single, s, false, true, !open_last);
   }
   const long long M = lay.N[l] / c;
   TaskSet* tasks = nullptr;
@@ -833,6 +874,22 @@ ctm_status recombine(ctm_plan* P, const double* u, double* out, hipStream_t s) {
 }
 
 // MGRIT on one block: X (start) -> Y (state at the block end).
+// Level-0 correction of a two-level FCF iteration, per size class on the
+// class's lane (after its coarse chain): U[m] = Un[m] + E[m], m = 1..M0.
+ctm_status correct_by_class(ctm_plan* P, double* U, double* Un, double* E, long long M0,
+                            hipStream_t s) {
+  TaskSet* single = nullptr;
+  ctm_status st = tasks_for(P, 1, &single);
+  if (st != CTM_OK) return st;
+  for (const auto& r : single->ranges) {
+    hipStream_t cs = nullptr;
+    if ((st = lane_stream(P, P->lane_of[r.shape], s, &cs)) != CTM_OK) return st;
+    CTM_HIP(launch_class_vec_add(single->d + r.offset, (int)r.count, P->dgrids, vref(U, 1, 1),
+                                 vref(Un, 1, 1), vref(E, 1, 1), (int)M0, P->slen, cs, P->skip));
+  }
+  return CTM_OK;
+}
+
 ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   const ctm_problem& p = P->prob;
   ctm_status st;
@@ -855,6 +912,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
                          P->slen, s));
   if (fcf) CTM_HIP(hipMemcpyAsync(lay.Un, lay.X, P->slen * sizeof(double), hipMemcpyDeviceToDevice, s));
   CTM_HIP(launch_fill_zero(lay.R[1], P->slen, s));
+  CTM_HIP(launch_fill_zero(lay.E[lay.L - 1], P->slen, s));  // e_0 = 0 on the last level
   CTM_HIP(launch_grid_norms2(P->dgrids, P->G, lay.X, P->dnorm2, s));
   double* U = lay.U;
   double* Un = lay.Un;
@@ -921,6 +979,15 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     return CTM_OK;
   };
   int seen = 0;  // iterations observed so far
+  // FCF: the C-relaxation writes the C-points to Un, and the level-0
+  // correction writes u_cm + e_m to U (out of place), from which the next
+  // FC-relaxation starts; Un keeps each iteration's C-points as its
+  // relaxation left them. With two levels the correction runs per size
+  // class, so the FC-, F- and coarse phases and the correction of one class
+  // read only what the same class wrote before and follow each other on its
+  // lane without cross-stream synchronisation; only the convergence test
+  // joins all lanes.
+  bool open = false;  // side streams hold work not yet joined into s
   for (int it = 1; it <= maxit; ++it) {
     // when the residuals seen so far predict that iteration it - 1 meets the
     // tolerance (geometric decrease), wait for its test before queueing more
@@ -945,7 +1012,8 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
           fc.guess_fin = vref(U, 1, 1);
         }
       }
-      if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
+      if ((st = run_chain(P, fc, *tasks, s, false, !open, false)) != CTM_OK) return st;
+      open = true;
       traj = (Tr != nullptr);
       C = Un;
     } else {
@@ -965,20 +1033,30 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
         fr.guess_fin = vref(C, 1, 1);
       }
     }
-    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s, false, !open, true)) != CTM_OK) return st;
+    open = false;
     traj = (Tr != nullptr);
-    CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, P->dmg, it, p.mgrit_tol,
-                                reinterpret_cast<const int*>(P->dsync + 1), s));
-    CTM_HIP(hipMemcpyAsync(P->hmg + 2 * it, P->dmg + 2 * it, 2 * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
+    CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, P->dmg, P->hmg_dev, it,
+                                p.mgrit_tol, reinterpret_cast<const int*>(P->dsync + 1), s));
     CTM_HIP(hipEventRecord(P->it_events[it], s));
     mark(it);
     queued = it;
     if (it < maxit) {
-      if ((st = cycle(P, lay, 1, s)) != CTM_OK) return st;
-      CTM_HIP(launch_vec_add(vref(C, 1, 0), vref(C, 1, 0), vref(lay.E[1], 1, 0), (int)(M0 + 1),
-                             P->slen, s, P->skip));
-      if (fcf) std::swap(U, Un);
+      if (fcf) {
+        const bool two = (lay.L == 2);
+        if ((st = cycle(P, lay, 1, s, two)) != CTM_OK) return st;
+        if (two) {
+          if ((st = correct_by_class(P, U, Un, lay.E[1], M0, s)) != CTM_OK) return st;
+          open = true;
+        } else {
+          CTM_HIP(launch_vec_add(vref(U, 1, 1), vref(Un, 1, 1), vref(lay.E[1], 1, 1), (int)M0,
+                                 P->slen, s, P->skip));
+        }
+      } else {
+        if ((st = cycle(P, lay, 1, s)) != CTM_OK) return st;
+        CTM_HIP(launch_vec_add(vref(C, 1, 0), vref(C, 1, 0), vref(lay.E[1], 1, 0),
+                               (int)(M0 + 1), P->slen, s, P->skip));
+      }
     }
     if (it >= 2 && seen < it - 1) {
       if ((st = observe(it - 1)) != CTM_OK) return st;
@@ -986,6 +1064,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     }
     if (stop) break;
   }
+  if (open && (st = join_lanes(P, s)) != CTM_OK) return st;
   if (!stop && seen < queued && (st = observe(queued)) != CTM_OK) return st;
   const int last = stop ? stop : queued;
   if (stop) rewind(stop);
@@ -1213,6 +1292,7 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     P->stream_ss = ((long long)maxstream + 63) / 64 * 64;
     P->stream_tasks = (long long)nstream * M;
   }
+  assign_lanes(P);
   if (P->htab.empty()) P->htab.push_back(0.0);
   P->order.resize(P->G);
   for (int g = 0; g < P->G; ++g) P->order[g] = g;
@@ -1256,7 +1336,10 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   {
     const size_t nmg = 2 * (size_t)(std::max(1, prob->mgrit_maxit) + 1);
     CTM_HIPC(hipMalloc(&P->dmg, nmg * sizeof(double)));
-    CTM_HIPC(hipHostMalloc(&P->hmg, nmg * sizeof(double), hipHostMallocDefault));
+    CTM_HIPC(hipHostMalloc(&P->hmg, nmg * sizeof(double),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(P->hmg, 0, nmg * sizeof(double));
+    CTM_HIPC(hipHostGetDevicePointer(reinterpret_cast<void**>(&P->hmg_dev), P->hmg, 0));
   }
   std::vector<int2> ident(P->G);
   for (int g = 0; g < P->G; ++g) ident[g] = make_int2(g, 0);

@@ -208,15 +208,21 @@ hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, doub
 // t of sqrt(res2[t] / norm2[grid(t)]) (norm2 = 0 -> 1). Unless mg[0] (the
 // stopping iteration, 0 while running) is set already, mg[2 it] = res and
 // mg[0] = it when res <= tol, res is not a number, or *status has the
-// non-finite bit. Always mg[2 it + 1] = mg[0].
+// non-finite bit. Always mg[2 it + 1] = mg[0]. host_mg (optional, mapped
+// pinned host memory) receives mg[2 it] and mg[2 it + 1] as well.
 hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
-                               const double* norm2, double* mg, int it, double tol,
-                               const int* status, hipStream_t s);
+                               const double* norm2, double* mg, double* host_mg, int it,
+                               double tol, const int* status, hipStream_t s);
 // dst[(ad q + bd) slen + e] = x[(ax q + bx) slen + e] (+ y[(ay q + by) slen + e]),
 // q = 0..nvec-1, e = 0..slen-1; y.base may be null.
 // skip (optional): the launch does nothing once *skip != 0.
 hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
                           hipStream_t s, const double* skip = nullptr);
+// The same restricted to the unknowns of the grids tasks[0..ntasks).x (one
+// size class): vectors q = 0..nvec-1, only the entries of those grids.
+hipError_t launch_class_vec_add(const int2* tasks, int ntasks, const GridDev* grids, VecRef dst,
+                                VecRef x, VecRef y, int nvec, long long slen, hipStream_t s,
+                                const double* skip);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s,
                             const double* skip = nullptr);
 

@@ -13,8 +13,8 @@ torch = pytest.importorskip("torch")
 from paper_2509_22156_amd import ctm  # noqa: E402
 from workloads import make, random_vectors  # noqa: E402
 
-from helpers import (combine, oracle_abs_apply, oracle_apply, oracle_propagate, rel_l2,  # noqa: E402
-                     solve, split)
+from helpers import (combine, oracle_abs_apply, oracle_apply, oracle_mgrit_history,  # noqa: E402
+                     oracle_propagate, rel_l2, solve, split)
 
 
 def _say(msg):
@@ -57,6 +57,22 @@ def test_streaming_solve_fp64(kw):
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
     assert rel_l2(u, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("relax", ["FCF", "F"])
+def test_streaming_mgrit_residual_history(relax):
+    # the first iterations' C-point residuals pin relaxation, restriction,
+    # coarse solve and correction on the streaming grids too
+    p = _heat2d_big(mgrit_maxit=3, mgrit_tol=1e-300, relax=relax)
+    _say(f"streaming mgrit history {relax}")
+    plan = ctm.Plan(p)
+    u, st_code = plan.solve(check=False)
+    assert st_code == ctm.ERR_NOCONV
+    hist = plan.stats()["mgrit_residual"]
+    ref = oracle_mgrit_history(p, 3)
+    assert len(hist) == 3
+    for a, b in zip(hist, ref):
+        assert abs(a - b) <= 1e-7 * b + 1e-13, (hist, ref)
 
 
 def test_streaming_solve_mixed():
