@@ -353,6 +353,9 @@ def main(argv=None):
 
     if not args.no_extras:
         result["comparators"] = _comparators(args, ctm, torch, oracle_u, dof_steps)
+        plain = result["comparators"]["fp64_per_grid_plain"]["seconds"]
+        # the whole timed step (solve + gather) against the plain schedule's solve
+        result["speedup_vs_plain_per_grid_fp64"] = plain / (ms_per_step / 1e3)
         result["streaming"] = _streaming(ctm, torch)
         log(f"streaming: {result['streaming']}")
     if args.copy_calibration:

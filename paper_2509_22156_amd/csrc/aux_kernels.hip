@@ -479,9 +479,10 @@ __global__ void class_vec_add_kernel(const int2* __restrict__ tasks,
   const long long q = blockIdx.y;
   const long long base = g.off;
   double* d = dst.base + (dst.a * q + dst.b) * slen + base;
-  const double* xs = x.base + (x.a * q + x.b) * slen + base;
+  const double* xs = x.base ? x.base + (x.a * q + x.b) * slen + base : nullptr;
   const double* ys = y.base ? y.base + (y.a * q + y.b) * slen + base : nullptr;
-  for (int e = threadIdx.x; e < g.npts; e += blockDim.x) d[e] = xs[e] + (ys ? ys[e] : 0.0);
+  for (int e = threadIdx.x; e < g.npts; e += blockDim.x)
+    d[e] = (xs ? xs[e] : 0.0) + (ys ? ys[e] : 0.0);
 }
 
 hipError_t launch_class_vec_add(const int2* tasks, int ntasks, const GridDev* grids, VecRef dst,

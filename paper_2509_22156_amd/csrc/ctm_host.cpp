@@ -735,40 +735,86 @@ Layout make_layout(const ctm_plan* P, char* base) {
 
 // One cycle on level l >= 1 for e_0 = g_0, e_n = Phi_l e_{n-1} + g_n from a
 // zero initial guess; writes all points of E[l].
+// dst = x + y (either may be null) on vectors q = 0..nvec-1, per size class
+// on the class's lane, restricted to the class's grids.
+ctm_status class_vec_add(ctm_plan* P, VecRef dst, VecRef x, VecRef y, long long nvec,
+                         hipStream_t s) {
+  TaskSet* single = nullptr;
+  ctm_status st = tasks_for(P, 1, &single);
+  if (st != CTM_OK) return st;
+  for (const auto& r : single->ranges) {
+    hipStream_t cs = nullptr;
+    if ((st = lane_stream(P, P->lane_of[r.shape], s, &cs)) != CTM_OK) return st;
+    CTM_HIP(launch_class_vec_add(single->d + r.offset, (int)r.count, P->dgrids, dst, x, y,
+                                 (int)nvec, P->slen, cs, P->skip));
+  }
+  return CTM_OK;
+}
+
+// Every side lane waits for the work queued on s so far.
+ctm_status fork_lanes(ctm_plan* P, hipStream_t s) {
+  size_t used = 0;
+  hipEvent_t ev = take_event(P, used, P->sync_events, false);
+  if (!ev) return fail(CTM_ERR_HIP, "event creation failed");
+  CTM_HIP(hipEventRecord(ev, s));
+  for (int l = 1; l <= ctm_plan::kSideStreams; ++l) {
+    hipStream_t cs = nullptr;
+    ctm_status st = lane_stream(P, l, s, &cs);
+    if (st != CTM_OK) return st;
+    CTM_HIP(hipStreamWaitEvent(cs, ev, 0));
+  }
+  return CTM_OK;
+}
+
 // One MGRIT cycle on level l >= 1 for the residual equation. On the last
 // level, e_m for m >= 1 is written and e_0 (= 0, cleared once per block) is
-// left alone; with open_last the coarse chain is not joined back into s
-// (its readers run on the same lanes).
-ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last = false) {
+// left alone. per_class: every step runs per size class on the class's lane
+// with no cross-stream synchronisation (each class's steps read only what
+// the same class wrote; the lanes must have been forked from s before);
+// otherwise every phase is forked from and joined back into s. The first
+// residual vector r_0 of every level is cleared once per block.
+ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool per_class) {
   const long long c = lay.c;
   double* G = lay.R[l];
   double* E = lay.E[l];
+  const bool sync = !per_class;
+  const VecRef none = vref(nullptr, 0, 0);
   ctm_status st;
   if (l == lay.L - 1) {
     ChainArgs a = coarse_args(P, l, (int)lay.N[l]);
-    a.start = vref(nullptr, 0, 0);
+    a.start = none;
     a.forcing = vref(G, 0, 0);
     a.inter = vref(E, 0, 0);
     a.fin = vref(E, 0, lay.N[l]);
     TaskSet* single = nullptr;
     if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
-    return run_chain(P, a, *single, s, false, true, !open_last);
+    return run_chain(P, a, *single, s, false, sync, sync);
   }
   const long long M = lay.N[l] / c;
   TaskSet* tasks = nullptr;
   if ((st = tasks_for(P, M, &tasks)) != CTM_OK) return st;
-  CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s, P->skip));
+  // the error starts from zero at this level's C-points (its F-points are
+  // written before they are read)
+  if (per_class) {
+    if ((st = class_vec_add(P, vref(E, c, 0), none, none, M, s)) != CTM_OK) return st;
+  } else {
+    CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s, P->skip));
+  }
   double* csrc;
   long long ca;
   if (P->prob.relax == CTM_RELAX_FCF) {
     double* Cn = lay.Cn[l];
-    CTM_HIP(launch_fill_zero(Cn, P->slen, s, P->skip));
+    if (per_class) {
+      if ((st = class_vec_add(P, vref(Cn, 0, 0), none, none, 1, s)) != CTM_OK) return st;
+    } else {
+      CTM_HIP(launch_fill_zero(Cn, P->slen, s, P->skip));
+    }
     ChainArgs fc = coarse_args(P, l, (int)c);
     fc.start = vref(E, c, 0);
     fc.forcing = vref(G, c, 0);
     fc.inter = vref(E, c, 0);
     fc.fin = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fc, *tasks, s, false, sync, sync)) != CTM_OK) return st;
     ChainArgs fr = coarse_args(P, l, (int)c);
     fr.start = vref(Cn, 1, 0);
     fr.start_wb = vref(E, c, 0);
@@ -776,7 +822,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last 
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s, false, sync, sync)) != CTM_OK) return st;
     csrc = Cn;
     ca = 1;
   } else {
@@ -786,21 +832,26 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last 
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(E, c, c);
-    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s, false, sync, sync)) != CTM_OK) return st;
     csrc = E;
     ca = c;
   }
-  CTM_HIP(launch_fill_zero(lay.R[l + 1], P->slen, s, P->skip));  // r_0 = 0
-  if ((st = cycle(P, lay, l + 1, s)) != CTM_OK) return st;
+  if ((st = cycle(P, lay, l + 1, s, per_class)) != CTM_OK) return st;
   // correction at the C-points, then F-relaxation (ideal interpolation)
-  CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0), (int)(M + 1),
-                         P->slen, s, P->skip));
+  if (per_class) {
+    if ((st = class_vec_add(P, vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0),
+                            M + 1, s)) != CTM_OK)
+      return st;
+  } else {
+    CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0),
+                           (int)(M + 1), P->slen, s, P->skip));
+  }
   ChainArgs fi = coarse_args(P, l, (int)(c - 1));
   fi.start = vref(E, c, 0);
   fi.forcing = vref(G, c, 0);
   fi.inter = vref(E, c, 0);
   fi.fin = vref(E, c, c - 1);
-  return run_chain(P, fi, *tasks, s);
+  return run_chain(P, fi, *tasks, s, false, sync, sync);
 }
 
 // Node map of the hierarchical basis: every unknown named by its node on
@@ -874,20 +925,11 @@ ctm_status recombine(ctm_plan* P, const double* u, double* out, hipStream_t s) {
 }
 
 // MGRIT on one block: X (start) -> Y (state at the block end).
-// Level-0 correction of a two-level FCF iteration, per size class on the
-// class's lane (after its coarse chain): U[m] = Un[m] + E[m], m = 1..M0.
+// Level-0 correction of an FCF iteration, per size class on the class's
+// lane (after its cycle): U[m] = Un[m] + E[m], m = 1..M0.
 ctm_status correct_by_class(ctm_plan* P, double* U, double* Un, double* E, long long M0,
                             hipStream_t s) {
-  TaskSet* single = nullptr;
-  ctm_status st = tasks_for(P, 1, &single);
-  if (st != CTM_OK) return st;
-  for (const auto& r : single->ranges) {
-    hipStream_t cs = nullptr;
-    if ((st = lane_stream(P, P->lane_of[r.shape], s, &cs)) != CTM_OK) return st;
-    CTM_HIP(launch_class_vec_add(single->d + r.offset, (int)r.count, P->dgrids, vref(U, 1, 1),
-                                 vref(Un, 1, 1), vref(E, 1, 1), (int)M0, P->slen, cs, P->skip));
-  }
-  return CTM_OK;
+  return class_vec_add(P, vref(U, 1, 1), vref(Un, 1, 1), vref(E, 1, 1), M0, s);
 }
 
 ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
@@ -911,7 +953,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   CTM_HIP(launch_vec_add(vref(lay.U, 1, 0), vref(lay.X, 0, 0), vref(nullptr, 0, 0), (int)(M0 + 1),
                          P->slen, s));
   if (fcf) CTM_HIP(hipMemcpyAsync(lay.Un, lay.X, P->slen * sizeof(double), hipMemcpyDeviceToDevice, s));
-  CTM_HIP(launch_fill_zero(lay.R[1], P->slen, s));
+  for (int l = 1; l < lay.L; ++l) CTM_HIP(launch_fill_zero(lay.R[l], P->slen, s));  // r_0 = 0
   CTM_HIP(launch_fill_zero(lay.E[lay.L - 1], P->slen, s));  // e_0 = 0 on the last level
   CTM_HIP(launch_grid_norms2(P->dgrids, P->G, lay.X, P->dnorm2, s));
   double* U = lay.U;
@@ -982,12 +1024,17 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   // FCF: the C-relaxation writes the C-points to Un, and the level-0
   // correction writes u_cm + e_m to U (out of place), from which the next
   // FC-relaxation starts; Un keeps each iteration's C-points as its
-  // relaxation left them. With two levels the correction runs per size
-  // class, so the FC-, F- and coarse phases and the correction of one class
-  // read only what the same class wrote before and follow each other on its
-  // lane without cross-stream synchronisation; only the convergence test
-  // joins all lanes.
+  // relaxation left them. Every phase of one class reads only what the same
+  // class wrote before, so with per_class the phases, the coarse cycle and
+  // the correction follow each other on the class's lane without
+  // cross-stream synchronisation; only the convergence test joins all lanes.
   bool open = false;  // side streams hold work not yet joined into s
+  // two levels: every phase per class without joins (measured faster on
+  // heat3d); three or more: each phase joined (measured faster on ou4d,
+  // where the slowest class's relaxation then has the machine to itself
+  // at the end of each phase instead of sharing it with the next phase of
+  // the other classes)
+  const bool per_class = (lay.L == 2);
   for (int it = 1; it <= maxit; ++it) {
     // when the residuals seen so far predict that iteration it - 1 meets the
     // tolerance (geometric decrease), wait for its test before queueing more
@@ -1012,8 +1059,8 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
           fc.guess_fin = vref(U, 1, 1);
         }
       }
-      if ((st = run_chain(P, fc, *tasks, s, false, !open, false)) != CTM_OK) return st;
-      open = true;
+      if ((st = run_chain(P, fc, *tasks, s, false, !open, !per_class)) != CTM_OK) return st;
+      open = per_class;
       traj = (Tr != nullptr);
       C = Un;
     } else {
@@ -1043,17 +1090,21 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     queued = it;
     if (it < maxit) {
       if (fcf) {
-        const bool two = (lay.L == 2);
-        if ((st = cycle(P, lay, 1, s, two)) != CTM_OK) return st;
-        if (two) {
+        if (per_class) {
+          // the lanes see the convergence test (its stop flag), then run the
+          // cycle and the correction class by class
+          if ((st = fork_lanes(P, s)) != CTM_OK) return st;
+          if ((st = cycle(P, lay, 1, s, true)) != CTM_OK) return st;
           if ((st = correct_by_class(P, U, Un, lay.E[1], M0, s)) != CTM_OK) return st;
           open = true;
         } else {
+          if ((st = cycle(P, lay, 1, s, false)) != CTM_OK) return st;
           CTM_HIP(launch_vec_add(vref(U, 1, 1), vref(Un, 1, 1), vref(lay.E[1], 1, 1), (int)M0,
                                  P->slen, s, P->skip));
+          open = false;
         }
       } else {
-        if ((st = cycle(P, lay, 1, s)) != CTM_OK) return st;
+        if ((st = cycle(P, lay, 1, s, false)) != CTM_OK) return st;
         CTM_HIP(launch_vec_add(vref(C, 1, 0), vref(C, 1, 0), vref(lay.E[1], 1, 0),
                                (int)(M0 + 1), P->slen, s, P->skip));
       }

@@ -219,7 +219,8 @@ hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2
 hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
                           hipStream_t s, const double* skip = nullptr);
 // The same restricted to the unknowns of the grids tasks[0..ntasks).x (one
-// size class): vectors q = 0..nvec-1, only the entries of those grids.
+// size class): vectors q = 0..nvec-1, only the entries of those grids; x.base
+// may be null as well (then dst = y, or zero).
 hipError_t launch_class_vec_add(const int2* tasks, int ntasks, const GridDev* grids, VecRef dst,
                                 VecRef x, VecRef y, int nvec, long long slen, hipStream_t s,
                                 const double* skip);
