@@ -168,10 +168,14 @@ ctm_status ctm_problem_defaults(ctm_problem* p);
 
 /* Validate *p, enumerate the component grids (Section 2.1.1, combination
  * formula), build per-grid geometry and coefficient tables and upload them
- * to the current device. Rejects: d outside 1..CTM_MAXD, n + d - 1 > 30,
- * no grid with l >= L0, N not divisible by s * c^(levels-1), nonpositive
- * tolerances, CG for a non-symmetric operator, a grid larger than the
- * on-chip solver holds (8192 unknowns), lattice box with hi - lo != 2^n. */
+ * to the current device. Grids up to 8,192 unknowns with lines of at most
+ * 512 take the on-chip solver, larger ones the streaming solver (Krylov
+ * vectors in device memory the plan allocates). Rejects: d outside
+ * 1..CTM_MAXD, n + d - 1 > 30, no grid with l >= L0, more than 65,535
+ * grids, N not divisible by s * c^(levels-1), nonpositive tolerances, CG for
+ * a non-symmetric operator, a grid with more than 2^20 unknowns or a line
+ * longer than 1,024, the manufactured forcing on a streaming grid, lattice
+ * box with hi - lo != 2^n. */
 ctm_status ctm_plan_create(const ctm_problem* p, ctm_plan** plan);
 void ctm_plan_destroy(ctm_plan* plan);
 

@@ -452,45 +452,53 @@ hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2
 }
 
 // ------------------------------------------------------------ vector ops
-__global__ void vec_add_kernel(VecRef dst, VecRef x, VecRef y, long long slen,
+// Vector index q runs over blockIdx.y, gridDim.y, ... < nvec (the grid's y
+// extent is capped at 65,535).
+constexpr int kMaxGridY = 65535;
+
+__global__ void vec_add_kernel(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
                                const double* skip) {
   if (skip && *skip != 0.0) return;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= slen) return;
-  const long long q = blockIdx.y;
-  double v = x.base[(x.a * q + x.b) * slen + e];
-  if (y.base) v += y.base[(y.a * q + y.b) * slen + e];
-  dst.base[(dst.a * q + dst.b) * slen + e] = v;
+  for (long long q = blockIdx.y; q < nvec; q += gridDim.y) {
+    double v = x.base[(x.a * q + x.b) * slen + e];
+    if (y.base) v += y.base[(y.a * q + y.b) * slen + e];
+    dst.base[(dst.a * q + dst.b) * slen + e] = v;
+  }
 }
 
 hipError_t launch_vec_add(VecRef dst, VecRef x, VecRef y, int nvec, long long slen,
                           hipStream_t s, const double* skip) {
   if (nvec <= 0 || slen <= 0) return hipSuccess;
-  hipLaunchKernelGGL(vec_add_kernel, dim3((unsigned)((slen + 255) / 256), nvec), dim3(256), 0, s,
-                     dst, x, y, slen, skip);
+  const unsigned gy = (unsigned)(nvec < kMaxGridY ? nvec : kMaxGridY);
+  hipLaunchKernelGGL(vec_add_kernel, dim3((unsigned)((slen + 255) / 256), gy), dim3(256), 0, s,
+                     dst, x, y, nvec, slen, skip);
   return hipGetLastError();
 }
 
 __global__ void class_vec_add_kernel(const int2* __restrict__ tasks,
                                      const GridDev* __restrict__ grids, VecRef dst, VecRef x,
-                                     VecRef y, long long slen, const double* skip) {
+                                     VecRef y, int nvec, long long slen, const double* skip) {
   if (skip && *skip != 0.0) return;
   const GridDev& g = grids[tasks[blockIdx.x].x];
-  const long long q = blockIdx.y;
   const long long base = g.off;
-  double* d = dst.base + (dst.a * q + dst.b) * slen + base;
-  const double* xs = x.base ? x.base + (x.a * q + x.b) * slen + base : nullptr;
-  const double* ys = y.base ? y.base + (y.a * q + y.b) * slen + base : nullptr;
-  for (int e = threadIdx.x; e < g.npts; e += blockDim.x)
-    d[e] = (xs ? xs[e] : 0.0) + (ys ? ys[e] : 0.0);
+  for (long long q = blockIdx.y; q < nvec; q += gridDim.y) {
+    double* d = dst.base + (dst.a * q + dst.b) * slen + base;
+    const double* xs = x.base ? x.base + (x.a * q + x.b) * slen + base : nullptr;
+    const double* ys = y.base ? y.base + (y.a * q + y.b) * slen + base : nullptr;
+    for (int e = threadIdx.x; e < g.npts; e += blockDim.x)
+      d[e] = (xs ? xs[e] : 0.0) + (ys ? ys[e] : 0.0);
+  }
 }
 
 hipError_t launch_class_vec_add(const int2* tasks, int ntasks, const GridDev* grids, VecRef dst,
                                 VecRef x, VecRef y, int nvec, long long slen, hipStream_t s,
                                 const double* skip) {
   if (ntasks <= 0 || nvec <= 0) return hipSuccess;
-  hipLaunchKernelGGL(class_vec_add_kernel, dim3((unsigned)ntasks, (unsigned)nvec), dim3(256), 0,
-                     s, tasks, grids, dst, x, y, slen, skip);
+  const unsigned gy = (unsigned)(nvec < kMaxGridY ? nvec : kMaxGridY);
+  hipLaunchKernelGGL(class_vec_add_kernel, dim3((unsigned)ntasks, gy), dim3(256), 0, s, tasks,
+                     grids, dst, x, y, nvec, slen, skip);
   return hipGetLastError();
 }
 

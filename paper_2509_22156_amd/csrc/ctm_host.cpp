@@ -515,7 +515,8 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   hipError_t e;
   if (shape == kStreamShape) {
     if (count > P->stream_tasks) return fail(CTM_ERR_INVALID, "streaming launch exceeds its scratch");
-    e = launch_stream(P->opc, P->solver, c, (int)count, P->tabmax, P->dstream, P->stream_ss, s);
+    e = launch_stream(P->opc, P->solver, P->d, c, (int)count, P->tabmax, P->dstream,
+                      P->stream_ss, s);
   } else {
     e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tabmax, s);
   }
@@ -1239,10 +1240,14 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   }
   P->G = (int)P->grids.size();
   P->slen = off;
+  if (P->G > 65535) {  // per-grid kernels index grids by the launch grid's y extent
+    delete P;
+    return fail(CTM_ERR_INVALID, "more than 65,535 component grids");
+  }
   for (auto& gh : P->grids) P->maxpts = (int)std::max<long long>(P->maxpts, gh.npts);
   if (P->maxpts > (1 << 20)) {
     delete P;
-    return fail(CTM_ERR_INVALID, "a component grid exceeds the on-chip solver");
+    return fail(CTM_ERR_INVALID, "a component grid has more than 2^20 unknowns");
   }
 
   const double dt0 = (prob->t1 - prob->t0) / (double)prob->nsteps;
@@ -1454,7 +1459,7 @@ ctm_status ctm_apply(ctm_plan* P, int level, const double* x, double* y, ctm_str
   if (level < 0 || level > 16) return fail(CTM_ERR_INVALID, "level out of range");
   if (x == y) return fail(CTM_ERR_INVALID, "x and y must not overlap");
   if (P->shape < 0)  // some grid streams: the point-wise apply for every grid
-    CTM_HIP(launch_stream_apply(P->opc, P->dgrids, P->G, P->dtab, P->prob.amp,
+    CTM_HIP(launch_stream_apply(P->opc, P->d, P->dgrids, P->G, P->dtab, P->prob.amp,
                                 level_dt(P, level), P->tabmax, x, y, (hipStream_t)s));
   else
     CTM_HIP(launch_apply(P->opc, P->shape, P->dgrids, P->G, P->dtab, P->prob.amp,

@@ -122,11 +122,12 @@ static_assert(kNumShapes + 1 <= 16, "ctm_stats keeps 16 shape slots");
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
                         int ntasks, size_t smem, int tabmax, hipStream_t s);
 // Streaming kernel (stream_ops.hip): task t of the launch uses the scratch
-// doubles [t * SV_N * ss, (t + 1) * SV_N * ss); FP64 whatever the precision.
+// doubles [t * SV_N * ss, (t + 1) * SV_N * ss); FP64 whatever the precision;
+// d is the grids' dimension (selects the compile-time dimension bound).
 constexpr int kStreamVectors = 9;
-hipError_t launch_stream(int opc, int solver, const ChainArgs& a, int ntasks, int tabmax,
+hipError_t launch_stream(int opc, int solver, int d, const ChainArgs& a, int ntasks, int tabmax,
                          double* scratch, long long ss, hipStream_t s);
-hipError_t launch_stream_apply(int opc, const GridDev* grids, int G, const double* tab64,
+hipError_t launch_stream_apply(int opc, int d, const GridDev* grids, int G, const double* tab64,
                                double amp, double dt, int tabmax, const double* x, double* y,
                                hipStream_t s);
 

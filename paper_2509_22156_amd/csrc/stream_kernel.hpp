@@ -27,21 +27,23 @@ enum { SV_X = 0, SV_B, SV_R, SV_P, SV_Q, SV_RH, SV_S, SV_T, SV_D, SV_N };
 
 // Coefficients of A = I + dt L at point p of grid g: the diagonal, and per
 // axis the couplings to the lower and upper neighbour (zero where that
-// neighbour is not an unknown), plus the point strides.
-template <int OPC>
+// neighbour is not an unknown), plus the point strides. D >= g.d bounds the
+// dimension at compile time (2, 4 or 8), so that a low-dimensional grid
+// keeps only its own axes in registers.
+template <int OPC, int D>
 struct PointCoef {
   double diag;
-  double lo[MAXD], up[MAXD];
-  int j[MAXD];
+  double lo[D], up[D];
+  int j[D];
 };
 
-template <int OPC>
+template <int OPC, int D>
 __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, double dt,
-                                           double amp, int p, PointCoef<OPC>& c) {
+                                           double amp, int p, PointCoef<OPC, D>& c) {
   const int d = g.d;
   int rem = p;
 #pragma unroll
-  for (int i = MAXD - 1; i >= 0; --i) {
+  for (int i = D - 1; i >= 0; --i) {
     c.j[i] = 0;
     if (i < d) {
       c.j[i] = rem % g.n[i];
@@ -50,7 +52,7 @@ __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, d
   }
   double diag = 1.0;
 #pragma unroll
-  for (int i = 0; i < MAXD; ++i) {
+  for (int i = 0; i < D; ++i) {
     c.lo[i] = c.up[i] = 0.0;
     if (i >= d) continue;
     const int j = c.j[i];
@@ -69,7 +71,7 @@ __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, d
       // a at the faces: 1 + amp * (face sine) * (node sines of the other axes)
       double es = 1.0;
 #pragma unroll
-      for (int k = 0; k < MAXD; ++k)
+      for (int k = 0; k < D; ++k)
         if (k < d && k != i) es *= tl[g.tab[k] + c.j[k]];
       const double* sm = tl + g.tab[i] + n;
       const double adn = 1.0 + amp * sm[j] * es, aup = 1.0 + amp * sm[j + 1] * es;
@@ -80,7 +82,7 @@ __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, d
     } else {  // OPC_DRIFT: theta (d x d), then H (d)
       double w = 0.0;
 #pragma unroll
-      for (int k = 0; k < MAXD; ++k)
+      for (int k = 0; k < D; ++k)
         if (k < d) w += tl[i * d + k] * (g.lo[k] + (double)(c.j[k] + g.j0) * g.h[k]);
       const double h = g.h[i], half = tl[i * d + i] * 0.5 * h, H = tl[d * d + i];
       const double wu = w + half, wd = w - half;
@@ -96,17 +98,17 @@ __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, d
 
 // y = A x at every point of the task; returns this thread's part of
 // sum w[p] y[p] when w is given.
-template <int OPC>
+template <int OPC, int D>
 __device__ __forceinline__ double stream_apply(const GridDev& g, const double* tl, double dt,
                                                double amp, const double* x, double* y,
                                                const double* w) {
   double acc = 0.0;
   for (int p = threadIdx.x; p < g.npts; p += kStreamThreads) {
-    PointCoef<OPC> c;
-    point_coef<OPC>(g, tl, dt, amp, p, c);
+    PointCoef<OPC, D> c;
+    point_coef<OPC, D>(g, tl, dt, amp, p, c);
     double v = c.diag * x[p];
 #pragma unroll
-    for (int i = 0; i < MAXD; ++i) {
+    for (int i = 0; i < D; ++i) {
       if (i >= g.d) continue;
       const int st = g.stride[i];
       if (c.lo[i] != 0.0) v += c.lo[i] * x[p - st];
@@ -124,7 +126,7 @@ __device__ __forceinline__ double stream_apply(const GridDev& g, const double* t
 // lines (ns' = ns rounded up to a power of two, at most 1024) and each is
 // solved by parallel cyclic reduction over its unknowns. Returns this
 // thread's part of sum w[p] z[p] when w is given. Ends with a barrier.
-template <int OPC>
+template <int OPC, int D>
 __device__ double stream_precond(const GridDev& g, const double* tl, double dt, double amp,
                                  const double* r, double* z, double* lds, const double* w) {
   const int s = g.sax, ns = g.ns;
@@ -145,17 +147,17 @@ __device__ double stream_precond(const GridDev& g, const double* tl, double dt, 
       int rem = line;
       p = i * g.stride[s];
 #pragma unroll
-      for (int m = 0; m < MAXD - 1; ++m)
+      for (int m = 0; m < D - 1; ++m)
         if (m < g.d - 1) {
           const int ax = g.oax[m];
           p += ((rem / g.lstride[m]) % g.n[ax]) * g.stride[ax];
         }
       (void)rem;
-      PointCoef<OPC> c;
-      point_coef<OPC>(g, tl, dt, amp, p, c);
+      PointCoef<OPC, D> c;
+      point_coef<OPC, D>(g, tl, dt, amp, p, c);
       double lo = 0.0, up = 0.0;  // (unrolled select: no dynamic register index)
 #pragma unroll
-      for (int ax = 0; ax < MAXD; ++ax)
+      for (int ax = 0; ax < D; ++ax)
         if (ax == s) {
           lo = c.lo[ax];
           up = c.up[ax];
@@ -205,7 +207,7 @@ __device__ double stream_precond(const GridDev& g, const double* tl, double dt, 
 
 // One implicit step: x <- (I + dt L)^-1 b, x holding the initial guess.
 // Preconditioned CG (symmetric operators).
-template <int OPC>
+template <int OPC, int D>
 __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a, double* sv,
                          long long ss, double* lds, RedRing& ring, double tol2, int* flag) {
   double* X = sv + SV_X * ss;
@@ -215,7 +217,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
   double* Q = sv + SV_Q * ss;
   double* Z = sv + SV_S * ss;
   const int np = g.npts;
-  stream_apply<OPC>(g, tl, a.dt, a.amp, X, Q, nullptr);
+  stream_apply<OPC, D>(g, tl, a.dt, a.amp, X, Q, nullptr);
   double s0[2] = {0.0, 0.0};  // (r, r), (b, b)
   for (int p = threadIdx.x; p < np; p += kStreamThreads) {
     const double r = B[p] - Q[p];
@@ -230,13 +232,13 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
     return 0;
   }
   if (s0[0] <= tol2 * bb) return 0;
-  double rz1[1] = {stream_precond<OPC>(g, tl, a.dt, a.amp, R, Z, lds, R)};
+  double rz1[1] = {stream_precond<OPC, D>(g, tl, a.dt, a.amp, R, Z, lds, R)};
   block_sum<kStreamW, 1, double>(rz1, ring);
   double rz = rz1[0];
   for (int p = threadIdx.x; p < np; p += kStreamThreads) P[p] = Z[p];
   __syncthreads();
   for (int it = 1; it <= a.maxit; ++it) {
-    double pq[1] = {stream_apply<OPC>(g, tl, a.dt, a.amp, P, Q, P)};
+    double pq[1] = {stream_apply<OPC, D>(g, tl, a.dt, a.amp, P, Q, P)};
     block_sum<kStreamW, 1, double>(pq, ring);
     if (!(pq[0] != 0.0) || !(pq[0] == pq[0])) {
       *flag |= (pq[0] == pq[0]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
@@ -256,7 +258,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
       return it;
     }
     if (s1[0] <= tol2 * bb) return it;
-    double rzn[1] = {stream_precond<OPC>(g, tl, a.dt, a.amp, R, Z, lds, R)};
+    double rzn[1] = {stream_precond<OPC, D>(g, tl, a.dt, a.amp, R, Z, lds, R)};
     block_sum<kStreamW, 1, double>(rzn, ring);
     const double beta = rzn[0] / rz;
     rz = rzn[0];
@@ -270,7 +272,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
 // Right-preconditioned BiCGStab (van der Vorst): p^ = M^-1 p, v = A p^,
 // s^ = M^-1 s, t = A s^, x += alpha p^ + omega s^ (the first part as soon as
 // alpha is known, so that p^ and s^ share one scratch vector).
-template <int OPC>
+template <int OPC, int D>
 __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainArgs& a,
                                double* sv, long long ss, double* lds, RedRing& ring, double tol2,
                                int* flag) {
@@ -284,7 +286,7 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
   double* T = sv + SV_T * ss;
   double* H = sv + SV_D * ss;  // p^, then s^
   const int np = g.npts;
-  stream_apply<OPC>(g, tl, a.dt, a.amp, X, V, nullptr);
+  stream_apply<OPC, D>(g, tl, a.dt, a.amp, X, V, nullptr);
   double s0[2] = {0.0, 0.0};
   for (int p = threadIdx.x; p < np; p += kStreamThreads) {
     const double r = B[p] - V[p];
@@ -303,8 +305,8 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
   if (s0[0] <= tol2 * bb) return 0;
   double rho = s0[0];
   for (int it = 1; it <= a.maxit; ++it) {
-    stream_precond<OPC>(g, tl, a.dt, a.amp, P, H, lds, nullptr);
-    double s2[1] = {stream_apply<OPC>(g, tl, a.dt, a.amp, H, V, RH)};
+    stream_precond<OPC, D>(g, tl, a.dt, a.amp, P, H, lds, nullptr);
+    double s2[1] = {stream_apply<OPC, D>(g, tl, a.dt, a.amp, H, V, RH)};
     block_sum<kStreamW, 1, double>(s2, ring);
     if (!(s2[0] != 0.0) || !(s2[0] == s2[0])) {
       *flag |= (s2[0] == s2[0]) ? FLAG_BREAKDOWN : FLAG_NONFINITE;
@@ -316,14 +318,14 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
       S[p] = R[p] - alpha * V[p];
     }
     __syncthreads();  // S complete before the preconditioner reads whole lines
-    stream_precond<OPC>(g, tl, a.dt, a.amp, S, H, lds, nullptr);
+    stream_precond<OPC, D>(g, tl, a.dt, a.amp, S, H, lds, nullptr);
     double s3[3] = {0.0, 0.0, 0.0};  // (t, s), (t, t), (s, s)
     for (int p = threadIdx.x; p < np; p += kStreamThreads) {
-      PointCoef<OPC> c;
-      point_coef<OPC>(g, tl, a.dt, a.amp, p, c);
+      PointCoef<OPC, D> c;
+      point_coef<OPC, D>(g, tl, a.dt, a.amp, p, c);
       double v = c.diag * H[p];
 #pragma unroll
-      for (int i = 0; i < MAXD; ++i) {
+      for (int i = 0; i < D; ++i) {
         if (i >= g.d) continue;
         const int st = g.stride[i];
         if (c.lo[i] != 0.0) v += c.lo[i] * H[p - st];
@@ -370,7 +372,7 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
 }
 
 // Scratch of task t of the launch: sv = scratch + t * SV_N * ss.
-template <int OPC, int SOLVER>
+template <int OPC, int SOLVER, int D>
 __global__ void __launch_bounds__(kStreamThreads)
     stream_kernel(ChainArgs a, int tabmax, double* scratch, long long ss) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -418,9 +420,9 @@ __global__ void __launch_bounds__(kStreamThreads)
     __syncthreads();
     int it;
     if constexpr (SOLVER == SOLV_CG)
-      it = stream_cg<OPC>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
+      it = stream_cg<OPC, D>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
     else
-      it = stream_bicgstab<OPC>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
+      it = stream_bicgstab<OPC, D>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
     kr_sum += it;
     kr_max = it > kr_max ? it : kr_max;
     const double* f = a.forcing.base ? at(a.forcing, a.forcing.a * q + a.forcing.b + j) : nullptr;
@@ -459,19 +461,19 @@ __global__ void __launch_bounds__(kStreamThreads)
   }
 }
 
-template <int OPC, int SOLVER>
+template <int OPC, int SOLVER, int D>
 hipError_t launch_stream_t(const ChainArgs& a, int ntasks, int tabmax, double* scratch,
                            long long ss, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   const size_t smem = (size_t)tabmax * sizeof(double);
-  hipLaunchKernelGGL((stream_kernel<OPC, SOLVER>), dim3(ntasks), dim3(kStreamThreads), smem, s,
+  hipLaunchKernelGGL((stream_kernel<OPC, SOLVER, D>), dim3(ntasks), dim3(kStreamThreads), smem, s,
                      a, tabmax, scratch, ss);
   return hipGetLastError();
 }
 
 // y = (I + dt L) x on every grid, point-wise (one work-group per grid); the
 // standalone apply for plans with streaming grids.
-template <int OPC>
+template <int OPC, int D>
 __global__ void __launch_bounds__(kStreamThreads)
     stream_apply_kernel(const GridDev* __restrict__ grids, const double* __restrict__ tab64,
                         double amp, double dt, const double* __restrict__ x,
@@ -488,7 +490,7 @@ __global__ void __launch_bounds__(kStreamThreads)
   __syncthreads();
   load_tables<OPC, double, kStreamThreads>(gs, tab64, dt, tl);
   __syncthreads();
-  stream_apply<OPC>(gs, tl, dt, amp, x + gs.off, y + gs.off, nullptr);
+  stream_apply<OPC, D>(gs, tl, dt, amp, x + gs.off, y + gs.off, nullptr);
 }
 
 }  // namespace ctm

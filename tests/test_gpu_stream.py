@@ -37,6 +37,16 @@ def test_streaming_classes_present():
     assert any(s["K"] == 0 for s in shapes) and any(s["K"] > 0 for s in shapes), shapes
 
 
+def test_streaming_grids_keep_their_shape():
+    plan = ctm.Plan(_heat2d_big())
+    stream = [g for g in range(plan.G) if plan.grid_shape(g) == (16, 0)]
+    assert stream
+    with pytest.raises(ctm.CtmError, match="streaming"):
+        plan.set_grid_shape(stream[0], 16, 8)
+    rep = plan.autotune(trial_iterations=1, repeats=1)
+    assert all(plan.grid_shape(g) == (16, 0) for g in stream), rep
+
+
 def test_streaming_apply():
     p = _heat2d_big()
     plan = ctm.Plan(p)
