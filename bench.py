@@ -454,8 +454,9 @@ def _comparators(args, ctm, torch, oracle_u, dof_steps):
 
 
 # HBM bytes per unknown of one streaming Krylov iteration (FP64 vectors in
-# HBM, every sweep counted once; neighbour reads served by the caches)
-STREAM_BYTES_PER_ITERATION = {"cg": 112, "bicgstab": 216}
+# HBM, every sweep counted once; neighbour reads served by the caches; each
+# preconditioner application reads r and five factor vectors and writes z)
+STREAM_BYTES_PER_ITERATION = {"cg": 152, "bicgstab": 296}
 
 
 def _streaming(ctm, torch):

@@ -124,7 +124,7 @@ hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainA
 // Streaming kernel (stream_ops.hip): task t of the launch uses the scratch
 // doubles [t * SV_N * ss, (t + 1) * SV_N * ss); FP64 whatever the precision;
 // d is the grids' dimension (selects the compile-time dimension bound).
-constexpr int kStreamVectors = 9;
+constexpr int kStreamVectors = 14;
 hipError_t launch_stream(int opc, int solver, int d, const ChainArgs& a, int ntasks, int tabmax,
                          double* scratch, long long ss, hipStream_t s);
 hipError_t launch_stream_apply(int opc, int d, const GridDev* grids, int G, const double* tab64,

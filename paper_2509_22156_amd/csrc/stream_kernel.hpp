@@ -7,14 +7,16 @@
 // vectors, with block-wide reductions between them. FP64 throughout, CG or
 // right-preconditioned BiCGStab (Section 4.1) with the same line-block
 // preconditioner as the on-chip solver (exact solves of the stiff-axis
-// lines), the same vector roles as the on-chip chain kernel (ChainArgs).
+// lines, here one wave per line segment with 16 unknowns per lane and the
+// factors kept in the task's scratch), the same vector roles as the on-chip
+// chain kernel (ChainArgs).
 //
 // The stencil coefficients are evaluated per point and sweep from the grid
 // descriptor and the coefficient tables in LDS; they match the on-chip
 // operators of every class.
 #pragma once
 
-#include "device_common.hpp"
+#include "line_layout.hpp"
 
 namespace ctm {
 
@@ -22,8 +24,12 @@ constexpr int kStreamThreads = 1024;
 constexpr int kStreamW = kStreamThreads / 64;
 
 // Scratch vectors of one task (each `sstride` doubles); SV_D holds the
-// preconditioned direction in BiCGStab.
-enum { SV_X = 0, SV_B, SV_R, SV_P, SV_Q, SV_RH, SV_S, SV_T, SV_D, SV_N };
+// preconditioned direction in BiCGStab; SV_FM .. SV_FPSI the factors of the
+// line preconditioner (stream_linepre_setup).
+enum {
+  SV_X = 0, SV_B, SV_R, SV_P, SV_Q, SV_RH, SV_S, SV_T, SV_D,
+  SV_FM, SV_FID, SV_FCU, SV_FPHI, SV_FPSI, SV_N
+};
 
 // Coefficients of A = I + dt L at point p of grid g: the diagonal, and per
 // axis the couplings to the lower and upper neighbour (zero where that
@@ -120,88 +126,256 @@ __device__ __forceinline__ double stream_apply(const GridDev& g, const double* t
   return acc;
 }
 
-// z = M^-1 r for the line-block preconditioner M: the part of A that couples
-// unknowns along the stiff axis (one tridiagonal block per line, as in the
-// on-chip solver). Lines are staged through LDS in batches of 1024 / ns'
-// lines (ns' = ns rounded up to a power of two, at most 1024) and each is
-// solved by parallel cyclic reduction over its unknowns. Returns this
-// thread's part of sum w[p] z[p] when w is given. Ends with a barrier.
+// ------------------------------------------------ line preconditioner
+// M = the part of A that couples unknowns along the stiff axis (one
+// tridiagonal block per line), as in the on-chip solver. A line of ns <=
+// 1,024 unknowns is split into chunks of kSK consecutive unknowns, one
+// chunk per lane of a segment of Lc = pow2ceil(ceil(ns / kSK)) <= 64 lanes
+// of one wave; the waves of the work-group take the lines round by round.
+// Per chunk: Thomas elimination of the first kSK-1 unknowns, whose
+// responses to the neighbouring interface unknowns (phi, psi) are
+// precomputed; the interface system (one unknown per lane, the chunk's
+// last) is solved by parallel cyclic reduction over the segment's lanes;
+// back-substitution. No barrier inside: a lane reads and writes only its own
+// chunk, and neighbours come by cross-lane shuffles.
+constexpr int kSK = 16;
+
+struct SLane {
+  int line, c, Lc, j0, nval;
+  bool nxt;        // the next chunk of the line holds unknowns
+  long long base;  // canonical index of the line's first unknown
+  int step;        // canonical stride along the stiff axis
+};
+
+__device__ __forceinline__ int stream_line_rounds(const GridDev& g) {
+  const int Lc = pow2ceil((g.ns + kSK - 1) / kSK);
+  const int per_round = kStreamW * (64 / Lc);
+  return (g.nlines + per_round - 1) / per_round;
+}
+
+template <int D>
+__device__ __forceinline__ void stream_lane(const GridDev& g, int round, SLane& L) {
+  const int Lc = pow2ceil((g.ns + kSK - 1) / kSK);
+  const int t = threadIdx.x, lane = t & 63;
+  L.Lc = Lc;
+  L.c = lane & (Lc - 1);
+  L.line = (round * kStreamW + (t >> 6)) * (64 / Lc) + lane / Lc;
+  L.j0 = L.c * kSK;
+  const bool live = L.line < g.nlines;
+  int nv = g.ns - L.j0;
+  nv = nv < 0 ? 0 : (nv > kSK ? kSK : nv);
+  L.nval = live ? nv : 0;
+  L.nxt = live && (L.j0 + kSK < g.ns);
+  L.step = g.stride[g.sax];
+  long long b = 0;
+  const int rem = live ? L.line : 0;
+#pragma unroll
+  for (int m = 0; m < D - 1; ++m)
+    if (m < g.d - 1) {
+      const int ax = g.oax[m];
+      b += (long long)((rem / g.lstride[m]) % g.n[ax]) * g.stride[ax];
+    }
+  L.base = b;
+}
+
+// Stiff-axis couplings and diagonal of A at point p.
 template <int OPC, int D>
-__device__ double stream_precond(const GridDev& g, const double* tl, double dt, double amp,
-                                 const double* r, double* z, double* lds, const double* w) {
-  const int s = g.sax, ns = g.ns;
-  int nsp = 1;
-  while (nsp < ns) nsp <<= 1;
-  const int per = kStreamThreads / nsp;  // lines per batch
-  const int t = threadIdx.x, li = t / nsp, i = t % nsp;
-  double* A = lds;
-  double* Bd = lds + kStreamThreads;
-  double* C = lds + 2 * kStreamThreads;
-  double* R = lds + 3 * kStreamThreads;
-  double acc = 0.0;
-  for (int l0 = 0; l0 < g.nlines; l0 += per) {
-    const int line = l0 + li;
-    const bool live = (li < per) && (line < g.nlines) && (i < ns);
-    int p = 0;
-    if (live) {
-      int rem = line;
-      p = i * g.stride[s];
+__device__ __forceinline__ void line_coef(const GridDev& g, const double* tl, double dt,
+                                          double amp, int p, double& lo, double& dg,
+                                          double& up) {
+  PointCoef<OPC, D> c;
+  point_coef<OPC, D>(g, tl, dt, amp, p, c);
+  lo = up = 0.0;  // (unrolled select: no dynamic register index)
 #pragma unroll
-      for (int m = 0; m < D - 1; ++m)
-        if (m < g.d - 1) {
-          const int ax = g.oax[m];
-          p += ((rem / g.lstride[m]) % g.n[ax]) * g.stride[ax];
-        }
-      (void)rem;
-      PointCoef<OPC, D> c;
-      point_coef<OPC, D>(g, tl, dt, amp, p, c);
-      double lo = 0.0, up = 0.0;  // (unrolled select: no dynamic register index)
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax)
-        if (ax == s) {
-          lo = c.lo[ax];
-          up = c.up[ax];
-        }
-      A[t] = lo;
-      Bd[t] = c.diag;
-      C[t] = up;
-      R[t] = r[p];
-    } else {
-      A[t] = 0.0;
-      Bd[t] = 1.0;
-      C[t] = 0.0;
-      R[t] = 0.0;
+  for (int ax = 0; ax < D; ++ax)
+    if (ax == g.sax) {
+      lo = c.lo[ax];
+      up = c.up[ax];
     }
-    __syncthreads();
-    for (int st = 1; st < nsp; st <<= 1) {
-      const double ai = A[t], bi = Bd[t], ci = C[t], ri = R[t];
-      double an = 0.0, cn = 0.0, bn = bi, rn = ri;
-      if (i >= st) {
-        const double al = -ai / Bd[t - st];
-        an = al * A[t - st];
-        bn += al * C[t - st];
-        rn += al * R[t - st];
+  dg = c.diag;
+}
+
+// Factors of M for every chunk of the task, stored at the chunk's unknowns:
+// FM = Thomas multipliers m_k (slot kSK-1: the diagonal of the interface
+// unknown), FID = reciprocal pivots, FCU = upper couplings inside the
+// chunk, FPHI/FPSI = responses of the eliminated unknowns to the previous
+// and own interface unknown (slot kSK-1: the interface's couplings aL, cL).
+// ftmp is a scratch vector (the forward spike). Called by every thread.
+template <int OPC, int D>
+__device__ void stream_linepre_setup(const GridDev& g, const double* tl, double dt, double amp,
+                                     double* sv, long long ss, double* ftmp) {
+  double* FM = sv + SV_FM * ss;
+  double* FID = sv + SV_FID * ss;
+  double* FCU = sv + SV_FCU * ss;
+  double* FPHI = sv + SV_FPHI * ss;
+  double* FPSI = sv + SV_FPSI * ss;
+  const int rounds = stream_line_rounds(g);
+  for (int rd = 0; rd < rounds; ++rd) {
+    SLane L;
+    stream_lane<D>(g, rd, L);
+    // forward over the eliminated unknowns k = 0..kSK-2
+    double idp = 0.0, cp = 0.0, fp = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < kSK - 1; ++k) {
+      const bool v = k < L.nval;
+      const int j = L.j0 + k;
+      const long long p = L.base + (long long)j * L.step;
+      double lo = 0.0, dg = 1.0, up = 0.0;
+      if (v) line_coef<OPC, D>(g, tl, dt, amp, (int)p, lo, dg, up);
+      const double a = (v && j > 0) ? lo : 0.0;
+      const double c = (v && k + 1 < L.nval) ? up : 0.0;
+      const double b = v ? dg : 1.0;
+      double m, id, f;
+      if (k == 0) {
+        m = 0.0;
+        id = 1.0 / b;
+        f = a;
+      } else {
+        m = a * idp;
+        id = 1.0 / (b - m * cp);
+        f = -m * fp;
       }
-      if (i + st < nsp) {
-        const double ga = -ci / Bd[t + st];
-        cn = ga * C[t + st];
-        bn += ga * A[t + st];
-        rn += ga * R[t + st];
+      if (v) {
+        FM[p] = m;
+        FID[p] = id;
+        FCU[p] = (k < kSK - 2) ? c : 0.0;
+        ftmp[p] = f;
       }
-      __syncthreads();
-      A[t] = an;
-      Bd[t] = bn;
-      C[t] = cn;
-      R[t] = rn;
-      __syncthreads();
+      idp = id;
+      cp = c;
+      fp = f;
     }
-    if (live) {
-      const double zv = R[t] / Bd[t];
-      z[p] = zv;
-      if (w) acc += w[p] * zv;
+    // the interface unknown kSK-1 (present only in a full chunk)
+    {
+      const bool v = (L.nval == kSK);
+      const long long p = L.base + (long long)(L.j0 + kSK - 1) * L.step;
+      if (v) {
+        double lo, dg, up;
+        line_coef<OPC, D>(g, tl, dt, amp, (int)p, lo, dg, up);
+        FM[p] = dg;
+        FPHI[p] = lo;                  // aL (j0 + kSK - 1 > 0 always)
+        FPSI[p] = L.nxt ? up : 0.0;    // cL
+      }
     }
-    __syncthreads();  // the next batch overwrites LDS; z complete for readers
+    // backward: phi = T^-1 (a_0 e_0), psi = T^-1 (c_{kSK-2} e_{kSK-2})
+    double php = 0.0, psp = 0.0;
+#pragma unroll 1
+    for (int k = kSK - 2; k >= 0; --k) {
+      const bool v = k < L.nval;
+      const long long p = L.base + (long long)(L.j0 + k) * L.step;
+      double ph = 0.0, ps = 0.0;
+      if (v) {
+        const double id = FID[p], f = ftmp[p];
+        if (k == kSK - 2) {
+          ph = f * id;
+          ps = cp * id;  // c_{kSK-2}, from the forward pass
+        } else {
+          const double cu = FCU[p];
+          ph = (f - cu * php) * id;
+          ps = -cu * psp * id;
+        }
+        FPHI[p] = ph;
+        FPSI[p] = ps;
+      }
+      php = ph;
+      psp = ps;
+    }
   }
+}
+
+// z = M^-1 r on every line of the task; returns this thread's part of
+// sum w[p] z[p] when w is given. r must be complete on entry; ends with a
+// barrier (z complete for the readers of neighbours). The eliminated
+// unknowns' intermediate values go through z itself (a lane's chunk stays
+// in the caches), so that no per-lane array competes for registers.
+template <int D>
+__device__ double stream_linepre_apply(const GridDev& g, const double* sv, long long ss,
+                                       const double* r, double* z, const double* w) {
+  const double* FM = sv + SV_FM * ss;
+  const double* FID = sv + SV_FID * ss;
+  const double* FCU = sv + SV_FCU * ss;
+  const double* FPHI = sv + SV_FPHI * ss;
+  const double* FPSI = sv + SV_FPSI * ss;
+  const int rounds = stream_line_rounds(g);
+  double acc = 0.0;
+  for (int rd = 0; rd < rounds; ++rd) {
+    SLane L;
+    stream_lane<D>(g, rd, L);
+    const bool full = (L.nval == kSK);
+    const int ne = L.nval < kSK - 1 ? L.nval : kSK - 1;  // eliminated unknowns present
+    const long long p0 = L.base + (long long)L.j0 * L.step;
+    const long long st = L.step;
+    // forward elimination: y_k = r_k - m_k y_{k-1}
+    double y = 0.0, ylast = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < ne; ++k) {
+      const long long p = p0 + k * st;
+      y = (k == 0) ? r[p] : r[p] - FM[p] * y;
+      z[p] = y;
+    }
+    ylast = (ne == kSK - 1) ? y : 0.0;  // y_{kSK-2} before the back-substitution
+    // back-substitution: y_k = (y_k - cu_k y_{k+1}) / pivot_k
+    double yn = 0.0;
+#pragma unroll 1
+    for (int k = ne - 1; k >= 0; --k) {
+      const long long p = p0 + k * st;
+      yn = (k == kSK - 2) ? z[p] * FID[p] : (z[p] - FCU[p] * yn) * FID[p];
+      z[p] = yn;
+    }
+    const double y0 = (ne > 0) ? yn : 0.0;
+    const double y2 = (ne == kSK - 1) ? z[p0 + (kSK - 2) * st] : 0.0;
+    (void)ylast;
+    // interface equation of the chunk's last unknown u_c:
+    //   A u_{c-1} + B u_c + C u_{c+1} = R
+    const long long pl = p0 + (kSK - 1) * st;
+    const long long p2 = p0 + (kSK - 2) * st;
+    const double phi0 = (L.nval > 0) ? FPHI[p0] : 0.0, psi0 = (L.nval > 0) ? FPSI[p0] : 0.0;
+    const double phi2 = (L.nval > kSK - 2) ? FPHI[p2] : 0.0;
+    const double psi2 = (L.nval > kSK - 2) ? FPSI[p2] : 0.0;
+    const double aL = full ? FPHI[pl] : 0.0, cL = full ? FPSI[pl] : 0.0;
+    const double bL = full ? FM[pl] : 1.0;
+    const double rL = full ? r[pl] : 0.0;
+    const double phi0n = from_plus(phi0, 1, L.Lc), psi0n = from_plus(psi0, 1, L.Lc);
+    const double y0n = from_plus(y0, 1, L.Lc);
+    double A = -aL * phi2;
+    double B = bL - aL * psi2 - cL * phi0n;
+    double C = -cL * psi0n;
+    double R = rL - aL * y2 - cL * y0n;
+    // cyclic reduction over the lanes of the segment
+#pragma unroll
+    for (int sp = 0; sp < kMaxPcr; ++sp) {
+      const int sh = 1 << sp;
+      if (sh < L.Lc) {
+        const double Am = from_minus(A, sh, L.Lc), Bm = from_minus(B, sh, L.Lc),
+                     Cm = from_minus(C, sh, L.Lc), Rm = from_minus(R, sh, L.Lc);
+        const double Ap = from_plus(A, sh, L.Lc), Bp = from_plus(B, sh, L.Lc),
+                     Cp = from_plus(C, sh, L.Lc), Rp = from_plus(R, sh, L.Lc);
+        const bool vm = L.c >= sh, vp = L.c + sh < L.Lc;
+        const double al = vm ? -A / Bm : 0.0;
+        const double ga = vp ? -C / Bp : 0.0;
+        B = B + (vm ? al * Cm : 0.0) + (vp ? ga * Ap : 0.0);
+        R = R + (vm ? al * Rm : 0.0) + (vp ? ga * Rp : 0.0);
+        A = vm ? al * Am : 0.0;
+        C = vp ? ga * Cp : 0.0;
+      }
+    }
+    const double u = R / B;
+    double um = from_minus(u, 1, L.Lc);
+    um = (L.c > 0) ? um : 0.0;
+    // z_k = y_k - phi_k u_{c-1} - psi_k u_c
+#pragma unroll 1
+    for (int k = 0; k < ne; ++k) {
+      const long long p = p0 + k * st;
+      const double zk = z[p] - FPHI[p] * um - FPSI[p] * u;
+      z[p] = zk;
+      if (w) acc += w[p] * zk;
+    }
+    if (full) {
+      z[pl] = u;
+      if (w) acc += w[pl] * u;
+    }
+  }
+  __syncthreads();  // z complete for readers of other lanes' points
   return acc;
 }
 
@@ -209,7 +383,7 @@ __device__ double stream_precond(const GridDev& g, const double* tl, double dt, 
 // Preconditioned CG (symmetric operators).
 template <int OPC, int D>
 __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a, double* sv,
-                         long long ss, double* lds, RedRing& ring, double tol2, int* flag) {
+                         long long ss, RedRing& ring, double tol2, int* flag) {
   double* X = sv + SV_X * ss;
   double* B = sv + SV_B * ss;
   double* R = sv + SV_R * ss;
@@ -232,7 +406,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
     return 0;
   }
   if (s0[0] <= tol2 * bb) return 0;
-  double rz1[1] = {stream_precond<OPC, D>(g, tl, a.dt, a.amp, R, Z, lds, R)};
+  double rz1[1] = {stream_linepre_apply<D>(g, sv, ss, R, Z, R)};
   block_sum<kStreamW, 1, double>(rz1, ring);
   double rz = rz1[0];
   for (int p = threadIdx.x; p < np; p += kStreamThreads) P[p] = Z[p];
@@ -258,7 +432,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
       return it;
     }
     if (s1[0] <= tol2 * bb) return it;
-    double rzn[1] = {stream_precond<OPC, D>(g, tl, a.dt, a.amp, R, Z, lds, R)};
+    double rzn[1] = {stream_linepre_apply<D>(g, sv, ss, R, Z, R)};
     block_sum<kStreamW, 1, double>(rzn, ring);
     const double beta = rzn[0] / rz;
     rz = rzn[0];
@@ -274,7 +448,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
 // alpha is known, so that p^ and s^ share one scratch vector).
 template <int OPC, int D>
 __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainArgs& a,
-                               double* sv, long long ss, double* lds, RedRing& ring, double tol2,
+                               double* sv, long long ss, RedRing& ring, double tol2,
                                int* flag) {
   double* X = sv + SV_X * ss;
   double* B = sv + SV_B * ss;
@@ -305,7 +479,7 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
   if (s0[0] <= tol2 * bb) return 0;
   double rho = s0[0];
   for (int it = 1; it <= a.maxit; ++it) {
-    stream_precond<OPC, D>(g, tl, a.dt, a.amp, P, H, lds, nullptr);
+    stream_linepre_apply<D>(g, sv, ss, P, H, nullptr);
     double s2[1] = {stream_apply<OPC, D>(g, tl, a.dt, a.amp, H, V, RH)};
     block_sum<kStreamW, 1, double>(s2, ring);
     if (!(s2[0] != 0.0) || !(s2[0] == s2[0])) {
@@ -318,7 +492,7 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
       S[p] = R[p] - alpha * V[p];
     }
     __syncthreads();  // S complete before the preconditioner reads whole lines
-    stream_precond<OPC, D>(g, tl, a.dt, a.amp, S, H, lds, nullptr);
+    stream_linepre_apply<D>(g, sv, ss, S, H, nullptr);
     double s3[3] = {0.0, 0.0, 0.0};  // (t, s), (t, t), (s, s)
     for (int p = threadIdx.x; p < np; p += kStreamThreads) {
       PointCoef<OPC, D> c;
@@ -378,7 +552,6 @@ __global__ void __launch_bounds__(kStreamThreads)
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ GridDev gs;
   __shared__ double red[2 * 64];
-  __shared__ double pcr[4 * kStreamThreads];  // cyclic-reduction staging of the lines
   if (a.skip && *a.skip != 0.0) return;  // whole work-group: queued past convergence
   double* tl = reinterpret_cast<double*>(smem);
   const int2 task = a.tasks[blockIdx.x];
@@ -407,6 +580,9 @@ __global__ void __launch_bounds__(kStreamThreads)
     B[p] = v;
     if (wb) wb[p] = v;
   }
+  // the preconditioner's factors, once per chain (each lane later reads only
+  // what it wrote here)
+  stream_linepre_setup<OPC, D>(g, tl, a.dt, a.amp, sv, ss, sv + SV_S * ss);
   __syncthreads();
   RedRing ring{red, 0};
   int flag = 0;
@@ -420,9 +596,9 @@ __global__ void __launch_bounds__(kStreamThreads)
     __syncthreads();
     int it;
     if constexpr (SOLVER == SOLV_CG)
-      it = stream_cg<OPC, D>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
+      it = stream_cg<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag);
     else
-      it = stream_bicgstab<OPC, D>(g, tl, a, sv, ss, pcr, ring, tol2, &flag);
+      it = stream_bicgstab<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag);
     kr_sum += it;
     kr_max = it > kr_max ? it : kr_max;
     const double* f = a.forcing.base ? at(a.forcing, a.forcing.a * q + a.forcing.b + j) : nullptr;
