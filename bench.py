@@ -176,6 +176,9 @@ def main(argv=None):
     ap.add_argument("--mms-sweep", action="store_true",
                     help="instead of the metric: the manufactured heat family of Section 4.2 "
                          "over d = 2..6 and two levels each (one JSON line per case)")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="instead of the metric: only the streaming-kernel workload (the "
+                         "paper-size 2-D oscillator), one JSON line")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plan's default launch shapes (no autotuning)")
     ap.add_argument("--save-shapes", default=None,
@@ -194,7 +197,7 @@ def main(argv=None):
 
     from workloads import targets
     par = None
-    if not args.mms_sweep:
+    if not (args.mms_sweep or args.streaming_only):
         prob = workload_problem(args.workload, "mixed")
         if not args.no_cpu:
             # the parallel oracle runs first: its worker processes start
@@ -210,6 +213,10 @@ def main(argv=None):
     if args.mms_sweep:
         torch.cuda.set_device(0)
         return mms_sweep(ctm, torch)
+    if args.streaming_only:
+        torch.cuda.set_device(0)
+        print(json.dumps(_streaming(ctm, torch)), flush=True)
+        return 0
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     plan = ctm.Plan(prob)

@@ -211,7 +211,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.ctm_plan_destroy(h)
             self._h = None
 
