@@ -135,6 +135,17 @@ typedef struct {
   double drift[CTM_MAXD * CTM_MAXD]; /* CTM_OP_DRIFT: theta, row-major d x d (row i = the
                          velocity component along axis i) */
   double diffusion[CTM_MAXD];        /* CTM_OP_DRIFT: H_ii = (2 sigma D sigma^T)_ii >= 0 */
+  int residual_mode;  /* nonzero: MGRIT in space-time residual mode (the optimized oscillator
+                         run of Section 4.4, XBraid's residual option). Every implicit step is
+                         exactly krylov_maxit Krylov iterations from the previous iterate at
+                         its time point (an inexact step; no NOCONV), the coarse equation is
+                         A_c e_m = e_{m-1} + rho_m with rho_m = u_{cm-1} - A u_cm computed
+                         exactly, and mgrit_tol bounds the largest relative space-time
+                         residual over the C-points and the F-steps of the F-relaxation. The
+                         fixed point is still the time-sequential solution. Needs prec =
+                         FP64, two MGRIT levels, warm_start, no manufactured forcing and no
+                         grid beyond the on-chip solver; krylov_tol and coarse_tol are
+                         unused. */
 } ctm_problem;
 
 typedef struct {

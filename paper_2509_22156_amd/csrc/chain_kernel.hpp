@@ -63,7 +63,7 @@ __device__ __forceinline__ void sapply(const Solver<OPC, T, K>& S, const T (&x)[
 template <int OPC, typename T, int W, int K>
 __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
                                           const T (&b)[K], bool x_zero, bool check_first,
-                                          T tol2, int maxit, int* flag) {
+                                          T tol2, int maxit, int* flag, T* rr0 = nullptr) {
   T r[K], z[K], w[K], p[K], s[K];
   if (x_zero) {
 #pragma unroll
@@ -82,6 +82,7 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
       s2[1] += b[k] * b[k];
     }
     block_sum<W, 2, T>(s2, ring);
+    if (rr0) *rr0 = s2[0];
     if (!finite_val(s2[0]) || !finite_val(s2[1])) {
       *flag |= FLAG_NONFINITE;
       return 0;
@@ -100,6 +101,7 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
     red[3] += b[k] * b[k];
   }
   block_sum<W, 4, T>(red, ring);
+  if (rr0 && !(check_first && !x_zero)) *rr0 = red[2];
   const T bb = x_zero ? red[2] : red[3];
   if (!finite_val(red[2]) || !finite_val(red[1]) || !finite_val(bb)) {
     *flag |= FLAG_NONFINITE;
@@ -156,7 +158,7 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
 template <int OPC, typename T, int W, int K>
 __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedRing& ring,
                                                 T (&x)[K], const T (&b)[K], bool x_zero, T tol2,
-                                                int maxit, int* flag) {
+                                                int maxit, int* flag, T* rr0 = nullptr) {
   T r[K], rh[K], p[K], v[K], s[K], t[K], h[K];
   if (x_zero) {
 #pragma unroll
@@ -175,6 +177,7 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
     s1[1] += b[k] * b[k];
   }
   block_sum<W, 2, T>(s1, ring);
+  if (rr0) *rr0 = s1[0];
   const T bb = x_zero ? s1[0] : s1[1];
   if (!finite_val(s1[0]) || !finite_val(bb)) {
     *flag |= FLAG_NONFINITE;
@@ -245,11 +248,11 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
 template <int OPC, int SOLVER, typename T, int W, int K>
 __device__ __forceinline__ int krylov(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
                                       const T (&b)[K], bool x_zero, T tol2, int maxit,
-                                      int* flag, bool check_first = false) {
+                                      int* flag, bool check_first = false, T* rr0 = nullptr) {
   if constexpr (SOLVER == SOLV_CG)
-    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, check_first, tol2, maxit, flag);
+    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, check_first, tol2, maxit, flag, rr0);
   else
-    return krylov_pbicgstab<OPC, T, W, K>(S, ring, x, b, x_zero, tol2, maxit, flag);
+    return krylov_pbicgstab<OPC, T, W, K>(S, ring, x, b, x_zero, tol2, maxit, flag, rr0);
 }
 
 __device__ __forceinline__ double* vec_at(const VecRef& r, long long idx, long long slen,
@@ -366,11 +369,23 @@ __device__ __forceinline__ void step_single32(const Solver<OPC, float, K>& S32, 
   kr_max = it > kr_max ? it : kr_max;
 }
 
-// FORCED (heat only): the steps add the manufactured-problem forcing; a
-// separate instantiation, so that the forcing's transcendental functions do
-// not raise the register budget of the unforced kernels.
-template <int OPC, int SOLVER, bool MIXED, bool FORCED, int W, int K>
+// MODE_FORCED (heat only): the steps add the manufactured-problem forcing;
+// a separate instantiation, so that the forcing's transcendental functions
+// do not raise the register budget of the plain kernels.
+// MODE_RESIDUAL (FP64): space-time residual mode of MGRIT. Every step is a
+// fixed number of Krylov iterations from the given initial guess (an
+// inexact step that refines the previous iterate), the forcing is added
+// before the step (the coarse equation A_c e_m = e_{m-1} + rho_m), and in
+// residual mode (target given) the last step is replaced by the exact
+// space-time residual rho = v - A target; the task's residual norm is the
+// largest over that and the initial residuals of its other steps.
+enum { MODE_PLAIN = 0, MODE_FORCED = 1, MODE_RESIDUAL = 2 };
+
+template <int OPC, int SOLVER, bool MIXED, int MODE, int W, int K>
 __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
+  constexpr bool FORCED = (MODE == MODE_FORCED);
+  constexpr bool RES = (MODE == MODE_RESIDUAL);
+  static_assert(!(RES && MIXED), "residual mode is FP64");
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
   const ChainSmem lay = chain_smem_layout(W, K, tabmax, MIXED, OPC == OPC_HEAT);
@@ -435,6 +450,7 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
   const Solver<OPC, double, K> S64{g, L, O64, M64, xl64};
   const Solver<OPC, float, K> S32{g, L, O32, M32, xl32};
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
+  double res_max = 0.0;  // residual mode: largest squared residual of the task's steps
 
   for (int j = 1; j <= a.nsteps; ++j) {
     // heat (few registers in use): the forcing of this step is loaded
@@ -461,24 +477,57 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
 #pragma unroll
       for (int k = 0; k < K; ++k) v[k] += a.dt * fj[k];
     }
-    if constexpr (MIXED) {
-      if (a.single32)
-        step_single32<OPC, SOLVER, W, K>(S32, ring, v, itol2, a.maxit, x, &flag, kr_sum, kr_max);
-      else
-        step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit,
-                                      x, &flag, kr_sum, kr_max, rf_sum, rf_max);
-    } else {
-      step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, gr.base != nullptr, x, &flag,
-                                   kr_sum, kr_max);
-    }
-    if (a.forcing.base) {
-      if (!kEarly)
-        gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
+    if constexpr (RES) {
+      if (a.forcing.base) {  // before the step
+        if (!kEarly)
+          gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[k] = x[k] + f[k];
-    } else {
+        for (int k = 0; k < K; ++k) v[k] += f[k];
+      }
+      if (last && a.target.base) {
+        // exact space-time residual at the C-point: rho = v - A target
+        double tg[K], y[K];
+        gload<K>(L, vec_at(a.target, a.target.a * q + a.target.b, a.slen, off), tg);
+        sapply<OPC, double, W, K>(S64, tg, y);
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[k] = x[k];
+        for (int k = 0; k < K; ++k) v[k] = (k < L.nval) ? v[k] - y[k] : 0.0;
+      } else {
+        // fixed-count inexact step from the previous iterate; its initial
+        // residual enters the task's residual norm
+        double r0 = 0.0;
+        const int it = krylov<OPC, SOLVER, double, W, K>(S64, ring, x, v, false, 0.0, a.maxit,
+                                                         &flag, gr.base != nullptr, &r0);
+        // an inexact step ends where it ends: the iteration limit, or a
+        // vanishing BiCGStab denominator once the step's residual is ~0,
+        // leaves a valid iterate (the space-time residual test decides)
+        flag &= ~(FLAG_NOCONV | FLAG_BREAKDOWN);
+        kr_sum += it;
+        kr_max = it > kr_max ? it : kr_max;
+        res_max = r0 > res_max ? r0 : res_max;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = x[k];
+      }
+    } else {
+      if constexpr (MIXED) {
+        if (a.single32)
+          step_single32<OPC, SOLVER, W, K>(S32, ring, v, itol2, a.maxit, x, &flag, kr_sum,
+                                           kr_max);
+        else
+          step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit,
+                                        x, &flag, kr_sum, kr_max, rf_sum, rf_max);
+      } else {
+        step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, gr.base != nullptr, x, &flag,
+                                     kr_sum, kr_max);
+      }
+      if (a.forcing.base) {
+        if (!kEarly)
+          gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = x[k] + f[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = x[k];
+      }
     }
     if (a.inter.base && j < a.nsteps)
       gstore<K>(L, vec_at(a.inter, a.inter.a * q + a.inter.b + j, a.slen, off), v);
@@ -487,16 +536,22 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
   if (a.fin.base) {
     double* dst = vec_at(a.fin, a.fin.a * q + a.fin.b, a.slen, off);
     if (a.target.base) {
-      double tg[K];
-      gload<K>(L, vec_at(a.target, a.target.a * q + a.target.b, a.slen, off), tg);
       double rr[1] = {0.0};
+      if constexpr (RES) {  // v holds the exact residual already
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        v[k] = (k < L.nval) ? v[k] - tg[k] : 0.0;
-        rr[0] += v[k] * v[k];
+        for (int k = 0; k < K; ++k) rr[0] += v[k] * v[k];
+      } else {
+        double tg[K];
+        gload<K>(L, vec_at(a.target, a.target.a * q + a.target.b, a.slen, off), tg);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          v[k] = (k < L.nval) ? v[k] - tg[k] : 0.0;
+          rr[0] += v[k] * v[k];
+        }
       }
       gstore<K>(L, dst, v);
       block_sum<W, 1, double>(rr, ring);
+      if (RES) rr[0] = rr[0] > res_max ? rr[0] : res_max;
       if (threadIdx.x == 0 && a.res2) a.res2[blockIdx.x] = rr[0];
     } else {
       gstore<K>(L, dst, v);
@@ -520,12 +575,17 @@ template <int OPC, int SOLVER>
 hipError_t launch_chain_t(bool mixed, int shape, const ChainArgs& a, int ntasks, size_t smem,
                           int tabmax, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-  // the manufactured forcing exists for the heat operator only
+  // the manufactured forcing exists for the heat operator only; residual
+  // mode is FP64 only
   const bool forced = (OPC == OPC_HEAT) && a.fkind;
-  constexpr bool kF = (OPC == OPC_HEAT);
+  constexpr int kF = (OPC == OPC_HEAT) ? MODE_FORCED : MODE_PLAIN;
+  if (a.resmode && (mixed || forced)) return hipErrorInvalidValue;
 #define CTM_CASE(IDX, W, K)                                                                  \
   case IDX:                                                                                  \
-    if (forced) {                                                                            \
+    if (a.resmode) {                                                                         \
+      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, MODE_RESIDUAL, W, K>),            \
+                         dim3(ntasks), dim3(64 * W), smem, s, a, tabmax);                    \
+    } else if (forced) {                                                                     \
       if (mixed)                                                                             \
         hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, kF, W, K>), dim3(ntasks),        \
                            dim3(64 * W), smem, s, a, tabmax);                                \
@@ -533,10 +593,10 @@ hipError_t launch_chain_t(bool mixed, int shape, const ChainArgs& a, int ntasks,
         hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, kF, W, K>), dim3(ntasks),       \
                            dim3(64 * W), smem, s, a, tabmax);                                \
     } else if (mixed) {                                                                      \
-      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, false, W, K>), dim3(ntasks),       \
+      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, MODE_PLAIN, W, K>), dim3(ntasks),  \
                          dim3(64 * W), smem, s, a, tabmax);                                  \
     } else {                                                                                 \
-      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, false, W, K>), dim3(ntasks),      \
+      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, MODE_PLAIN, W, K>), dim3(ntasks), \
                          dim3(64 * W), smem, s, a, tabmax);                                  \
     }                                                                                        \
     break;

@@ -285,6 +285,12 @@ ctm_status validate(const ctm_problem* p) {
     return fail(CTM_ERR_INVALID, "mixed precision needs refine_tol, inner_tol > 0, refine_maxit >= 1");
   if (!(p->coarse_tol >= 0) || !(p->coarse_tol < 1))
     return fail(CTM_ERR_INVALID, "coarse_tol must be in [0, 1)");
+  if (p->residual_mode != 0 &&
+      (p->residual_mode != 1 || p->prec != CTM_PREC_FP64 || p->mgrit_levels != 2 ||
+       !p->warm_start || p->manufactured != CTM_MMS_NONE))
+    return fail(CTM_ERR_INVALID,
+                "residual_mode needs prec FP64, two MGRIT levels, warm_start and no manufactured "
+                "forcing");
   if (p->op == CTM_OP_DRIFT) {
     for (int i = 0; i < p->d; ++i)
       if (!(p->diffusion[i] >= 0) || !std::isfinite(p->diffusion[i]))
@@ -417,7 +423,10 @@ void set_shape(ctm_plan* P, int g, int sh) {
   assign_lanes(P);
 }
 
-ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) {
+// mgrit: arguments of an MGRIT relaxation or coarse chain (residual mode
+// applies there only; plain time stepping always solves to tolerance).
+ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false,
+                    bool mgrit = false) {
   ChainArgs a;
   std::memset(&a, 0, sizeof(a));
   a.grids = P->dgrids;
@@ -433,6 +442,10 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
   a.inner_tol = P->prob.inner_tol;
   a.status = reinterpret_cast<int*>(P->dsync + 1);
   a.skip = P->skip;
+  if (mgrit && P->prob.residual_mode) {  // fixed-count steps on every level
+    a.resmode = 1;
+    a.tol = 0.0;
+  }
   // the forcing enters the level-0 steps only (coarse levels solve for
   // corrections, whose right-hand sides are residuals)
   if (level == 0 && P->prob.manufactured == CTM_MMS_HEAT) {
@@ -448,9 +461,9 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false) 
 // by itself (>= 1e-5) makes each coarse step a single FP32 solve; otherwise
 // the inner FP32 target follows it.
 ChainArgs coarse_args(ctm_plan* P, int level, int nsteps) {
-  ChainArgs a = base_args(P, level, nsteps);
+  ChainArgs a = base_args(P, level, nsteps, false, true);
   const double ct = P->prob.coarse_tol;
-  if (ct > 0) {
+  if (ct > 0 && !a.resmode) {
     a.tol = ct;
     a.inner_tol = std::max(P->prob.inner_tol, 0.25 * ct);
     if (P->mixed && ct >= 1e-5) {
@@ -1049,7 +1062,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     }
     double* C;
     if (fcf) {
-      ChainArgs fc = base_args(P, 0, (int)c);
+      ChainArgs fc = base_args(P, 0, (int)c, false, true);
       fc.ftq = (double)c * fc.dt;  // task q starts at fine step c q
       fc.start = vref(U, 1, 0);
       fc.fin = vref(Un, 1, 1);
@@ -1068,7 +1081,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
       C = U;
     }
     Cit[it] = C;
-    ChainArgs fr = base_args(P, 0, (int)c);
+    ChainArgs fr = base_args(P, 0, (int)c, false, true);
     fr.ftq = (double)c * fr.dt;
     fr.start = vref(C, 1, 0);
     fr.fin = vref(lay.R[1], 1, 1);
@@ -1333,6 +1346,10 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     }
   }
   if (nstream) {
+    if (prob->residual_mode) {
+      delete P;
+      return fail(CTM_ERR_INVALID, "residual_mode needs every grid on chip");
+    }
     if (prob->manufactured != CTM_MMS_NONE) {
       delete P;
       return fail(CTM_ERR_INVALID, "the manufactured forcing needs every grid on chip");

@@ -76,7 +76,8 @@ struct ChainArgs {
   int single32;             // mixed path: each step is one FP32 solve to inner_tol (no
                             // FP64 refinement); for loose coarse-level tolerances
   int fkind;                // forcing: 0 none, 1 manufactured heat problem (heat only)
-  int pad_;
+  int resmode;              // MGRIT residual mode (FP64): fixed-count steps, forcing before
+                            // the step, exact space-time residual against a target
   double ft0, ftq;          // time of step j of task q: ft0 + q ftq + j dt
   double tol;               // FP64 path Krylov tolerance, or mixed refinement tolerance
   double inner_tol;         // mixed path FP32 Krylov tolerance

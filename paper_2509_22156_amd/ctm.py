@@ -44,6 +44,7 @@ class Problem(ctypes.Structure):
         ("coarse_tol", ctypes.c_double), ("warm_start", ctypes.c_int),
         ("manufactured", ctypes.c_int),
         ("drift", ctypes.c_double * (MAXD * MAXD)), ("diffusion", ctypes.c_double * MAXD),
+        ("residual_mode", ctypes.c_int),
     ]
 
 
@@ -174,6 +175,7 @@ def problem_struct(prob: dict):
     s.coarse_tol = float(prob.get("coarse_tol", 0.0))
     s.warm_start = int(prob.get("warm_start", 1))
     s.manufactured = 1 if prob.get("manufactured") == "heat" else 0
+    s.residual_mode = int(prob.get("residual_mode", 0))
     if prob["op"] == "drift":
         th = np.asarray(prob["drift"], dtype=np.float64)
         for i in range(d):

@@ -80,6 +80,10 @@ def _create(prob):
     (lambda s: setattr(s, "t1", -1.0), "t1"),
     (lambda s: setattr(s, "coarse_tol", -1e-3), "coarse_tol"),
     (lambda s: setattr(s, "coarse_tol", 1.0), "coarse_tol"),
+    (lambda s: (setattr(s, "residual_mode", 1), setattr(s, "prec", 1)), "residual_mode"),
+    (lambda s: (setattr(s, "residual_mode", 1), setattr(s, "mgrit_levels", 3)), "residual_mode"),
+    (lambda s: (setattr(s, "residual_mode", 1), setattr(s, "warm_start", 0)), "residual_mode"),
+    (lambda s: setattr(s, "residual_mode", 2), "residual_mode"),
 ])
 def test_invalid_problems_rejected_on_host(mutate, msg):
     s, keep = _create(make("heat2d"))
@@ -108,7 +112,8 @@ def test_status_strings():
 
 
 def test_lines_beyond_streaming_limit_rejected():
-    # lines of 2,047 unknowns exceed the streaming preconditioner's LDS lines
+    # lines of 2,047 unknowns exceed the streaming preconditioner's line
+    # segments (16 unknowns per lane, one wave)
     s, keep = ctm.problem_struct(make("heat2d", n=12))
     h = ctypes.c_void_p()
     assert ctm.lib().ctm_plan_create(ctypes.byref(s), ctypes.byref(h)) == ctm.ERR_INVALID
@@ -124,3 +129,13 @@ def test_shape_entry_points_reject_null_plan():
     rep = ctm.TuneReport()
     assert lib.ctm_autotune(None, None, 0, None, 0, 1, ctypes.byref(rep), None) == 1
     assert "NULL" in lib.ctm_last_error().decode()
+
+
+def test_residual_mode_needs_on_chip_grids():
+    p = make("heat2d", n=10, nsteps=32, t1=0.05)
+    p.update(residual_mode=1, krylov_maxit=2)
+    s, keep = ctm.problem_struct(p)
+    h = ctypes.c_void_p()
+    assert ctm.lib().ctm_plan_create(ctypes.byref(s), ctypes.byref(h)) == ctm.ERR_INVALID
+    assert "on chip" in ctm.lib().ctm_last_error().decode()
+    assert not h.value
