@@ -143,9 +143,8 @@ typedef struct {
                          exactly, and mgrit_tol bounds the largest relative space-time
                          residual over the C-points and the F-steps of the F-relaxation. The
                          fixed point is still the time-sequential solution. Needs prec =
-                         FP64, two MGRIT levels, warm_start, no manufactured forcing and no
-                         grid beyond the on-chip solver; krylov_tol and coarse_tol are
-                         unused. */
+                         FP64, two MGRIT levels, warm_start and no manufactured forcing;
+                         krylov_tol and coarse_tol are unused. */
 } ctm_problem;
 
 typedef struct {
@@ -185,8 +184,9 @@ ctm_status ctm_problem_defaults(ctm_problem* p);
  * 1..CTM_MAXD, n + d - 1 > 30, no grid with l >= L0, more than 65,535
  * grids, N not divisible by s * c^(levels-1), nonpositive tolerances, CG for
  * a non-symmetric operator, a grid with more than 2^20 unknowns or a line
- * longer than 1,024, the manufactured forcing on a streaming grid, lattice
- * box with hi - lo != 2^n. */
+ * longer than 1,024, the manufactured forcing on a streaming grid, residual
+ * mode outside its conditions (ctm_problem.residual_mode), lattice box with
+ * hi - lo != 2^n. */
 ctm_status ctm_plan_create(const ctm_problem* p, ctm_plan** plan);
 void ctm_plan_destroy(ctm_plan* plan);
 

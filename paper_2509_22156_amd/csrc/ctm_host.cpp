@@ -1346,10 +1346,6 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     }
   }
   if (nstream) {
-    if (prob->residual_mode) {
-      delete P;
-      return fail(CTM_ERR_INVALID, "residual_mode needs every grid on chip");
-    }
     if (prob->manufactured != CTM_MMS_NONE) {
       delete P;
       return fail(CTM_ERR_INVALID, "the manufactured forcing needs every grid on chip");

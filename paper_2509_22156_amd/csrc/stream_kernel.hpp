@@ -383,7 +383,7 @@ __device__ double stream_linepre_apply(const GridDev& g, const double* sv, long 
 // Preconditioned CG (symmetric operators).
 template <int OPC, int D>
 __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a, double* sv,
-                         long long ss, RedRing& ring, double tol2, int* flag) {
+                         long long ss, RedRing& ring, double tol2, int* flag, double* rr0) {
   double* X = sv + SV_X * ss;
   double* B = sv + SV_B * ss;
   double* R = sv + SV_R * ss;
@@ -405,6 +405,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
     *flag |= FLAG_NONFINITE;
     return 0;
   }
+  *rr0 = s0[0];  // the initial residual (residual mode's F-step norm)
   if (s0[0] <= tol2 * bb) return 0;
   double rz1[1] = {stream_linepre_apply<D>(g, sv, ss, R, Z, R)};
   block_sum<kStreamW, 1, double>(rz1, ring);
@@ -449,7 +450,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
 template <int OPC, int D>
 __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainArgs& a,
                                double* sv, long long ss, RedRing& ring, double tol2,
-                               int* flag) {
+                               int* flag, double* rr0) {
   double* X = sv + SV_X * ss;
   double* B = sv + SV_B * ss;
   double* R = sv + SV_R * ss;
@@ -476,6 +477,7 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
     *flag |= FLAG_NONFINITE;
     return 0;
   }
+  *rr0 = s0[0];  // the initial residual (residual mode's F-step norm)
   if (s0[0] <= tol2 * bb) return 0;
   double rho = s0[0];
   for (int it = 1; it <= a.maxit; ++it) {
@@ -588,25 +590,50 @@ __global__ void __launch_bounds__(kStreamThreads)
   int flag = 0;
   long long kr_sum = 0, kr_max = 0;
   const double tol2 = a.tol * a.tol;
+  // residual mode (as in the on-chip kernel): fixed-count steps from the
+  // previous iterate, the forcing before the step, and the exact space-time
+  // residual rho = v - A target in place of the last step
+  const bool res = a.resmode != 0;
+  double res_max = 0.0;
+  bool have_rho = false;
   for (int j = 1; j <= a.nsteps; ++j) {
     const bool last = (j == a.nsteps);
+    const double* f = a.forcing.base ? at(a.forcing, a.forcing.a * q + a.forcing.b + j) : nullptr;
+    double* is = (a.inter.base && j < a.nsteps) ? at(a.inter, a.inter.a * q + a.inter.b + j)
+                                                 : nullptr;
+    if (res && f) {
+      for (int p = threadIdx.x; p < np; p += kStreamThreads) B[p] += f[p];
+      __syncthreads();
+    }
+    if (res && last && a.target.base) {
+      const double* tg = at(a.target, a.target.a * q + a.target.b);
+      double* Q = sv + SV_Q * ss;
+      stream_apply<OPC, D>(g, tl, a.dt, a.amp, tg, Q, nullptr);
+      __syncthreads();
+      for (int p = threadIdx.x; p < np; p += kStreamThreads) B[p] -= Q[p];
+      __syncthreads();
+      have_rho = true;
+      break;
+    }
     const VecRef gr = last ? a.guess_fin : a.guess;
     const double* gx = gr.base ? at(gr, gr.a * q + gr.b + (last ? 0 : j)) : nullptr;
     for (int p = threadIdx.x; p < np; p += kStreamThreads) X[p] = gx ? gx[p] : B[p];
     __syncthreads();
     int it;
+    double r0 = 0.0;
     if constexpr (SOLVER == SOLV_CG)
-      it = stream_cg<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag);
+      it = stream_cg<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag, &r0);
     else
-      it = stream_bicgstab<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag);
+      it = stream_bicgstab<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag, &r0);
+    if (res) {
+      flag &= ~(FLAG_NOCONV | FLAG_BREAKDOWN);
+      res_max = r0 > res_max ? r0 : res_max;
+    }
     kr_sum += it;
     kr_max = it > kr_max ? it : kr_max;
-    const double* f = a.forcing.base ? at(a.forcing, a.forcing.a * q + a.forcing.b + j) : nullptr;
-    double* is = (a.inter.base && j < a.nsteps) ? at(a.inter, a.inter.a * q + a.inter.b + j)
-                                                 : nullptr;
     __syncthreads();  // every thread's X final
     for (int p = threadIdx.x; p < np; p += kStreamThreads) {
-      const double v = X[p] + (f ? f[p] : 0.0);
+      const double v = X[p] + ((f && !res) ? f[p] : 0.0);
       B[p] = v;
       if (is) is[p] = v;
     }
@@ -614,15 +641,17 @@ __global__ void __launch_bounds__(kStreamThreads)
   }
   if (a.fin.base) {
     double* dst = at(a.fin, a.fin.a * q + a.fin.b);
-    const double* tg = a.target.base ? at(a.target, a.target.a * q + a.target.b) : nullptr;
+    const double* tg = (a.target.base && !have_rho) ? at(a.target, a.target.a * q + a.target.b)
+                                                     : nullptr;
     double rr[1] = {0.0};
     for (int p = threadIdx.x; p < np; p += kStreamThreads) {
       const double v = tg ? B[p] - tg[p] : B[p];
       dst[p] = v;
       rr[0] += v * v;
     }
-    if (tg) {
+    if (a.target.base) {
       block_sum<kStreamW, 1, double>(rr, ring);
+      if (res) rr[0] = rr[0] > res_max ? rr[0] : res_max;
       if (threadIdx.x == 0 && a.res2) a.res2[blockIdx.x] = rr[0];
     }
   }

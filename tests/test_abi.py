@@ -129,13 +129,3 @@ def test_shape_entry_points_reject_null_plan():
     rep = ctm.TuneReport()
     assert lib.ctm_autotune(None, None, 0, None, 0, 1, ctypes.byref(rep), None) == 1
     assert "NULL" in lib.ctm_last_error().decode()
-
-
-def test_residual_mode_needs_on_chip_grids():
-    p = make("heat2d", n=10, nsteps=32, t1=0.05)
-    p.update(residual_mode=1, krylov_maxit=2)
-    s, keep = ctm.problem_struct(p)
-    h = ctypes.c_void_p()
-    assert ctm.lib().ctm_plan_create(ctypes.byref(s), ctypes.byref(h)) == ctm.ERR_INVALID
-    assert "on chip" in ctm.lib().ctm_last_error().decode()
-    assert not h.value

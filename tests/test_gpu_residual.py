@@ -7,7 +7,6 @@ F-relaxation, residual tolerance 1e-4, two Krylov iterations per step) the
 result is held to the accuracy such a tolerance gives."""
 import sys
 
-import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -74,3 +73,38 @@ def test_residual_mode_paper_settings_oscillator():
     # sum of the residuals over the steps (a useless 0.3 here). The bar is
     # empirical: 1e-3, against ~5e-6 measured on MI355X.
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("relax", ["FCF", "F"])
+def test_residual_mode_streaming_grids(relax):
+    # level 10: the grids (10, 1) and (1, 10) run on the streaming kernel
+    p = make("heat2d", n=10, nsteps=32, t1=0.05)
+    p.update(RES, relax=relax, cf=4)
+    _say(f"residual mode with streaming grids {relax}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    assert any(s["K"] == 0 for s in st["shapes"])
+    assert st["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(u, ref) <= 1e-11, rel_l2(u, ref)
+
+
+@pytest.mark.parametrize("tol,bar", [(1e-10, 1e-9), (1e-4, 1e-3)])
+def test_residual_mode_paper_level_oscillator(tol, bar):
+    # the paper's own levels (L = 14, L0 = 6, every grid on the streaming
+    # path) with the optimized run's settings, on a shorter interval (288
+    # steps of 1/3204) so that the oracle finishes in seconds
+    p = make("fp_osc2d", n=14, L0=6, t1=288 / 3204, nsteps=288)
+    p.update(cf=12, relax="F", prec="fp64", krylov_maxit=2, residual_mode=1, mgrit_tol=tol,
+             mgrit_maxit=200)
+    _say(f"residual mode paper-level oscillator tol={tol}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    _say(f"  iterations {st['mgrit_iterations']}")
+    assert st["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    err = rel_l2(u, ref)
+    _say(f"  rel. L2 against the sequential solution {err:.2e}")
+    assert err <= bar
