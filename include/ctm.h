@@ -142,9 +142,10 @@ typedef struct {
                          A_c e_m = e_{m-1} + rho_m with rho_m = u_{cm-1} - A u_cm computed
                          exactly, and mgrit_tol bounds the largest relative space-time
                          residual over the C-points and the F-steps of the F-relaxation. The
-                         fixed point is still the time-sequential solution. Needs prec =
-                         FP64, two MGRIT levels, warm_start and no manufactured forcing;
-                         krylov_tol and coarse_tol are unused. */
+                         fixed point is still the time-sequential solution; every coarser
+                         level solves its equation in the same residual form. Needs prec =
+                         FP64, MGRIT (two or more levels), warm_start and no manufactured
+                         forcing; krylov_tol and coarse_tol are unused. */
 } ctm_problem;
 
 typedef struct {

@@ -26,7 +26,7 @@ def _say(msg):
 def _small(name):
     return make(name, **{
         "heat3d": dict(n=6, nsteps=64, t1=0.05),
-        "ou4d": dict(n=5, nsteps=64, t1=0.25, mgrit_levels=2),
+        "ou4d": dict(n=5, nsteps=64, t1=0.25),  # three levels
         "fp_osc2d": dict(n=9, L0=4, nsteps=32),
         "fp_lin4d": dict(n=5, nsteps=32, prec="fp64"),
     }[name])
