@@ -191,8 +191,9 @@ def main(argv=None):
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
-              "(per-GPU sharding by component grid is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (it would "
+              "shard by component grid, with one all-reduce of the combined target vector per "
+              "recombination step)", file=sys.stderr)
         return 2
 
     from workloads import targets
