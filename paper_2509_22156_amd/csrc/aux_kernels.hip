@@ -226,28 +226,43 @@ __device__ double interp_grid(const GridDev& g, const double* __restrict__ u, co
   return acc;
 }
 
-__global__ void gather_kernel(const GridDev* __restrict__ grids, int G,
-                              const double* __restrict__ u, const double* __restrict__ pts,
-                              long long npts, double* __restrict__ out) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= npts) return;
+// One work-group of kGatherSplit waves per 64 points: wave w sums the grids
+// w, w + kGatherSplit, ... for the same 64 points (the grid index stays
+// uniform across a wave, so the descriptors come through scalar loads), and
+// the partial sums are added in LDS in wave order.
+constexpr int kGatherSplit = 4;
+
+__global__ void __launch_bounds__(64 * kGatherSplit)
+    gather_kernel(const GridDev* __restrict__ grids, int G, const double* __restrict__ u,
+                  const double* __restrict__ pts, long long npts, double* __restrict__ out) {
+  __shared__ double part[kGatherSplit][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long j = (long long)blockIdx.x * 64 + lane;
+  const bool live = j < npts;
   const int d = grids[0].d;
   double x[MAXD];
 #pragma unroll
-  for (int i = 0; i < MAXD; ++i) x[i] = (i < d) ? pts[j * d + i] : 0.0;
+  for (int i = 0; i < MAXD; ++i) x[i] = (live && i < d) ? pts[j * d + i] : 0.0;
   double acc = 0.0;
-  for (int gi = 0; gi < G; ++gi) {
+  for (int gi = w; gi < G; gi += kGatherSplit) {
     const GridDev& g = grids[gi];
     acc += g.coef * interp_grid(g, u, x);
   }
-  out[j] = acc;
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && live) {
+    double s = part[0][lane];
+#pragma unroll
+    for (int k = 1; k < kGatherSplit; ++k) s += part[k][lane];
+    out[j] = s;
+  }
 }
 
 hipError_t launch_gather(const GridDev* grids, int G, const double* u, const double* pts,
                          long long npts, double* out, hipStream_t s) {
   if (npts <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, grids,
-                     G, u, pts, npts, out);
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((npts + 63) / 64)), dim3(64 * kGatherSplit),
+                     0, s, grids, G, u, pts, npts, out);
   return hipGetLastError();
 }
 
