@@ -143,9 +143,12 @@ typedef struct {
                          exactly, and mgrit_tol bounds the largest relative space-time
                          residual over the C-points and the F-steps of the F-relaxation. The
                          fixed point is still the time-sequential solution; every coarser
-                         level solves its equation in the same residual form. Needs prec =
-                         FP64, MGRIT (two or more levels), warm_start and no manufactured
-                         forcing; krylov_tol and coarse_tol are unused. */
+                         level solves its equation in the same residual form. In the mixed
+                         precision a step is one FP32 correction solve of krylov_maxit
+                         iterations on the FP64 residual, ended early at inner_tol (the
+                         FP32 noise floor); streaming grids step in FP64. Needs MGRIT (two
+                         or more levels), warm_start and no manufactured forcing;
+                         krylov_tol, coarse_tol and refine_tol are unused. */
 } ctm_problem;
 
 typedef struct {

@@ -372,9 +372,10 @@ __device__ __forceinline__ void step_single32(const Solver<OPC, float, K>& S32, 
 // MODE_FORCED (heat only): the steps add the manufactured-problem forcing;
 // a separate instantiation, so that the forcing's transcendental functions
 // do not raise the register budget of the plain kernels.
-// MODE_RESIDUAL (FP64): space-time residual mode of MGRIT. Every step is a
-// fixed number of Krylov iterations from the given initial guess (an
-// inexact step that refines the previous iterate), the forcing is added
+// MODE_RESIDUAL: space-time residual mode of MGRIT. Every step is a fixed
+// number of Krylov iterations from the given initial guess (an inexact step
+// that refines the previous iterate; in the mixed path one FP32 correction
+// solve of that many iterations on the FP64 residual), the forcing is added
 // before the step (the coarse equation A_c e_m = e_{m-1} + rho_m), and in
 // residual mode (target given) the last step is replaced by the exact
 // space-time residual rho = v - A target; the task's residual norm is the
@@ -385,7 +386,6 @@ template <int OPC, int SOLVER, bool MIXED, int MODE, int W, int K>
 __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
   constexpr bool FORCED = (MODE == MODE_FORCED);
   constexpr bool RES = (MODE == MODE_RESIDUAL);
-  static_assert(!(RES && MIXED), "residual mode is FP64");
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
   const ChainSmem lay = chain_smem_layout(W, K, tabmax, MIXED, OPC == OPC_HEAT);
@@ -495,8 +495,43 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
         // fixed-count inexact step from the previous iterate; its initial
         // residual enters the task's residual norm
         double r0 = 0.0;
-        const int it = krylov<OPC, SOLVER, double, W, K>(S64, ring, x, v, false, 0.0, a.maxit,
-                                                         &flag, gr.base != nullptr, &r0);
+        int it;
+        if constexpr (MIXED) {
+          // x += d, A d = v - A x solved in FP32 by a.maxit iterations
+          double rq[K];
+          sapply<OPC, double, W, K>(S64, x, rq);
+          double rr[1] = {0.0};
+          float r32[K], d32[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            rq[k] = v[k] - rq[k];
+            rr[0] += rq[k] * rq[k];
+            r32[k] = 0.0f;
+            d32[k] = 0.0f;
+          }
+          block_sum<W, 1, double>(rr, ring);
+          r0 = rr[0];
+          it = 0;
+          if (r0 > 0.0 && finite_val(r0)) {
+            // the residual is normalised before rounding to FP32
+            const double nr = sqrt(r0), inv = 1.0 / nr;
+#pragma unroll
+            for (int k = 0; k < K; ++k) r32[k] = (float)(rq[k] * inv);
+            int iflag = 0;
+            // FP32 stops at inner_tol (its own noise floor) if it gets
+            // there before a.maxit iterations
+            it = krylov<OPC, SOLVER, float, W, K>(S32, ring, d32, r32, true, itol2, a.maxit,
+                                                  &iflag);
+            flag |= iflag & FLAG_NONFINITE;
+#pragma unroll
+            for (int k = 0; k < K; ++k) x[k] += nr * (double)d32[k];
+          } else if (!finite_val(r0)) {
+            flag |= FLAG_NONFINITE;
+          }
+        } else {
+          it = krylov<OPC, SOLVER, double, W, K>(S64, ring, x, v, false, 0.0, a.maxit, &flag,
+                                                 gr.base != nullptr, &r0);
+        }
         // an inexact step ends where it ends: the iteration limit, or a
         // vanishing BiCGStab denominator once the step's residual is ~0,
         // leaves a valid iterate (the space-time residual test decides)
@@ -579,12 +614,16 @@ hipError_t launch_chain_t(bool mixed, int shape, const ChainArgs& a, int ntasks,
   // mode is FP64 only
   const bool forced = (OPC == OPC_HEAT) && a.fkind;
   constexpr int kF = (OPC == OPC_HEAT) ? MODE_FORCED : MODE_PLAIN;
-  if (a.resmode && (mixed || forced)) return hipErrorInvalidValue;
+  if (a.resmode && forced) return hipErrorInvalidValue;
 #define CTM_CASE(IDX, W, K)                                                                  \
   case IDX:                                                                                  \
     if (a.resmode) {                                                                         \
-      hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, MODE_RESIDUAL, W, K>),            \
-                         dim3(ntasks), dim3(64 * W), smem, s, a, tabmax);                    \
+      if (mixed)                                                                             \
+        hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, MODE_RESIDUAL, W, K>),           \
+                           dim3(ntasks), dim3(64 * W), smem, s, a, tabmax);                  \
+      else                                                                                   \
+        hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, false, MODE_RESIDUAL, W, K>),          \
+                           dim3(ntasks), dim3(64 * W), smem, s, a, tabmax);                  \
     } else if (forced) {                                                                     \
       if (mixed)                                                                             \
         hipLaunchKernelGGL((chain_kernel<OPC, SOLVER, true, kF, W, K>), dim3(ntasks),        \

@@ -286,11 +286,11 @@ ctm_status validate(const ctm_problem* p) {
   if (!(p->coarse_tol >= 0) || !(p->coarse_tol < 1))
     return fail(CTM_ERR_INVALID, "coarse_tol must be in [0, 1)");
   if (p->residual_mode != 0 &&
-      (p->residual_mode != 1 || p->prec != CTM_PREC_FP64 || p->mgrit_levels < 2 ||
-       !p->warm_start || p->manufactured != CTM_MMS_NONE))
+      (p->residual_mode != 1 || p->mgrit_levels < 2 || !p->warm_start ||
+       p->manufactured != CTM_MMS_NONE))
     return fail(CTM_ERR_INVALID,
-                "residual_mode needs prec FP64, MGRIT (two or more levels), warm_start and no "
-                "manufactured forcing");
+                "residual_mode needs MGRIT (two or more levels), warm_start and no manufactured "
+                "forcing");
   if (p->op == CTM_OP_DRIFT) {
     for (int i = 0; i < p->d; ++i)
       if (!(p->diffusion[i] >= 0) || !std::isfinite(p->diffusion[i]))

@@ -80,7 +80,7 @@ def _create(prob):
     (lambda s: setattr(s, "t1", -1.0), "t1"),
     (lambda s: setattr(s, "coarse_tol", -1e-3), "coarse_tol"),
     (lambda s: setattr(s, "coarse_tol", 1.0), "coarse_tol"),
-    (lambda s: (setattr(s, "residual_mode", 1), setattr(s, "prec", 1)), "residual_mode"),
+    (lambda s: (setattr(s, "residual_mode", 1), setattr(s, "manufactured", 1)), "residual_mode"),
     (lambda s: (setattr(s, "residual_mode", 1), setattr(s, "mgrit_levels", 1)), "residual_mode"),
     (lambda s: (setattr(s, "residual_mode", 1), setattr(s, "warm_start", 0)), "residual_mode"),
     (lambda s: setattr(s, "residual_mode", 2), "residual_mode"),

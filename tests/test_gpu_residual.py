@@ -52,6 +52,22 @@ def test_residual_mode_reaches_sequential_solution(name, relax):
     assert rel_l2(u, ref) <= 1e-11, rel_l2(u, ref)
 
 
+@pytest.mark.parametrize("name", ["heat3d", "ou4d", "fp_lin4d"])
+def test_residual_mode_mixed_precision(name):
+    # one FP32 correction solve of two iterations per step on the FP64
+    # residual; the space-time residual is FP64, so the fixed point is the
+    # same
+    p = _small(name)
+    p.update(RES, prec="mixed", mgrit_tol=1e-11)
+    _say(f"residual mode mixed {name}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    assert st["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(u, ref) <= 1e-8, rel_l2(u, ref)
+
+
 def test_residual_mode_paper_settings_oscillator():
     # Section 4.4, optimized run: T = 1, c = 12, F-relaxation, two temporal
     # levels, residual tolerance 1e-4, two iterations of the spatial solver
