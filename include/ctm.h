@@ -279,7 +279,8 @@ ctm_status ctm_plan_grid_shape(const ctm_plan* plan, int g, int* waves, int* per
  * cannot hold the grid's lines (every line of n_s unknowns needs
  * 2^ceil(log2(ceil(n_s / per_lane))) <= 64 lanes of one wave), and grids on
  * the streaming solver. Results do not depend on the shape beyond rounding;
- * the next solve uses it. */
+ * the next solve uses it. The plan's task lists are rebuilt (device memory
+ * is freed and allocated): call it with no work of this plan in flight. */
 ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lane);
 
 typedef struct {

@@ -782,53 +782,40 @@ ctm_status fork_lanes(ctm_plan* P, hipStream_t s) {
 
 // One MGRIT cycle on level l >= 1 for the residual equation. On the last
 // level, e_m for m >= 1 is written and e_0 (= 0, cleared once per block) is
-// left alone. per_class: every step runs per size class on the class's lane
-// with no cross-stream synchronisation (each class's steps read only what
-// the same class wrote; the lanes must have been forked from s before);
-// otherwise every phase is forked from and joined back into s. The first
-// residual vector r_0 of every level is cleared once per block.
-ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool per_class) {
+// left alone; with open_last the last level's chain runs per size class on
+// the lanes forked before, without a join (the readers of its output run on
+// the same lanes). Every other phase is forked from and joined back into s.
+// The first residual vector r_0 of every level is cleared once per block.
+ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last) {
   const long long c = lay.c;
   double* G = lay.R[l];
   double* E = lay.E[l];
-  const bool sync = !per_class;
-  const VecRef none = vref(nullptr, 0, 0);
   ctm_status st;
   if (l == lay.L - 1) {
     ChainArgs a = coarse_args(P, l, (int)lay.N[l]);
-    a.start = none;
+    a.start = vref(nullptr, 0, 0);
     a.forcing = vref(G, 0, 0);
     a.inter = vref(E, 0, 0);
     a.fin = vref(E, 0, lay.N[l]);
     TaskSet* single = nullptr;
     if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
-    return run_chain(P, a, *single, s, false, sync, sync);
+    return run_chain(P, a, *single, s, false, !open_last, !open_last);
   }
   const long long M = lay.N[l] / c;
   TaskSet* tasks = nullptr;
   if ((st = tasks_for(P, M, &tasks)) != CTM_OK) return st;
-  // the error starts from zero at this level's C-points (its F-points are
-  // written before they are read)
-  if (per_class) {
-    if ((st = class_vec_add(P, vref(E, c, 0), none, none, M, s)) != CTM_OK) return st;
-  } else {
-    CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s, P->skip));
-  }
+  CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s, P->skip));
   double* csrc;
   long long ca;
   if (P->prob.relax == CTM_RELAX_FCF) {
     double* Cn = lay.Cn[l];
-    if (per_class) {
-      if ((st = class_vec_add(P, vref(Cn, 0, 0), none, none, 1, s)) != CTM_OK) return st;
-    } else {
-      CTM_HIP(launch_fill_zero(Cn, P->slen, s, P->skip));
-    }
+    CTM_HIP(launch_fill_zero(Cn, P->slen, s, P->skip));
     ChainArgs fc = coarse_args(P, l, (int)c);
     fc.start = vref(E, c, 0);
     fc.forcing = vref(G, c, 0);
     fc.inter = vref(E, c, 0);
     fc.fin = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fc, *tasks, s, false, sync, sync)) != CTM_OK) return st;
+    if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
     ChainArgs fr = coarse_args(P, l, (int)c);
     fr.start = vref(Cn, 1, 0);
     fr.start_wb = vref(E, c, 0);
@@ -836,7 +823,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool per_class)
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fr, *tasks, s, false, sync, sync)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
     csrc = Cn;
     ca = 1;
   } else {
@@ -846,26 +833,20 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool per_class)
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(E, c, c);
-    if ((st = run_chain(P, fr, *tasks, s, false, sync, sync)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
     csrc = E;
     ca = c;
   }
-  if ((st = cycle(P, lay, l + 1, s, per_class)) != CTM_OK) return st;
+  if ((st = cycle(P, lay, l + 1, s, false)) != CTM_OK) return st;
   // correction at the C-points, then F-relaxation (ideal interpolation)
-  if (per_class) {
-    if ((st = class_vec_add(P, vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0),
-                            M + 1, s)) != CTM_OK)
-      return st;
-  } else {
-    CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0),
-                           (int)(M + 1), P->slen, s, P->skip));
-  }
+  CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0), (int)(M + 1),
+                         P->slen, s, P->skip));
   ChainArgs fi = coarse_args(P, l, (int)(c - 1));
   fi.start = vref(E, c, 0);
   fi.forcing = vref(G, c, 0);
   fi.inter = vref(E, c, 0);
   fi.fin = vref(E, c, c - 1);
-  return run_chain(P, fi, *tasks, s, false, sync, sync);
+  return run_chain(P, fi, *tasks, s);
 }
 
 // Node map of the hierarchical basis: every unknown named by its node on
@@ -1106,7 +1087,7 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
       if (fcf) {
         if (per_class) {
           // the lanes see the convergence test (its stop flag), then run the
-          // cycle and the correction class by class
+          // coarse chain and the correction class by class
           if ((st = fork_lanes(P, s)) != CTM_OK) return st;
           if ((st = cycle(P, lay, 1, s, true)) != CTM_OK) return st;
           if ((st = correct_by_class(P, U, Un, lay.E[1], M0, s)) != CTM_OK) return st;
@@ -1533,6 +1514,10 @@ ctm_status ctm_solve(ctm_plan* P, void* ws, size_t ws_bytes, const double* u0, d
     if (b > 0 && (st = recombine(P, lay.Y, lay.X, hs)) != CTM_OK) return st;
     P->block_t0 = P->prob.t0 + (double)(b * Nb) * dt0;
     st = mgrit_block(P, lay, hs);
+    // the caller's stream waits for the side lanes whatever happened (an
+    // error can leave a phase running on them)
+    const ctm_status js = join_lanes(P, hs);
+    if (st == CTM_OK && js != CTM_OK) st = js;
     P->stats.blocks += 1;
     if (st == CTM_ERR_NOCONV) {
       result = st;
