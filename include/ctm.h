@@ -283,6 +283,18 @@ ctm_status ctm_plan_grid_shape(const ctm_plan* plan, int g, int* waves, int* per
  * is freed and allocated): call it with no work of this plan in flight. */
 ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lane);
 
+/* Grids beyond the on-chip shapes (the streaming solver): a launch of at
+ * most max_tasks such tasks (grid, interval) - typically MGRIT's sequential
+ * coarse chain or time-sequential stepping, one task per grid - spreads
+ * every task over many work-groups (one launch per Krylov phase, reductions
+ * across work-groups); larger launches keep one 1,024-thread work-group per
+ * task. The same operator, preconditioner, Krylov method and stopping test
+ * (Section 4.1), so results agree to rounding. A wide launch waits on the
+ * host once per step for its convergence test (the stream's earlier work
+ * included), so ctm_solve and ctm_step return only when that part is done.
+ * max_tasks in [0, 64]; 0 disables; the default is 32. */
+ctm_status ctm_plan_set_wide(ctm_plan* plan, int max_tasks);
+
 typedef struct {
   int classes;       /* anisotropy classes with more than one candidate shape */
   int trials;        /* timed trial solves run */

@@ -127,6 +127,19 @@ struct ctm_plan {
   // for each of up to stream_tasks tasks
   long long stream_ss = 0, stream_tasks = 0;
   double* dstream = nullptr;
+  // wide streaming solver: launch ranges of at most wide_max_tasks streaming
+  // tasks spread every task over wide_pb (point-wise) / wide_lb (line)
+  // work-groups; per-task state and partial sums for up to kWideCap tasks;
+  // the poll's busy count in mapped pinned memory
+  static constexpr int kWideCap = 64;
+  int wide_max_tasks = 32;
+  int wide_pb = 0, wide_lb = 0, wide_maxblk = 0;
+  WideTask* dwide = nullptr;
+  double* dwpart = nullptr;
+  int* hwide = nullptr;
+  int* hwide_dev = nullptr;
+  int wide_est = 4;  // Krylov iterations launched per step before the first poll
+  hipEvent_t wide_ev = nullptr;
   // MGRIT convergence on the device: dmg[0] = stopping iteration (0 while
   // running), dmg[2 it], dmg[2 it + 1] = residual and dmg[0] after iteration
   // it; hmg its pinned per-iteration mirror; skip = dmg while a block's
@@ -165,6 +178,10 @@ struct ctm_plan {
     hipFree(dhcoef);
     hipFree(dhsg);
     hipFree(dstream);
+    hipFree(dwide);
+    hipFree(dwpart);
+    if (hwide) hipHostFree(hwide);
+    if (wide_ev) hipEventDestroy(wide_ev);
     hipFree(dmg);
     if (hmg) hipHostFree(hmg);
     for (auto e : it_events) hipEventDestroy(e);
@@ -503,6 +520,81 @@ hipEvent_t take_event(ctm_plan* P, size_t& used, std::vector<hipEvent_t>& pool, 
   return pool[used++];
 }
 
+// Whether a launch range runs on the wide streaming solver.
+bool use_wide(const ctm_plan* P, int shape, long long count) {
+  return shape == kStreamShape && count > 0 && count <= P->wide_max_tasks;
+}
+
+// The chain of a launch range on the wide solver: per step, the step
+// transition, the initial residual and Krylov iterations in batches; after a
+// batch, a poll kernel applies the next stopping test and the host waits for
+// its busy count (the only host synchronisation), then launches more
+// iterations or the next step. The first batch of a step has as many
+// iterations as the previous step needed. Residual mode iterates a fixed
+// count and never waits.
+ctm_status run_wide(ctm_plan* P, const ChainArgs& c, int count, hipStream_t s) {
+  WideArgs w{};
+  w.a = c;
+  w.scratch = P->dstream;
+  w.ss = P->stream_ss;
+  w.st = P->dwide;
+  w.part = P->dwpart;
+  w.maxblk = P->wide_maxblk;
+  w.host_out = P->hwide_dev;
+  const dim3 gp(P->wide_pb, count), gl(P->wide_lb, count);
+  const bool bicg = (P->solver == SOLV_BICG);
+  const bool res = c.resmode != 0;
+  auto go = [&](int kind, dim3 grid) -> ctm_status {
+    const hipError_t e = launch_wide(P->opc, P->solver, P->d, kind, w, grid, P->tabmax, count, s);
+    if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("wide launch: ") + hipGetErrorString(e));
+    return CTM_OK;
+  };
+  ctm_status st;
+  if ((st = go(WK_SETUP, gl)) != CTM_OK) return st;
+  int prev = 0;
+  for (int j = 1; j <= c.nsteps; ++j) {
+    w.j = j;
+    w.prev_its = prev;
+    if ((st = go(WK_STEP, gp)) != CTM_OK) return st;
+    if (res && j == c.nsteps && c.target.base) break;  // the step kernel formed the residual
+    if ((st = go(WK_INIT, gp)) != CTM_OK) return st;
+    int i = 1;  // next iteration
+    if (bicg) {
+      w.i = 1;
+      if ((st = go(WK_BA, gl)) != CTM_OK) return st;
+    }
+    int budget = res ? c.maxit : std::max(1, std::min(c.maxit, P->wide_est));
+    for (;;) {
+      for (int n = 0; n < budget && i <= c.maxit; ++n, ++i) {
+        w.i = i;
+        if (bicg) {
+          if ((st = go(WK_BB, gp)) != CTM_OK) return st;
+          if ((st = go(WK_BC, gl)) != CTM_OK) return st;
+          if ((st = go(WK_BD, gp)) != CTM_OK) return st;
+          w.i = i + 1;
+          if ((st = go(WK_BA, gl)) != CTM_OK) return st;
+        } else {
+          if ((st = go(WK_CA, gl)) != CTM_OK) return st;
+          if ((st = go(WK_CB, gp)) != CTM_OK) return st;
+          if ((st = go(WK_CC, gp)) != CTM_OK) return st;
+        }
+      }
+      w.i = i;
+      if ((st = go(WK_POLL, dim3(1, 1))) != CTM_OK) return st;
+      if (res || i > c.maxit) break;
+      CTM_HIP(hipEventRecord(P->wide_ev, s));
+      CTM_HIP(hipEventSynchronize(P->wide_ev));
+      if (__atomic_load_n(P->hwide, __ATOMIC_ACQUIRE) == 0) break;
+      budget = std::max(1, (i - 1) / 4);
+    }
+    prev = i - 1;
+    if (!res) P->wide_est = std::max(1, prev);
+  }
+  w.j = c.nsteps;
+  w.prev_its = prev;
+  return go(WK_FIN, gp);
+}
+
 // One launch of the chain kernel for the tasks [offset, offset + count) of a
 // task array, all of one shape, on stream s.
 ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int shape,
@@ -528,8 +620,14 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   hipError_t e;
   if (shape == kStreamShape) {
     if (count > P->stream_tasks) return fail(CTM_ERR_INVALID, "streaming launch exceeds its scratch");
-    e = launch_stream(P->opc, P->solver, P->d, c, (int)count, P->tabmax, P->dstream,
-                      P->stream_ss, s);
+    if (use_wide(P, shape, count)) {
+      ctm_status st = run_wide(P, c, (int)count, s);
+      if (st != CTM_OK) return st;
+      e = hipSuccess;
+    } else {
+      e = launch_stream(P->opc, P->solver, P->d, c, (int)count, P->tabmax, P->dstream,
+                        P->stream_ss, s);
+    }
   } else {
     e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tabmax, s);
   }
@@ -577,7 +675,12 @@ ctm_status run_chain(ctm_plan* P, const ChainArgs& a, const TaskSet& ts, hipStre
   // launch order: decreasing work (unknowns x tasks)
   std::vector<int> order(ts.ranges.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  // (ranges on the wide solver wait for their poll on the host: they go last,
+  // once everything else of the phase is queued)
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const bool wx = use_wide(P, ts.ranges[x].shape, ts.ranges[x].count);
+    const bool wy = use_wide(P, ts.ranges[y].shape, ts.ranges[y].count);
+    if (wx != wy) return wy;
     return ts.ranges[x].points > ts.ranges[y].points;
   });
   size_t used = 0;
@@ -1341,6 +1444,17 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     const long long M = (prob->mgrit_levels > 1) ? std::max<long long>(1, nb / prob->mgrit_cf) : 1;
     P->stream_ss = ((long long)maxstream + 63) / 64 * 64;
     P->stream_tasks = (long long)nstream * M;
+    // work-groups per task of the wide solver, for the largest grid
+    for (int g = 0; g < P->G; ++g) {
+      if (P->gshape[g] != kStreamShape) continue;
+      const GridDev& gd = P->hdev[g];
+      int Lc = 1;
+      while (Lc < (gd.ns + kWideSK - 1) / kWideSK) Lc <<= 1;
+      const int waves = (gd.nlines + 64 / Lc - 1) / (64 / Lc);
+      P->wide_lb = std::max(P->wide_lb, (waves + kWW - 1) / kWW);
+      P->wide_pb = std::max(P->wide_pb, (gd.npts + kWP - 1) / kWP);
+    }
+    P->wide_maxblk = std::max(P->wide_pb, P->wide_lb);
   }
   assign_lanes(P);
   if (P->htab.empty()) P->htab.push_back(0.0);
@@ -1382,6 +1496,14 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
         (size_t)P->stream_tasks * kStreamVectors * (size_t)P->stream_ss * sizeof(double);
     if (hipMalloc(&P->dstream, bytes) != hipSuccess)
       return cleanup(fail(CTM_ERR_NOMEM, "streaming scratch allocation failed"));
+    const int cap = ctm_plan::kWideCap;
+    CTM_HIPC(hipMalloc(&P->dwide, cap * sizeof(WideTask)));
+    CTM_HIPC(hipMemset(P->dwide, 0, cap * sizeof(WideTask)));
+    CTM_HIPC(hipMalloc(&P->dwpart, (size_t)cap * WS_N * P->wide_maxblk * sizeof(double)));
+    CTM_HIPC(hipHostMalloc(&P->hwide, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    *P->hwide = 0;
+    CTM_HIPC(hipHostGetDevicePointer(reinterpret_cast<void**>(&P->hwide_dev), P->hwide, 0));
+    CTM_HIPC(hipEventCreateWithFlags(&P->wide_ev, hipEventDisableTiming));
   }
   {
     const size_t nmg = 2 * (size_t)(std::max(1, prob->mgrit_maxit) + 1);
@@ -1582,6 +1704,14 @@ ctm_status ctm_plan_set_grid_shape(ctm_plan* P, int g, int waves, int per_lane) 
   if (gd.ns > 64 * per_lane || lanes_needed(gd, per_lane) > 64 * waves)
     return fail(CTM_ERR_INVALID, "the launch shape cannot hold the grid's lines");
   set_shape(P, g, sh);
+  return CTM_OK;
+}
+
+ctm_status ctm_plan_set_wide(ctm_plan* P, int max_tasks) {
+  if (!P) return fail(CTM_ERR_INVALID, "plan is NULL");
+  if (max_tasks < 0 || max_tasks > ctm_plan::kWideCap)
+    return fail(CTM_ERR_INVALID, "max_tasks must be in [0, 64]");
+  P->wide_max_tasks = max_tasks;
   return CTM_OK;
 }
 

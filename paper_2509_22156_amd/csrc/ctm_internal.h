@@ -132,6 +132,65 @@ hipError_t launch_stream_apply(int opc, int d, const GridDev* grids, int G, cons
                                double amp, double dt, int tabmax, const double* x, double* y,
                                hipStream_t s);
 
+// Wide streaming solver (wide_kernel.hpp, wide_ops.hip): the implicit steps
+// of a few streaming tasks, each spread over many work-groups; one launch
+// per Krylov phase, driven step by step from the host.
+constexpr int kWT = 256;           // threads per work-group
+constexpr int kWW = kWT / 64;      // waves per work-group
+constexpr int kWPT = 2;            // points per thread in the point-wise kernels
+constexpr int kWP = kWT * kWPT;    // points per work-group
+constexpr int kWideSK = 16;        // unknowns per lane along a line (as the streaming kernel)
+
+// Reduced sums of a task.
+enum {
+  WS_RR0 = 0,  // (r0, r0) of the step
+  WS_BB,       // (b, b) of the step
+  WS_RHV,      // (r^, v)
+  WS_D = 3,    // t-phase of BiCGStab: WS_D + 5 parity + {ts, tt, ss, rhs, rht}
+  WS_RR = 13,  // (r, r) after the update
+  WS_PQ,       // CG: (p, q)
+  WS_RZ = 15,  // CG: (r, z), WS_RZ + parity
+  WS_FIN = 17, // ||fin||^2
+  WS_N = 18
+};
+// Reductions, one arrival counter each.
+enum { WR_INIT = 0, WR_RHV, WR_D, WR_RR, WR_PQ, WR_RZ, WR_FIN, WR_N };
+
+// Per-task state (device memory, one per task of the range).
+struct WideTask {
+  double sum[WS_N];
+  unsigned cnt[WR_N];
+  int done;       // the step's Krylov solve has stopped
+  int it;         // its iteration count
+  int pend;       // BiCGStab: breakdown found in the direction update
+  int flag;       // status bits of the chain
+  long long kr_sum, kr_max;
+  double res_max;  // residual mode: max initial residual over the steps
+};
+
+struct WideArgs {
+  ChainArgs a;
+  double* scratch;  // task t of the range: scratch + t * SV_N * ss (as the streaming kernel)
+  long long ss;
+  WideTask* st;     // [tasks of the range]
+  double* part;     // partial sums: [task][WS_N][maxblk]
+  int maxblk;
+  int j;            // step (1-based)
+  int i;            // Krylov iteration
+  int prev_its;     // iterations launched for the step being accounted
+  int* host_out;    // poll: tasks still iterating (mapped host memory)
+};
+
+// Kernels of the wide solver: SETUP (line factors, once per chain), STEP
+// (step transition), INIT (initial residual), BA..BD (BiCGStab phases), CA..CC
+// (CG phases), FIN (final store and accounting), POLL (one work-group: the
+// next stopping test, busy count to the host).
+enum WideKind { WK_SETUP = 0, WK_STEP, WK_INIT, WK_BA, WK_BB, WK_BC, WK_BD, WK_CA, WK_CB,
+                WK_CC, WK_FIN, WK_POLL };
+// grid: (blocks per task, tasks); ntasks: the poll's task count.
+hipError_t launch_wide(int opc, int solver, int d, int kind, const WideArgs& w, dim3 grid,
+                       int tabmax, int ntasks, hipStream_t s);
+
 // LDS copy of a vector the stencil reads: K rows (one per chunk position k)
 // of pitch 64 W + kLdsGhost; thread t owns column t, and the columns from
 // 64 W on hold zeros that lanes without a neighbour line read instead.

@@ -153,13 +153,14 @@ __device__ __forceinline__ int stream_line_rounds(const GridDev& g) {
   return (g.nlines + per_round - 1) / per_round;
 }
 
+// Lane `lane` of wave `vwave` of the task: the wave holds 64 / Lc line
+// segments, lines vwave * (64 / Lc) + lane / Lc.
 template <int D>
-__device__ __forceinline__ void stream_lane(const GridDev& g, int round, SLane& L) {
+__device__ __forceinline__ void stream_lane_at(const GridDev& g, int vwave, int lane, SLane& L) {
   const int Lc = pow2ceil((g.ns + kSK - 1) / kSK);
-  const int t = threadIdx.x, lane = t & 63;
   L.Lc = Lc;
   L.c = lane & (Lc - 1);
-  L.line = (round * kStreamW + (t >> 6)) * (64 / Lc) + lane / Lc;
+  L.line = vwave * (64 / Lc) + lane / Lc;
   L.j0 = L.c * kSK;
   const bool live = L.line < g.nlines;
   int nv = g.ns - L.j0;
@@ -176,6 +177,13 @@ __device__ __forceinline__ void stream_lane(const GridDev& g, int round, SLane& 
       b += (long long)((rem / g.lstride[m]) % g.n[ax]) * g.stride[ax];
     }
   L.base = b;
+}
+
+// The waves of the 1,024-thread work-group take the lines round by round.
+template <int D>
+__device__ __forceinline__ void stream_lane(const GridDev& g, int round, SLane& L) {
+  const int t = threadIdx.x;
+  stream_lane_at<D>(g, round * kStreamW + (t >> 6), t & 63, L);
 }
 
 // Stiff-axis couplings and diagonal of A at point p.
@@ -195,24 +203,22 @@ __device__ __forceinline__ void line_coef(const GridDev& g, const double* tl, do
   dg = c.diag;
 }
 
-// Factors of M for every chunk of the task, stored at the chunk's unknowns:
+// Factors of M for the chunk of lane L, stored at the chunk's unknowns:
 // FM = Thomas multipliers m_k (slot kSK-1: the diagonal of the interface
 // unknown), FID = reciprocal pivots, FCU = upper couplings inside the
 // chunk, FPHI/FPSI = responses of the eliminated unknowns to the previous
 // and own interface unknown (slot kSK-1: the interface's couplings aL, cL).
-// ftmp is a scratch vector (the forward spike). Called by every thread.
+// ftmp is a scratch vector (the forward spike).
 template <int OPC, int D>
-__device__ void stream_linepre_setup(const GridDev& g, const double* tl, double dt, double amp,
-                                     double* sv, long long ss, double* ftmp) {
+__device__ __forceinline__ void linepre_setup_lane(const GridDev& g, const double* tl, double dt,
+                                                   double amp, double* sv, long long ss,
+                                                   double* ftmp, const SLane& L) {
   double* FM = sv + SV_FM * ss;
   double* FID = sv + SV_FID * ss;
   double* FCU = sv + SV_FCU * ss;
   double* FPHI = sv + SV_FPHI * ss;
   double* FPSI = sv + SV_FPSI * ss;
-  const int rounds = stream_line_rounds(g);
-  for (int rd = 0; rd < rounds; ++rd) {
-    SLane L;
-    stream_lane<D>(g, rd, L);
+  {
     // forward over the eliminated unknowns k = 0..kSK-2
     double idp = 0.0, cp = 0.0, fp = 0.0;
 #pragma unroll 1
@@ -280,6 +286,18 @@ __device__ void stream_linepre_setup(const GridDev& g, const double* tl, double 
       php = ph;
       psp = ps;
     }
+  }
+}
+
+// The factors of every chunk of the task; called by every thread.
+template <int OPC, int D>
+__device__ void stream_linepre_setup(const GridDev& g, const double* tl, double dt, double amp,
+                                     double* sv, long long ss, double* ftmp) {
+  const int rounds = stream_line_rounds(g);
+  for (int rd = 0; rd < rounds; ++rd) {
+    SLane L;
+    stream_lane<D>(g, rd, L);
+    linepre_setup_lane<OPC, D>(g, tl, dt, amp, sv, ss, ftmp, L);
   }
 }
 

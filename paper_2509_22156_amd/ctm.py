@@ -103,6 +103,7 @@ def _load():
         "ctm_set_timing": [P, i],
         "ctm_plan_grid_shape": [P, i, ctypes.POINTER(i), ctypes.POINTER(i)],
         "ctm_plan_set_grid_shape": [P, i, i, i],
+        "ctm_plan_set_wide": [P, i],
         "ctm_autotune": [P, P, sz, P, i, i, ctypes.POINTER(TuneReport), P],
     }
     for name, args in sigs.items():
@@ -313,6 +314,11 @@ class Plan:
     def set_grid_shape(self, g: int, waves: int, per_lane: int):
         _check(_lib.ctm_plan_set_grid_shape(self._h, g, waves, per_lane))
 
+    def set_wide(self, max_tasks: int):
+        """Streaming-solver launches of at most max_tasks tasks run on the wide
+        (many work-groups per task) solver; 0 disables it (default 32)."""
+        _check(_lib.ctm_plan_set_wide(self._h, max_tasks))
+
     def autotune(self, trial_iterations: int = 0, repeats: int = 2) -> dict:
         """Choose the launch shape of every anisotropy class by timed trial
         solves (ctm_autotune); returns its report."""
@@ -333,5 +339,5 @@ def exported_symbols():
             "ctm_plan_grid_info", "ctm_plan_state_len", "ctm_plan_workspace_bytes",
             "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_gather",
             "ctm_combine_project", "ctm_hierarchize", "ctm_recombine", "ctm_get_stats", "ctm_set_timing", "ctm_plan_grid_shape",
-            "ctm_plan_set_grid_shape", "ctm_autotune", "ctm_status_string",
+            "ctm_plan_set_grid_shape", "ctm_plan_set_wide", "ctm_autotune", "ctm_status_string",
             "ctm_last_error"]

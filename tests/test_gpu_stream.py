@@ -109,3 +109,50 @@ def test_streaming_other_operators(name, kw):
     assert any(s["K"] == 0 for s in plan.stats()["shapes"])
     ref = solve.packed(solve.component_states(p))
     assert rel_l2(u, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("kw", [dict(mgrit_levels=1), dict(), dict(krylov="bicgstab"),
+                                dict(relax="F", cf=8), dict(krylov="bicgstab", mgrit_levels=1)])
+def test_streaming_wide_against_narrow(kw):
+    # the same solve with every streaming launch of at most 64 tasks on the
+    # wide solver (many work-groups per task), and with none: both meet the
+    # oracle, and agree with each other to the Krylov tolerance
+    p = _heat2d_big(**kw)
+    out = {}
+    for wide in (0, 64):
+        _say(f"streaming wide={wide} {kw}")
+        plan = ctm.Plan(p)
+        plan.set_wide(wide)
+        out[wide] = plan.solve().cpu().numpy()
+        st = plan.stats()
+        assert st["status_flags"] == 0
+        assert st["krylov_iterations"] > 0
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(out[0], ref) <= 1e-11
+    assert rel_l2(out[64], ref) <= 1e-11
+    assert rel_l2(out[64], out[0]) <= 1e-11
+
+
+def test_streaming_wide_drift_oscillator():
+    # the full-drift operator (BiCGStab) with every streaming launch wide
+    p = make("fp_osc2d", n=12, L0=3, nsteps=16)
+    p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100)
+    _say("streaming wide fp_osc2d")
+    plan = ctm.Plan(p)
+    plan.set_wide(64)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(u, ref) <= 1e-11
+
+
+def test_streaming_wide_noconv_flag():
+    # a Krylov cap the tolerance cannot meet: the wide solver stops at the
+    # cap and reports non-convergence, like the one-work-group kernel
+    p = _heat2d_big(mgrit_levels=1, krylov_maxit=2, krylov_tol=1e-14)
+    for wide in (0, 64):
+        plan = ctm.Plan(p)
+        plan.set_wide(wide)
+        _, code = plan.solve(check=False)
+        assert code == ctm.ERR_NOCONV, wide
+        assert plan.stats()["krylov_max"] == 2, wide
