@@ -488,25 +488,32 @@ def _streaming(ctm, torch):
     sec = time.perf_counter() - t0
     st = plan.stats()
     plan.set_timing(False)
-    cls = [sh for sh in st["shapes"] if sh["K"] == 0]
-    if not cls:
-        return None
-    c = cls[0]
     bpi = STREAM_BYTES_PER_ITERATION[p["krylov"]]
-    achieved = c["work"] * bpi / (c["ms"] / 1e3) / 1e9 if c["ms"] > 0 else None
+    forms = {16: ("stream_kernel<drift, BiCGStab>: one 1,024-thread work-group per task "
+                  "(F- and C-relaxation, many tasks)"),
+             4: ("wide solver: many 256-thread work-groups per task, one launch per Krylov "
+                 "phase (the sequential coarse chain, one task per grid)")}
+    roof = {}
+    for c in st["shapes"]:
+        if c["K"] != 0 or c["W"] not in forms:
+            continue
+        achieved = c["work"] * bpi / (c["ms"] / 1e3) / 1e9 if c["ms"] > 0 else None
+        roof["one_group_per_task" if c["W"] == 16 else "wide"] = {
+            "kernel": forms[c["W"]], "bound": "hbm", "achieved": achieved,
+            "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBPS if achieved else None,
+            "bytes_per_unknown_iteration": bpi, "ms": c["ms"],
+            "krylov_work": c["work"], "launches": c["launches"]}
+    if not roof:
+        return None
     return {
         "workload": f"fp_osc2d at L = 14, L0 = 6: {plan.G} grids, {plan.slen} DoF per level, "
                     f"{p['nsteps']} steps, 2-level MGRIT c = 2, BiCGStab, FP64",
         "seconds": sec,
         "value": plan.slen * p["nsteps"] / sec,
         "mgrit_iterations": st["mgrit_iterations"],
-        "roofline": {"kernel": "stream_kernel<drift, BiCGStab> (Krylov vectors in HBM)",
-                     "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS if achieved else None,
-                     "bytes_per_unknown_iteration": bpi,
-                     "avg_launch_ms": c["ms"] / max(c["launches"], 1),
-                     "launches": c["launches"]},
+        "krylov_iterations": st["krylov_iterations"],
+        "roofline": roof,
     }
 
 

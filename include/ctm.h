@@ -168,7 +168,10 @@ typedef struct {
   double chain_bytes;                 /* algorithmic HBM bytes those launches move: the
                                          vectors each task must read and write once */
   /* per launch shape (size class) of the implicit-step kernel: waves per
-     work-group, unknowns per lane, timed duration, launches, Krylov work */
+     work-group, unknowns per lane, timed duration, launches, Krylov work.
+     Grids on the streaming solver report unknowns per lane 0, with 16 waves
+     (one 1,024-thread work-group per task) or 4 (the wide solver, many
+     256-thread work-groups per task; a launch is its whole chain) */
   int shape_w[16], shape_k[16];
   double shape_ms[16];
   long long shape_launches[16];
@@ -284,15 +287,16 @@ ctm_status ctm_plan_grid_shape(const ctm_plan* plan, int g, int* waves, int* per
 ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lane);
 
 /* Grids beyond the on-chip shapes (the streaming solver): a launch of at
- * most max_tasks such tasks (grid, interval) - typically MGRIT's sequential
- * coarse chain or time-sequential stepping, one task per grid - spreads
- * every task over many work-groups (one launch per Krylov phase, reductions
- * across work-groups); larger launches keep one 1,024-thread work-group per
- * task. The same operator, preconditioner, Krylov method and stopping test
- * (Section 4.1), so results agree to rounding. A wide launch waits on the
- * host once per step for its convergence test (the stream's earlier work
- * included), so ctm_solve and ctm_step return only when that part is done.
- * max_tasks in [0, 64]; 0 disables; the default is 32. */
+ * most max_tasks such tasks (grid, interval) runs on the wide solver, which
+ * spreads every task over many work-groups (one launch per Krylov phase for
+ * all tasks of the launch, sums across work-groups); a larger launch keeps
+ * one 1,024-thread work-group per task. Both use the same operator,
+ * preconditioner, Krylov method and stopping test (Section 4.1), so results
+ * agree to rounding. A wide launch waits on the host once per step for its
+ * convergence test (the stream's earlier work included), so ctm_solve and
+ * ctm_step return only when that part is done. max_tasks >= 0 (capped at
+ * 65,535); 0 disables the wide solver; the default is 64 (MGRIT's coarse
+ * chain and time-sequential stepping: one task per grid). */
 ctm_status ctm_plan_set_wide(ctm_plan* plan, int max_tasks);
 
 typedef struct {

@@ -129,14 +129,19 @@ struct ctm_plan {
   double* dstream = nullptr;
   // wide streaming solver: launch ranges of at most wide_max_tasks streaming
   // tasks spread every task over wide_pb (point-wise) / wide_lb (line)
-  // work-groups; per-task state and partial sums for up to kWideCap tasks;
-  // the poll's busy count in mapped pinned memory
-  static constexpr int kWideCap = 64;
-  int wide_max_tasks = 32;
+  // work-groups; per-task state and partial sums for wide_cap tasks (every
+  // streaming task of the plan); the poll's busy flags in mapped pinned memory
+  // (default 64: the launches with few tasks - the sequential coarse chain,
+  // time-sequential stepping - where one work-group per task would leave
+  // most CUs idle; on the many-task relaxation launches the one-work-group
+  // kernel is as fast, its line sweeps run at higher occupancy)
+  static constexpr int kWideMaxGridY = 65535;
+  int wide_cap = 0;
+  int wide_max_tasks = 64;
   int wide_pb = 0, wide_lb = 0, wide_maxblk = 0;
   WideTask* dwide = nullptr;
   double* dwpart = nullptr;
-  int* hwide = nullptr;
+  int* hwide = nullptr;      // [wide_cap] the poll's per-task busy flags
   int* hwide_dev = nullptr;
   int wide_est = 4;  // Krylov iterations launched per step before the first poll
   hipEvent_t wide_ev = nullptr;
@@ -522,14 +527,15 @@ hipEvent_t take_event(ctm_plan* P, size_t& used, std::vector<hipEvent_t>& pool, 
 
 // Whether a launch range runs on the wide streaming solver.
 bool use_wide(const ctm_plan* P, int shape, long long count) {
-  return shape == kStreamShape && count > 0 && count <= P->wide_max_tasks;
+  return shape == kStreamShape && count > 0 && count <= P->wide_max_tasks &&
+         count <= P->wide_cap;
 }
 
 // The chain of a launch range on the wide solver: per step, the step
 // transition, the initial residual and Krylov iterations in batches; after a
 // batch, a poll kernel applies the next stopping test and the host waits for
-// its busy count (the only host synchronisation), then launches more
-// iterations or the next step. The first batch of a step has as many
+// its per-task busy flags (the only host synchronisation), then launches
+// more iterations or the next step. The first batch of a step has as many
 // iterations as the previous step needed. Residual mode iterates a fixed
 // count and never waits.
 ctm_status run_wide(ctm_plan* P, const ChainArgs& c, int count, hipStream_t s) {
@@ -545,7 +551,7 @@ ctm_status run_wide(ctm_plan* P, const ChainArgs& c, int count, hipStream_t s) {
   const bool bicg = (P->solver == SOLV_BICG);
   const bool res = c.resmode != 0;
   auto go = [&](int kind, dim3 grid) -> ctm_status {
-    const hipError_t e = launch_wide(P->opc, P->solver, P->d, kind, w, grid, P->tabmax, count, s);
+    const hipError_t e = launch_wide(P->opc, P->solver, P->d, kind, w, grid, P->tabmax, s);
     if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("wide launch: ") + hipGetErrorString(e));
     return CTM_OK;
   };
@@ -580,11 +586,13 @@ ctm_status run_wide(ctm_plan* P, const ChainArgs& c, int count, hipStream_t s) {
         }
       }
       w.i = i;
-      if ((st = go(WK_POLL, dim3(1, 1))) != CTM_OK) return st;
+      if ((st = go(WK_POLL, dim3(1, count))) != CTM_OK) return st;
       if (res || i > c.maxit) break;
       CTM_HIP(hipEventRecord(P->wide_ev, s));
       CTM_HIP(hipEventSynchronize(P->wide_ev));
-      if (__atomic_load_n(P->hwide, __ATOMIC_ACQUIRE) == 0) break;
+      int busy = 0;
+      for (int t = 0; t < count; ++t) busy += __atomic_load_n(P->hwide + t, __ATOMIC_ACQUIRE);
+      if (busy == 0) break;
       budget = std::max(1, (i - 1) / 4);
     }
     prev = i - 1;
@@ -592,7 +600,8 @@ ctm_status run_wide(ctm_plan* P, const ChainArgs& c, int count, hipStream_t s) {
   }
   w.j = c.nsteps;
   w.prev_its = prev;
-  return go(WK_FIN, gp);
+  if ((st = go(WK_FIN, gp)) != CTM_OK) return st;
+  return go(WK_FINISH, dim3(1, count));
 }
 
 // One launch of the chain kernel for the tasks [offset, offset + count) of a
@@ -603,24 +612,26 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   ChainArgs c = a;
   c.tasks = tasks + offset;
   if (a.res2) c.res2 = a.res2 + offset;
-  c.counters = P->dcounters + (size_t)shape * CNT_N;
+  const bool wide = use_wide(P, shape, count);
+  const int slot = wide ? kWideSlot : shape;  // statistics slot
+  c.counters = P->dcounters + (size_t)slot * CNT_N;
   const size_t smem =
       (shape == kStreamShape) ? 0 : chain_smem_bytes(shape, P->tabmax, mixed, P->opc == OPC_HEAT);
   // algorithmic bytes: every vector role of every task once
-  P->stats.shape_bytes[shape] += 8.0 * points * chain_vectors_per_task(a);
+  P->stats.shape_bytes[slot] += 8.0 * points * chain_vectors_per_task(a);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (P->timing) {
     e0 = take_event(P, P->events_used, P->events, true);
     e1 = take_event(P, P->events_used, P->events, true);
     if (!e0 || !e1) return fail(CTM_ERR_HIP, "event creation failed");
     P->event_shape.resize(P->events.size());
-    P->event_shape[P->events_used - 2] = shape;
+    P->event_shape[P->events_used - 2] = slot;
     CTM_HIP(hipEventRecord(e0, s));
   }
   hipError_t e;
   if (shape == kStreamShape) {
     if (count > P->stream_tasks) return fail(CTM_ERR_INVALID, "streaming launch exceeds its scratch");
-    if (use_wide(P, shape, count)) {
+    if (wide) {
       ctm_status st = run_wide(P, c, (int)count, s);
       if (st != CTM_OK) return st;
       e = hipSuccess;
@@ -745,7 +756,7 @@ void reset_stats(ctm_plan* P) {
 }
 
 ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
-  CTM_HIP(hipMemsetAsync(P->dcounters, 0, (kNumShapes + 1) * CNT_N * sizeof(unsigned long long), s));
+  CTM_HIP(hipMemsetAsync(P->dcounters, 0, kStatSlots * CNT_N * sizeof(unsigned long long), s));
   CTM_HIP(hipMemsetAsync(P->dsync, 0, 2 * sizeof(double), s));
   return CTM_OK;
 }
@@ -754,7 +765,7 @@ ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
 void fold_counters(const ctm_plan* P, const unsigned long long* c, ctm_stats* st) {
   st->krylov_iterations = st->krylov_max = st->refine_sweeps = st->refine_max = 0;
   st->phi_solves = st->krylov_work = 0;
-  for (int s = 0; s <= kStreamShape; ++s) {
+  for (int s = 0; s < kStatSlots; ++s) {
     const unsigned long long* k = c + (size_t)s * CNT_N;
     st->krylov_iterations += (long long)k[CNT_KRYLOV];
     st->krylov_max = std::max(st->krylov_max, (long long)k[CNT_KRYLOV_MAX]);
@@ -763,14 +774,16 @@ void fold_counters(const ctm_plan* P, const unsigned long long* c, ctm_stats* st
     st->phi_solves += (long long)k[CNT_SOLVES];
     st->krylov_work += (long long)k[CNT_WORK];
     st->shape_work[s] = (long long)k[CNT_WORK];
-    st->shape_w[s] = (s == kStreamShape) ? 16 : kShapes[s].W;  // streaming: 1,024 threads
-    st->shape_k[s] = (s == kStreamShape) ? 0 : kShapes[s].K;
+    // streaming: K = 0, and W = 16 (1,024 threads per task) or the wide
+    // solver's kWW waves per work-group
+    st->shape_w[s] = (s == kStreamShape) ? 16 : (s == kWideSlot) ? kWW : kShapes[s].W;
+    st->shape_k[s] = (s >= kStreamShape) ? 0 : kShapes[s].K;
   }
   (void)P;
 }
 
 ctm_status collect_device_stats(ctm_plan* P, hipStream_t s) {
-  unsigned long long c[(kNumShapes + 1) * CNT_N];
+  unsigned long long c[kStatSlots * CNT_N];
   CTM_HIP(hipMemcpyAsync(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost, s));
   CTM_HIP(hipMemcpyAsync(P->hsync, P->dsync, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   CTM_HIP(hipStreamSynchronize(s));
@@ -1451,7 +1464,7 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
       int Lc = 1;
       while (Lc < (gd.ns + kWideSK - 1) / kWideSK) Lc <<= 1;
       const int waves = (gd.nlines + 64 / Lc - 1) / (64 / Lc);
-      P->wide_lb = std::max(P->wide_lb, (waves + kWW - 1) / kWW);
+      P->wide_lb = std::max(P->wide_lb, (waves + kWLW - 1) / kWLW);
       P->wide_pb = std::max(P->wide_pb, (gd.npts + kWP - 1) / kWP);
     }
     P->wide_maxblk = std::max(P->wide_pb, P->wide_lb);
@@ -1485,8 +1498,8 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   CTM_HIPC(hipMemcpy(P->dicw, P->icw.data(), P->icw.size() * sizeof(double), hipMemcpyHostToDevice));
   CTM_HIPC(hipMalloc(&P->dicf, P->icf.size() * sizeof(double)));
   CTM_HIPC(hipMemcpy(P->dicf, P->icf.data(), P->icf.size() * sizeof(double), hipMemcpyHostToDevice));
-  CTM_HIPC(hipMalloc(&P->dcounters, (kNumShapes + 1) * CNT_N * sizeof(unsigned long long)));
-  CTM_HIPC(hipMemset(P->dcounters, 0, (kNumShapes + 1) * CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMalloc(&P->dcounters, kStatSlots * CNT_N * sizeof(unsigned long long)));
+  CTM_HIPC(hipMemset(P->dcounters, 0, kStatSlots * CNT_N * sizeof(unsigned long long)));
   CTM_HIPC(hipMalloc(&P->dsync, 2 * sizeof(double)));
   CTM_HIPC(hipMemset(P->dsync, 0, 2 * sizeof(double)));
   CTM_HIPC(hipMalloc(&P->dnorm2, P->G * sizeof(double)));
@@ -1496,12 +1509,14 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
         (size_t)P->stream_tasks * kStreamVectors * (size_t)P->stream_ss * sizeof(double);
     if (hipMalloc(&P->dstream, bytes) != hipSuccess)
       return cleanup(fail(CTM_ERR_NOMEM, "streaming scratch allocation failed"));
-    const int cap = ctm_plan::kWideCap;
+    const int cap = (int)std::min<long long>(P->stream_tasks, ctm_plan::kWideMaxGridY);
+    P->wide_cap = cap;
     CTM_HIPC(hipMalloc(&P->dwide, cap * sizeof(WideTask)));
     CTM_HIPC(hipMemset(P->dwide, 0, cap * sizeof(WideTask)));
     CTM_HIPC(hipMalloc(&P->dwpart, (size_t)cap * WS_N * P->wide_maxblk * sizeof(double)));
-    CTM_HIPC(hipHostMalloc(&P->hwide, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
-    *P->hwide = 0;
+    CTM_HIPC(hipHostMalloc(&P->hwide, cap * sizeof(int),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(P->hwide, 0, cap * sizeof(int));
     CTM_HIPC(hipHostGetDevicePointer(reinterpret_cast<void**>(&P->hwide_dev), P->hwide, 0));
     CTM_HIPC(hipEventCreateWithFlags(&P->wide_ev, hipEventDisableTiming));
   }
@@ -1709,9 +1724,8 @@ ctm_status ctm_plan_set_grid_shape(ctm_plan* P, int g, int waves, int per_lane) 
 
 ctm_status ctm_plan_set_wide(ctm_plan* P, int max_tasks) {
   if (!P) return fail(CTM_ERR_INVALID, "plan is NULL");
-  if (max_tasks < 0 || max_tasks > ctm_plan::kWideCap)
-    return fail(CTM_ERR_INVALID, "max_tasks must be in [0, 64]");
-  P->wide_max_tasks = max_tasks;
+  if (max_tasks < 0) return fail(CTM_ERR_INVALID, "max_tasks must be >= 0");
+  P->wide_max_tasks = std::min(max_tasks, ctm_plan::kWideMaxGridY);
   return CTM_OK;
 }
 
@@ -1815,7 +1829,7 @@ ctm_status ctm_get_stats(const ctm_plan* Pc, ctm_stats* st) {
     if (s2 != CTM_OK) return s2;
   }
   // counters live on the device; the caller has synchronised its stream
-  unsigned long long c[(kNumShapes + 1) * CNT_N];
+  unsigned long long c[kStatSlots * CNT_N];
   int flags = 0;
   CTM_HIP(hipMemcpy(c, P->dcounters, sizeof(c), hipMemcpyDeviceToHost));
   CTM_HIP(hipMemcpy(&flags, P->dsync + 1, sizeof(int), hipMemcpyDeviceToHost));

@@ -118,7 +118,10 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // Grids beyond the on-chip shapes go to the streaming kernel (vectors in HBM
 // scratch, one 1,024-thread work-group per task); its size class index:
 constexpr int kStreamShape = kNumShapes;
-static_assert(kNumShapes + 1 <= 16, "ctm_stats keeps 16 shape slots");
+// Statistics slot of the wide streaming solver (after the size classes).
+constexpr int kWideSlot = kNumShapes + 1;
+constexpr int kStatSlots = kNumShapes + 2;
+static_assert(kStatSlots <= 16, "ctm_stats keeps 16 shape slots");
 
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,
                         int ntasks, size_t smem, int tabmax, hipStream_t s);
@@ -135,13 +138,14 @@ hipError_t launch_stream_apply(int opc, int d, const GridDev* grids, int G, cons
 // Wide streaming solver (wide_kernel.hpp, wide_ops.hip): the implicit steps
 // of a few streaming tasks, each spread over many work-groups; one launch
 // per Krylov phase, driven step by step from the host.
-constexpr int kWT = 256;           // threads per work-group
-constexpr int kWW = kWT / 64;      // waves per work-group
+constexpr int kWT = 256;           // threads per point-wise work-group
+constexpr int kWW = kWT / 64;      // its waves
 constexpr int kWPT = 2;            // points per thread in the point-wise kernels
-constexpr int kWP = kWT * kWPT;    // points per work-group
+constexpr int kWP = kWT * kWPT;    // points per point-wise work-group
+constexpr int kWLW = 1;            // waves per line work-group
 constexpr int kWideSK = 16;        // unknowns per lane along a line (as the streaming kernel)
 
-// Reduced sums of a task.
+// Sums of a task; each has a partial per producing work-group.
 enum {
   WS_RR0 = 0,  // (r0, r0) of the step
   WS_BB,       // (b, b) of the step
@@ -153,13 +157,9 @@ enum {
   WS_FIN = 17, // ||fin||^2
   WS_N = 18
 };
-// Reductions, one arrival counter each.
-enum { WR_INIT = 0, WR_RHV, WR_D, WR_RR, WR_PQ, WR_RZ, WR_FIN, WR_N };
 
 // Per-task state (device memory, one per task of the range).
 struct WideTask {
-  double sum[WS_N];
-  unsigned cnt[WR_N];
   int done;       // the step's Krylov solve has stopped
   int it;         // its iteration count
   int pend;       // BiCGStab: breakdown found in the direction update
@@ -178,18 +178,19 @@ struct WideArgs {
   int j;            // step (1-based)
   int i;            // Krylov iteration
   int prev_its;     // iterations launched for the step being accounted
-  int* host_out;    // poll: tasks still iterating (mapped host memory)
+  int* host_out;    // poll: per task 1 while still iterating (mapped host memory)
 };
 
 // Kernels of the wide solver: SETUP (line factors, once per chain), STEP
 // (step transition), INIT (initial residual), BA..BD (BiCGStab phases), CA..CC
-// (CG phases), FIN (final store and accounting), POLL (one work-group: the
-// next stopping test, busy count to the host).
+// (CG phases), FIN (final store), FINISH (accounting, one wave per task),
+// POLL (one wave per task: the next stopping test, busy flag to the host).
+// SETUP, BA, BC and CA are line kernels.
 enum WideKind { WK_SETUP = 0, WK_STEP, WK_INIT, WK_BA, WK_BB, WK_BC, WK_BD, WK_CA, WK_CB,
-                WK_CC, WK_FIN, WK_POLL };
-// grid: (blocks per task, tasks); ntasks: the poll's task count.
+                WK_CC, WK_FIN, WK_FINISH, WK_POLL };
+// grid: (work-groups per task, tasks).
 hipError_t launch_wide(int opc, int solver, int d, int kind, const WideArgs& w, dim3 grid,
-                       int tabmax, int ntasks, hipStream_t s);
+                       int tabmax, hipStream_t s);
 
 // LDS copy of a vector the stencil reads: K rows (one per chunk position k)
 // of pitch 64 W + kLdsGhost; thread t owns column t, and the columns from

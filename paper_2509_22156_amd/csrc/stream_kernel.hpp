@@ -102,6 +102,24 @@ __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, d
   c.diag = diag;
 }
 
+// Neighbour indices of point p along axis i < D for the stencil: the point
+// itself where the neighbour is not an unknown or the axis is past the
+// grid's dimension (the coupling is zero there), computed without branches,
+// so that every load is unconditional and the loads of a point issue
+// together.
+template <int OPC, int D>
+__device__ __forceinline__ int stencil_lo(const GridDev& g, const PointCoef<OPC, D>& c, int i,
+                                          int p) {
+  const int has = (i < g.d) & (c.j[i] > 0);
+  return p - has * g.stride[i];
+}
+template <int OPC, int D>
+__device__ __forceinline__ int stencil_up(const GridDev& g, const PointCoef<OPC, D>& c, int i,
+                                          int p) {
+  const int has = (i < g.d) & (c.j[i] < g.n[i] - 1);
+  return p + has * g.stride[i];
+}
+
 // y = A x at every point of the task; returns this thread's part of
 // sum w[p] y[p] when w is given.
 template <int OPC, int D>
@@ -112,14 +130,15 @@ __device__ __forceinline__ double stream_apply(const GridDev& g, const double* t
   for (int p = threadIdx.x; p < g.npts; p += kStreamThreads) {
     PointCoef<OPC, D> c;
     point_coef<OPC, D>(g, tl, dt, amp, p, c);
-    double v = c.diag * x[p];
+    double xl[D], xu[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      if (i >= g.d) continue;
-      const int st = g.stride[i];
-      if (c.lo[i] != 0.0) v += c.lo[i] * x[p - st];
-      if (c.up[i] != 0.0) v += c.up[i] * x[p + st];
+      xl[i] = x[stencil_lo(g, c, i, p)];
+      xu[i] = x[stencil_up(g, c, i, p)];
     }
+    double v = c.diag * x[p];
+#pragma unroll
+    for (int i = 0; i < D; ++i) v += c.lo[i] * xl[i] + c.up[i] * xu[i];
     y[p] = v;
     if (w) acc += w[p] * v;
   }
@@ -517,14 +536,15 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
     for (int p = threadIdx.x; p < np; p += kStreamThreads) {
       PointCoef<OPC, D> c;
       point_coef<OPC, D>(g, tl, a.dt, a.amp, p, c);
-      double v = c.diag * H[p];
+      double hl[D], hu[D];
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        if (i >= g.d) continue;
-        const int st = g.stride[i];
-        if (c.lo[i] != 0.0) v += c.lo[i] * H[p - st];
-        if (c.up[i] != 0.0) v += c.up[i] * H[p + st];
+        hl[i] = H[stencil_lo(g, c, i, p)];
+        hu[i] = H[stencil_up(g, c, i, p)];
       }
+      double v = c.diag * H[p];
+#pragma unroll
+      for (int i = 0; i < D; ++i) v += c.lo[i] * hl[i] + c.up[i] * hu[i];
       T[p] = v;
       s3[0] += v * S[p];
       s3[1] += v * v;

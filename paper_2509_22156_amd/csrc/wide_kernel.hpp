@@ -5,7 +5,8 @@
 // MGRIT, one task per grid; time-sequential stepping). Every Krylov phase
 // is one launch over all work-groups of all tasks of the range (grid
 // dimension y = task), and the kernel boundaries are the only grid-wide
-// synchronisation: nothing ever waits on another work-group.
+// synchronisation: nothing ever waits on another work-group, and no kernel
+// needs a device-wide fence.
 //
 // The arithmetic is the streaming kernel's: FP64, the same (2d+1)-point
 // operator evaluated per point, the same exact line-block preconditioner
@@ -16,12 +17,11 @@
 // direction update and the next preconditioner application share one
 // launch; the convergence test uses the directly summed (r, r).
 //
-// Sums: every work-group writes its partial sums, and the last work-group
-// of the task to arrive (an atomic counter) adds them in block order, so
-// the result does not depend on the arrival order. A kernel reads only sums
-// that earlier launches completed; the per-task `done` flag is read once
-// per work-group (LDS broadcast), and every work-group of a task derives
-// the same decision from the same sums.
+// Sums: a producing kernel stores one partial per work-group; the kernels
+// that need the sum add the partials themselves (one wave, in block order,
+// so every consumer gets the same value). Point-wise kernels use 256-thread
+// work-groups of kWP points; line kernels one wave per work-group, so that
+// their uncoalesced line sweeps spread over as many CUs as possible.
 #pragma once
 
 #include "stream_kernel.hpp"
@@ -29,6 +29,7 @@
 namespace ctm {
 
 static_assert(kWideSK == kSK, "the wide solver reads the streaming kernel's line factors");
+constexpr int kWLT = 64 * kWLW;  // threads per line work-group
 
 __device__ __forceinline__ int wide_point_blocks(const GridDev& g) {
   return (g.npts + kWP - 1) / kWP;
@@ -36,77 +37,93 @@ __device__ __forceinline__ int wide_point_blocks(const GridDev& g) {
 __device__ __forceinline__ int wide_line_blocks(const GridDev& g) {
   const int Lc = pow2ceil((g.ns + kSK - 1) / kSK);
   const int waves = (g.nlines + (64 / Lc) - 1) / (64 / Lc);
-  return (waves + kWW - 1) / kWW;
+  return (waves + kWLW - 1) / kWLW;
 }
 
-// Shared preamble: the launch-level skip, the task's grid (LDS) and its
-// coefficient tables, the block range of the grid, and the done flag.
-// Returns false (uniformly over the work-group) when the block has nothing
-// to do.
 struct WideSmem {
-  GridDev g;
   double red[2 * 64];
-  int flag;  // done broadcast / last-arrival broadcast
+  int flag;  // done broadcast (multi-wave work-groups)
 };
 
-template <int OPC>
-__device__ __forceinline__ bool wide_begin(const WideArgs& w, WideSmem& sm, double* tl,
-                                           bool line, bool check_done) {
+// Shared preamble: the launch-level skip, the task's grid and coefficient
+// tables, the block range of the grid, and the done flag. The grid
+// descriptor is read in place (uniform loads); only the per-axis tables of
+// the SEP and VAR classes are staged in LDS (tl_lds), the constant-size
+// DRIFT table is read in place and HEAT has none. A single-wave work-group
+// reads `done` itself; a larger one broadcasts thread 0's read, so that its
+// waves agree. Returns false (uniformly over the work-group) when the block
+// has nothing to do.
+template <int OPC, int BT>
+__device__ __forceinline__ bool wide_begin(const WideArgs& w, WideSmem& sm, double* tl_lds,
+                                           bool line, bool check_done, const GridDev*& gp,
+                                           const double*& tl) {
   const ChainArgs& a = w.a;
   if (a.skip && *a.skip != 0.0) return false;
-  const int2 task = a.tasks[blockIdx.y];
-  {
-    const int* src = reinterpret_cast<const int*>(a.grids + task.x);
-    int* dst = reinterpret_cast<int*>(&sm.g);
-    for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += kWT) dst[t] = src[t];
+  gp = a.grids + a.tasks[blockIdx.y].x;
+  const GridDev& g = *gp;
+  const int nb = line ? wide_line_blocks(g) : wide_point_blocks(g);
+  if ((int)blockIdx.x >= nb) return false;
+  int done = 0;
+  if constexpr (BT == 64) {
+    done = check_done ? w.st[blockIdx.y].done : 0;
+  } else {
+    if (threadIdx.x == 0) sm.flag = check_done ? w.st[blockIdx.y].done : 0;
   }
-  if (threadIdx.x == 0) sm.flag = check_done ? w.st[blockIdx.y].done : 0;
-  __syncthreads();
-  const int nb = line ? wide_line_blocks(sm.g) : wide_point_blocks(sm.g);
-  if ((int)blockIdx.x >= nb || sm.flag) return false;
-  load_tables<OPC, double, kWT>(sm.g, a.tab64, a.dt, tl);
-  __syncthreads();
-  return true;
+  if constexpr (OPC == OPC_SEP || OPC == OPC_VAR) {
+    load_tables<OPC, double, BT>(g, a.tab64, a.dt, tl_lds);
+    tl = tl_lds;
+  } else {
+    tl = a.tab64 + g.tab0;
+  }
+  if constexpr (BT > 64 || OPC == OPC_SEP || OPC == OPC_VAR) __syncthreads();
+  if constexpr (BT > 64) done = sm.flag;
+  return done == 0;
 }
 
 __device__ __forceinline__ double* wide_sv(const WideArgs& w) {
   return w.scratch + (long long)blockIdx.y * SV_N * w.ss;
 }
+__device__ __forceinline__ double* wide_part(const WideArgs& w, int slot) {
+  return w.part + ((size_t)blockIdx.y * WS_N + slot) * w.maxblk;
+}
 
-// Sum NS values over the work-groups of the task into sum[slot0 ..]: every
-// work-group stores its partials; the last to arrive adds them in block
-// order and resets the counter. nblk = the task's participating blocks.
-template <int NS>
-__device__ __forceinline__ void wide_reduce(const WideArgs& w, WideSmem& sm, int nblk, int kind,
-                                            int slot0, double (&v)[NS]) {
+// Store this work-group's partials of slots slot0 .. slot0 + NS - 1.
+template <int BT, int NS>
+__device__ __forceinline__ void wide_put(const WideArgs& w, WideSmem& sm, int slot0,
+                                         double (&v)[NS]) {
   RedRing ring{sm.red, 0};
-  block_sum<kWW, NS, double>(v, ring);
-  WideTask* T = w.st + blockIdx.y;
-  double* part = w.part + (size_t)blockIdx.y * WS_N * w.maxblk;
+  block_sum<BT / 64, NS, double>(v, ring);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) part[(size_t)(slot0 + s) * w.maxblk + blockIdx.x] = v[s];
-    __threadfence();
-    const unsigned prev = atomicAdd(&T->cnt[kind], 1u);
-    sm.flag = (prev == (unsigned)(nblk - 1));
+    for (int s = 0; s < NS; ++s) wide_part(w, slot0 + s)[blockIdx.x] = v[s];
   }
-  __syncthreads();
-  if (!sm.flag) return;
-  __threadfence();
+}
+
+// The sums of NS slots over their producers' nb[s] work-groups: every wave
+// adds the partials in block order itself (no LDS, no barrier), so every
+// thread gets the same values.
+template <int NS>
+__device__ __forceinline__ void wide_sums(const WideArgs& w, const int (&slot)[NS],
+                                          const int (&nb)[NS], double (&out)[NS]) {
+  const int lane = threadIdx.x & 63;
+  int nbmax = 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) nbmax = nb[s] > nbmax ? nb[s] : nbmax;
   double acc[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    acc[s] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kWT)
-      acc[s] += __hip_atomic_load(part + (size_t)(slot0 + s) * w.maxblk + b, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum<kWW, NS, double>(acc, ring);
-  if (threadIdx.x == 0) {
+  for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+  // every slot's loads of a round are issued together, unconditionally (a
+  // block index past a slot's producers reads entry 0, which every slot
+  // holds, and adds nothing)
+  for (int b = lane; b - lane < nbmax; b += 64) {
+    double x[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) T->sum[slot0 + s] = acc[s];
-    atomicExch(&T->cnt[kind], 0u);
+    for (int s = 0; s < NS; ++s) x[s] = wide_part(w, slot[s])[b < nb[s] ? b : 0];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] += (b < nb[s]) ? x[s] : 0.0;
   }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) out[s] = wave_sum(acc[s]);
 }
 
 // Stops the task's step (thread 0 of any deciding work-group; idempotent).
@@ -114,7 +131,6 @@ __device__ __forceinline__ void wide_stop(WideTask* T, int it, int flag) {
   if (threadIdx.x != 0) return;
   if (flag) atomicOr(&T->flag, flag);
   T->it = it;
-  __threadfence();
   T->done = 1;
 }
 
@@ -122,8 +138,8 @@ __device__ __forceinline__ bool isnan_(double x) { return !(x == x); }
 
 // ------------------------------------------------------- stopping tests
 // The start of a step (iteration 1): the initial residual.
-__device__ __forceinline__ bool wide_test_init(const WideTask* T, double tol2, int& it, int& fl) {
-  const double rr0 = T->sum[WS_RR0], bb = T->sum[WS_BB];
+__device__ __forceinline__ bool wide_test_init(double rr0, double bb, double tol2, int& it,
+                                               int& fl) {
   it = 0;
   fl = 0;
   if (isnan_(rr0) || isnan_(bb)) {
@@ -132,11 +148,10 @@ __device__ __forceinline__ bool wide_test_init(const WideTask* T, double tol2, i
   }
   return rr0 <= tol2 * bb;
 }
-// After the r update of iteration it (CG: (r, r); BiCGStab: also a
+// After the r update of iteration itd (CG: (r, r); BiCGStab: also a
 // breakdown found in the direction update).
-__device__ __forceinline__ bool wide_test_rr(const WideTask* T, double tol2, int itd, int& it,
-                                             int& fl) {
-  const double rr = T->sum[WS_RR], bb = T->sum[WS_BB];
+__device__ __forceinline__ bool wide_test_rr(double rr, double bb, int pend, double tol2, int itd,
+                                             int& it, int& fl) {
   it = itd;
   fl = 0;
   if (isnan_(rr)) {
@@ -144,27 +159,47 @@ __device__ __forceinline__ bool wide_test_rr(const WideTask* T, double tol2, int
     return true;
   }
   if (rr <= tol2 * bb) return true;
-  if (T->pend) {
+  if (pend) {
     fl = FLAG_BREAKDOWN;
     return true;
   }
   return false;
 }
-// The test the next kernel of iteration i would make first (BiCGStab: the
-// start of K_B(i); CG: the start of the preconditioner phase of i).
-__device__ __forceinline__ bool wide_test_next(const WideTask* T, double tol2, int i, int& it,
-                                               int& fl) {
-  return (i == 1) ? wide_test_init(T, tol2, it, fl) : wide_test_rr(T, tol2, i - 1, it, fl);
-}
 
-// BiCGStab scalars from the t-phase sums of iteration k (k >= 1).
-__device__ __forceinline__ const double* wide_dsums(const WideTask* T, int k) {
-  return T->sum + WS_D + 5 * (k & 1);
+// The BiCGStab scalars a phase needs: (r0, r0), (b, b), (r^, v) and both
+// parities of the t-phase sums.
+struct BicgSums {
+  double rr0, bb, rhv;
+  double d[2][5];  // {ts, tt, ss, rhs, rht} of the iterations of each parity
+};
+__device__ __forceinline__ void bicg_sums(const WideArgs& w, const GridDev& g, BicgSums& S) {
+  const int nb = wide_point_blocks(g);
+  constexpr int slot[13] = {WS_RR0, WS_BB, WS_RHV, WS_D, WS_D + 1, WS_D + 2, WS_D + 3, WS_D + 4,
+                            WS_D + 5, WS_D + 6, WS_D + 7, WS_D + 8, WS_D + 9};
+  const int nbs[13] = {nb, nb, nb, nb, nb, nb, nb, nb, nb, nb, nb, nb, nb};
+  double v[13];
+  wide_sums<13>(w, slot, nbs, v);
+  S.rr0 = v[0];
+  S.bb = v[1];
+  S.rhv = v[2];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    S.d[0][m] = v[3 + m];
+    S.d[1][m] = v[8 + m];
+  }
+}
+// The t-phase sums of iteration k (selected, not indexed: the parity is a
+// run-time value and an indexed register array would live in scratch).
+__device__ __forceinline__ void bicg_d(const BicgSums& S, int k, double (&D)[5]) {
+  const bool odd = (k & 1) != 0;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) D[m] = odd ? S.d[1][m] : S.d[0][m];
 }
 // rho_k = (r^, r_{k-1}): rho_1 = (r0, r0); rho_k = rhs - omega rht of k-1.
-__device__ __forceinline__ double wide_rho(const WideTask* T, int k) {
-  if (k == 1) return T->sum[WS_RR0];
-  const double* D = wide_dsums(T, k - 1);
+__device__ __forceinline__ double bicg_rho(const BicgSums& S, int k) {
+  if (k == 1) return S.rr0;
+  double D[5];
+  bicg_d(S, k - 1, D);
   return D[3] - (D[0] / D[1]) * D[4];
 }
 
@@ -174,30 +209,45 @@ __device__ __forceinline__ double wide_Ax(const GridDev& g, const double* tl, do
                                           double amp, int p, F x) {
   PointCoef<OPC, D> c;
   point_coef<OPC, D>(g, tl, dt, amp, p, c);
-  double v = c.diag * x(p);
+  double xl[D], xu[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    if (i >= g.d) continue;
-    const int st = g.stride[i];
-    if (c.lo[i] != 0.0) v += c.lo[i] * x(p - st);
-    if (c.up[i] != 0.0) v += c.up[i] * x(p + st);
+    xl[i] = x(stencil_lo(g, c, i, p));
+    xu[i] = x(stencil_up(g, c, i, p));
   }
+  double v = c.diag * x(p);
+#pragma unroll
+  for (int i = 0; i < D; ++i) v += c.lo[i] * xl[i] + c.up[i] * xu[i];
   return v;
 }
 
 // ------------------------------------------------------- line helpers
 // Lane of this thread in the line layout (block b, wave w: virtual wave
-// b * kWW + w of the task).
+// b * kWLW + w of the task).
 template <int D>
 __device__ __forceinline__ void wide_lane(const GridDev& g, SLane& L) {
-  stream_lane_at<D>(g, (int)blockIdx.x * kWW + (threadIdx.x >> 6), threadIdx.x & 63, L);
+  stream_lane_at<D>(g, (int)blockIdx.x * kWLW + (threadIdx.x >> 6), threadIdx.x & 63, L);
 }
-__device__ __forceinline__ long long lane_pt(const SLane& L, int k) {
-  return L.base + (long long)(L.j0 + k) * L.step;
+// Point index of unknown k of the lane's chunk (< 2^20: a 32-bit offset).
+__device__ __forceinline__ unsigned lane_pt(const SLane& L, int k) {
+  return (unsigned)L.base + (unsigned)((L.j0 + k) * L.step);
+}
+// Loads and stores at a 32-bit element offset from a work-group-uniform
+// base, so that the compiler addresses with a scalar base and one 32-bit
+// offset register per unknown (shared by every vector), not a 64-bit
+// address per load.
+__device__ __forceinline__ double ldo(const double* base, unsigned i) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) +
+                                          (size_t)(i * 8u));
+}
+__device__ __forceinline__ void sto(double* base, unsigned i, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (size_t)(i * 8u)) = v;
 }
 
-// z = M^-1 r on the chunk of lane L, everything in registers (r and z hold
-// the chunk's kSK unknowns; entries past nval are ignored / returned 0).
+// z = M^-1 r on the chunk of lane L in registers (r and z hold the chunk's
+// kSK unknowns; entries past nval are ignored / returned 0). Every factor
+// load is issued before the first use: the launches of few tasks that this
+// solver serves are latency-bound, one round trip beats three.
 __device__ __forceinline__ void wide_pre(const double* sv, long long ss, const SLane& L,
                                          const double (&r)[kSK], double (&z)[kSK]) {
   const double* FM = sv + SV_FM * ss;
@@ -211,12 +261,12 @@ __device__ __forceinline__ void wide_pre(const double* sv, long long ss, const S
 #pragma unroll
   for (int k = 0; k < kSK; ++k) {
     const bool v = k < L.nval;
-    const long long p = lane_pt(L, k);
-    fm[k] = v ? FM[p] : 0.0;
-    fid[k] = v ? FID[p] : 0.0;
-    fcu[k] = v ? FCU[p] : 0.0;
-    fph[k] = v ? FPHI[p] : 0.0;
-    fps[k] = v ? FPSI[p] : 0.0;
+    const unsigned p = lane_pt(L, k);
+    fm[k] = v ? ldo(FM, p) : 0.0;
+    fid[k] = v ? ldo(FID, p) : 0.0;
+    fcu[k] = v ? ldo(FCU, p) : 0.0;
+    fph[k] = v ? ldo(FPHI, p) : 0.0;
+    fps[k] = v ? ldo(FPSI, p) : 0.0;
   }
   // forward elimination over the eliminated unknowns 0..ne-1
   double y[kSK];
@@ -272,22 +322,22 @@ __device__ __forceinline__ void wide_pre(const double* sv, long long ss, const S
 }
 
 // ------------------------------------------------------------- kernels
-#define WIDE_KERNEL(name) \
-  template <int OPC, int D> \
-  __global__ void __launch_bounds__(kWT) name(WideArgs w)
 #define WIDE_SMEM                                        \
   extern __shared__ __align__(16) unsigned char smem[]; \
   __shared__ WideSmem sm;                               \
-  double* tl = reinterpret_cast<double*>(smem)
+  const GridDev* gp = nullptr;                          \
+  const double* tl = nullptr;                           \
+  double* tl_lds = reinterpret_cast<double*>(smem)
 
 // Factors of the line preconditioner (once per chain).
-WIDE_KERNEL(wide_setup_kernel) {
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWLT) wide_setup_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, true, false)) return;
+  if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, false, gp, tl)) return;
   double* sv = wide_sv(w);
   SLane L;
-  wide_lane<D>(sm.g, L);
-  linepre_setup_lane<OPC, D>(sm.g, tl, w.a.dt, w.a.amp, sv, w.ss, sv + SV_S * w.ss, L);
+  wide_lane<D>(*gp, L);
+  linepre_setup_lane<OPC, D>(*gp, tl, w.a.dt, w.a.amp, sv, w.ss, sv + SV_S * w.ss, L);
 }
 
 // Step transition (point-wise; step j): finish step j-1 (B = x + forcing,
@@ -295,33 +345,42 @@ WIDE_KERNEL(wide_setup_kernel) {
 // forcing; then either the exact residual b - A target (residual mode, last
 // step) or the initial guess. Work-group 0 accounts step j-1 and resets the
 // task's step state.
-WIDE_KERNEL(wide_step_kernel) {
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, false, false)) return;
+  if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, false, gp, tl)) return;
   const ChainArgs& a = w.a;
-  const GridDev& g = sm.g;
+  const GridDev& g = *gp;
   const int q = a.tasks[blockIdx.y].y;
   const int j = w.j;
   const bool last = (j == a.nsteps), res = a.resmode != 0;
-  WideTask* T = w.st + blockIdx.y;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (j == 1) {
-      T->kr_sum = T->kr_max = 0;
-      T->res_max = 0.0;
-      T->flag = 0;
-    } else {
-      const int it = T->done ? T->it : w.prev_its;
-      int fl = T->flag | ((T->done || res) ? 0 : FLAG_NOCONV);
-      if (res) {
-        fl &= ~(FLAG_NOCONV | FLAG_BREAKDOWN);
-        T->res_max = fmax(T->res_max, T->sum[WS_RR0]);
-      }
-      T->flag = fl;
-      T->kr_sum += it;
-      T->kr_max = it > T->kr_max ? it : T->kr_max;
+  if (blockIdx.x == 0) {
+    double rr0 = 0.0;
+    if (j > 1 && res) {
+      const int slot[1] = {WS_RR0}, nb[1] = {wide_point_blocks(g)};
+      double v[1];
+      wide_sums<1>(w, slot, nb, v);
+      rr0 = v[0];
     }
-    T->done = T->it = T->pend = 0;
-    for (int k = 0; k < WR_N; ++k) T->cnt[k] = 0;
+    if (threadIdx.x == 0) {
+      WideTask* T = w.st + blockIdx.y;
+      if (j == 1) {
+        T->kr_sum = T->kr_max = 0;
+        T->res_max = 0.0;
+        T->flag = 0;
+      } else {
+        const int it = T->done ? T->it : w.prev_its;
+        int fl = T->flag | ((T->done || res) ? 0 : FLAG_NOCONV);
+        if (res) {
+          fl &= ~(FLAG_NOCONV | FLAG_BREAKDOWN);
+          T->res_max = fmax(T->res_max, rr0);
+        }
+        T->flag = fl;
+        T->kr_sum += it;
+        T->kr_max = it > T->kr_max ? it : T->kr_max;
+      }
+      T->done = T->it = T->pend = 0;
+    }
   }
   double* sv = wide_sv(w);
   double* X = sv + SV_X * w.ss;
@@ -341,36 +400,39 @@ WIDE_KERNEL(wide_step_kernel) {
   const double* tg = rho ? at(a.target, a.target.a * q + a.target.b) : nullptr;
   const VecRef gr = last ? a.guess_fin : a.guess;
   const double* gx = (!rho && gr.base) ? at(gr, gr.a * q + gr.b + (last ? 0 : j)) : nullptr;
+  // (every load before the stores: the vectors may share a base)
+  double b0[kWPT], b1[kWPT], xg[kWPT];
+#pragma unroll
+  for (int k = 0; k < kWPT; ++k) {
+    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    b0[k] = b1[k] = xg[k] = 0.0;
+    if (p >= g.npts) continue;
+    const double b = (j == 1) ? (st ? st[p] : 0.0) : X[p] + (fp ? fp[p] : 0.0);
+    double bb = b + (fj ? fj[p] : 0.0);
+    if (rho) bb -= wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int i) { return tg[i]; });
+    b0[k] = b;
+    b1[k] = bb;
+    xg[k] = gx ? gx[p] : bb;
+  }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
     const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
-    double b;
-    if (j == 1) {
-      b = st ? st[p] : 0.0;
-      if (wb) wb[p] = b;
-    } else {
-      b = X[p] + (fp ? fp[p] : 0.0);
-      if (is) is[p] = b;
-    }
-    if (fj) b += fj[p];
-    if (rho) {
-      b -= wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int i) { return tg[i]; });
-    } else {
-      X[p] = gx ? gx[p] : b;
-    }
-    B[p] = b;
+    if (wb) wb[p] = b0[k];
+    if (is) is[p] = b0[k];
+    if (!rho) X[p] = xg[k];
+    B[p] = b1[k];
   }
 }
 
 // Initial residual of the step (stencil): r = b - A x; BiCGStab also sets
-// r^ = p = r. Sums (r, r), (b, b).
+// r^ = p = r. Partials of (r, r), (b, b).
 template <int OPC, int SOLVER, int D>
 __global__ void __launch_bounds__(kWT) wide_init_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, false, false)) return;
+  if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, false, gp, tl)) return;
   const ChainArgs& a = w.a;
-  const GridDev& g = sm.g;
+  const GridDev& g = *gp;
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   const double* X = sv + SV_X * ss;
@@ -379,31 +441,42 @@ __global__ void __launch_bounds__(kWT) wide_init_kernel(WideArgs w) {
   double* RH = sv + SV_RH * ss;
   double* P = sv + SV_P * ss;
   double v[2] = {0.0, 0.0};
+  double rv[kWPT];
+#pragma unroll
+  for (int k = 0; k < kWPT; ++k) {
+    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    rv[k] = 0.0;
+    if (p >= g.npts) continue;
+    const double b = B[p];
+    const double r = b - wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int i) { return X[i]; });
+    rv[k] = r;
+    v[0] += r * r;
+    v[1] += b * b;
+  }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
     const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
-    const double r = B[p] - wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int i) { return X[i]; });
-    R[p] = r;
+    R[p] = rv[k];
     if constexpr (SOLVER == SOLV_BICG) {
-      RH[p] = r;
-      P[p] = r;
+      RH[p] = rv[k];
+      P[p] = rv[k];
     }
-    v[0] += r * r;
-    v[1] += B[p] * B[p];
   }
-  wide_reduce<2>(w, sm, wide_point_blocks(g), WR_INIT, WS_RR0, v);
+  static_assert(WS_BB == WS_RR0 + 1, "slot order");
+  wide_put<kWT, 2>(w, sm, WS_RR0, v);
 }
 
 // ---- BiCGStab, iteration i: K_A(i) [lines], K_B(i), K_C(i) [lines], K_D(i)
-// K_A(i): i = 1: h = M^-1 p. i > 1: the end of iteration i-1 (omega: x +=
-// omega h, r = s - omega t, sum (r, r)), the direction p = r + beta (p -
-// omega v), h = M^-1 p.
-WIDE_KERNEL(wide_bicg_a_kernel) {
+// K_A(i): i = 1: the initial test, h = M^-1 p. i > 1: the end of iteration
+// i-1 (tests on (s, s) and (t, t); omega: x += omega h, r = s - omega t,
+// partial (r, r)), the direction p = r + beta (p - omega v), h = M^-1 p.
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, true, true)) return;
+  if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const ChainArgs& a = w.a;
-  const GridDev& g = sm.g;
+  const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
   const double tol2 = a.tol * a.tol;
   const int i = w.i;
@@ -411,14 +484,20 @@ WIDE_KERNEL(wide_bicg_a_kernel) {
   double omega = 0.0, beta = 0.0;
   bool pend = false;
   if (i == 1) {
-    if (wide_test_init(T, tol2, it, fl)) {
+    const int slot[2] = {WS_RR0, WS_BB}, nb[2] = {wide_point_blocks(g), wide_point_blocks(g)};
+    double v[2];
+    wide_sums<2>(w, slot, nb, v);
+    if (wide_test_init(v[0], v[1], tol2, it, fl)) {
       wide_stop(T, it, fl);
       return;
     }
   } else {
-    const double* Dn = wide_dsums(T, i - 1);
-    const double ss_ = Dn[2], tt = Dn[1], bb = T->sum[WS_BB];
-    if (ss_ <= tol2 * bb) {
+    BicgSums S;
+    bicg_sums(w, g, S);
+    double Dn[5];
+    bicg_d(S, i - 1, Dn);
+    const double tt = Dn[1];
+    if (Dn[2] <= tol2 * S.bb) {
       wide_stop(T, i - 1, 0);  // x already holds x + alpha h
       return;
     }
@@ -427,13 +506,12 @@ WIDE_KERNEL(wide_bicg_a_kernel) {
       return;
     }
     omega = Dn[0] / tt;
-    const double rho_o = wide_rho(T, i - 1), rho_n = wide_rho(T, i);
-    const double alpha = rho_o / T->sum[WS_RHV];
-    if (rho_n == 0.0 || omega == 0.0) {
+    const double rho_o = bicg_rho(S, i - 1), rho_n = bicg_rho(S, i);
+    const double alpha = rho_o / S.rhv;
+    if (rho_n == 0.0 || omega == 0.0)
       pend = true;
-    } else {
+    else
       beta = (rho_n / rho_o) * (alpha / omega);
-    }
   }
   double* sv = wide_sv(w);
   const long long ss = w.ss;
@@ -446,46 +524,81 @@ WIDE_KERNEL(wide_bicg_a_kernel) {
   double* H = sv + SV_D * ss;
   SLane L;
   wide_lane<D>(g, L);
+  // (all loads of a pass are issued before its stores: the vectors share
+  // one base, so the compiler cannot move a load above an earlier store)
   double pr[kSK], hz[kSK];
   double rr[1] = {0.0};
+  if (i == 1) {
 #pragma unroll
-  for (int k = 0; k < kSK; ++k) {
-    pr[k] = 0.0;
-    if (k >= L.nval) continue;
-    const long long p = lane_pt(L, k);
-    if (i == 1) {
-      pr[k] = P[p];
-    } else {
-      X[p] += omega * H[p];
-      const double r = S[p] - omega * Tv[p];
-      R[p] = r;
-      rr[0] += r * r;
-      const double pn = r + beta * (P[p] - omega * V[p]);
-      P[p] = pn;
-      pr[k] = pn;
+    for (int k = 0; k < kSK; ++k) pr[k] = (k < L.nval) ? ldo(P, lane_pt(L, k)) : 0.0;
+  } else {
+    // r = s - omega t, x += omega h (one pass of loads), then p = r + beta
+    // (p - omega v)
+    {
+      double xv[kSK], hv[kSK], sv_[kSK], tv[kSK];
+#pragma unroll
+      for (int k = 0; k < kSK; ++k) {
+        const bool ok = k < L.nval;
+        const unsigned p = lane_pt(L, k);
+        xv[k] = ok ? ldo(X, p) : 0.0;
+        hv[k] = ok ? ldo(H, p) : 0.0;
+        sv_[k] = ok ? ldo(S, p) : 0.0;
+        tv[k] = ok ? ldo(Tv, p) : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kSK; ++k) {
+        const double r = sv_[k] - omega * tv[k];
+        pr[k] = r;
+        rr[0] += r * r;
+        if (k < L.nval) {
+          const unsigned p = lane_pt(L, k);
+          sto(X, p, xv[k] + omega * hv[k]);
+          sto(R, p, r);
+        }
+      }
+    }
+    double pv[kSK], vv[kSK];
+#pragma unroll
+    for (int k = 0; k < kSK; ++k) {
+      const bool ok = k < L.nval;
+      const unsigned p = lane_pt(L, k);
+      pv[k] = ok ? ldo(P, p) : 0.0;
+      vv[k] = ok ? ldo(V, p) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kSK; ++k) {
+      const double pn = pr[k] + beta * (pv[k] - omega * vv[k]);
+      pr[k] = (k < L.nval) ? pn : 0.0;
+      if (k < L.nval) sto(P, lane_pt(L, k), pn);
     }
   }
   wide_pre(sv, ss, L, pr, hz);
 #pragma unroll
   for (int k = 0; k < kSK; ++k)
-    if (k < L.nval) H[lane_pt(L, k)] = hz[k];
+    if (k < L.nval) sto(H, lane_pt(L, k), hz[k]);
   if (i > 1) {
     if (pend && blockIdx.x == 0 && threadIdx.x == 0) T->pend = 1;
-    wide_reduce<1>(w, sm, wide_line_blocks(g), WR_RR, WS_RR, rr);
+    wide_put<kWLT, 1>(w, sm, WS_RR, rr);
   }
 }
 
-// K_B(i): the test of the r update (i > 1); v = A h, sum (r^, v).
-WIDE_KERNEL(wide_bicg_b_kernel) {
+// K_B(i): the test of the r update (i > 1); v = A h, partial (r^, v).
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWT) wide_bicg_b_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, false, true)) return;
+  if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, true, gp, tl)) return;
   const ChainArgs& a = w.a;
-  const GridDev& g = sm.g;
+  const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
-  int it, fl;
-  if (w.i > 1 && wide_test_rr(T, a.tol * a.tol, w.i - 1, it, fl)) {
-    wide_stop(T, it, fl);
-    return;
+  if (w.i > 1) {
+    const int slot[2] = {WS_RR, WS_BB}, nb[2] = {wide_line_blocks(g), wide_point_blocks(g)};
+    double v[2];
+    wide_sums<2>(w, slot, nb, v);
+    int it, fl;
+    if (wide_test_rr(v[0], v[1], T->pend, a.tol * a.tol, w.i - 1, it, fl)) {
+      wide_stop(T, it, fl);
+      return;
+    }
   }
   double* sv = wide_sv(w);
   const long long ss = w.ss;
@@ -493,29 +606,39 @@ WIDE_KERNEL(wide_bicg_b_kernel) {
   const double* RH = sv + SV_RH * ss;
   double* V = sv + SV_Q * ss;
   double v[1] = {0.0};
+  double yv[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
     const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    yv[k] = 0.0;
     if (p >= g.npts) continue;
     const double y = wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int m) { return H[m]; });
-    V[p] = y;
+    yv[k] = y;
     v[0] += RH[p] * y;
   }
-  wide_reduce<1>(w, sm, wide_point_blocks(g), WR_RHV, WS_RHV, v);
+#pragma unroll
+  for (int k = 0; k < kWPT; ++k) {
+    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    if (p < g.npts) V[p] = yv[k];
+  }
+  wide_put<kWT, 1>(w, sm, WS_RHV, v);
 }
 
 // K_C(i): alpha = rho / (r^, v); x += alpha h, s = r - alpha v, h = M^-1 s.
-WIDE_KERNEL(wide_bicg_c_kernel) {
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, true, true)) return;
-  const GridDev& g = sm.g;
+  if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
+  const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
-  const double rhv = T->sum[WS_RHV];
+  BicgSums Sm;
+  bicg_sums(w, g, Sm);
+  const double rhv = Sm.rhv;
   if (!(rhv != 0.0) || isnan_(rhv)) {
     wide_stop(T, w.i, isnan_(rhv) ? FLAG_NONFINITE : FLAG_BREAKDOWN);
     return;
   }
-  const double alpha = wide_rho(T, w.i) / rhv;
+  const double alpha = bicg_rho(Sm, w.i) / rhv;
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   double* X = sv + SV_X * ss;
@@ -526,28 +649,41 @@ WIDE_KERNEL(wide_bicg_c_kernel) {
   SLane L;
   wide_lane<D>(g, L);
   double sr[kSK], hz[kSK];
+  {
+    double xv[kSK], hv[kSK], rv[kSK], vv[kSK];
 #pragma unroll
-  for (int k = 0; k < kSK; ++k) {
-    sr[k] = 0.0;
-    if (k >= L.nval) continue;
-    const long long p = lane_pt(L, k);
-    X[p] += alpha * H[p];
-    const double s = R[p] - alpha * V[p];
-    S[p] = s;
-    sr[k] = s;
+    for (int k = 0; k < kSK; ++k) {
+      const bool ok = k < L.nval;
+      const unsigned p = lane_pt(L, k);
+      xv[k] = ok ? ldo(X, p) : 0.0;
+      hv[k] = ok ? ldo(H, p) : 0.0;
+      rv[k] = ok ? ldo(R, p) : 0.0;
+      vv[k] = ok ? ldo(V, p) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kSK; ++k) {
+      const double s = rv[k] - alpha * vv[k];
+      sr[k] = s;
+      if (k < L.nval) {
+        const unsigned p = lane_pt(L, k);
+        sto(X, p, xv[k] + alpha * hv[k]);
+        sto(S, p, s);
+      }
+    }
   }
   wide_pre(sv, ss, L, sr, hz);
 #pragma unroll
   for (int k = 0; k < kSK; ++k)
-    if (k < L.nval) H[lane_pt(L, k)] = hz[k];
+    if (k < L.nval) sto(H, lane_pt(L, k), hz[k]);
 }
 
-// K_D(i): t = A h; sums (t, s), (t, t), (s, s), (r^, s), (r^, t).
-WIDE_KERNEL(wide_bicg_d_kernel) {
+// K_D(i): t = A h; partials (t, s), (t, t), (s, s), (r^, s), (r^, t).
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWT) wide_bicg_d_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, false, true)) return;
+  if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, true, gp, tl)) return;
   const ChainArgs& a = w.a;
-  const GridDev& g = sm.g;
+  const GridDev& g = *gp;
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   const double* H = sv + SV_D * ss;
@@ -555,12 +691,14 @@ WIDE_KERNEL(wide_bicg_d_kernel) {
   const double* RH = sv + SV_RH * ss;
   double* Tv = sv + SV_T * ss;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double tv[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
     const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    tv[k] = 0.0;
     if (p >= g.npts) continue;
     const double t = wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int m) { return H[m]; });
-    Tv[p] = t;
+    tv[k] = t;
     const double s = S[p], rh = RH[p];
     v[0] += t * s;
     v[1] += t * t;
@@ -568,20 +706,36 @@ WIDE_KERNEL(wide_bicg_d_kernel) {
     v[3] += rh * s;
     v[4] += rh * t;
   }
-  wide_reduce<5>(w, sm, wide_point_blocks(g), WR_D, WS_D + 5 * (w.i & 1), v);
+#pragma unroll
+  for (int k = 0; k < kWPT; ++k) {
+    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    if (p < g.npts) Tv[p] = tv[k];
+  }
+  wide_put<kWT, 5>(w, sm, WS_D + 5 * (w.i & 1), v);
 }
 
 // ---- CG, iteration i: K_CA(i) [lines], K_CB(i), K_CC(i)
-// K_CA(i): the test of the previous r update; z = M^-1 r, sum (r, z).
-WIDE_KERNEL(wide_cg_a_kernel) {
+// K_CA(i): the test of the previous r update; z = M^-1 r, partial (r, z).
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, true, true)) return;
-  const GridDev& g = sm.g;
+  if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
+  const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
-  int it, fl;
-  if (wide_test_next(T, w.a.tol * w.a.tol, w.i, it, fl)) {
-    wide_stop(T, it, fl);
-    return;
+  const double tol2 = w.a.tol * w.a.tol;
+  {
+    const int slot[3] = {WS_RR0, WS_BB, WS_RR};
+    const int nb[3] = {wide_point_blocks(g), wide_point_blocks(g),
+                       w.i > 1 ? wide_point_blocks(g) : 0};
+    double v[3];
+    wide_sums<3>(w, slot, nb, v);
+    int it, fl;
+    const bool stop = (w.i == 1) ? wide_test_init(v[0], v[1], tol2, it, fl)
+                                 : wide_test_rr(v[2], v[1], 0, tol2, w.i - 1, it, fl);
+    if (stop) {
+      wide_stop(T, it, fl);
+      return;
+    }
   }
   double* sv = wide_sv(w);
   const long long ss = w.ss;
@@ -591,63 +745,86 @@ WIDE_KERNEL(wide_cg_a_kernel) {
   wide_lane<D>(g, L);
   double rv[kSK], zv[kSK];
 #pragma unroll
-  for (int k = 0; k < kSK; ++k) rv[k] = (k < L.nval) ? R[lane_pt(L, k)] : 0.0;
+  for (int k = 0; k < kSK; ++k) rv[k] = (k < L.nval) ? ldo(R, lane_pt(L, k)) : 0.0;
   wide_pre(sv, ss, L, rv, zv);
   double v[1] = {0.0};
 #pragma unroll
   for (int k = 0; k < kSK; ++k)
     if (k < L.nval) {
-      Z[lane_pt(L, k)] = zv[k];
+      sto(Z, lane_pt(L, k), zv[k]);
       v[0] += rv[k] * zv[k];
     }
-  wide_reduce<1>(w, sm, wide_line_blocks(g), WR_RZ, WS_RZ + (w.i & 1), v);
+  wide_put<kWLT, 1>(w, sm, WS_RZ + (w.i & 1), v);
 }
 
 // K_CB(i): p_i = z + beta p_{i-1} (the two directions alternate between
 // two vectors, so that neighbours read the old one while it is replaced),
-// q = A p_i, sum (p, q).
-WIDE_KERNEL(wide_cg_b_kernel) {
+// q = A p_i, partial (p, q).
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWT) wide_cg_b_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, false, true)) return;
+  if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, true, gp, tl)) return;
   const ChainArgs& a = w.a;
-  const GridDev& g = sm.g;
-  const WideTask* T = w.st + blockIdx.y;
+  const GridDev& g = *gp;
   const int i = w.i;
-  const double beta = (i == 1) ? 0.0 : T->sum[WS_RZ + (i & 1)] / T->sum[WS_RZ + ((i - 1) & 1)];
+  double beta = 0.0;
+  if (i > 1) {
+    const int slot[2] = {WS_RZ + (i & 1), WS_RZ + ((i - 1) & 1)};
+    const int nb[2] = {wide_line_blocks(g), wide_line_blocks(g)};
+    double v[2];
+    wide_sums<2>(w, slot, nb, v);
+    beta = v[0] / v[1];
+  }
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   const double* Z = sv + SV_S * ss;
-  const double* Po = sv + ((i & 1) ? SV_RH : SV_P) * ss;
+  // (iteration 1: beta = 0 and the old direction reads z, so that no
+  // unwritten vector is read)
+  const double* Po = (i == 1) ? Z : sv + ((i & 1) ? SV_RH : SV_P) * ss;
   double* Pn = sv + ((i & 1) ? SV_P : SV_RH) * ss;
   double* Q = sv + SV_Q * ss;
   double v[1] = {0.0};
+  double pvv[kWPT], yv[kWPT];
+#pragma unroll
+  for (int k = 0; k < kWPT; ++k) {
+    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    pvv[k] = yv[k] = 0.0;
+    if (p >= g.npts) continue;
+    auto pv = [&](int m) { return Z[m] + beta * Po[m]; };
+    const double y = wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, pv);
+    const double pp = pv(p);
+    pvv[k] = pp;
+    yv[k] = y;
+    v[0] += pp * y;
+  }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
     const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
-    auto pv = [&](int m) { return (i == 1) ? Z[m] : Z[m] + beta * Po[m]; };
-    const double y = wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, pv);
-    const double pp = pv(p);
-    Pn[p] = pp;
-    Q[p] = y;
-    v[0] += pp * y;
+    Pn[p] = pvv[k];
+    Q[p] = yv[k];
   }
-  wide_reduce<1>(w, sm, wide_point_blocks(g), WR_PQ, WS_PQ, v);
+  wide_put<kWT, 1>(w, sm, WS_PQ, v);
 }
 
-// K_CC(i): alpha = (r, z) / (p, q); x += alpha p, r -= alpha q, sum (r, r).
-WIDE_KERNEL(wide_cg_c_kernel) {
+// K_CC(i): alpha = (r, z) / (p, q); x += alpha p, r -= alpha q, partial (r, r).
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWT) wide_cg_c_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, false, true)) return;
-  const GridDev& g = sm.g;
+  if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, true, gp, tl)) return;
+  const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
   const int i = w.i;
-  const double pq = T->sum[WS_PQ];
+  const int slot[2] = {WS_PQ, WS_RZ + (i & 1)};
+  const int nb[2] = {wide_point_blocks(g), wide_line_blocks(g)};
+  double sc[2];
+  wide_sums<2>(w, slot, nb, sc);
+  const double pq = sc[0];
   if (!(pq != 0.0) || isnan_(pq)) {
     wide_stop(T, i, isnan_(pq) ? FLAG_NONFINITE : FLAG_BREAKDOWN);
     return;
   }
-  const double alpha = T->sum[WS_RZ + (i & 1)] / pq;
+  const double alpha = sc[1] / pq;
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   double* X = sv + SV_X * ss;
@@ -655,27 +832,36 @@ WIDE_KERNEL(wide_cg_c_kernel) {
   const double* Pn = sv + ((i & 1) ? SV_P : SV_RH) * ss;
   const double* Q = sv + SV_Q * ss;
   double v[1] = {0.0};
+  double xv[kWPT], rv[kWPT];
+#pragma unroll
+  for (int k = 0; k < kWPT; ++k) {
+    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    xv[k] = rv[k] = 0.0;
+    if (p >= g.npts) continue;
+    xv[k] = X[p] + alpha * Pn[p];
+    const double r = R[p] - alpha * Q[p];
+    rv[k] = r;
+    v[0] += r * r;
+  }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
     const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
-    X[p] += alpha * Pn[p];
-    const double r = R[p] - alpha * Q[p];
-    R[p] = r;
-    v[0] += r * r;
+    X[p] = xv[k];
+    R[p] = rv[k];
   }
-  wide_reduce<1>(w, sm, wide_point_blocks(g), WR_RR, WS_RR, v);
+  wide_put<kWT, 1>(w, sm, WS_RR, v);
 }
 
 // The end of the chain (point-wise): the last step's x + forcing (or the
-// exact residual formed by the step kernel), fin = v - target, sum
-// ||fin||^2; the last work-group to arrive accounts the last step and
-// publishes res2, the counters and the status bits.
-WIDE_KERNEL(wide_fin_kernel) {
+// exact residual formed by the step kernel), fin = v - target, partial
+// ||fin||^2.
+template <int OPC, int D>
+__global__ void __launch_bounds__(kWT) wide_fin_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC>(w, sm, tl, false, false)) return;
+  if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, false, gp, tl)) return;
   const ChainArgs& a = w.a;
-  const GridDev& g = sm.g;
+  const GridDev& g = *gp;
   const int q = a.tasks[blockIdx.y].y;
   const bool res = a.resmode != 0;
   const bool rho = res && a.target.base;  // the step kernel formed the residual
@@ -684,7 +870,7 @@ WIDE_KERNEL(wide_fin_kernel) {
   const double* B = sv + SV_B * w.ss;
   const long long off = g.off;
   auto at = [&](const VecRef& r, long long idx) { return r.base + idx * a.slen + off; };
-  const double* fl = (!rho && !res && a.forcing.base)
+  const double* fl = (!res && a.forcing.base)
                          ? at(a.forcing, a.forcing.a * q + a.forcing.b + a.nsteps) : nullptr;
   double* dst = a.fin.base ? at(a.fin, a.fin.a * q + a.fin.b) : nullptr;
   const double* tg = (!rho && a.target.base) ? at(a.target, a.target.a * q + a.target.b)
@@ -699,8 +885,24 @@ WIDE_KERNEL(wide_fin_kernel) {
     dst[p] = u;
     v[0] += u * u;
   }
-  wide_reduce<1>(w, sm, wide_point_blocks(g), WR_FIN, WS_FIN, v);
-  if (!sm.flag || threadIdx.x != 0) return;  // the last work-group of the task
+  wide_put<kWT, 1>(w, sm, WS_FIN, v);
+}
+
+// After the chain (one wave per task): account the last step, publish
+// res2 (residual mode: the max with the steps' initial residuals), the
+// counters and the status bits.
+template <int OPC>
+__global__ void __launch_bounds__(64) wide_finish_kernel(WideArgs w) {
+  WIDE_SMEM;
+  if (!wide_begin<OPC, 64>(w, sm, tl_lds, false, false, gp, tl)) return;
+  const ChainArgs& a = w.a;
+  const GridDev& g = *gp;
+  const bool res = a.resmode != 0;
+  const bool rho = res && a.target.base;
+  const int slot[2] = {WS_FIN, WS_RR0}, nb[2] = {wide_point_blocks(g), wide_point_blocks(g)};
+  double v[2];
+  wide_sums<2>(w, slot, nb, v);
+  if (threadIdx.x != 0) return;
   WideTask* T = w.st + blockIdx.y;
   int flag = T->flag;
   long long kr_sum = T->kr_sum, kr_max = T->kr_max;
@@ -710,15 +912,12 @@ WIDE_KERNEL(wide_fin_kernel) {
     flag |= (T->done || res) ? 0 : FLAG_NOCONV;
     if (res) {
       flag &= ~(FLAG_NOCONV | FLAG_BREAKDOWN);
-      res_max = fmax(res_max, T->sum[WS_RR0]);
+      res_max = fmax(res_max, v[1]);
     }
     kr_sum += it;
     kr_max = it > kr_max ? it : kr_max;
   }
-  if (a.target.base && a.res2) {
-    const double rr = T->sum[WS_FIN];
-    a.res2[blockIdx.y] = res ? fmax(rr, res_max) : rr;
-  }
+  if (a.target.base && a.res2) a.res2[blockIdx.y] = res ? fmax(v[0], res_max) : v[0];
   if (a.counters) {
     atomicAdd(&a.counters[CNT_KRYLOV], (unsigned long long)kr_sum);
     atomicMax(&a.counters[CNT_KRYLOV_MAX], (unsigned long long)kr_max);
@@ -728,33 +927,36 @@ WIDE_KERNEL(wide_fin_kernel) {
   if (flag && a.status) atomicOr(a.status, flag);
 }
 
-// Poll (one work-group, the range's tasks): the test the next kernel of
-// iteration i would make, then the number of tasks still iterating into
-// mapped host memory. With the launch skipped, nothing is iterating.
-template <int SOLVER>
-__global__ void __launch_bounds__(64) wide_poll_kernel(WideArgs w, int ntasks) {
-  int busy = 0;
+// Poll (one wave per task): the test the next kernel of iteration i would
+// make first (BiCGStab: the start of K_B(i); CG: the start of K_CA(i)),
+// then 1 (still iterating) or 0 into host_out[task] (mapped host memory).
+// With the launch skipped, nothing is iterating.
+template <int OPC, int SOLVER>
+__global__ void __launch_bounds__(64) wide_poll_kernel(WideArgs w) {
+  WIDE_SMEM;
   const bool skipped = w.a.skip && *w.a.skip != 0.0;
-  for (int t = threadIdx.x; t < ntasks && !skipped; t += 64) {
-    WideTask* T = w.st + t;
-    if (T->done) continue;
+  int busy = 0;
+  if (!skipped && wide_begin<OPC, 64>(w, sm, tl_lds, false, true, gp, tl)) {
+    const GridDev& g = *gp;
+    const int nbr = (SOLVER == SOLV_BICG) ? wide_line_blocks(g) : wide_point_blocks(g);
+    const int slot[3] = {WS_RR0, WS_BB, WS_RR};
+    const int nb[3] = {wide_point_blocks(g), wide_point_blocks(g), w.i > 1 ? nbr : 0};
+    double v[3];
+    wide_sums<3>(w, slot, nb, v);
+    WideTask* T = w.st + blockIdx.y;
     int it, fl;
-    if (wide_test_next(T, w.a.tol * w.a.tol, w.i, it, fl)) {
-      if (fl) T->flag |= fl;
-      T->it = it;
-      T->done = 1;
-    } else {
-      ++busy;
-    }
+    const double tol2 = w.a.tol * w.a.tol;
+    const bool stop = (w.i == 1) ? wide_test_init(v[0], v[1], tol2, it, fl)
+                                 : wide_test_rr(v[2], v[1], T->pend, tol2, w.i - 1, it, fl);
+    if (stop)
+      wide_stop(T, it, fl);
+    else
+      busy = 1;
   }
-  busy = (int)wave_sum((double)busy);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(w.host_out, busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __threadfence_system();
-  }
+  if (threadIdx.x == 0)
+    __hip_atomic_store(w.host_out + blockIdx.y, busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-#undef WIDE_KERNEL
 #undef WIDE_SMEM
 
 }  // namespace ctm

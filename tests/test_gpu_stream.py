@@ -17,6 +17,9 @@ from helpers import (combine, oracle_abs_apply, oracle_apply, oracle_mgrit_histo
                      oracle_propagate, rel_l2, solve, split)
 
 
+ALL = 1 << 20  # set_wide: every streaming launch on the wide solver
+
+
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
@@ -114,12 +117,12 @@ def test_streaming_other_operators(name, kw):
 @pytest.mark.parametrize("kw", [dict(mgrit_levels=1), dict(), dict(krylov="bicgstab"),
                                 dict(relax="F", cf=8), dict(krylov="bicgstab", mgrit_levels=1)])
 def test_streaming_wide_against_narrow(kw):
-    # the same solve with every streaming launch of at most 64 tasks on the
-    # wide solver (many work-groups per task), and with none: both meet the
-    # oracle, and agree with each other to the Krylov tolerance
+    # the same solve with every streaming launch on the wide solver (many
+    # work-groups per task), and with none (one work-group per task): both
+    # meet the oracle, and agree with each other to the Krylov tolerance
     p = _heat2d_big(**kw)
     out = {}
-    for wide in (0, 64):
+    for wide in (0, ALL):
         _say(f"streaming wide={wide} {kw}")
         plan = ctm.Plan(p)
         plan.set_wide(wide)
@@ -129,8 +132,8 @@ def test_streaming_wide_against_narrow(kw):
         assert st["krylov_iterations"] > 0
     ref = solve.packed(solve.component_states(p))
     assert rel_l2(out[0], ref) <= 1e-11
-    assert rel_l2(out[64], ref) <= 1e-11
-    assert rel_l2(out[64], out[0]) <= 1e-11
+    assert rel_l2(out[ALL], ref) <= 1e-11
+    assert rel_l2(out[ALL], out[0]) <= 1e-11
 
 
 def test_streaming_wide_drift_oscillator():
@@ -139,7 +142,7 @@ def test_streaming_wide_drift_oscillator():
     p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100)
     _say("streaming wide fp_osc2d")
     plan = ctm.Plan(p)
-    plan.set_wide(64)
+    plan.set_wide(ALL)
     u = plan.solve().cpu().numpy()
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
@@ -150,7 +153,7 @@ def test_streaming_wide_noconv_flag():
     # a Krylov cap the tolerance cannot meet: the wide solver stops at the
     # cap and reports non-convergence, like the one-work-group kernel
     p = _heat2d_big(mgrit_levels=1, krylov_maxit=2, krylov_tol=1e-14)
-    for wide in (0, 64):
+    for wide in (0, ALL):
         plan = ctm.Plan(p)
         plan.set_wide(wide)
         _, code = plan.solve(check=False)
