@@ -159,3 +159,23 @@ def test_streaming_wide_noconv_flag():
         _, code = plan.solve(check=False)
         assert code == ctm.ERR_NOCONV, wide
         assert plan.stats()["krylov_max"] == 2, wide
+
+
+@pytest.mark.parametrize("kw", [dict(mgrit_levels=1), dict(), dict(krylov="bicgstab")])
+def test_streaming_three_dimensional(kw):
+    # d = 3 (the dimension bound 4 of both streaming solvers): at level 10
+    # the grids (10,1,1), (1,10,1), (1,1,10) have lines of 1,023 unknowns
+    # and run on the streaming solvers, the other 133 on chip
+    p = make("heat3d", n=10, nsteps=16, t1=0.01)
+    p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100, cf=4)
+    p.update(kw)
+    ref = solve.packed(solve.component_states(p))
+    for wide in (0, ALL):
+        _say(f"streaming heat3d n=10 wide={wide} {kw}")
+        plan = ctm.Plan(p)
+        plan.set_wide(wide)
+        u = plan.solve().cpu().numpy()
+        st = plan.stats()
+        assert st["status_flags"] == 0
+        assert any(s["K"] == 0 for s in st["shapes"])
+        assert rel_l2(u, ref) <= 1e-11, wide
