@@ -160,6 +160,8 @@ enum {
 
 // Per-task state (device memory, one per task of the range).
 struct WideTask {
+  GridDev g;      // the task's grid (copied by the chain's first kernel)
+  int q;          // the task's interval
   int done;       // the step's Krylov solve has stopped
   int it;         // its iteration count
   int pend;       // BiCGStab: breakdown found in the direction update

@@ -47,27 +47,30 @@ struct WideSmem {
 
 // Shared preamble: the launch-level skip, the task's grid and coefficient
 // tables, the block range of the grid, and the done flag. The grid
-// descriptor is read in place (uniform loads); only the per-axis tables of
-// the SEP and VAR classes are staged in LDS (tl_lds), the constant-size
-// DRIFT table is read in place and HEAT has none. A single-wave work-group
-// reads `done` itself; a larger one broadcasts thread 0's read, so that its
-// waves agree. Returns false (uniformly over the work-group) when the block
-// has nothing to do.
+// descriptor is read in place from the task's state (the chain's first
+// kernel copies it there), so that the skip flag, the grid and the done flag
+// load in parallel instead of through the task list; only the per-axis
+// tables of the SEP and VAR classes are staged in LDS (tl_lds), the
+// constant-size DRIFT table is read in place and HEAT has none. A
+// single-wave work-group reads `done` itself; a larger one broadcasts thread
+// 0's read, so that its waves agree. Returns false (uniformly over the
+// work-group) when the block has nothing to do.
 template <int OPC, int BT>
 __device__ __forceinline__ bool wide_begin(const WideArgs& w, WideSmem& sm, double* tl_lds,
                                            bool line, bool check_done, const GridDev*& gp,
                                            const double*& tl) {
   const ChainArgs& a = w.a;
-  if (a.skip && *a.skip != 0.0) return false;
-  gp = a.grids + a.tasks[blockIdx.y].x;
+  WideTask* T = w.st + blockIdx.y;
+  const double skipv = a.skip ? *a.skip : 0.0;
+  gp = &T->g;
   const GridDev& g = *gp;
+  int done = 0;
+  if constexpr (BT == 64) done = check_done ? T->done : 0;
+  if (skipv != 0.0) return false;
   const int nb = line ? wide_line_blocks(g) : wide_point_blocks(g);
   if ((int)blockIdx.x >= nb) return false;
-  int done = 0;
-  if constexpr (BT == 64) {
-    done = check_done ? w.st[blockIdx.y].done : 0;
-  } else {
-    if (threadIdx.x == 0) sm.flag = check_done ? w.st[blockIdx.y].done : 0;
+  if constexpr (BT > 64) {
+    if (threadIdx.x == 0) sm.flag = check_done ? T->done : 0;
   }
   if constexpr (OPC == OPC_SEP || OPC == OPC_VAR) {
     load_tables<OPC, double, BT>(g, a.tab64, a.dt, tl_lds);
@@ -333,11 +336,34 @@ __device__ __forceinline__ void wide_pre(const double* sv, long long ss, const S
 template <int OPC, int D>
 __global__ void __launch_bounds__(kWLT) wide_setup_kernel(WideArgs w) {
   WIDE_SMEM;
-  if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, false, gp, tl)) return;
+  // the chain's first kernel: the grid comes from the task list, and work-
+  // group 0 of each task copies it (and the interval) into the task's state
+  // for the kernels that follow
+  const ChainArgs& a = w.a;
+  if (a.skip && *a.skip != 0.0) return;
+  const int2 task = a.tasks[blockIdx.y];
+  const GridDev& g = a.grids[task.x];
+  WideTask* T = w.st + blockIdx.y;
+  if (blockIdx.x == 0) {
+    const int* src = reinterpret_cast<const int*>(&g);
+    int* dst = reinterpret_cast<int*>(&T->g);
+    for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += kWLT) dst[t] = src[t];
+    if (threadIdx.x == 0) T->q = task.y;
+  }
+  if ((int)blockIdx.x >= wide_line_blocks(g)) return;
+  if constexpr (OPC == OPC_SEP || OPC == OPC_VAR) {
+    load_tables<OPC, double, kWLT>(g, a.tab64, a.dt, tl_lds);
+    tl = tl_lds;
+    __syncthreads();
+  } else {
+    tl = a.tab64 + g.tab0;
+  }
+  (void)sm;
+  (void)gp;
   double* sv = wide_sv(w);
   SLane L;
-  wide_lane<D>(*gp, L);
-  linepre_setup_lane<OPC, D>(*gp, tl, w.a.dt, w.a.amp, sv, w.ss, sv + SV_S * w.ss, L);
+  wide_lane<D>(g, L);
+  linepre_setup_lane<OPC, D>(g, tl, a.dt, a.amp, sv, w.ss, sv + SV_S * w.ss, L);
 }
 
 // Step transition (point-wise; step j): finish step j-1 (B = x + forcing,
@@ -351,7 +377,7 @@ __global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
   if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, false, gp, tl)) return;
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
-  const int q = a.tasks[blockIdx.y].y;
+  const int q = w.st[blockIdx.y].q;
   const int j = w.j;
   const bool last = (j == a.nsteps), res = a.resmode != 0;
   if (blockIdx.x == 0) {
@@ -480,39 +506,6 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
   WideTask* T = w.st + blockIdx.y;
   const double tol2 = a.tol * a.tol;
   const int i = w.i;
-  int it, fl;
-  double omega = 0.0, beta = 0.0;
-  bool pend = false;
-  if (i == 1) {
-    const int slot[2] = {WS_RR0, WS_BB}, nb[2] = {wide_point_blocks(g), wide_point_blocks(g)};
-    double v[2];
-    wide_sums<2>(w, slot, nb, v);
-    if (wide_test_init(v[0], v[1], tol2, it, fl)) {
-      wide_stop(T, it, fl);
-      return;
-    }
-  } else {
-    BicgSums S;
-    bicg_sums(w, g, S);
-    double Dn[5];
-    bicg_d(S, i - 1, Dn);
-    const double tt = Dn[1];
-    if (Dn[2] <= tol2 * S.bb) {
-      wide_stop(T, i - 1, 0);  // x already holds x + alpha h
-      return;
-    }
-    if (!(tt != 0.0) || isnan_(tt)) {
-      wide_stop(T, i - 1, isnan_(tt) ? FLAG_NONFINITE : FLAG_BREAKDOWN);
-      return;
-    }
-    omega = Dn[0] / tt;
-    const double rho_o = bicg_rho(S, i - 1), rho_n = bicg_rho(S, i);
-    const double alpha = rho_o / S.rhv;
-    if (rho_n == 0.0 || omega == 0.0)
-      pend = true;
-    else
-      beta = (rho_n / rho_o) * (alpha / omega);
-  }
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   double* X = sv + SV_X * ss;
@@ -524,37 +517,63 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
   double* H = sv + SV_D * ss;
   SLane L;
   wide_lane<D>(g, L);
-  // (all loads of a pass are issued before its stores: the vectors share
-  // one base, so the compiler cannot move a load above an earlier store)
+  // The first pass's loads go out before the sums' loads (they do not
+  // depend on them; a stopped task discards them). All loads of a pass are
+  // issued before its stores: the vectors share one base, so the compiler
+  // cannot move a load above an earlier store.
   double pr[kSK], hz[kSK];
   double rr[1] = {0.0};
+  int it, fl;
   if (i == 1) {
 #pragma unroll
     for (int k = 0; k < kSK; ++k) pr[k] = (k < L.nval) ? ldo(P, lane_pt(L, k)) : 0.0;
+    const int slot[2] = {WS_RR0, WS_BB}, nb[2] = {wide_point_blocks(g), wide_point_blocks(g)};
+    double v[2];
+    wide_sums<2>(w, slot, nb, v);
+    if (wide_test_init(v[0], v[1], tol2, it, fl)) {
+      wide_stop(T, it, fl);
+      return;
+    }
   } else {
-    // r = s - omega t, x += omega h (one pass of loads), then p = r + beta
-    // (p - omega v)
-    {
-      double xv[kSK], hv[kSK], sv_[kSK], tv[kSK];
+    double xv[kSK], hv[kSK], sv_[kSK], tv[kSK];
 #pragma unroll
-      for (int k = 0; k < kSK; ++k) {
-        const bool ok = k < L.nval;
+    for (int k = 0; k < kSK; ++k) {
+      const bool ok = k < L.nval;
+      const unsigned p = lane_pt(L, k);
+      xv[k] = ok ? ldo(X, p) : 0.0;
+      hv[k] = ok ? ldo(H, p) : 0.0;
+      sv_[k] = ok ? ldo(S, p) : 0.0;
+      tv[k] = ok ? ldo(Tv, p) : 0.0;
+    }
+    BicgSums Sm;
+    bicg_sums(w, g, Sm);
+    double Dn[5];
+    bicg_d(Sm, i - 1, Dn);
+    const double tt = Dn[1];
+    if (Dn[2] <= tol2 * Sm.bb) {
+      wide_stop(T, i - 1, 0);  // x already holds x + alpha h
+      return;
+    }
+    if (!(tt != 0.0) || isnan_(tt)) {
+      wide_stop(T, i - 1, isnan_(tt) ? FLAG_NONFINITE : FLAG_BREAKDOWN);
+      return;
+    }
+    const double omega = Dn[0] / tt;
+    const double rho_o = bicg_rho(Sm, i - 1), rho_n = bicg_rho(Sm, i);
+    const double alpha = rho_o / Sm.rhv;
+    const bool pend = (rho_n == 0.0 || omega == 0.0);
+    const double beta = pend ? 0.0 : (rho_n / rho_o) * (alpha / omega);
+    if (pend && blockIdx.x == 0 && threadIdx.x == 0) T->pend = 1;
+    // r = s - omega t, x += omega h; then p = r + beta (p - omega v)
+#pragma unroll
+    for (int k = 0; k < kSK; ++k) {
+      const double r = sv_[k] - omega * tv[k];
+      pr[k] = r;
+      rr[0] += r * r;
+      if (k < L.nval) {
         const unsigned p = lane_pt(L, k);
-        xv[k] = ok ? ldo(X, p) : 0.0;
-        hv[k] = ok ? ldo(H, p) : 0.0;
-        sv_[k] = ok ? ldo(S, p) : 0.0;
-        tv[k] = ok ? ldo(Tv, p) : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < kSK; ++k) {
-        const double r = sv_[k] - omega * tv[k];
-        pr[k] = r;
-        rr[0] += r * r;
-        if (k < L.nval) {
-          const unsigned p = lane_pt(L, k);
-          sto(X, p, xv[k] + omega * hv[k]);
-          sto(R, p, r);
-        }
+        sto(X, p, xv[k] + omega * hv[k]);
+        sto(R, p, r);
       }
     }
     double pv[kSK], vv[kSK];
@@ -576,10 +595,7 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
 #pragma unroll
   for (int k = 0; k < kSK; ++k)
     if (k < L.nval) sto(H, lane_pt(L, k), hz[k]);
-  if (i > 1) {
-    if (pend && blockIdx.x == 0 && threadIdx.x == 0) T->pend = 1;
-    wide_put<kWLT, 1>(w, sm, WS_RR, rr);
-  }
+  if (i > 1) wide_put<kWLT, 1>(w, sm, WS_RR, rr);
 }
 
 // K_B(i): the test of the r update (i > 1); v = A h, partial (r^, v).
@@ -590,21 +606,13 @@ __global__ void __launch_bounds__(kWT) wide_bicg_b_kernel(WideArgs w) {
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
-  if (w.i > 1) {
-    const int slot[2] = {WS_RR, WS_BB}, nb[2] = {wide_line_blocks(g), wide_point_blocks(g)};
-    double v[2];
-    wide_sums<2>(w, slot, nb, v);
-    int it, fl;
-    if (wide_test_rr(v[0], v[1], T->pend, a.tol * a.tol, w.i - 1, it, fl)) {
-      wide_stop(T, it, fl);
-      return;
-    }
-  }
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   const double* H = sv + SV_D * ss;
   const double* RH = sv + SV_RH * ss;
   double* V = sv + SV_Q * ss;
+  // (the stencil's loads go out before the sums' loads; a stopped task
+  // discards them)
   double v[1] = {0.0};
   double yv[kWPT];
 #pragma unroll
@@ -615,6 +623,16 @@ __global__ void __launch_bounds__(kWT) wide_bicg_b_kernel(WideArgs w) {
     const double y = wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int m) { return H[m]; });
     yv[k] = y;
     v[0] += RH[p] * y;
+  }
+  if (w.i > 1) {
+    const int slot[2] = {WS_RR, WS_BB}, nb[2] = {wide_line_blocks(g), wide_point_blocks(g)};
+    double sr[2];
+    wide_sums<2>(w, slot, nb, sr);
+    int it, fl;
+    if (wide_test_rr(sr[0], sr[1], T->pend, a.tol * a.tol, w.i - 1, it, fl)) {
+      wide_stop(T, it, fl);
+      return;
+    }
   }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
@@ -631,14 +649,6 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
   if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
-  BicgSums Sm;
-  bicg_sums(w, g, Sm);
-  const double rhv = Sm.rhv;
-  if (!(rhv != 0.0) || isnan_(rhv)) {
-    wide_stop(T, w.i, isnan_(rhv) ? FLAG_NONFINITE : FLAG_BREAKDOWN);
-    return;
-  }
-  const double alpha = bicg_rho(Sm, w.i) / rhv;
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   double* X = sv + SV_X * ss;
@@ -648,27 +658,35 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
   double* H = sv + SV_D * ss;
   SLane L;
   wide_lane<D>(g, L);
+  // the data loads go out before the sums' (they do not depend on them; a
+  // stopped task discards them), so both share one memory round trip
+  double xv[kSK], hv[kSK], rv[kSK], vv[kSK];
+#pragma unroll
+  for (int k = 0; k < kSK; ++k) {
+    const bool ok = k < L.nval;
+    const unsigned p = lane_pt(L, k);
+    xv[k] = ok ? ldo(X, p) : 0.0;
+    hv[k] = ok ? ldo(H, p) : 0.0;
+    rv[k] = ok ? ldo(R, p) : 0.0;
+    vv[k] = ok ? ldo(V, p) : 0.0;
+  }
+  BicgSums Sm;
+  bicg_sums(w, g, Sm);
+  const double rhv = Sm.rhv;
+  if (!(rhv != 0.0) || isnan_(rhv)) {
+    wide_stop(T, w.i, isnan_(rhv) ? FLAG_NONFINITE : FLAG_BREAKDOWN);
+    return;
+  }
+  const double alpha = bicg_rho(Sm, w.i) / rhv;
   double sr[kSK], hz[kSK];
-  {
-    double xv[kSK], hv[kSK], rv[kSK], vv[kSK];
 #pragma unroll
-    for (int k = 0; k < kSK; ++k) {
-      const bool ok = k < L.nval;
+  for (int k = 0; k < kSK; ++k) {
+    const double s = rv[k] - alpha * vv[k];
+    sr[k] = s;
+    if (k < L.nval) {
       const unsigned p = lane_pt(L, k);
-      xv[k] = ok ? ldo(X, p) : 0.0;
-      hv[k] = ok ? ldo(H, p) : 0.0;
-      rv[k] = ok ? ldo(R, p) : 0.0;
-      vv[k] = ok ? ldo(V, p) : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < kSK; ++k) {
-      const double s = rv[k] - alpha * vv[k];
-      sr[k] = s;
-      if (k < L.nval) {
-        const unsigned p = lane_pt(L, k);
-        sto(X, p, xv[k] + alpha * hv[k]);
-        sto(S, p, s);
-      }
+      sto(X, p, xv[k] + alpha * hv[k]);
+      sto(S, p, s);
     }
   }
   wide_pre(sv, ss, L, sr, hz);
@@ -723,6 +741,16 @@ __global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
   const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
   const double tol2 = w.a.tol * w.a.tol;
+  double* sv = wide_sv(w);
+  const long long ss = w.ss;
+  const double* R = sv + SV_R * ss;
+  double* Z = sv + SV_S * ss;
+  SLane L;
+  wide_lane<D>(g, L);
+  // (the r loads go out before the sums' loads)
+  double rv[kSK], zv[kSK];
+#pragma unroll
+  for (int k = 0; k < kSK; ++k) rv[k] = (k < L.nval) ? ldo(R, lane_pt(L, k)) : 0.0;
   {
     const int slot[3] = {WS_RR0, WS_BB, WS_RR};
     const int nb[3] = {wide_point_blocks(g), wide_point_blocks(g),
@@ -737,15 +765,6 @@ __global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
       return;
     }
   }
-  double* sv = wide_sv(w);
-  const long long ss = w.ss;
-  const double* R = sv + SV_R * ss;
-  double* Z = sv + SV_S * ss;
-  SLane L;
-  wide_lane<D>(g, L);
-  double rv[kSK], zv[kSK];
-#pragma unroll
-  for (int k = 0; k < kSK; ++k) rv[k] = (k < L.nval) ? ldo(R, lane_pt(L, k)) : 0.0;
   wide_pre(sv, ss, L, rv, zv);
   double v[1] = {0.0};
 #pragma unroll
@@ -862,7 +881,7 @@ __global__ void __launch_bounds__(kWT) wide_fin_kernel(WideArgs w) {
   if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, false, gp, tl)) return;
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
-  const int q = a.tasks[blockIdx.y].y;
+  const int q = w.st[blockIdx.y].q;
   const bool res = a.resmode != 0;
   const bool rho = res && a.target.base;  // the step kernel formed the residual
   double* sv = wide_sv(w);
