@@ -470,11 +470,12 @@ STREAM_BYTES_PER_ITERATION = {"cg": 152, "bicgstab": 296}
 
 
 def _streaming(ctm, torch):
-    """The streaming kernel on grids beyond the on-chip solver: the 2-D
+    """The streaming solvers on grids beyond the on-chip solver: the 2-D
     oscillator of Section 4.4 at the paper's own levels (L = 14, L0 = 6:
-    seven grids of up to 32,193 unknowns), FP64 MGRIT. Its roofline is HBM:
-    algorithmic bytes (sweeps x unknowns x Krylov iterations) over the
-    streaming launches' own event-timed duration."""
+    seven grids of up to 32,193 unknowns), FP64 MGRIT. Their roofline is
+    HBM: algorithmic bytes (sweeps x unknowns x Krylov iterations) over each
+    solver's event-timed launches (a wide launch is a whole chain, its host
+    polls included)."""
     from workloads import make
     p = make("fp_osc2d", n=14, L0=6, prec="fp64")
     p.update(krylov_tol=1e-10, mgrit_tol=1e-9, mgrit_maxit=64, krylov_maxit=20000)
@@ -489,10 +490,9 @@ def _streaming(ctm, torch):
     st = plan.stats()
     plan.set_timing(False)
     bpi = STREAM_BYTES_PER_ITERATION[p["krylov"]]
-    forms = {16: ("stream_kernel<drift, BiCGStab>: one 1,024-thread work-group per task "
-                  "(F- and C-relaxation, many tasks)"),
-             4: ("wide solver: many 256-thread work-groups per task, one launch per Krylov "
-                 "phase (the sequential coarse chain, one task per grid)")}
+    forms = {16: ("stream_kernel<drift, BiCGStab>: one 1,024-thread work-group per task"),
+             4: ("wide solver: many work-groups per task, one launch per Krylov phase for "
+                 "all tasks of a launch (every streaming launch by default)")}
     roof = {}
     for c in st["shapes"]:
         if c["K"] != 0 or c["W"] not in forms:

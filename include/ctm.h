@@ -294,9 +294,10 @@ ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lan
  * preconditioner, Krylov method and stopping test (Section 4.1), so results
  * agree to rounding. A wide launch waits on the host once per step for its
  * convergence test (the stream's earlier work included), so ctm_solve and
- * ctm_step return only when that part is done. max_tasks >= 0 (capped at
- * 65,535); 0 disables the wide solver; the default is 64 (MGRIT's coarse
- * chain and time-sequential stepping: one task per grid). */
+ * ctm_propagate return only when that part is done. max_tasks >= 0 (capped
+ * at 65,535, the default: every streaming launch); 0 disables the wide
+ * solver. Plans whose coefficient tables need more than 18 KiB of LDS keep
+ * the one-work-group kernel. */
 ctm_status ctm_plan_set_wide(ctm_plan* plan, int max_tasks);
 
 typedef struct {

@@ -131,13 +131,12 @@ struct ctm_plan {
   // tasks spread every task over wide_pb (point-wise) / wide_lb (line)
   // work-groups; per-task state and partial sums for wide_cap tasks (every
   // streaming task of the plan); the poll's busy flags in mapped pinned memory
-  // (default 64: the launches with few tasks - the sequential coarse chain,
-  // time-sequential stepping - where one work-group per task would leave
-  // most CUs idle; on the many-task relaxation launches the one-work-group
-  // kernel is as fast, its line sweeps run at higher occupancy)
+  // (default: every streaming launch; the one-work-group-per-task kernel
+  // remains for comparison and for plans whose coefficient tables leave no
+  // room for the line tiles in LDS)
   static constexpr int kWideMaxGridY = 65535;
   int wide_cap = 0;
-  int wide_max_tasks = 64;
+  int wide_max_tasks = kWideMaxGridY;
   int wide_pb = 0, wide_lb = 0, wide_maxblk = 0;
   WideTask* dwide = nullptr;
   double* dwpart = nullptr;
@@ -528,7 +527,8 @@ hipEvent_t take_event(ctm_plan* P, size_t& used, std::vector<hipEvent_t>& pool, 
 // Whether a launch range runs on the wide streaming solver.
 bool use_wide(const ctm_plan* P, int shape, long long count) {
   return shape == kStreamShape && count > 0 && count <= P->wide_max_tasks &&
-         count <= P->wide_cap;
+         count <= P->wide_cap &&
+         (size_t)P->tabmax * sizeof(double) + kWideStaticLds <= 65536;
 }
 
 // The chain of a launch range on the wide solver: per step, the step
@@ -547,6 +547,7 @@ ctm_status run_wide(ctm_plan* P, const ChainArgs& c, int count, hipStream_t s) {
   w.part = P->dwpart;
   w.maxblk = P->wide_maxblk;
   w.host_out = P->hwide_dev;
+  w.stage = count > 64;  // (LDS-staged line sweeps on launches of many tasks)
   const dim3 gp(P->wide_pb, count), gl(P->wide_lb, count);
   const bool bicg = (P->solver == SOLV_BICG);
   const bool res = c.resmode != 0;

@@ -144,6 +144,9 @@ constexpr int kWPT = 2;            // points per thread in the point-wise kernel
 constexpr int kWP = kWT * kWPT;    // points per point-wise work-group
 constexpr int kWLW = 1;            // waves per line work-group
 constexpr int kWideSK = 16;        // unknowns per lane along a line (as the streaming kernel)
+// static LDS of a line kernel of the wide solver (line tiles and sums); the
+// coefficient tables (dynamic LDS) must fit beside it in 64 KiB
+constexpr int kWideStaticLds = 46 * 1024;
 
 // Sums of a task; each has a partial per producing work-group.
 enum {
@@ -180,6 +183,7 @@ struct WideArgs {
   int j;            // step (1-based)
   int i;            // Krylov iteration
   int prev_its;     // iterations launched for the step being accounted
+  int stage;        // line kernels stage contiguous lines through LDS
   int* host_out;    // poll: per task 1 while still iterating (mapped host memory)
 };
 

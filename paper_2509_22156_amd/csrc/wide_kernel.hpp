@@ -247,30 +247,137 @@ __device__ __forceinline__ void sto(double* base, unsigned i, double v) {
   *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (size_t)(i * 8u)) = v;
 }
 
-// z = M^-1 r on the chunk of lane L in registers (r and z hold the chunk's
-// kSK unknowns; entries past nval are ignored / returned 0). Every factor
-// load is issued before the first use: the launches of few tasks that this
-// solver serves are latency-bound, one round trip beats three.
-__device__ __forceinline__ void wide_pre(const double* sv, long long ss, const SLane& L,
-                                         const double (&r)[kSK], double (&z)[kSK]) {
-  const double* FM = sv + SV_FM * ss;
-  const double* FID = sv + SV_FID * ss;
-  const double* FCU = sv + SV_FCU * ss;
-  const double* FPHI = sv + SV_FPHI * ss;
-  const double* FPSI = sv + SV_FPSI * ss;
-  const bool full = (L.nval == kSK);
-  const int ne = L.nval < kSK - 1 ? L.nval : kSK - 1;
-  double fm[kSK], fid[kSK], fcu[kSK], fph[kSK], fps[kSK];
+// Line sweeps of a wave. Where the stiff axis is the grid's fastest axis
+// (stride 1), the wave's 64 / Lc lines are one contiguous range of at most
+// 64 kSK unknowns, and a lane's chunk is kSK consecutive values: read
+// directly, every load instruction touches 64 cache lines. For launches of
+// many tasks (WideArgs::stage) the wave stages its lines through LDS there:
+// coalesced global loads (element m * 64 + lane) into a padded tile (one
+// pad slot per chunk, so that the lanes' chunk reads fall in different
+// banks), then each lane reads its chunk; stores the other way round.
+// Otherwise the lanes read their chunks directly (launches of few tasks are
+// latency-bound, and the extra LDS round trip did not pay there).
+constexpr int kTileMax = 64 * kSK;                   // unknowns of a wave's lines
+constexpr int kTilePad = kTileMax + kTileMax / kSK;  // with one pad per chunk
+constexpr int kTileVecs = 5;                         // vectors staged at once
+__device__ __forceinline__ int tpad(int e) { return e + e / kSK; }
+
+struct WaveTile {
+  bool on;      // staged
+  unsigned t0;  // first unknown of the wave's lines
+  int n;        // unknowns of the wave's lines
+  int e0;       // this lane's chunk start inside the range
+};
+__device__ __forceinline__ WaveTile wave_tile(const WideArgs& w, const GridDev& g,
+                                              const SLane& L) {
+  WaveTile T;
+  T.on = w.stage && (g.sax == g.d - 1);
+  const int G = 64 / L.Lc;
+  const int line0 = ((int)blockIdx.x * kWLW + (int)(threadIdx.x >> 6)) * G;
+  const int gv = g.nlines - line0 < G ? g.nlines - line0 : G;
+  T.t0 = (unsigned)line0 * (unsigned)g.ns;
+  T.n = gv * g.ns;
+  T.e0 = ((int)(threadIdx.x & 63) / L.Lc) * g.ns + L.j0;
+  return T;
+}
+
+// out[s][k] = vector s at unknown k of the lane's chunk (0 past nval).
+template <int NV>
+__device__ __forceinline__ void line_gather(const WaveTile& T, const SLane& L,
+                                            const double* const (&v)[NV], double* tile,
+                                            double (&out)[NV][kSK]) {
+  static_assert(NV <= kTileVecs, "tile slots");
+  if (!T.on) {
+#pragma unroll
+    for (int k = 0; k < kSK; ++k) {
+      const bool ok = k < L.nval;
+      const unsigned p = lane_pt(L, k);
+#pragma unroll
+      for (int s = 0; s < NV; ++s) out[s][k] = ok ? ldo(v[s], p) : 0.0;
+    }
+    return;
+  }
+  double* tw = tile + (threadIdx.x >> 6) * (kTileVecs * kTilePad);
+  const int lane = threadIdx.x & 63;
+  double tmp[NV][kSK];
+#pragma unroll
+  for (int m = 0; m < kSK; ++m) {
+    const int e = m * 64 + lane;
+    const bool ok = e < T.n;
+#pragma unroll
+    for (int s = 0; s < NV; ++s) tmp[s][m] = ok ? ldo(v[s], T.t0 + (unsigned)e) : 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < kSK; ++m) {
+    const int e = m * 64 + lane;
+    if (e < T.n) {
+#pragma unroll
+      for (int s = 0; s < NV; ++s) tw[s * kTilePad + tpad(e)] = tmp[s][m];
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < kSK; ++k) {
-    const bool v = k < L.nval;
-    const unsigned p = lane_pt(L, k);
-    fm[k] = v ? ldo(FM, p) : 0.0;
-    fid[k] = v ? ldo(FID, p) : 0.0;
-    fcu[k] = v ? ldo(FCU, p) : 0.0;
-    fph[k] = v ? ldo(FPHI, p) : 0.0;
-    fps[k] = v ? ldo(FPSI, p) : 0.0;
+    const bool ok = k < L.nval;
+#pragma unroll
+    for (int s = 0; s < NV; ++s) out[s][k] = ok ? tw[s * kTilePad + tpad(T.e0 + k)] : 0.0;
   }
+  __syncthreads();  // the tile is reused by the next gather or scatter
+}
+
+// vector s at unknown k of the lane's chunk = in[s][k] (k < nval).
+template <int NV>
+__device__ __forceinline__ void line_scatter(const WaveTile& T, const SLane& L,
+                                             double* const (&v)[NV], double* tile,
+                                             const double (&in)[NV][kSK]) {
+  static_assert(NV <= kTileVecs, "tile slots");
+  if (!T.on) {
+#pragma unroll
+    for (int k = 0; k < kSK; ++k)
+      if (k < L.nval) {
+        const unsigned p = lane_pt(L, k);
+#pragma unroll
+        for (int s = 0; s < NV; ++s) sto(v[s], p, in[s][k]);
+      }
+    return;
+  }
+  double* tw = tile + (threadIdx.x >> 6) * (kTileVecs * kTilePad);
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kSK; ++k)
+    if (k < L.nval) {
+#pragma unroll
+      for (int s = 0; s < NV; ++s) tw[s * kTilePad + tpad(T.e0 + k)] = in[s][k];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kSK; ++m) {
+    const int e = m * 64 + lane;
+    if (e < T.n) {
+#pragma unroll
+      for (int s = 0; s < NV; ++s) sto(v[s], T.t0 + (unsigned)e, tw[s * kTilePad + tpad(e)]);
+    }
+  }
+  __syncthreads();
+}
+
+// z = M^-1 r on the chunk of lane L in registers (r and z hold the chunk's
+// kSK unknowns; entries past nval are ignored / returned 0). The five factor
+// vectors are gathered in one pass.
+__device__ __forceinline__ void wide_pre(const double* sv, long long ss, const WaveTile& T,
+                                         const SLane& L, double* tile, const double (&r)[kSK],
+                                         double (&z)[kSK]) {
+  const double* const fv[5] = {sv + SV_FM * ss, sv + SV_FID * ss, sv + SV_FCU * ss,
+                               sv + SV_FPHI * ss, sv + SV_FPSI * ss};
+  double f[5][kSK];
+  line_gather<5>(T, L, fv, tile, f);
+  const double* fm = f[0];
+  const double* fid = f[1];
+  const double* fcu = f[2];
+  const double* fph = f[3];
+  const double* fps = f[4];
+  const bool full = (L.nval == kSK);
+  const int ne = L.nval < kSK - 1 ? L.nval : kSK - 1;
   // forward elimination over the eliminated unknowns 0..ne-1
   double y[kSK];
 #pragma unroll
@@ -331,6 +438,10 @@ __device__ __forceinline__ void wide_pre(const double* sv, long long ss, const S
   const GridDev* gp = nullptr;                          \
   const double* tl = nullptr;                           \
   double* tl_lds = reinterpret_cast<double*>(smem)
+
+#define WIDE_TILE __shared__ double tile[kWLW * kTileVecs * kTilePad]
+static_assert(kWLW * kTileVecs * kTilePad * sizeof(double) + sizeof(WideSmem) <= kWideStaticLds,
+              "static LDS of the line kernels");
 
 // Factors of the line preconditioner (once per chain).
 template <int OPC, int D>
@@ -500,6 +611,7 @@ __global__ void __launch_bounds__(kWT) wide_init_kernel(WideArgs w) {
 template <int OPC, int D>
 __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
   WIDE_SMEM;
+  WIDE_TILE;
   if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
@@ -517,6 +629,7 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
   double* H = sv + SV_D * ss;
   SLane L;
   wide_lane<D>(g, L);
+  const WaveTile Tl = wave_tile(w, g, L);
   // The first pass's loads go out before the sums' loads (they do not
   // depend on them; a stopped task discards them). All loads of a pass are
   // issued before its stores: the vectors share one base, so the compiler
@@ -525,8 +638,13 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
   double rr[1] = {0.0};
   int it, fl;
   if (i == 1) {
+    {
+      const double* const v1[1] = {P};
+      double o[1][kSK];
+      line_gather<1>(Tl, L, v1, tile, o);
 #pragma unroll
-    for (int k = 0; k < kSK; ++k) pr[k] = (k < L.nval) ? ldo(P, lane_pt(L, k)) : 0.0;
+      for (int k = 0; k < kSK; ++k) pr[k] = o[0][k];
+    }
     const int slot[2] = {WS_RR0, WS_BB}, nb[2] = {wide_point_blocks(g), wide_point_blocks(g)};
     double v[2];
     wide_sums<2>(w, slot, nb, v);
@@ -535,16 +653,9 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
       return;
     }
   } else {
-    double xv[kSK], hv[kSK], sv_[kSK], tv[kSK];
-#pragma unroll
-    for (int k = 0; k < kSK; ++k) {
-      const bool ok = k < L.nval;
-      const unsigned p = lane_pt(L, k);
-      xv[k] = ok ? ldo(X, p) : 0.0;
-      hv[k] = ok ? ldo(H, p) : 0.0;
-      sv_[k] = ok ? ldo(S, p) : 0.0;
-      tv[k] = ok ? ldo(Tv, p) : 0.0;
-    }
+    const double* const v4[4] = {X, H, S, Tv};
+    double o[4][kSK];
+    line_gather<4>(Tl, L, v4, tile, o);
     BicgSums Sm;
     bicg_sums(w, g, Sm);
     double Dn[5];
@@ -565,36 +676,39 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
     const double beta = pend ? 0.0 : (rho_n / rho_o) * (alpha / omega);
     if (pend && blockIdx.x == 0 && threadIdx.x == 0) T->pend = 1;
     // r = s - omega t, x += omega h; then p = r + beta (p - omega v)
+    {
+      double st[2][kSK];
 #pragma unroll
-    for (int k = 0; k < kSK; ++k) {
-      const double r = sv_[k] - omega * tv[k];
-      pr[k] = r;
-      rr[0] += r * r;
-      if (k < L.nval) {
-        const unsigned p = lane_pt(L, k);
-        sto(X, p, xv[k] + omega * hv[k]);
-        sto(R, p, r);
+      for (int k = 0; k < kSK; ++k) {
+        const double r = o[2][k] - omega * o[3][k];
+        pr[k] = r;
+        rr[0] += r * r;
+        st[0][k] = o[0][k] + omega * o[1][k];
+        st[1][k] = r;
       }
+      double* const d2[2] = {X, R};
+      line_scatter<2>(Tl, L, d2, tile, st);
     }
-    double pv[kSK], vv[kSK];
+    {
+      const double* const v2[2] = {P, V};
+      double o2[2][kSK], st[1][kSK];
+      line_gather<2>(Tl, L, v2, tile, o2);
 #pragma unroll
-    for (int k = 0; k < kSK; ++k) {
-      const bool ok = k < L.nval;
-      const unsigned p = lane_pt(L, k);
-      pv[k] = ok ? ldo(P, p) : 0.0;
-      vv[k] = ok ? ldo(V, p) : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < kSK; ++k) {
-      const double pn = pr[k] + beta * (pv[k] - omega * vv[k]);
-      pr[k] = (k < L.nval) ? pn : 0.0;
-      if (k < L.nval) sto(P, lane_pt(L, k), pn);
+      for (int k = 0; k < kSK; ++k) {
+        const double pn = pr[k] + beta * (o2[0][k] - omega * o2[1][k]);
+        pr[k] = (k < L.nval) ? pn : 0.0;
+        st[0][k] = pn;
+      }
+      double* const d1[1] = {P};
+      line_scatter<1>(Tl, L, d1, tile, st);
     }
   }
-  wide_pre(sv, ss, L, pr, hz);
-#pragma unroll
-  for (int k = 0; k < kSK; ++k)
-    if (k < L.nval) sto(H, lane_pt(L, k), hz[k]);
+  wide_pre(sv, ss, Tl, L, tile, pr, hz);
+  {
+    double* const d1[1] = {H};
+    const double(&st)[1][kSK] = reinterpret_cast<const double(&)[1][kSK]>(hz);
+    line_scatter<1>(Tl, L, d1, tile, st);
+  }
   if (i > 1) wide_put<kWLT, 1>(w, sm, WS_RR, rr);
 }
 
@@ -646,6 +760,7 @@ __global__ void __launch_bounds__(kWT) wide_bicg_b_kernel(WideArgs w) {
 template <int OPC, int D>
 __global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
   WIDE_SMEM;
+  WIDE_TILE;
   if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
@@ -658,18 +773,12 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
   double* H = sv + SV_D * ss;
   SLane L;
   wide_lane<D>(g, L);
+  const WaveTile Tl = wave_tile(w, g, L);
   // the data loads go out before the sums' (they do not depend on them; a
   // stopped task discards them), so both share one memory round trip
-  double xv[kSK], hv[kSK], rv[kSK], vv[kSK];
-#pragma unroll
-  for (int k = 0; k < kSK; ++k) {
-    const bool ok = k < L.nval;
-    const unsigned p = lane_pt(L, k);
-    xv[k] = ok ? ldo(X, p) : 0.0;
-    hv[k] = ok ? ldo(H, p) : 0.0;
-    rv[k] = ok ? ldo(R, p) : 0.0;
-    vv[k] = ok ? ldo(V, p) : 0.0;
-  }
+  const double* const v4[4] = {X, H, R, V};
+  double o[4][kSK];
+  line_gather<4>(Tl, L, v4, tile, o);
   BicgSums Sm;
   bicg_sums(w, g, Sm);
   const double rhv = Sm.rhv;
@@ -679,20 +788,24 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
   }
   const double alpha = bicg_rho(Sm, w.i) / rhv;
   double sr[kSK], hz[kSK];
+  {
+    double st[2][kSK];
 #pragma unroll
-  for (int k = 0; k < kSK; ++k) {
-    const double s = rv[k] - alpha * vv[k];
-    sr[k] = s;
-    if (k < L.nval) {
-      const unsigned p = lane_pt(L, k);
-      sto(X, p, xv[k] + alpha * hv[k]);
-      sto(S, p, s);
+    for (int k = 0; k < kSK; ++k) {
+      const double sk = o[2][k] - alpha * o[3][k];
+      sr[k] = sk;
+      st[0][k] = o[0][k] + alpha * o[1][k];
+      st[1][k] = sk;
     }
+    double* const d2[2] = {X, S};
+    line_scatter<2>(Tl, L, d2, tile, st);
   }
-  wide_pre(sv, ss, L, sr, hz);
-#pragma unroll
-  for (int k = 0; k < kSK; ++k)
-    if (k < L.nval) sto(H, lane_pt(L, k), hz[k]);
+  wide_pre(sv, ss, Tl, L, tile, sr, hz);
+  {
+    double* const d1[1] = {H};
+    const double(&st)[1][kSK] = reinterpret_cast<const double(&)[1][kSK]>(hz);
+    line_scatter<1>(Tl, L, d1, tile, st);
+  }
 }
 
 // K_D(i): t = A h; partials (t, s), (t, t), (s, s), (r^, s), (r^, t).
@@ -737,6 +850,7 @@ __global__ void __launch_bounds__(kWT) wide_bicg_d_kernel(WideArgs w) {
 template <int OPC, int D>
 __global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
   WIDE_SMEM;
+  WIDE_TILE;
   if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const GridDev& g = *gp;
   WideTask* T = w.st + blockIdx.y;
@@ -747,10 +861,16 @@ __global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
   double* Z = sv + SV_S * ss;
   SLane L;
   wide_lane<D>(g, L);
+  const WaveTile Tl = wave_tile(w, g, L);
   // (the r loads go out before the sums' loads)
   double rv[kSK], zv[kSK];
+  {
+    const double* const v1[1] = {R};
+    double o[1][kSK];
+    line_gather<1>(Tl, L, v1, tile, o);
 #pragma unroll
-  for (int k = 0; k < kSK; ++k) rv[k] = (k < L.nval) ? ldo(R, lane_pt(L, k)) : 0.0;
+    for (int k = 0; k < kSK; ++k) rv[k] = o[0][k];
+  }
   {
     const int slot[3] = {WS_RR0, WS_BB, WS_RR};
     const int nb[3] = {wide_point_blocks(g), wide_point_blocks(g),
@@ -765,14 +885,15 @@ __global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
       return;
     }
   }
-  wide_pre(sv, ss, L, rv, zv);
+  wide_pre(sv, ss, Tl, L, tile, rv, zv);
   double v[1] = {0.0};
 #pragma unroll
-  for (int k = 0; k < kSK; ++k)
-    if (k < L.nval) {
-      sto(Z, lane_pt(L, k), zv[k]);
-      v[0] += rv[k] * zv[k];
-    }
+  for (int k = 0; k < kSK; ++k) v[0] += rv[k] * zv[k];
+  {
+    double* const d1[1] = {Z};
+    const double(&st)[1][kSK] = reinterpret_cast<const double(&)[1][kSK]>(zv);
+    line_scatter<1>(Tl, L, d1, tile, st);
+  }
   wide_put<kWLT, 1>(w, sm, WS_RZ + (w.i & 1), v);
 }
 
@@ -977,5 +1098,6 @@ __global__ void __launch_bounds__(64) wide_poll_kernel(WideArgs w) {
 }
 
 #undef WIDE_SMEM
+#undef WIDE_TILE
 
 }  // namespace ctm

@@ -316,7 +316,7 @@ class Plan:
 
     def set_wide(self, max_tasks: int):
         """Streaming-solver launches of at most max_tasks tasks run on the wide
-        (many work-groups per task) solver; 0 disables it (default 64)."""
+        (many work-groups per task) solver; 0 disables it (default: every launch)."""
         _check(_lib.ctm_plan_set_wide(self._h, max_tasks))
 
     def autotune(self, trial_iterations: int = 0, repeats: int = 2) -> dict:

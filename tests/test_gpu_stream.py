@@ -179,3 +179,22 @@ def test_streaming_three_dimensional(kw):
         assert st["status_flags"] == 0
         assert any(s["K"] == 0 for s in st["shapes"])
         assert rel_l2(u, ref) <= 1e-11, wide
+
+
+@pytest.mark.parametrize("krylov", ["cg", "bicgstab"])
+def test_streaming_wide_many_tasks(krylov):
+    # 128 intervals x 2 streaming grids: relaxation launches of 256 tasks,
+    # where the wide solver stages the lines of the grid whose stiff axis is
+    # its fastest axis through LDS; against the oracle and the one-work-group
+    # kernel
+    p = _heat2d_big(nsteps=256, cf=2, krylov=krylov)
+    ref = solve.packed(solve.component_states(p))
+    out = {}
+    for wide in (0, ALL):
+        _say(f"streaming many tasks wide={wide} {krylov}")
+        plan = ctm.Plan(p)
+        plan.set_wide(wide)
+        out[wide] = plan.solve().cpu().numpy()
+        assert plan.stats()["status_flags"] == 0
+        assert rel_l2(out[wide], ref) <= 1e-11, wide
+    assert rel_l2(out[ALL], out[0]) <= 1e-11
