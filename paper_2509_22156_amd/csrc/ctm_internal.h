@@ -165,6 +165,7 @@ enum {
 struct WideTask {
   GridDev g;      // the task's grid (copied by the chain's first kernel)
   int q;          // the task's interval
+  int fsrc;       // the task of the launch whose scratch holds this grid's line factors
   int done;       // the step's Krylov solve has stopped
   int it;         // its iteration count
   int pend;       // BiCGStab: breakdown found in the direction update

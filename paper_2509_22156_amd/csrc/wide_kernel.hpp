@@ -86,6 +86,10 @@ __device__ __forceinline__ bool wide_begin(const WideArgs& w, WideSmem& sm, doub
 __device__ __forceinline__ double* wide_sv(const WideArgs& w) {
   return w.scratch + (long long)blockIdx.y * SV_N * w.ss;
 }
+// Scratch of the task holding this task's line factors.
+__device__ __forceinline__ const double* wide_fsv(const WideArgs& w) {
+  return w.scratch + (long long)w.st[blockIdx.y].fsrc * SV_N * w.ss;
+}
 __device__ __forceinline__ double* wide_part(const WideArgs& w, int slot) {
   return w.part + ((size_t)blockIdx.y * WS_N + slot) * w.maxblk;
 }
@@ -364,11 +368,11 @@ __device__ __forceinline__ void line_scatter(const WaveTile& T, const SLane& L,
 // z = M^-1 r on the chunk of lane L in registers (r and z hold the chunk's
 // kSK unknowns; entries past nval are ignored / returned 0). The five factor
 // vectors are gathered in one pass.
-__device__ __forceinline__ void wide_pre(const double* sv, long long ss, const WaveTile& T,
+__device__ __forceinline__ void wide_pre(const double* fsv, long long ss, const WaveTile& T,
                                          const SLane& L, double* tile, const double (&r)[kSK],
                                          double (&z)[kSK]) {
-  const double* const fv[5] = {sv + SV_FM * ss, sv + SV_FID * ss, sv + SV_FCU * ss,
-                               sv + SV_FPHI * ss, sv + SV_FPSI * ss};
+  const double* const fv[5] = {fsv + SV_FM * ss, fsv + SV_FID * ss, fsv + SV_FCU * ss,
+                               fsv + SV_FPHI * ss, fsv + SV_FPSI * ss};
   double f[5][kSK];
   line_gather<5>(T, L, fv, tile, f);
   const double* fm = f[0];
@@ -455,13 +459,31 @@ __global__ void __launch_bounds__(kWLT) wide_setup_kernel(WideArgs w) {
   const int2 task = a.tasks[blockIdx.y];
   const GridDev& g = a.grids[task.x];
   WideTask* T = w.st + blockIdx.y;
+  // the factors depend on the grid and the step only: the first task of the
+  // launch on this grid computes them, the others read that task's copy
+  // (one wave: the lanes scan the earlier tasks, a shuffle tree takes the
+  // minimum)
+  int fsrc = (int)blockIdx.y;
+  for (int t = (int)threadIdx.x; t < (int)blockIdx.y; t += 64)
+    if (a.tasks[t].x == task.x) {
+      fsrc = t;
+      break;
+    }
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) {
+    const int o = __shfl_xor(fsrc, sh, 64);
+    fsrc = o < fsrc ? o : fsrc;
+  }
   if (blockIdx.x == 0) {
     const int* src = reinterpret_cast<const int*>(&g);
     int* dst = reinterpret_cast<int*>(&T->g);
     for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += kWLT) dst[t] = src[t];
-    if (threadIdx.x == 0) T->q = task.y;
+    if (threadIdx.x == 0) {
+      T->q = task.y;
+      T->fsrc = fsrc;
+    }
   }
-  if ((int)blockIdx.x >= wide_line_blocks(g)) return;
+  if ((int)blockIdx.x >= wide_line_blocks(g) || fsrc != (int)blockIdx.y) return;
   if constexpr (OPC == OPC_SEP || OPC == OPC_VAR) {
     load_tables<OPC, double, kWLT>(g, a.tab64, a.dt, tl_lds);
     tl = tl_lds;
@@ -703,7 +725,7 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
       line_scatter<1>(Tl, L, d1, tile, st);
     }
   }
-  wide_pre(sv, ss, Tl, L, tile, pr, hz);
+  wide_pre(wide_fsv(w), ss, Tl, L, tile, pr, hz);
   {
     double* const d1[1] = {H};
     const double(&st)[1][kSK] = reinterpret_cast<const double(&)[1][kSK]>(hz);
@@ -800,7 +822,7 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
     double* const d2[2] = {X, S};
     line_scatter<2>(Tl, L, d2, tile, st);
   }
-  wide_pre(sv, ss, Tl, L, tile, sr, hz);
+  wide_pre(wide_fsv(w), ss, Tl, L, tile, sr, hz);
   {
     double* const d1[1] = {H};
     const double(&st)[1][kSK] = reinterpret_cast<const double(&)[1][kSK]>(hz);
@@ -885,7 +907,7 @@ __global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
       return;
     }
   }
-  wide_pre(sv, ss, Tl, L, tile, rv, zv);
+  wide_pre(wide_fsv(w), ss, Tl, L, tile, rv, zv);
   double v[1] = {0.0};
 #pragma unroll
   for (int k = 0; k < kSK; ++k) v[0] += rv[k] * zv[k];
