@@ -198,3 +198,24 @@ def test_streaming_wide_many_tasks(krylov):
         assert plan.stats()["status_flags"] == 0
         assert rel_l2(out[wide], ref) <= 1e-11, wide
     assert rel_l2(out[ALL], out[0]) <= 1e-11
+
+
+@pytest.mark.parametrize("tight", [False, True])
+def test_streaming_paper_size_oscillator(tight):
+    # the benchmark's streaming workload at full size (Section 4.4, L = 14,
+    # L0 = 6: 7 grids, 177,415 unknowns per level, 256 steps, every grid on
+    # the wide solver): with the measurement tolerances (MGRIT 1e-9 on the
+    # C-point residual, the final state's error then ~1e-8) and with tight
+    # ones, against the oracle
+    p = make("fp_osc2d", n=14, L0=6, prec="fp64")
+    if tight:
+        p.update(krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100, krylov_maxit=20000)
+    else:
+        p.update(krylov_tol=1e-10, mgrit_tol=1e-9, mgrit_maxit=64, krylov_maxit=20000,
+                 coarse_tol=1e-3)
+    _say(f"paper-size oscillator tight={tight}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(u, ref) <= (1e-10 if tight else 5e-8)
