@@ -1,7 +1,8 @@
 """GPU parity of the streaming path: component grids beyond the on-chip
 solver (lines longer than 512 unknowns, or more than 8,192 unknowns) are
-solved by the streaming kernel with their Krylov vectors in HBM, alongside
-the on-chip grids of the same plan."""
+solved with their Krylov vectors in HBM - by the wide solver (many
+work-groups per system, the default) or by the one-work-group-per-system
+streaming kernel - alongside the on-chip grids of the same plan."""
 import sys
 
 import numpy as np
