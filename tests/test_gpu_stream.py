@@ -41,6 +41,14 @@ def test_streaming_classes_present():
     assert any(s["K"] == 0 for s in shapes) and any(s["K"] > 0 for s in shapes), shapes
 
 
+def test_set_wide_rejects_a_negative_count():
+    plan = ctm.Plan(_heat2d_big())
+    with pytest.raises(ctm.CtmError):
+        plan.set_wide(-1)
+    plan.set_wide(0)
+    plan.set_wide(1 << 30)  # capped
+
+
 def test_streaming_grids_keep_their_shape():
     plan = ctm.Plan(_heat2d_big())
     stream = [g for g in range(plan.G) if plan.grid_shape(g) == (16, 0)]
