@@ -90,11 +90,14 @@ __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, d
 #pragma unroll
       for (int k = 0; k < D; ++k)
         if (k < d) w += tl[i * d + k] * (g.lo[k] + (double)(c.j[k] + g.j0) * g.h[k]);
+      // (reciprocals instead of divisions: the streaming kernels' stencil
+      // sweeps are VALU-bound on this operator; 1/h is uniform per grid)
       const double h = g.h[i], half = tl[i * d + i] * 0.5 * h, H = tl[d * d + i];
+      const double ih = 1.0 / h, ih2 = g.ih2[i];
       const double wu = w + half, wd = w - half;
-      diag += dt * ((fmax(wu, 0.0) - fmin(wd, 0.0)) / h + H / (h * h));
-      up = dt * (fmin(wu, 0.0) / h - 0.5 * H / (h * h));
-      lo = dt * (-fmax(wd, 0.0) / h - 0.5 * H / (h * h));
+      diag += dt * ((fmax(wu, 0.0) - fmin(wd, 0.0)) * ih + H * ih2);
+      up = dt * (fmin(wu, 0.0) * ih - 0.5 * H * ih2);
+      lo = dt * (-fmax(wd, 0.0) * ih - 0.5 * H * ih2);
     }
     c.lo[i] = (j > 0) ? lo : 0.0;
     c.up[i] = (j < n - 1) ? up : 0.0;

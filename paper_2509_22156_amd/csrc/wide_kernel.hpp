@@ -263,7 +263,7 @@ __device__ __forceinline__ void sto(double* base, unsigned i, double v) {
 // latency-bound, and the extra LDS round trip did not pay there).
 constexpr int kTileMax = 64 * kSK;                   // unknowns of a wave's lines
 constexpr int kTilePad = kTileMax + kTileMax / kSK;  // with one pad per chunk
-constexpr int kTileVecs = 5;                         // vectors staged at once
+constexpr int kTileVecs = 2;                         // tile slots (vectors per LDS pass)
 __device__ __forceinline__ int tpad(int e) { return e + e / kSK; }
 
 struct WaveTile {
@@ -290,7 +290,6 @@ template <int NV>
 __device__ __forceinline__ void line_gather(const WaveTile& T, const SLane& L,
                                             const double* const (&v)[NV], double* tile,
                                             double (&out)[NV][kSK]) {
-  static_assert(NV <= kTileVecs, "tile slots");
   if (!T.on) {
 #pragma unroll
     for (int k = 0; k < kSK; ++k) {
@@ -303,6 +302,9 @@ __device__ __forceinline__ void line_gather(const WaveTile& T, const SLane& L,
   }
   double* tw = tile + (threadIdx.x >> 6) * (kTileVecs * kTilePad);
   const int lane = threadIdx.x & 63;
+  // every global load first (one round trip), then the vectors pass
+  // through the tile kTileVecs at a time (a small tile keeps more
+  // work-groups resident per CU)
   double tmp[NV][kSK];
 #pragma unroll
   for (int m = 0; m < kSK; ++m) {
@@ -312,21 +314,26 @@ __device__ __forceinline__ void line_gather(const WaveTile& T, const SLane& L,
     for (int s = 0; s < NV; ++s) tmp[s][m] = ok ? ldo(v[s], T.t0 + (unsigned)e) : 0.0;
   }
 #pragma unroll
-  for (int m = 0; m < kSK; ++m) {
-    const int e = m * 64 + lane;
-    if (e < T.n) {
+  for (int s0 = 0; s0 < NV; s0 += kTileVecs) {
 #pragma unroll
-      for (int s = 0; s < NV; ++s) tw[s * kTilePad + tpad(e)] = tmp[s][m];
+    for (int m = 0; m < kSK; ++m) {
+      const int e = m * 64 + lane;
+      if (e < T.n) {
+#pragma unroll
+        for (int s = s0; s < NV && s < s0 + kTileVecs; ++s)
+          tw[(s - s0) * kTilePad + tpad(e)] = tmp[s][m];
+      }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kSK; ++k) {
-    const bool ok = k < L.nval;
+    for (int k = 0; k < kSK; ++k) {
+      const bool ok = k < L.nval;
 #pragma unroll
-    for (int s = 0; s < NV; ++s) out[s][k] = ok ? tw[s * kTilePad + tpad(T.e0 + k)] : 0.0;
+      for (int s = s0; s < NV && s < s0 + kTileVecs; ++s)
+        out[s][k] = ok ? tw[(s - s0) * kTilePad + tpad(T.e0 + k)] : 0.0;
+    }
+    __syncthreads();  // the tile is reused by the next pass, gather or scatter
   }
-  __syncthreads();  // the tile is reused by the next gather or scatter
 }
 
 // vector s at unknown k of the lane's chunk = in[s][k] (k < nval).
@@ -334,7 +341,6 @@ template <int NV>
 __device__ __forceinline__ void line_scatter(const WaveTile& T, const SLane& L,
                                              double* const (&v)[NV], double* tile,
                                              const double (&in)[NV][kSK]) {
-  static_assert(NV <= kTileVecs, "tile slots");
   if (!T.on) {
 #pragma unroll
     for (int k = 0; k < kSK; ++k)
@@ -348,21 +354,26 @@ __device__ __forceinline__ void line_scatter(const WaveTile& T, const SLane& L,
   double* tw = tile + (threadIdx.x >> 6) * (kTileVecs * kTilePad);
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < kSK; ++k)
-    if (k < L.nval) {
+  for (int s0 = 0; s0 < NV; s0 += kTileVecs) {
 #pragma unroll
-      for (int s = 0; s < NV; ++s) tw[s * kTilePad + tpad(T.e0 + k)] = in[s][k];
+    for (int k = 0; k < kSK; ++k)
+      if (k < L.nval) {
+#pragma unroll
+        for (int s = s0; s < NV && s < s0 + kTileVecs; ++s)
+          tw[(s - s0) * kTilePad + tpad(T.e0 + k)] = in[s][k];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kSK; ++m) {
+      const int e = m * 64 + lane;
+      if (e < T.n) {
+#pragma unroll
+        for (int s = s0; s < NV && s < s0 + kTileVecs; ++s)
+          sto(v[s], T.t0 + (unsigned)e, tw[(s - s0) * kTilePad + tpad(e)]);
+      }
     }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < kSK; ++m) {
-    const int e = m * 64 + lane;
-    if (e < T.n) {
-#pragma unroll
-      for (int s = 0; s < NV; ++s) sto(v[s], T.t0 + (unsigned)e, tw[s * kTilePad + tpad(e)]);
-    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // z = M^-1 r on the chunk of lane L in registers (r and z hold the chunk's
