@@ -296,7 +296,7 @@ ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lan
  * convergence test (the stream's earlier work included), so ctm_solve and
  * ctm_propagate return only when that part is done. max_tasks >= 0 (capped
  * at 65,535, the default: every streaming launch); 0 disables the wide
- * solver. Plans whose coefficient tables need more than 18 KiB of LDS keep
+ * solver. Plans whose coefficient tables need more than 44 KiB of LDS keep
  * the one-work-group kernel. */
 ctm_status ctm_plan_set_wide(ctm_plan* plan, int max_tasks);
 

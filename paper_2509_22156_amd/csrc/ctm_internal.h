@@ -146,7 +146,7 @@ constexpr int kWLW = 1;            // waves per line work-group
 constexpr int kWideSK = 16;        // unknowns per lane along a line (as the streaming kernel)
 // static LDS of a line kernel of the wide solver (line tiles and sums); the
 // coefficient tables (dynamic LDS) must fit beside it in 64 KiB
-constexpr int kWideStaticLds = 46 * 1024;
+constexpr int kWideStaticLds = 20 * 1024;
 
 // Sums of a task; each has a partial per producing work-group.
 enum {
