@@ -228,3 +228,21 @@ def test_streaming_paper_size_oscillator(tight):
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
     assert rel_l2(u, ref) <= (1e-10 if tight else 5e-8)
+
+
+@pytest.mark.parametrize("name,kw", [("varcoef6d", dict(d=2, n=10, nsteps=256, t1=0.01, cf=2)),
+                                     ("cme5d", dict(d=2, n=10, hi=[1024.0] * 2, nsteps=256,
+                                                    t1=0.1, cf=2))])
+def test_streaming_many_tasks_with_tables(name, kw):
+    # relaxation launches of more than 64 tasks (staged line sweeps) for the
+    # operators whose coefficient tables the kernels keep in LDS beside the
+    # line tile
+    p = make(name, **kw)
+    p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100)
+    _say(f"streaming many tasks {name}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    assert any(s["K"] == 0 for s in plan.stats()["shapes"])
+    ref = solve.packed(solve.component_states(p))
+    assert rel_l2(u, ref) <= 1e-11
