@@ -1,12 +1,15 @@
-// The wide streaming solver: the implicit steps of a few large systems
-// (streaming grids, vectors in HBM) spread over many work-groups each, for
-// launches whose task count would leave most of the chip idle under the
+// The wide streaming solver: the implicit steps of large systems (streaming
+// grids, vectors in HBM), every system spread over many work-groups. Built
+// for launches whose task count would leave most of the chip idle under the
 // one-work-group-per-task streaming kernel (the sequential coarse chain of
-// MGRIT, one task per grid; time-sequential stepping). Every Krylov phase
-// is one launch over all work-groups of all tasks of the range (grid
-// dimension y = task), and the kernel boundaries are the only grid-wide
-// synchronisation: nothing ever waits on another work-group, and no kernel
-// needs a device-wide fence.
+// MGRIT, one task per grid; time-sequential stepping), and with its line
+// sweeps staged through LDS also the faster choice for the relaxation
+// launches of hundreds of tasks. Every Krylov phase is one launch over all
+// work-groups of all tasks of the range (grid dimension y = task), and the
+// kernel boundaries are the only grid-wide synchronisation: nothing ever
+// waits on another work-group, and no kernel needs a device-wide fence. The
+// line factors are computed once per grid and launch and shared by the
+// grid's tasks.
 //
 // The arithmetic is the streaming kernel's: FP64, the same (2d+1)-point
 // operator evaluated per point, the same exact line-block preconditioner
