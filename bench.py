@@ -469,6 +469,27 @@ def _comparators(args, ctm, torch, oracle_u, dof_steps):
 STREAM_BYTES_PER_ITERATION = {"cg": 152, "bicgstab": 296}
 
 
+def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (GB/s, read + write bytes) of a
+    plain 1 GiB copy: the practical HBM ceiling the streaming solvers'
+    algorithmic rate is also quoted against."""
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * n * 8 / sec / 1e9
+
+
 def _streaming(ctm, torch):
     """The streaming solvers on grids beyond the on-chip solver: the 2-D
     oscillator of Section 4.4 at the paper's own levels (L = 14, L0 = 6:
@@ -508,6 +529,10 @@ def _streaming(ctm, torch):
             "krylov_work": c["work"], "launches": c["launches"]}
     if not roof:
         return None
+    copy_gbps = copy_bandwidth(torch)
+    for r in roof.values():
+        r["copy_GBps"] = copy_gbps
+        r["frac_of_copy"] = r["achieved"] / copy_gbps if r["achieved"] else None
     return {
         "workload": f"fp_osc2d at L = 14, L0 = 6: {plan.G} grids, {plan.slen} DoF per level, "
                     f"{p['nsteps']} steps, 2-level MGRIT c = 2, BiCGStab, FP64, Krylov 1e-10, "
