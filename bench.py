@@ -294,6 +294,7 @@ def main(argv=None):
         "phase_ms_per_step": agg["chain_ms"] / args.steps,
         "algorithmic_hbm_GBps": agg["chain_bytes"] / chain_s / 1e9 if chain_s > 0 else None,
         "hbm_frac": (agg["chain_bytes"] / chain_s / 1e9 / PEAK_HBM_GBPS) if chain_s > 0 else None,
+        "copy_GBps": copy_bandwidth(torch),  # measured after the timed steps
     }
     u_mixed = u.cpu().numpy()
     vals_mixed = vals.cpu().numpy()
