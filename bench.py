@@ -4,10 +4,19 @@ MI355X.
 A step is one pass of the whole hot path over the workload: sampling of the
 initial value on every component grid, MGRIT over the time interval on all
 grids (FP32 Krylov inside FP64-refined implicit steps), and the FP64
-combination gather at 1e5 seeded points. The workload is the 3-D heat
-equation at sparse-grid level 9 (109 component grids, 73,915 unknowns per
-time level, 256 backward-Euler steps on [0, 0.05], two-level MGRIT with
-c = 8).
+combination gather at 1e5 seeded points. The default workload is the
+largest one that fits one GPU: the 6-D variable-coefficient heat equation
+u_t = div(a grad u), a = 1 + 0.5 prod sin(2 pi x_i), at sparse-grid level 8
+(1,709 component grids, 849,161 unknowns per time level), 1,024
+backward-Euler steps on [0, 0.1], three-level MGRIT with c = 8 and FCF
+relaxation, CG.
+
+Beside the timed path the line carries: the FP64 MGRIT path and batched
+time-sequential stepping (both precisions) on the same workload, the plain
+per-grid FP64 schedule (timed on a bounded number of steps and scaled), the
+error of every path against the CPU oracle over all component grids, the
+oracle itself timed on the host (one core on a grid sample; all allotted
+cores on the whole workload), and the roofline of the dominant kernel.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -29,10 +38,48 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 GATHER_POINTS = 100_000
+METRIC = "DoF*timesteps/s + HBM GB/s, mixed vs FP64 GPU path at 1e-8 rel. L2 error"
+# algorithmic HBM bytes of one implicit step per unknown: read the previous
+# state, write the new one (FP64); every Krylov vector stays on chip
+STEP_BYTES_PER_DOF = 16
+# algorithmic HBM bytes per unknown of one streaming Krylov iteration with
+# the vectors in HBM (FP64): CG fused apply+dot, fused update+dot, direction
+# update = 40 B in FP32, doubled; BiCGStab twice that
+STREAM_ALG_BYTES = {"cg": 80, "bicgstab": 160}
+# what the streaming solvers as built move per unknown and iteration: every
+# Krylov sweep once, plus r, z and the five line-factor vectors of each
+# preconditioner application
+STREAM_IMPL_BYTES = {"cg": 152, "bicgstab": 296}
+# one-core oracle sample: every SAMPLE_STRIDE-th grid in canonical order
+# (all layers of the index set), about 15 s of host work at the 6-D size
+SAMPLE_STRIDE = 8
+PLAIN_STEPS = 16  # steps of the plain per-grid schedule that are timed
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+OP_TEXT = {
+    "heat": "heat equation u_t = Laplace(u)",
+    "varcoef": "variable-coefficient heat equation u_t = div(a grad u), "
+               "a = 1 + {amp} prod sin(2 pi x_i)",
+    "ou": "Fokker-Planck equation of an Ornstein-Uhlenbeck process",
+    "cme": "master equation of independent immigration-death species",
+    "drift": "Fokker-Planck equation with a full drift matrix",
+}
+
+
+def describe(name: str, p: dict, G: int, slen: int) -> str:
+    op = OP_TEXT[p["op"]].format(amp=p.get("amp", 0.0))
+    lv = p["mgrit_levels"]
+    mg = (f"{lv}-level MGRIT c={p['cf']} {p.get('relax', 'FCF')}" if lv > 1
+          else "time-sequential stepping")
+    prec = "mixed FP32/FP64" if p["prec"] == "mixed" else "FP64"
+    return (f"{name}: {op}, d={p['d']}, sparse-grid level {p['n']} (L0={p.get('L0', 1)}), "
+            f"{G} component grids, {slen} DoF per time level, {p['nsteps']} backward-Euler "
+            f"steps on [{p['t0']},{p['t1']}], {mg}, {p['krylov'].upper()}, {prec}, gather at "
+            f"{GATHER_POINTS} points")
 
 
 def workload_problem(name: str, prec: str):
@@ -41,7 +88,7 @@ def workload_problem(name: str, prec: str):
     err_vs_oracle)."""
     from workloads import make, metric_settings
     p = make(name, prec=prec)
-    p.update(metric_settings(prec))
+    p.update(metric_settings(prec, name))
     return p
 
 
@@ -53,16 +100,18 @@ def flops_per_iteration(d: int, krylov: str) -> int:
     return 2 * (2 * d + 1) + 10
 
 
-def measured_traffic(cls_key: str):
+def measured_traffic(workload: str, cls_key: str):
     """Calibrated HBM bytes per launch of a chain-kernel size class from the
-    committed hardware-counter runs, or None once the kernel sources differ
-    from the ones the counters were taken on."""
+    committed hardware-counter runs of this workload, or None once the
+    kernel sources differ from the ones the counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "chain_kernel_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
+    if rec.get("workload") != workload:
+        return None
     h = hashlib.sha256()
     for src in rec["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
@@ -72,14 +121,14 @@ def measured_traffic(cls_key: str):
     return rec["classes"][cls_key]["bytes_per_launch"]
 
 
-def cpu_oracle(prob, pts):
-    """The oracle as it stands on this host: time-sequential backward Euler
-    with sparse LU on every grid, then the combination at the points."""
-    from oracle import combine, solve
-    t0 = time.perf_counter()
-    states = solve.component_states(prob)
-    vals = combine.combine_at(prob, solve.grid_list(prob), states, pts)
-    return time.perf_counter() - t0, solve.packed(states), vals
+def host_workers() -> int:
+    """Host processes for the parallel oracle: the CPUs this process may run
+    on, at most 16 (the share of the host that one GPU of the box gets)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def _oracle_grids(prob, sel):
@@ -97,11 +146,24 @@ def _oracle_warm(_):
     return os.getpid()
 
 
+def cpu_oracle_sample(prob, stride):
+    """The oracle as it stands on one host core: time-sequential backward
+    Euler with sparse LU on every stride-th component grid. Returns the
+    seconds and the unknowns of the sample."""
+    from oracle import solve
+    gl = solve.grid_list(prob)
+    sizes = np.diff(solve.offsets(prob))
+    sel = list(range(0, len(gl), stride))
+    t0 = time.perf_counter()
+    solve.component_states(prob, sel)
+    return time.perf_counter() - t0, int(sizes[sel].sum()), len(sel)
+
+
 def cpu_oracle_parallel(prob, pts, workers):
-    """The same oracle spread over `workers` host processes: the grids
-    (longest-first by unknowns), then the points of the combination. Started
-    before the process touches the GPU; the worker start-up is outside the
-    clock."""
+    """The whole oracle (every grid, then the combination at the points)
+    spread over `workers` host processes: the grids longest-first by
+    unknowns, then the points. Started before the process touches the GPU;
+    the worker start-up is outside the clock."""
     import concurrent.futures as cf
     import multiprocessing as mp
     from oracle import solve
@@ -125,7 +187,7 @@ def cpu_oracle_parallel(prob, pts, workers):
         vals = np.concatenate(list(ex.map(_oracle_combine, [prob] * workers,
                                           [states] * workers, chunks)))
         t = time.perf_counter() - t0
-    return t, max(len(bins), workers), solve.packed(states), vals
+    return t, workers, solve.packed(states), vals
 
 
 # (d, n) cases of the manufactured heat family: two sparse-grid levels per d
@@ -138,7 +200,6 @@ def mms_sweep(ctm, torch):
     MGRIT tolerance 1e-8, mixed precision. Reports the MGRIT iterations (the
     paper observes them independent of d, L and the grid), the solve time
     and the error of the combination against u*(., T) at seeded points."""
-    import numpy as np
     from workloads import make
     for d, n in MMS_CASES:
         p = make("heat_mms", d=d, n=n, nsteps=64, t1=1.0)
@@ -165,12 +226,277 @@ def mms_sweep(ctm, torch):
     return 0
 
 
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _per_grid_max_rel(prob, a, b):
+    """Largest relative L2 error of one component grid."""
+    from oracle import solve
+    off = solve.offsets(prob)
+    worst = 0.0
+    for g in range(len(off) - 1):
+        x, y = a[off[g]:off[g + 1]], b[off[g]:off[g + 1]]
+        worst = max(worst, float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)))
+    return worst
+
+
+def _errors(prob, u, oracle_u):
+    if oracle_u is None:
+        return {}
+    return {"state_rel_l2_vs_oracle": _rel(u, oracle_u),
+            "max_grid_rel_l2_vs_oracle": _per_grid_max_rel(prob, u, oracle_u)}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _shapes(args, plan):
+    """Launch shapes of the timed plan, outside the timed region: autotuned
+    (ctm_autotune), taken from a file, or the defaults."""
+    if args.load_shapes:
+        with open(args.load_shapes) as f:
+            rec = json.load(f)
+        assert rec["workload"] == args.workload and len(rec["shapes"]) == plan.G
+        for g, (w, k) in enumerate(rec["shapes"]):
+            if k:
+                plan.set_grid_shape(g, w, k)
+        return {"source": args.load_shapes}
+    tune = None
+    if args.tune:
+        tune = plan.autotune(trial_iterations=2, repeats=1)
+        log(f"autotune: {tune}")
+    if args.save_shapes:
+        with open(args.save_shapes, "w") as f:
+            json.dump({"workload": args.workload,
+                       "shapes": [plan.grid_shape(g) for g in range(plan.G)]}, f)
+    return tune
+
+
+def _timed(torch, fn, reps=1):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def _comparators(args, ctm, torch, oracle_u, dof_steps):
+    """FP64 MGRIT at the measurement's tolerances, batched
+    time-sequential stepping (mixed and FP64), and the plain per-grid FP64
+    schedule on the same workload, outside the timed region, each with its
+    error against the oracle. The plain schedule launches one kernel per
+    grid and step; it is timed on PLAIN_STEPS steps and scaled to N."""
+    out = {}
+    runs = [
+        ("fp64_mgrit", workload_problem(args.workload, "fp64"), "solve"),
+        ("mixed_sequential_batched", dict(workload_problem(args.workload, "mixed"),
+                                          mgrit_levels=1), "solve"),
+        ("fp64_sequential_batched", dict(workload_problem(args.workload, "fp64"),
+                                         mgrit_levels=1), "solve"),
+        ("fp64_per_grid_plain", workload_problem(args.workload, "fp64"), "per_grid"),
+    ]
+    for name, prob, kind in runs:
+        plan = ctm.Plan(prob)
+        entry = {"tolerances": {k: prob.get(k) for k in ("krylov_tol", "mgrit_tol", "coarse_tol",
+                                                          "refine_tol", "inner_tol")}}
+        if kind == "solve":
+            sec, u = _timed(torch, lambda: plan.solve(), reps=2)
+            st = plan.stats()
+            entry.update(seconds=sec, value=dof_steps / sec,
+                         mgrit_iterations=st["mgrit_iterations"],
+                         krylov_iterations=st["krylov_iterations"],
+                         phi_solves=st["phi_solves"])
+            entry.update(_errors(prob, u.cpu().numpy(), oracle_u))
+        else:
+            u0 = plan.initial_state()
+            n = min(PLAIN_STEPS, prob["nsteps"])
+            sec, _ = _timed(torch, lambda: plan.propagate(u0, n, per_grid=True))
+            scaled = sec * prob["nsteps"] / n
+            entry.update(seconds=scaled, value=dof_steps / scaled, timed_steps=n,
+                         timed_seconds=sec, launches=plan.G * n,
+                         note=f"one launch per grid and step; {n} of {prob['nsteps']} steps "
+                              "timed, scaled linearly")
+        out[name] = entry
+        log(f"{name}: {entry['seconds'] * 1e3:.1f} ms ({entry['value']:.3e} DoF*steps/s)")
+        del plan
+    return out
+
+
+def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (GB/s, read + write bytes) of a
+    plain 1 GiB copy: the practical HBM ceiling beside the 8 TB/s peak."""
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * n * 8 / sec / 1e9
+
+
+def _streaming(ctm, torch):
+    """The streaming solvers on grids beyond the on-chip solver: the 2-D
+    oscillator of Section 4.4 at the paper's own levels (L = 14, L0 = 6:
+    seven grids of up to 32,193 unknowns), FP64 MGRIT. Their roofline is
+    HBM. Algorithmic bytes (the streaming BiCGStab iteration: 160 B per
+    unknown in FP64) and the bytes the solver as built moves (296 B: the
+    line-factor vectors of the preconditioner besides the Krylov sweeps),
+    both over the wall time of the solve and over the wide solver's own
+    launch time (a wide launch is its whole chain, host polls included)."""
+    from workloads import make
+    p = make("fp_osc2d", n=14, L0=6, prec="fp64")
+    # the measurement tolerances of the main workload (coarse levels to 1e-3)
+    p.update(krylov_tol=1e-10, mgrit_tol=1e-9, mgrit_maxit=64, krylov_maxit=20000,
+             coarse_tol=1e-3)
+    plan = ctm.Plan(p)
+    plan.solve()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    plan.solve()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    st = plan.stats()
+    plan.set_timing(False)
+    alg = STREAM_ALG_BYTES[p["krylov"]]
+    impl = STREAM_IMPL_BYTES[p["krylov"]]
+    wide = [c for c in st["shapes"] if c["K"] == 0 and c["W"] == 4]
+    if not wide:
+        return None
+    c = wide[0]
+    copy_gbps = copy_bandwidth(torch)
+    launch_s = c["ms"] / 1e3
+    achieved = c["work"] * alg / launch_s / 1e9 if launch_s > 0 else None
+    return {
+        "workload": f"fp_osc2d at L = 14, L0 = 6: {plan.G} grids, {plan.slen} DoF per level, "
+                    f"{p['nsteps']} steps, 2-level MGRIT c = 2, BiCGStab, FP64, Krylov 1e-10, "
+                    f"coarse levels 1e-3, MGRIT 1e-9",
+        "seconds": sec,
+        "value": plan.slen * p["nsteps"] / sec,
+        "mgrit_iterations": st["mgrit_iterations"],
+        "krylov_iterations": st["krylov_iterations"],
+        "roofline": {
+            "kernel": "wide solver: many work-groups per task, one launch per Krylov phase "
+                      "for all tasks of a launch",
+            "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBPS if achieved else None,
+            "bytes_per_unknown_iteration": alg,
+            "implementation_bytes_per_unknown_iteration": impl,
+            "implementation_GBps": c["work"] * impl / launch_s / 1e9 if launch_s > 0 else None,
+            "algorithmic_GBps_over_solve_wall": c["work"] * alg / sec / 1e9,
+            "wide_launch_ms": c["ms"], "krylov_work": c["work"],
+            "copy_GBps": copy_gbps,
+            "frac_of_copy": achieved / copy_gbps if achieved else None,
+        },
+    }
+
+
+def _residual_mode(ctm, torch):
+    """The optimized oscillator run of Section 4.4 (T = 1, N = 3204, c = 12,
+    F-relaxation, tolerance 1e-4): MGRIT in space-time residual mode with two
+    Krylov iterations per step, beside the same MGRIT with every step solved
+    to 1e-10. Solve time (second of two solves) and MGRIT iterations."""
+    from workloads import make
+    out = {}
+    for tag, kw in (("residual_mode_2_iterations", dict(residual_mode=1, krylov_maxit=2)),
+                    ("exact_steps", dict(residual_mode=0, krylov_maxit=20000,
+                                         krylov_tol=1e-10))):
+        p = make("fp_osc2d", t1=1.0, nsteps=3204)
+        p.update(cf=12, relax="F", prec="fp64", mgrit_tol=1e-4, mgrit_maxit=100, **kw)
+        plan = ctm.Plan(p)
+        sec, _ = _timed(torch, lambda: plan.solve())
+        st = plan.stats()
+        out[tag] = {"seconds": sec, "mgrit_iterations": st["mgrit_iterations"],
+                    "krylov_iterations": st["krylov_iterations"]}
+    return out
+
+
+def _heat3d(ctm, torch):
+    """The 3-D heat workload (109 grids, 73,915 unknowns per level, 256 steps,
+    two-level MGRIT c = 8) at the measurement's settings: solve times of the
+    mixed and FP64 MGRIT paths and the mixed path's error against the
+    oracle."""
+    from oracle import solve
+    out = {}
+    ref = None
+    for prec in ("mixed", "fp64"):
+        p = workload_problem("heat3d", prec)
+        if ref is None:
+            ref = solve.packed(solve.component_states(p))
+        plan = ctm.Plan(p)
+        sec, u = _timed(torch, lambda: plan.solve(), reps=3)
+        st = plan.stats()
+        out[f"{prec}_mgrit"] = {"seconds": sec, "value": plan.slen * p["nsteps"] / sec,
+                                "mgrit_iterations": st["mgrit_iterations"],
+                                **_errors(p, u.cpu().numpy(), ref)}
+    return out
+
+
+def _roofline(shapes, d, krylov, prec, copy_gbps):
+    """Roofline of the dominant kernel: the size class of the implicit-step
+    kernel with the most device time. Its algorithmic HBM bytes are 16 B per
+    unknown and implicit step (read the previous state, write the new one);
+    the FP32/FP64 flops of its Krylov iterations are reported beside."""
+    (dw, dk), dom = max(shapes.items(), key=lambda kv: kv[1]["ms"])
+    dom_s = dom["ms"] / 1e3
+    nl = max(dom["launches"], 1)
+    alg_bytes = STEP_BYTES_PER_DOF * dom["dofsteps"]
+    achieved = alg_bytes / dom_s / 1e9 if dom_s > 0 else None
+    fpi = flops_per_iteration(d, krylov)
+    tflops = dom["work"] * fpi / dom_s / 1e12 if dom_s > 0 else None
+    peak_f = PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS
+    return (dw, dk), {
+        "kernel": f"chain_kernel W={dw} K={dk} (batched implicit steps of one size class: "
+                  f"{'FP32 preconditioned ' if prec == 'mixed' else 'FP64 preconditioned '}"
+                  f"{krylov.upper()} on chip{' inside FP64 refinement' if prec == 'mixed' else ''})",
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": PEAK_HBM_GBPS,
+        "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBPS if achieved else None,
+        "traffic": None,
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "avg_launch_ms": dom["ms"] / nl,
+        "launches": dom["launches"],
+        "bytes_per_dof_step": STEP_BYTES_PER_DOF,
+        "dof_steps_per_launch": dom["dofsteps"] / nl,
+        "algorithmic_bytes_per_launch": alg_bytes / nl,
+        "vector_role_bytes_per_launch": dom["bytes"] / nl,
+        "krylov_flops": {"achieved_TFLOPs": tflops, "peak_TFLOPs": peak_f,
+                         "frac": tflops / peak_f if tflops else None,
+                         "flops_per_unknown_iteration": fpi,
+                         "note": "vector peak; the on-chip Krylov iteration is bound by "
+                                 "latency (occupancy, barriers, reductions)"},
+        "copy_GBps": copy_gbps,
+        "all_classes": {f"W{w}K{k}": v for (w, k), v in sorted(shapes.items())},
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="heat3d")
+    ap.add_argument("--workload", default="varcoef6d")
     ap.add_argument("--no-extras", action="store_true", help="skip the comparator runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--mms-sweep", action="store_true",
@@ -179,12 +505,12 @@ def main(argv=None):
     ap.add_argument("--streaming-only", action="store_true",
                     help="instead of the metric: only the streaming-kernel workload (the "
                          "paper-size 2-D oscillator), one JSON line")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="keep the plan's default launch shapes (no autotuning)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch shapes before timing (ctm_autotune)")
     ap.add_argument("--save-shapes", default=None,
-                    help="write the tuned launch shape of every grid to this JSON file")
+                    help="write the launch shape of every grid to this JSON file")
     ap.add_argument("--load-shapes", default=None,
-                    help="take the launch shapes from this JSON file instead of tuning")
+                    help="take the launch shapes from this JSON file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 256 MiB device copy (hardware-counter calibration)")
     args = ap.parse_args(argv)
@@ -203,22 +529,20 @@ def main(argv=None):
         if not args.no_cpu:
             # the parallel oracle runs first: its worker processes start
             # before this process loads the HIP library or touches the GPU
-            workers = max(1, min(16, os.cpu_count() or 1))
-            log(f"cpu baseline: oracle over {workers} host processes")
+            workers = host_workers()
+            log(f"cpu baseline: the whole oracle over {workers} host processes")
             par = cpu_oracle_parallel(prob, targets(prob, GATHER_POINTS, seed=0), workers)
             log(f"parallel oracle {par[0]:.2f} s on {par[1]} processes")
 
     import torch
     from paper_2509_22156_amd import ctm
 
+    torch.cuda.set_device(0)
     if args.mms_sweep:
-        torch.cuda.set_device(0)
         return mms_sweep(ctm, torch)
     if args.streaming_only:
-        torch.cuda.set_device(0)
         print(json.dumps(_streaming(ctm, torch)), flush=True)
         return 0
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     plan = ctm.Plan(prob)
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -254,11 +578,9 @@ def main(argv=None):
             agg[k] += st[k]
         for sh in st["shapes"]:
             key = (sh["W"], sh["K"])
-            acc = shapes.setdefault(key, dict(ms=0.0, launches=0, work=0, bytes=0.0))
-            acc["ms"] += sh["ms"]
-            acc["launches"] += sh["launches"]
-            acc["work"] += sh["work"]
-            acc["bytes"] += sh["bytes"]
+            acc = shapes.setdefault(key, dict(ms=0.0, launches=0, work=0, bytes=0.0, dofsteps=0))
+            for k in acc:
+                acc[k] += sh[k]
         log(f"step {i + 1}/{args.steps}: mgrit it={st['mgrit_iterations']} "
             f"res={st['mgrit_residual'][-1]:.2e}")
     torch.cuda.synchronize()
@@ -266,44 +588,16 @@ def main(argv=None):
     plan.set_timing(False)
     ms_per_step = elapsed * 1e3 / args.steps
     value = dof_steps / (elapsed / args.steps)
-
-    d = prob["d"]
-    fpi = flops_per_iteration(d, prob["krylov"])
-    chain_s = agg["chain_ms"] / 1e3
-    # dominant kernel: the size class of the implicit-step kernel with the
-    # most device time; its algorithmic FP32 flops over its own timed launches
-    (dw, dk), dom = max(shapes.items(), key=lambda kv: kv[1]["ms"])
-    dom_s = dom["ms"] / 1e3
-    achieved_tflops = dom["work"] * fpi / dom_s / 1e12 if dom_s > 0 else None
-    launches = max(agg["chain_launches"], 1)
-    roofline = {
-        "kernel": f"chain_kernel<heat, CG, mixed, W={dw}, K={dk}> (batched implicit steps, "
-                  "FP32 preconditioned CG inside FP64 refinement)",
-        "bound": "alu",
-        "achieved": achieved_tflops,
-        "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": (achieved_tflops / PEAK_FP32_TFLOPS) if achieved_tflops else None,
-        "traffic": measured_traffic(f"W{dw}K{dk}"),
-        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "avg_launch_ms": dom["ms"] / max(dom["launches"], 1),
-        "launches": dom["launches"],
-        "algorithmic_flops_per_launch": dom["work"] * fpi / max(dom["launches"], 1),
-        "algorithmic_bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
-        "all_classes": {f"W{w}K{k}": v for (w, k), v in sorted(shapes.items())},
-        "phase_ms_per_step": agg["chain_ms"] / args.steps,
-        "algorithmic_hbm_GBps": agg["chain_bytes"] / chain_s / 1e9 if chain_s > 0 else None,
-        "hbm_frac": (agg["chain_bytes"] / chain_s / 1e9 / PEAK_HBM_GBPS) if chain_s > 0 else None,
-        "copy_GBps": copy_bandwidth(torch),  # measured after the timed steps
-    }
+    copy_gbps = copy_bandwidth(torch)  # measured after the timed steps
+    (dw, dk), roofline = _roofline(shapes, prob["d"], prob["krylov"], prob["prec"], copy_gbps)
+    roofline["traffic"] = measured_traffic(args.workload, f"W{dw}K{dk}")
     u_mixed = u.cpu().numpy()
     vals_mixed = vals.cpu().numpy()
-    it_per_step = agg["mgrit_iterations"] / args.steps
-    log(f"mixed MGRIT: {ms_per_step:.2f} ms/step, {value:.3e} DoF*steps/s, "
-        f"chain {agg['chain_ms'] / args.steps:.2f} ms/step in {launches // args.steps} launches")
+    log(f"mixed MGRIT: {ms_per_step:.2f} ms/step, {value:.3e} DoF*steps/s, dominant W{dw}K{dk} "
+        f"{roofline['avg_launch_ms']:.3f} ms/launch, {roofline['achieved']:.1f} GB/s")
 
     result = {
-        "metric": "DoF*timesteps/s (mixed FP32/FP64 batched MGRIT + combination)",
+        "metric": METRIC,
         "value": value,
         "unit": "DoF*timesteps/s",
         "n_gpus": 1,
@@ -316,15 +610,14 @@ def main(argv=None):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: heat equation d={d}, sparse-grid level {prob['n']}, "
-                        f"{plan.G} component grids, {plan.slen} DoF per time level, {N} "
-                        f"backward-Euler steps on [0,{prob['t1']}], {prob['mgrit_levels']}-level "
-                        f"MGRIT c={prob['cf']} FCF, CG, mixed precision, gather at "
-                        f"{GATHER_POINTS} points",
+            "workload": describe(args.workload, prob, plan.G, plan.slen),
             "grids": plan.G, "dof_per_level": plan.slen, "nsteps": N,
-            "mgrit_iterations_per_step": it_per_step,
+            "tolerances": {k: prob.get(k) for k in ("refine_tol", "inner_tol", "mgrit_tol",
+                                                     "coarse_tol")},
+            "mgrit_iterations_per_step": agg["mgrit_iterations"] / args.steps,
             "phi_solves_per_step": agg["phi_solves"] / args.steps,
             "krylov_iterations_per_step": agg["krylov_iterations"] / args.steps,
+            "refine_sweeps_per_step": agg["refine_sweeps"] / args.steps,
             "plan_ms": plan_ms,
             "autotune": tune,
         },
@@ -332,43 +625,54 @@ def main(argv=None):
     }
 
     oracle_u = oracle_vals = None
-    if not args.no_cpu:
-        log("cpu baseline: oracle on the host")
-        t_cpu, oracle_u, oracle_vals = cpu_oracle(prob, pts_np)
+    if par is not None:
+        oracle_u, oracle_vals = par[2], par[3]
+        result["err_vs_oracle"] = {
+            "grids_compared": plan.G,
+            "mixed_state_rel_l2": _rel(u_mixed, oracle_u),
+            "mixed_max_grid_rel_l2": _per_grid_max_rel(prob, u_mixed, oracle_u),
+            "mixed_gather_rel_l2": _rel(vals_mixed, oracle_vals),
+        }
+        log(f"mixed error vs oracle {result['err_vs_oracle']}")
+        log("cpu baseline: oracle on one host core (grid sample)")
+        t_cpu, dof_sample, nsample = cpu_oracle_sample(prob, SAMPLE_STRIDE)
         result["cpu_baseline"] = {
-            "value": dof_steps / t_cpu,
+            "value": dof_sample * N / t_cpu,
             "unit": "DoF*timesteps/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"whole workload ({plan.G} grids x {N} steps, sparse LU, single thread) "
-                      f"+ combination at {GATHER_POINTS} points; {t_cpu:.2f} s",
+            "sample": f"every {SAMPLE_STRIDE}th component grid ({nsample} of {plan.G} grids, "
+                      f"{dof_sample} of {plan.slen} DoF per level, all layers) x {N} steps, "
+                      f"sparse LU, single thread; {t_cpu:.2f} s",
             "cpu": _cpu_model(),
         }
-        if par is not None:
-            result["cpu_baseline_parallel"] = {
-                "value": dof_steps / par[0],
-                "unit": "DoF*timesteps/s",
-                "cores": par[1],
-                "kind": "oracle",
-                "sample": f"whole workload over {par[1]} host processes: grids longest-first, "
-                          f"then the {GATHER_POINTS} combination points; {par[0]:.2f} s",
-            }
-            assert _rel(par[2], oracle_u) == 0.0
-        result["err_vs_oracle"] = {
-            "mixed_state_rel_l2": _rel(u_mixed, oracle_u),
-            "mixed_gather_rel_l2": _rel(vals_mixed, oracle_vals),
+        result["cpu_baseline_parallel"] = {
+            "value": dof_steps / par[0],
+            "unit": "DoF*timesteps/s",
+            "cores": par[1],
+            "kind": "oracle",
+            "sample": f"whole workload over {par[1]} host processes (the CPUs allotted to this "
+                      f"process, at most 16): grids longest-first, then the {GATHER_POINTS} "
+                      f"combination points; {par[0]:.2f} s",
+            "cpu": _cpu_model(),
         }
-        log(f"cpu {t_cpu:.2f} s; mixed err {result['err_vs_oracle']}")
 
     if not args.no_extras:
-        result["comparators"] = _comparators(args, ctm, torch, oracle_u, dof_steps)
-        plain = result["comparators"]["fp64_per_grid_plain"]["seconds"]
-        # the whole timed step (solve + gather) against the plain schedule's solve
-        result["speedup_vs_plain_per_grid_fp64"] = plain / (ms_per_step / 1e3)
+        comp = _comparators(args, ctm, torch, oracle_u, dof_steps)
+        result["comparators"] = comp
+        # the whole timed step (solve + gather) against the other paths' solves
+        step_s = ms_per_step / 1e3
+        result["speedup_vs_plain_per_grid_fp64"] = comp["fp64_per_grid_plain"]["seconds"] / step_s
+        result["speedup_vs_fp64_mgrit"] = comp["fp64_mgrit"]["seconds"] / step_s
+        result["speedup_vs_fp64_sequential_batched"] = (
+            comp["fp64_sequential_batched"]["seconds"] / step_s)
         result["streaming"] = _streaming(ctm, torch)
+        log(f"streaming: {result['streaming']}")
         result["residual_mode"] = _residual_mode(ctm, torch)
         log(f"residual mode: {result['residual_mode']}")
-        log(f"streaming: {result['streaming']}")
+        if args.workload != "heat3d":
+            result["heat3d"] = _heat3d(ctm, torch)
+            log(f"heat3d: {result['heat3d']}")
     if args.copy_calibration:
         src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -378,192 +682,6 @@ def main(argv=None):
 
     print(json.dumps(result), flush=True)
     return 0
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
-def _cpu_model():
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return None
-
-
-def _shapes(args, plan):
-    """Launch shapes of the timed plan, outside the timed region: autotuned
-    (ctm_autotune, full trial solves, fastest of two), taken from a file, or
-    the defaults."""
-    if args.load_shapes:
-        with open(args.load_shapes) as f:
-            rec = json.load(f)
-        assert rec["workload"] == args.workload and len(rec["shapes"]) == plan.G
-        for g, (w, k) in enumerate(rec["shapes"]):
-            if k:
-                plan.set_grid_shape(g, w, k)
-        return {"source": args.load_shapes}
-    tune = None
-    if not args.no_tune:
-        tune = plan.autotune(trial_iterations=0, repeats=2)
-        log(f"autotune: {tune}")
-    if args.save_shapes:
-        with open(args.save_shapes, "w") as f:
-            json.dump({"workload": args.workload,
-                       "shapes": [plan.grid_shape(g) for g in range(plan.G)]}, f)
-    return tune
-
-
-def _timed(torch, fn, reps=1):
-    fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        out = fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps, out
-
-
-def _comparators(args, ctm, torch, oracle_u, dof_steps):
-    """FP64 MGRIT, batched time-sequential stepping (mixed and FP64) and the
-    plain per-grid FP64 schedule on the same workload, outside the timed
-    region, each with its error against the oracle. The batched ones are
-    autotuned like the timed plan (unless --no-tune) and timed as the mean
-    of three solves; the plain schedule keeps the default shapes."""
-    out = {}
-    runs = [
-        ("fp64_mgrit", workload_problem(args.workload, "fp64"), "solve"),
-        ("mixed_sequential_batched", dict(workload_problem(args.workload, "mixed"),
-                                          mgrit_levels=1), "solve"),
-        ("fp64_sequential_batched", dict(workload_problem(args.workload, "fp64"),
-                                         mgrit_levels=1), "solve"),
-        ("fp64_per_grid_plain", workload_problem(args.workload, "fp64"), "per_grid"),
-    ]
-    for name, prob, kind in runs:
-        plan = ctm.Plan(prob)
-        u0 = plan.initial_state()
-        if kind == "solve":
-            if not args.no_tune:
-                plan.autotune(trial_iterations=0, repeats=2)
-            sec, u = _timed(torch, lambda: plan.solve(), reps=3)
-            st = plan.stats()
-        else:
-            sec, u = _timed(torch, lambda: plan.propagate(u0, prob["nsteps"], per_grid=True))
-            st = plan.stats()
-        entry = {"seconds": sec, "value": dof_steps / sec,
-                 "mgrit_iterations": st["mgrit_iterations"],
-                 "krylov_iterations": st["krylov_iterations"]}
-        if oracle_u is not None:
-            entry["state_rel_l2_vs_oracle"] = _rel(u.cpu().numpy(), oracle_u)
-        out[name] = entry
-        log(f"{name}: {sec * 1e3:.1f} ms ({dof_steps / sec:.3e} DoF*steps/s) {entry}")
-    return out
-
-
-# HBM bytes per unknown of one streaming Krylov iteration (FP64 vectors in
-# HBM, every sweep counted once; neighbour reads served by the caches; each
-# preconditioner application reads r and five factor vectors and writes z)
-STREAM_BYTES_PER_ITERATION = {"cg": 152, "bicgstab": 296}
-
-
-def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
-    """Measured device-to-device copy rate (GB/s, read + write bytes) of a
-    plain 1 GiB copy: the practical HBM ceiling the streaming solvers'
-    algorithmic rate is also quoted against."""
-    n = nbytes // 8
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / reps
-    del src, dst
-    return 2.0 * n * 8 / sec / 1e9
-
-
-def _streaming(ctm, torch):
-    """The streaming solvers on grids beyond the on-chip solver: the 2-D
-    oscillator of Section 4.4 at the paper's own levels (L = 14, L0 = 6:
-    seven grids of up to 32,193 unknowns), FP64 MGRIT. Their roofline is
-    HBM: algorithmic bytes (sweeps x unknowns x Krylov iterations) over each
-    solver's event-timed launches (a wide launch is a whole chain, its host
-    polls included)."""
-    from workloads import make
-    p = make("fp_osc2d", n=14, L0=6, prec="fp64")
-    # the measurement tolerances of the main workload (coarse levels to 1e-3)
-    p.update(krylov_tol=1e-10, mgrit_tol=1e-9, mgrit_maxit=64, krylov_maxit=20000,
-             coarse_tol=1e-3)
-    plan = ctm.Plan(p)
-    plan.solve()
-    torch.cuda.synchronize()
-    plan.set_timing(True)
-    t0 = time.perf_counter()
-    plan.solve()
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    st = plan.stats()
-    plan.set_timing(False)
-    bpi = STREAM_BYTES_PER_ITERATION[p["krylov"]]
-    forms = {16: ("stream_kernel<drift, BiCGStab>: one 1,024-thread work-group per task"),
-             4: ("wide solver: many work-groups per task, one launch per Krylov phase for "
-                 "all tasks of a launch (every streaming launch by default)")}
-    roof = {}
-    for c in st["shapes"]:
-        if c["K"] != 0 or c["W"] not in forms:
-            continue
-        achieved = c["work"] * bpi / (c["ms"] / 1e3) / 1e9 if c["ms"] > 0 else None
-        roof["one_group_per_task" if c["W"] == 16 else "wide"] = {
-            "kernel": forms[c["W"]], "bound": "hbm", "achieved": achieved,
-            "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBPS if achieved else None,
-            "bytes_per_unknown_iteration": bpi, "ms": c["ms"],
-            "krylov_work": c["work"], "launches": c["launches"]}
-    if not roof:
-        return None
-    copy_gbps = copy_bandwidth(torch)
-    for r in roof.values():
-        r["copy_GBps"] = copy_gbps
-        r["frac_of_copy"] = r["achieved"] / copy_gbps if r["achieved"] else None
-    return {
-        "workload": f"fp_osc2d at L = 14, L0 = 6: {plan.G} grids, {plan.slen} DoF per level, "
-                    f"{p['nsteps']} steps, 2-level MGRIT c = 2, BiCGStab, FP64, Krylov 1e-10, "
-                    f"coarse levels 1e-3, MGRIT 1e-9",
-        "seconds": sec,
-        "value": plan.slen * p["nsteps"] / sec,
-        "mgrit_iterations": st["mgrit_iterations"],
-        "krylov_iterations": st["krylov_iterations"],
-        "roofline": roof,
-    }
-
-
-def _residual_mode(ctm, torch):
-    """The optimized oscillator run of Section 4.4 (T = 1, N = 3204, c = 12,
-    F-relaxation, tolerance 1e-4): MGRIT in space-time residual mode with two
-    Krylov iterations per step, beside the same MGRIT with every step solved
-    to 1e-10. Solve time (second of two solves) and MGRIT iterations."""
-    from workloads import make
-    out = {}
-    for tag, kw in (("residual_mode_2_iterations", dict(residual_mode=1, krylov_maxit=2)),
-                    ("exact_steps", dict(residual_mode=0, krylov_maxit=20000,
-                                         krylov_tol=1e-10))):
-        p = make("fp_osc2d", t1=1.0, nsteps=3204)
-        p.update(cf=12, relax="F", prec="fp64", mgrit_tol=1e-4, mgrit_maxit=100, **kw)
-        plan = ctm.Plan(p)
-        sec, _ = _timed(torch, lambda: plan.solve())
-        st = plan.stats()
-        out[tag] = {"seconds": sec, "mgrit_iterations": st["mgrit_iterations"],
-                    "krylov_iterations": st["krylov_iterations"]}
-    return out
 
 
 if __name__ == "__main__":

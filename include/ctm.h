@@ -177,6 +177,9 @@ typedef struct {
   long long shape_launches[16];
   long long shape_work[16];
   double shape_bytes[16];             /* algorithmic HBM bytes of that class's launches */
+  long long shape_dofsteps[16];       /* implicit steps x unknowns of that class's launches
+                                         (the unit of the 16 B per unknown and step minimum:
+                                         read the previous state, write the new one) */
 } ctm_stats;
 
 /* Fill *p with the paper's solver defaults (Section 4.1): two-level MGRIT,

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(64 * W)
                  int tabmax) {
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
-  const ChainSmem lay = chain_smem_layout(W, K, tabmax, false, OPC == OPC_HEAT);
+  const ChainSmem lay = chain_smem_layout(W, K, tabmax, false, OPC == OPC_HEAT, -1);
   double* xl = reinterpret_cast<double*>(smem);
   double* tl = reinterpret_cast<double*>(smem + lay.tab);
   HeatTab<double, K>* ht = reinterpret_cast<HeatTab<double, K>*>(smem + lay.heat);
@@ -121,8 +121,9 @@ __global__ void __launch_bounds__(64 * W)
   Lane<K> L;
   setup_lane<K>(g, L);
   LineOp<OPC, double, K> O;
-  lineop_setup<OPC, double, K>(g, L, dt, amp, tl, ht, O);
-  __syncthreads();  // constant-coefficient table written
+  lineop_setup<OPC, double, K>(g, L, dt, amp, tl, ht,
+                               reinterpret_cast<double*>(smem + lay.ocv), O);
+  __syncthreads();  // constant-coefficient and uniform-coupling tables written
   double xs[K], ys[K];
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -140,7 +141,8 @@ static hipError_t launch_apply_t(int shape, const GridDev* grids, int G, const d
                                  double amp, double dt, int tabmax, const double* x, double* y,
                                  hipStream_t s) {
   const size_t smem =
-      chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, false, OPC == OPC_HEAT).total;
+      chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, false, OPC == OPC_HEAT, -1)
+          .total;
 #define CTM_ACASE(IDX, W, K)                                                                   \
   case IDX:                                                                                    \
     hipLaunchKernelGGL((apply_kernel<OPC, W, K>), dim3(G), dim3(64 * W), smem, s, grids, tab64, \

@@ -120,6 +120,9 @@ struct ctm_plan {
   // Fixed per plan, so that consecutive phases of one class need no
   // cross-stream synchronisation.
   int lane_of[kNumShapes + 1] = {};
+  // cyclic-reduction steps of the line preconditioner each size class's LDS
+  // table must hold: the largest log2(lanes per line) over its grids
+  int pcr_of[kNumShapes] = {};
   // hierarchical basis (built on first use): node id of every unknown; per
   // node, the unknowns of all grids that share its basis function
   double block_t0 = 0.0;     // start time of the recombination block being solved
@@ -275,7 +278,25 @@ ctm_status validate(const ctm_problem* p) {
     return fail(CTM_ERR_INVALID, "no component grid with l >= level_min");
   for (int i = 0; i < p->d; ++i)
     if (!(p->hi[i] > p->lo[i])) return fail(CTM_ERR_INVALID, "box must have hi > lo");
-  if (p->op < CTM_OP_HEAT || p->op > CTM_OP_DRIFT) return fail(CTM_ERR_INVALID, "unknown operator");
+  // the enumerations arrive from C, where any int value can be stored: they
+  // are read as ints (a C++ load of an out-of-range enumerator is undefined)
+  auto as_int = [](const void* e) {
+    int v;
+    std::memcpy(&v, e, sizeof v);
+    return v;
+  };
+  const int op = as_int(&p->op);
+  if (op < CTM_OP_HEAT || op > CTM_OP_DRIFT) return fail(CTM_ERR_INVALID, "unknown operator");
+  const int prec = as_int(&p->prec), kry = as_int(&p->krylov), relax = as_int(&p->relax),
+            mms = as_int(&p->manufactured);
+  if (prec != CTM_PREC_FP64 && prec != CTM_PREC_MIXED)
+    return fail(CTM_ERR_INVALID, "unknown precision");
+  if (kry < CTM_KRYLOV_AUTO || kry > CTM_KRYLOV_BICGSTAB)
+    return fail(CTM_ERR_INVALID, "unknown Krylov method");
+  if (relax != CTM_RELAX_F && relax != CTM_RELAX_FCF)
+    return fail(CTM_ERR_INVALID, "unknown relaxation");
+  if (mms != CTM_MMS_NONE && mms != CTM_MMS_HEAT)
+    return fail(CTM_ERR_INVALID, "unknown manufactured problem");
   if (p->op == CTM_OP_CME)
     for (int i = 0; i < p->d; ++i) {
       const double span = p->hi[i] - p->lo[i];
@@ -377,15 +398,45 @@ int min_waves_shape(const GridDev& gd, int K) {
 }
 
 // Default size class of one grid: K = 4 while its lines fit a wave (fewer
-// registers, higher occupancy) and it needs at most 256 lanes, else 8; then
-// the fewest waves that hold it. ctm_autotune revises it per anisotropy class.
-int grid_shape(const GridDev& gd) {
+// registers, higher occupancy) and it needs at most 256 lanes (512 for the
+// operators with per-line coefficients, whose K = 8 kernels need twice the
+// registers of K = 4 and run one wave per SIMD), else 8; then the fewest
+// waves that hold it. ctm_autotune revises it per anisotropy class.
+int grid_shape(const GridDev& gd, bool heat) {
   const int s4 = min_waves_shape(gd, 4);
-  if (s4 >= 0 && lanes_needed(gd, 4) > 256) {
+  if (s4 >= 0 && lanes_needed(gd, 4) > (heat ? 256 : 512)) {
     const int s8 = min_waves_shape(gd, 8);
     if (s8 >= 0) return s8;
   }
   return s4 >= 0 ? s4 : min_waves_shape(gd, 8);
+}
+
+// Cyclic-reduction steps of grid gd's lines with K unknowns per lane.
+int pcr_steps(const GridDev& gd, int K) {
+  int lc = 1, steps = 0;
+  while (lc < (gd.ns + K - 1) / K) {
+    lc <<= 1;
+    ++steps;
+  }
+  return steps;
+}
+
+// LDS of one compute unit of gfx950: the most a work-group can allocate.
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+// Whether grid gd's chain-kernel work-group fits the LDS in shape sh (its
+// line preconditioner's table grows with log2 of the lanes per line).
+bool shape_fits(const ctm_plan* P, const GridDev& gd, int sh) {
+  return chain_smem_bytes(sh, P->tabmax, P->mixed, P->opc == OPC_HEAT,
+                          pcr_steps(gd, kShapes[sh].K)) <= kMaxLdsBytes;
+}
+
+// The default shape of grid gd among those whose LDS fits, or -1 (streaming).
+int grid_shape_fitting(const ctm_plan* P, const GridDev& gd) {
+  const int sh = grid_shape(gd, P->opc == OPC_HEAT);
+  if (sh < 0 || shape_fits(P, gd, sh)) return sh;
+  const int alt = min_waves_shape(gd, kShapes[sh].K == 4 ? 8 : 4);
+  return (alt >= 0 && shape_fits(P, gd, alt)) ? alt : -1;
 }
 
 ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
@@ -418,7 +469,13 @@ ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
 
 // Lanes of the size classes: in decreasing order of unknowns, each class
 // onto the lane (caller's stream or a side stream) with the fewest so far.
+// Also refreshes the classes' cyclic-reduction table sizes.
 void assign_lanes(ctm_plan* P) {
+  for (int s = 0; s < kNumShapes; ++s) P->pcr_of[s] = 0;
+  for (int g = 0; g < P->G; ++g) {
+    const int s = P->gshape[g];
+    if (s < kNumShapes) P->pcr_of[s] = std::max(P->pcr_of[s], pcr_steps(P->hdev[g], kShapes[s].K));
+  }
   constexpr int nlanes = ctm_plan::kSideStreams + 1;
   double pts[kNumShapes + 1] = {};
   for (int g = 0; g < P->G; ++g) pts[P->gshape[g]] += (double)P->grids[g].npts;
@@ -616,8 +673,10 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   const bool wide = use_wide(P, shape, count);
   const int slot = wide ? kWideSlot : shape;  // statistics slot
   c.counters = P->dcounters + (size_t)slot * CNT_N;
-  const size_t smem =
-      (shape == kStreamShape) ? 0 : chain_smem_bytes(shape, P->tabmax, mixed, P->opc == OPC_HEAT);
+  c.pcrmax = (shape == kStreamShape) ? 0 : P->pcr_of[shape];
+  const size_t smem = (shape == kStreamShape)
+                          ? 0
+                          : chain_smem_bytes(shape, P->tabmax, mixed, P->opc == OPC_HEAT, c.pcrmax);
   // algorithmic bytes: every vector role of every task once
   P->stats.shape_bytes[slot] += 8.0 * points * chain_vectors_per_task(a);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -775,6 +834,7 @@ void fold_counters(const ctm_plan* P, const unsigned long long* c, ctm_stats* st
     st->phi_solves += (long long)k[CNT_SOLVES];
     st->krylov_work += (long long)k[CNT_WORK];
     st->shape_work[s] = (long long)k[CNT_WORK];
+    st->shape_dofsteps[s] = (long long)k[CNT_DOFSTEPS];
     // streaming: K = 0, and W = 16 (1,024 threads per task) or the wide
     // solver's kWW waves per work-group
     st->shape_w[s] = (s == kStreamShape) ? 16 : (s == kWideSlot) ? kWW : kShapes[s].W;
@@ -794,6 +854,8 @@ ctm_status collect_device_stats(ctm_plan* P, hipStream_t s) {
 }
 
 ctm_status status_from_flags(int flags) {
+  if (flags & (1 << CTM_ERR_INVALID))
+    return fail(CTM_ERR_INVALID, "a launch's cyclic-reduction table was too small for a grid");
   if (flags & (1 << CTM_ERR_NONFINITE)) return fail(CTM_ERR_NONFINITE, "non-finite value in a solve");
   if (flags & (1 << CTM_ERR_BREAKDOWN)) return fail(CTM_ERR_BREAKDOWN, "BiCGStab breakdown");
   if (flags & (1 << CTM_ERR_NOCONV)) return fail(CTM_ERR_NOCONV, "an implicit solve did not converge");
@@ -1007,19 +1069,32 @@ ctm_status ensure_hier(ctm_plan* P) {
   }
   off.push_back((int)N);
   const int nodes = (int)off.size() - 1;
-  auto alloc = [&](void** ptr, size_t bytes, const void* src) -> ctm_status {
-    if (hipMalloc(ptr, bytes) != hipSuccess) return fail(CTM_ERR_NOMEM, "device allocation failed");
-    if (src && hipMemcpy(*ptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
-      return fail(CTM_ERR_HIP, "hipMemcpy failed");
-    return CTM_OK;
-  };
-  ctm_status st;
-  if ((st = alloc((void**)&P->dhoff, off.size() * sizeof(int), off.data())) != CTM_OK ||
-      (st = alloc((void**)&P->dhidx, ord.size() * sizeof(int), ord.data())) != CTM_OK ||
-      (st = alloc((void**)&P->dhcoef, coef.size() * sizeof(double), coef.data())) != CTM_OK ||
-      (st = alloc((void**)&P->dhsg, (size_t)nodes * sizeof(double), nullptr)) != CTM_OK ||
-      (st = alloc((void**)&P->dhnode, node.size() * sizeof(int), node.data())) != CTM_OK)
-    return st;
+  // every table is allocated into a local first and handed to the plan only
+  // once all of them exist (dhnode, the "built" marker, last), so that a
+  // failed allocation leaves nothing behind and a later call starts over
+  void* bufs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t bytes[5] = {off.size() * sizeof(int), ord.size() * sizeof(int),
+                           coef.size() * sizeof(double), (size_t)nodes * sizeof(double),
+                           node.size() * sizeof(int)};
+  const void* src[5] = {off.data(), ord.data(), coef.data(), nullptr, node.data()};
+  for (int i = 0; i < 5; ++i) {
+    ctm_status st = CTM_OK;
+    if (hipMalloc(&bufs[i], bytes[i]) != hipSuccess) {
+      bufs[i] = nullptr;
+      st = fail(CTM_ERR_NOMEM, "device allocation failed");
+    } else if (src[i] && hipMemcpy(bufs[i], src[i], bytes[i], hipMemcpyHostToDevice) != hipSuccess) {
+      st = fail(CTM_ERR_HIP, "hipMemcpy failed");
+    }
+    if (st != CTM_OK) {
+      for (int k = 0; k <= i; ++k) hipFree(bufs[k]);
+      return st;
+    }
+  }
+  P->dhoff = static_cast<int*>(bufs[0]);
+  P->dhidx = static_cast<int*>(bufs[1]);
+  P->dhcoef = static_cast<double*>(bufs[2]);
+  P->dhsg = static_cast<double*>(bufs[3]);
+  P->dhnode = static_cast<int*>(bufs[4]);
   P->hnodes = nodes;
   return CTM_OK;
 }
@@ -1432,7 +1507,7 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   P->gshape.resize(P->G);
   int nstream = 0, maxstream = 0;
   for (int g = 0; g < P->G; ++g) {
-    const int sh = grid_shape(P->hdev[g]);
+    const int sh = grid_shape_fitting(P, P->hdev[g]);
     P->gshape[g] = sh >= 0 ? sh : kStreamShape;
     if (sh < 0) {
       ++nstream;
@@ -1719,6 +1794,8 @@ ctm_status ctm_plan_set_grid_shape(ctm_plan* P, int g, int waves, int per_lane) 
   const GridDev& gd = P->hdev[g];
   if (gd.ns > 64 * per_lane || lanes_needed(gd, per_lane) > 64 * waves)
     return fail(CTM_ERR_INVALID, "the launch shape cannot hold the grid's lines");
+  if (!shape_fits(P, gd, sh))
+    return fail(CTM_ERR_INVALID, "the launch shape's LDS would exceed a compute unit's");
   set_shape(P, g, sh);
   return CTM_OK;
 }
@@ -1752,8 +1829,9 @@ ctm_status ctm_autotune(ctm_plan* P, void* ws, size_t ws_bytes, double* u_scratc
     TuneClass& tc = by_key[{gd.ns, gd.nlines}];
     tc.grids.push_back(g);
     tc.points += (double)gd.npts;
-    tc.cand[0] = min_waves_shape(gd, 4);
-    tc.cand[1] = min_waves_shape(gd, 8);
+    const int c4 = min_waves_shape(gd, 4), c8 = min_waves_shape(gd, 8);
+    tc.cand[0] = (c4 >= 0 && shape_fits(P, gd, c4)) ? c4 : -1;
+    tc.cand[1] = (c8 >= 0 && shape_fits(P, gd, c8)) ? c8 : -1;
   }
   std::vector<TuneClass> classes;
   for (auto& kv : by_key)

@@ -76,8 +76,9 @@ struct ChainArgs {
   int single32;             // mixed path: each step is one FP32 solve to inner_tol (no
                             // FP64 refinement); for loose coarse-level tolerances
   int fkind;                // forcing: 0 none, 1 manufactured heat problem (heat only)
-  int resmode;              // MGRIT residual mode (FP64): fixed-count steps, forcing before
-                            // the step, exact space-time residual against a target
+  int resmode;              // MGRIT residual mode (both precisions): fixed-count steps,
+                            // forcing before the step, exact space-time residual against a
+                            // target
   double ft0, ftq;          // time of step j of task q: ft0 + q ftq + j dt
   double tol;               // FP64 path Krylov tolerance, or mixed refinement tolerance
   double inner_tol;         // mixed path FP32 Krylov tolerance
@@ -94,6 +95,8 @@ struct ChainArgs {
   int* status;              // OR of (1 << ctm_status)
   const double* skip;       // optional: the launch does nothing once *skip != 0 (MGRIT
                             // work queued past the converged iteration)
+  int pcrmax;               // cyclic-reduction steps the LDS of the launch holds per lane
+                            // (at least log2 of the lanes per line of every grid of it)
 };
 
 enum {
@@ -103,6 +106,7 @@ enum {
   CNT_REFINE_MAX = 3,
   CNT_SOLVES = 4,
   CNT_WORK = 5,
+  CNT_DOFSTEPS = 6,  // implicit steps x unknowns
   CNT_N = 8
 };
 
@@ -223,9 +227,14 @@ struct HeatTab {
 
 // Dynamic LDS of the chain kernel: FP64 vector, FP32 vector (mixed), the
 // coefficient tables (FP64, then FP32 if mixed), the constant-coefficient
-// tables (heat; FP64, then FP32 if mixed), two reduction slots.
+// tables (heat; FP64, then FP32 if mixed), the uniform off-axis couplings
+// of the variable-coefficient operator (FP64 and FP32), two reduction slots,
+// and the cyclic-reduction factors of the line preconditioner (operators with
+// per-line coefficients, in the precision the preconditioner runs in):
+// row 0 the reciprocal reduced diagonal, rows 1 + 2r and 2 + 2r the factors
+// of step r, one column per thread.
 struct ChainSmem {
-  size_t x32, tab, heat, red, total;  // byte offsets and total
+  size_t x32, tab, heat, ocv, red, pre, total;  // byte offsets and total
 };
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 __host__ __device__ constexpr size_t heat_tab_bytes(int K, bool mixed) {
@@ -234,18 +243,25 @@ __host__ __device__ constexpr size_t heat_tab_bytes(int K, bool mixed) {
                 : align16(sizeof(HeatTab<double, 8>)) +
                       (mixed ? align16(sizeof(HeatTab<float, 8>)) : 0);
 }
+constexpr size_t kOcvBytes = MAXD * sizeof(double) + MAXD * sizeof(float);
+// rows of the cyclic-reduction table for pcr steps (0: no table)
+__host__ __device__ constexpr int pcr_rows(int pcr) { return pcr < 0 ? 0 : 2 * pcr + 1; }
 __host__ __device__ constexpr ChainSmem chain_smem_layout(int W, int K, int tabmax, bool mixed,
-                                                          bool heat) {
+                                                          bool heat, int pcr) {
   const size_t elems = (size_t)K * lds_pitch(W);
   const size_t x32 = align16(elems * sizeof(double));
   const size_t tab = x32 + (mixed ? align16(elems * sizeof(float)) : 0);
   const size_t hb = tab + align16((size_t)tabmax * sizeof(double) +
                                   (mixed ? (size_t)tabmax * sizeof(float) : 0));
-  const size_t red = hb + (heat ? heat_tab_bytes(K, mixed) : 0);
-  return ChainSmem{x32, tab, hb, red, red + 2u * 64u * sizeof(double)};
+  const size_t ocv = hb + (heat ? heat_tab_bytes(K, mixed) : 0);
+  const size_t red = ocv + align16(kOcvBytes);
+  const size_t pre = red + 2u * 64u * sizeof(double);
+  const size_t prebytes =
+      heat ? 0 : align16((size_t)pcr_rows(pcr) * 64u * W * (mixed ? sizeof(float) : sizeof(double)));
+  return ChainSmem{x32, tab, hb, ocv, red, pre, pre + prebytes};
 }
-inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed, bool heat) {
-  return chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, mixed, heat).total;
+inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed, bool heat, int pcr) {
+  return chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, mixed, heat, pcr).total;
 }
 
 // Auxiliary kernels (aux_kernels.hip).

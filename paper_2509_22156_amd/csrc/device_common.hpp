@@ -67,7 +67,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // Status bits a solver kernel ORs into ChainArgs::status.
 enum { FLAG_NOCONV = 1 << CTM_ERR_NOCONV, FLAG_BREAKDOWN = 1 << CTM_ERR_BREAKDOWN,
-       FLAG_NONFINITE = 1 << CTM_ERR_NONFINITE };
+       FLAG_NONFINITE = 1 << CTM_ERR_NONFINITE,
+       FLAG_INVALID = 1 << CTM_ERR_INVALID };
 
 // Two LDS slot arrays for cross-wave sums, used strictly alternately: the
 // barrier of every call then separates a slot's reads from its next writes.

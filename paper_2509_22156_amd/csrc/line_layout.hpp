@@ -137,6 +137,20 @@ template <typename T, int K>
 struct LineOp<OPC_HEAT, T, K> {
   HeatTab<T, K>* h;
 };
+// VAR: the coupling along the stiff axis between unknowns k-1 and k is the
+// face value face[k] (shared by both unknowns, the operator is symmetric);
+// the coupling to the neighbour line along oax[m] at unknown k is
+// oc[m] + q{lo,up}[m] * snj[k]: a part -dt/h_m^2 that is the same for the
+// whole grid (a work-group table in LDS, oc) and a per-lane factor times the
+// stiff-axis node sine of the unknown.
+template <typename T, int K>
+struct LineOp<OPC_VAR, T, K> {
+  T diag[K];
+  T face[K + 1];
+  T snj[K];
+  T qlo[MAXD - 1], qup[MAXD - 1];
+  const T* oc;
+};
 // DRIFT: the face velocity along a non-stiff axis a at unknown k is
 // base[m] + theta[a][s] x_s(k) -/+ theta[a][a] h_a / 2, so a lane keeps
 // base[m] (the contribution of its fixed coordinates) and computes the
@@ -154,11 +168,13 @@ struct LineOp<OPC_DRIFT, T, K> {
 // tab: this grid's tables in LDS (SEP: per axis Lo, D, Up of L scaled by
 // dt; VAR: per axis node sines then face sines). ht: the work-group's
 // constant-coefficient table (HEAT only; thread 0 fills its weights, and a
-// barrier must follow before they are read).
+// barrier must follow before they are read). ocv: the work-group's table of
+// uniform off-axis couplings (VAR only; thread 0 fills it, and a barrier
+// must follow before the first apply reads it).
 template <int OPC, typename T, int K>
 __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L, double dt,
                                              double amp, const T* tab, HeatTab<T, K>* ht,
-                                             LineOp<OPC, T, K>& O) {
+                                             T* ocv, LineOp<OPC, T, K>& O) {
   const int s = g.sax;
   const double cs = dt * g.ih2[s];
   if constexpr (OPC == OPC_HEAT) {
@@ -266,12 +282,17 @@ __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L,
       suf[m] = run;
       run *= sn[m];
     }
-    T diag_lane = (T)1;  // per-lane part of the diagonal: 1 + sum_m c_m (2 + ...)
     const T A = (T)amp;
+    O.oc = ocv;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int m = 0; m < MAXD - 1; ++m)
+        ocv[m] = (m < g.d - 1) ? (T)(-(dt * g.ih2[g.oax[m]])) : (T)0;
+    }
+    T diag_lane = (T)1;  // 1 + sum_m (dt/h_m^2) (a_lo + a_up) without the snj parts
+    T qsum = (T)0;       // sum_m (qlo[m] + qup[m]): the snj-proportional diagonal part
 #pragma unroll
     for (int m = 0; m < MAXD - 1; ++m) {
-      O.olo[m] = (T)0;
-      O.oup[m] = (T)0;
       O.qlo[m] = (T)0;
       O.qup[m] = (T)0;
       if (m < g.d - 1) {
@@ -279,30 +300,25 @@ __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L,
         const T cm = (T)(dt * g.ih2[ax]);
         const T* sm = tab + g.tab[ax] + g.n[ax];
         const T pm = pre[m] * suf[m];
-        O.olo[m] = -cm;
-        O.oup[m] = -cm;
         O.qlo[m] = -cm * A * sm[L.jo[m]] * pm;
         O.qup[m] = -cm * A * sm[L.jo[m] + 1] * pm;
+        diag_lane += cm + cm;
+        qsum += O.qlo[m] + O.qup[m];
       }
     }
     const T* sns = tab + g.tab[s];
     const T* sms = tab + g.tab[s] + g.n[s];
     const T csT = (T)cs;
+    // faces j0 .. j0 + nval of the chunk (face k lies below unknown k)
+#pragma unroll
+    for (int k = 0; k <= K; ++k)
+      O.face[k] = (L.nval > 0 && k <= L.nval) ? -csT * ((T)1 + A * sms[L.j0 + k] * es) : (T)0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int j = L.j0 + k;
       const bool v = k < L.nval;
-      const T snv = v ? sns[j] : (T)0;
+      const T snv = v ? sns[L.j0 + k] : (T)0;
       O.snj[k] = snv;
-      const T adn = (T)1 + A * (v ? sms[j] : (T)0) * es;
-      const T aup = (T)1 + A * (v ? sms[j + 1] : (T)0) * es;
-      T dg = diag_lane + csT * (adn + aup);
-#pragma unroll
-      for (int m = 0; m < MAXD - 1; ++m)
-        if (m < g.d - 1) dg -= (O.olo[m] + O.qlo[m] * snv) + (O.oup[m] + O.qup[m] * snv);
-      O.diag[k] = v ? dg : (T)1;
-      O.slo[k] = v ? -csT * adn : (T)0;
-      O.sup[k] = v ? -csT * aup : (T)0;
+      O.diag[k] = v ? diag_lane - (O.face[k] + O.face[k + 1]) - qsum * snv : (T)1;
     }
   }
 }
@@ -315,21 +331,25 @@ __device__ __forceinline__ T op_diag(const LineOp<OPC, T, K>& O, int k) {
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_slo(const LineOp<OPC, T, K>& O, int k) {
   if constexpr (OPC == OPC_HEAT) return O.h->s;
+  else if constexpr (OPC == OPC_VAR) return O.face[k];
   else return O.slo[k];
 }
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_sup(const LineOp<OPC, T, K>& O, int k) {
   if constexpr (OPC == OPC_HEAT) return O.h->s;
+  else if constexpr (OPC == OPC_VAR) return O.face[k + 1];
   else return O.sup[k];
 }
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_olo(const LineOp<OPC, T, K>& O, int m) {
   if constexpr (OPC == OPC_HEAT) return O.h->o[m];
+  else if constexpr (OPC == OPC_VAR) return O.oc[m];
   else return O.olo[m];
 }
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_oup(const LineOp<OPC, T, K>& O, int m) {
   if constexpr (OPC == OPC_HEAT) return O.h->o[m];
+  else if constexpr (OPC == OPC_VAR) return O.oc[m];
   else return O.oup[m];
 }
 
@@ -412,21 +432,32 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
 }
 
 // ------------------------------------------------------ preconditioner
+// Per-lane factors of the chunk interior in registers; the cyclic-reduction
+// factors of the interface system live in a work-group table in LDS (one
+// column per thread, row stride BS: row 0 the reciprocal reduced diagonal,
+// rows 1 + 2r and 2 + 2r the factors of step r), read back by the same
+// thread only, so no barrier is needed between setup and use.
+// The Thomas multipliers m_k = a_k / pivot_{k-1} and the upper couplings c_k
+// of the chunk interior are the operator's own couplings times the stored
+// reciprocal pivots, so they are formed from the LineOp in the apply rather
+// than kept in registers.
 template <typename T, int K>
 struct LinePre {
-  T m[K];            // Thomas multipliers of the chunk interior (k = 1..K-2)
   T id[K];           // reciprocal pivots (k = 0..K-2)
-  T cu[K];           // upper couplings inside the interior (k = 0..K-3)
   T phi[K], psi[K];  // interior responses to the previous / own interface unknown
   T aL, cL;          // couplings of the chunk's last unknown
-  T pa[kMaxPcr], pc[kMaxPcr];  // cyclic-reduction factors per step
-  T pinv;            // reciprocal of the reduced diagonal
+  T* pl;             // this thread's column of the cyclic-reduction table
   int steps;         // log2(Lc)
 };
 
-template <int OPC, typename T, int K>
+// pre: the work-group's cyclic-reduction table (pcrmax steps); a grid whose
+// lines need more steps than the table holds raises FLAG_INVALID in *flag
+// and is left unpreconditioned along its interface (the launch reports an
+// error; the host sizes the table so that this does not happen).
+template <int OPC, typename T, int K, int BS>
 __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC, T, K>& O,
-                                              LinePre<T, K>& M) {
+                                              LinePre<T, K>& M, T* pre, int pcrmax,
+                                              int* flag) {
   static_assert(K >= 2, "chunks hold at least two unknowns");
   T a[K], b[K], c[K];
 #pragma unroll
@@ -437,26 +468,25 @@ __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC
     c[k] = (v && k + 1 < L.nval) ? op_sup(O, k) : (T)0;
     b[k] = v ? op_diag(O, k) : (T)1;
   }
-  M.m[0] = (T)0;
+  T mm[K];
+  mm[0] = (T)0;
   M.id[0] = (T)1 / b[0];
 #pragma unroll
   for (int k = 1; k < K - 1; ++k) {
-    M.m[k] = a[k] * M.id[k - 1];
-    M.id[k] = (T)1 / (b[k] - M.m[k] * c[k - 1]);
+    mm[k] = a[k] * M.id[k - 1];
+    M.id[k] = (T)1 / (b[k] - mm[k] * c[k - 1]);
   }
-#pragma unroll
-  for (int k = 0; k < K; ++k) M.cu[k] = (k < K - 2) ? c[k] : (T)0;
   // phi = T_I^-1 (a_0 e_0), psi = T_I^-1 (c_{K-2} e_{K-2})
   T f[K];
   f[0] = a[0];
 #pragma unroll
-  for (int k = 1; k < K - 1; ++k) f[k] = -M.m[k] * f[k - 1];
+  for (int k = 1; k < K - 1; ++k) f[k] = -mm[k] * f[k - 1];
   M.phi[K - 2] = f[K - 2] * M.id[K - 2];
 #pragma unroll
-  for (int k = K - 3; k >= 0; --k) M.phi[k] = (f[k] - M.cu[k] * M.phi[k + 1]) * M.id[k];
+  for (int k = K - 3; k >= 0; --k) M.phi[k] = (f[k] - c[k] * M.phi[k + 1]) * M.id[k];
   M.psi[K - 2] = c[K - 2] * M.id[K - 2];
 #pragma unroll
-  for (int k = K - 3; k >= 0; --k) M.psi[k] = -M.cu[k] * M.psi[k + 1] * M.id[k];
+  for (int k = K - 3; k >= 0; --k) M.psi[k] = -c[k] * M.psi[k + 1] * M.id[k];
   M.phi[K - 1] = (T)0;
   M.psi[K - 1] = (T)0;
   // interface equation of the chunk's last unknown u_c:
@@ -471,15 +501,19 @@ __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC
   T A = -M.aL * M.phi[K - 2];
   T B = b[K - 1] - M.aL * M.psi[K - 2] - M.cL * phi0n;
   T C = -M.cL * psi0n;
+  M.pl = pre + threadIdx.x;
   // cyclic reduction factors over the Lc lanes of the line
-  M.steps = 0;
+  int steps = 0;
+  while ((1 << steps) < L.Lc) ++steps;
+  if (steps > pcrmax) {
+    *flag |= FLAG_INVALID;
+    steps = pcrmax;
+  }
+  M.steps = steps;
 #pragma unroll
   for (int r = 0; r < kMaxPcr; ++r) {
-    M.pa[r] = (T)0;
-    M.pc[r] = (T)0;
     const int s = 1 << r;
-    if (s < L.Lc) {
-      M.steps = r + 1;
+    if (r < steps) {
       const T Am = from_minus(A, s, L.Lc), Bm = from_minus(B, s, L.Lc),
               Cm = from_minus(C, s, L.Lc);
       const T Ap = from_plus(A, s, L.Lc), Bp = from_plus(B, s, L.Lc),
@@ -487,8 +521,8 @@ __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC
       const bool vm = L.c >= s, vp = L.c + s < L.Lc;
       const T al = vm ? -A / Bm : (T)0;
       const T ga = vp ? -C / Bp : (T)0;
-      M.pa[r] = al;
-      M.pc[r] = ga;
+      M.pl[(1 + 2 * r) * BS] = al;
+      M.pl[(2 + 2 * r) * BS] = ga;
       const T An = vm ? al * Am : (T)0;
       const T Cn = vp ? ga * Cp : (T)0;
       B = B + (vm ? al * Cm : (T)0) + (vp ? ga * Ap : (T)0);
@@ -496,20 +530,27 @@ __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC
       C = Cn;
     }
   }
-  M.pinv = (T)1 / B;
+  M.pl[0] = (T)1 / B;
 }
 
 // z = M^-1 r for the chunk (padding entries of r must be zero).
-template <typename T, int K>
-__device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LinePre<T, K>& M,
-                                              const T (&r)[K], T (&z)[K]) {
+template <int OPC, typename T, int K, int BS>
+__device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LineOp<OPC, T, K>& O,
+                                              const LinePre<T, K>& M, const T (&r)[K],
+                                              T (&z)[K]) {
   T y[K];
   y[0] = r[0];
+  // interior unknowns k >= 1 have j > 0, so their lower coupling is the
+  // operator's; a padding unknown's y never reaches a live one (its upper
+  // coupling below is masked, and aL is zero in a partial chunk)
 #pragma unroll
-  for (int k = 1; k < K - 1; ++k) y[k] = r[k] - M.m[k] * y[k - 1];
+  for (int k = 1; k < K - 1; ++k) y[k] = r[k] - op_slo(O, k) * M.id[k - 1] * y[k - 1];
   y[K - 2] = y[K - 2] * M.id[K - 2];
 #pragma unroll
-  for (int k = K - 3; k >= 0; --k) y[k] = (y[k] - M.cu[k] * y[k + 1]) * M.id[k];
+  for (int k = K - 3; k >= 0; --k) {
+    const T cu = (k + 1 < L.nval) ? op_sup(O, k) : (T)0;
+    y[k] = (y[k] - cu * y[k + 1]) * M.id[k];
+  }
   const T y0n = from_plus(y[0], 1, L.Lc);
   T R = r[K - 1] - M.aL * y[K - 2] - M.cL * y0n;
 #pragma unroll
@@ -518,10 +559,10 @@ __device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LinePre<T,
       const int s = 1 << st;
       const T Rm = from_minus(R, s, L.Lc);
       const T Rp = from_plus(R, s, L.Lc);
-      R = R + M.pa[st] * Rm + M.pc[st] * Rp;
+      R = R + M.pl[(1 + 2 * st) * BS] * Rm + M.pl[(2 + 2 * st) * BS] * Rp;
     }
   }
-  const T u = R * M.pinv;
+  const T u = R * M.pl[0];
   T um = from_minus(u, 1, L.Lc);
   um = (L.c > 0) ? um : (T)0;
 #pragma unroll
@@ -552,10 +593,12 @@ template <int OPC, typename T, int K>
 using PreOf = typename std::conditional<OPC == OPC_HEAT, LinePreH<T, K>, LinePre<T, K>>::type;
 
 // Builds the table's factors. Every thread of the work-group calls it after
-// lineop_setup; it contains the barriers that publish the table.
-template <int OPC, typename T, int K>
+// lineop_setup; it contains the barriers that publish the table. (The
+// cyclic-reduction table arguments of the per-line preconditioner are not
+// used: these factors live in the HeatTab.)
+template <int OPC, typename T, int K, int BS>
 __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC_HEAT, T, K>& O,
-                                              LinePreH<T, K>& M) {
+                                              LinePreH<T, K>& M, T*, int, int*) {
   static_assert(OPC == OPC_HEAT, "constant-coefficient preconditioner");
   static_assert(K >= 2, "chunks hold at least two unknowns");
   HeatTab<T, K>* h = O.h;
@@ -651,8 +694,9 @@ __device__ __forceinline__ void linepre_setup(const Lane<K>& L, const LineOp<OPC
 }
 
 // z = M^-1 r for the chunk (padding entries of r must be zero).
-template <typename T, int K>
-__device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LinePreH<T, K>& M,
+template <int OPC, typename T, int K, int BS>
+__device__ __forceinline__ void linepre_apply(const Lane<K>& L, const LineOp<OPC, T, K>&,
+                                              const LinePreH<T, K>& M,
                                               const T (&r)[K], T (&z)[K]) {
   const HeatTab<T, K>* h = M.h;
   T y[K];

@@ -702,6 +702,7 @@ __global__ void __launch_bounds__(kStreamThreads)
       atomicMax(&a.counters[CNT_KRYLOV_MAX], (unsigned long long)kr_max);
       atomicAdd(&a.counters[CNT_SOLVES], (unsigned long long)a.nsteps);
       atomicAdd(&a.counters[CNT_WORK], (unsigned long long)kr_sum * (unsigned long long)np);
+      atomicAdd(&a.counters[CNT_DOFSTEPS], (unsigned long long)a.nsteps * (unsigned long long)np);
     }
     if (flag && a.status) atomicOr(a.status, flag);
   }

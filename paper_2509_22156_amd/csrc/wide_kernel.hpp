@@ -1099,6 +1099,7 @@ __global__ void __launch_bounds__(64) wide_finish_kernel(WideArgs w) {
     atomicMax(&a.counters[CNT_KRYLOV_MAX], (unsigned long long)kr_max);
     atomicAdd(&a.counters[CNT_SOLVES], (unsigned long long)a.nsteps);
     atomicAdd(&a.counters[CNT_WORK], (unsigned long long)kr_sum * (unsigned long long)g.npts);
+    atomicAdd(&a.counters[CNT_DOFSTEPS], (unsigned long long)a.nsteps * (unsigned long long)g.npts);
   }
   if (flag && a.status) atomicOr(a.status, flag);
 }

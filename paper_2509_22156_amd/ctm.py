@@ -61,6 +61,7 @@ class Stats(ctypes.Structure):
         ("shape_w", ctypes.c_int * 16), ("shape_k", ctypes.c_int * 16),
         ("shape_ms", ctypes.c_double * 16), ("shape_launches", ctypes.c_longlong * 16),
         ("shape_work", ctypes.c_longlong * 16), ("shape_bytes", ctypes.c_double * 16),
+        ("shape_dofsteps", ctypes.c_longlong * 16),
     ]
 
 
@@ -135,6 +136,23 @@ def _ptr(t) -> ctypes.c_void_p:
     if t is None:
         return None
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _device_vec(t, n: int, name: str):
+    """Guard of every device vector handed to the library: a contiguous
+    float64 tensor on the current HIP device holding at least n entries
+    (the kernels read and write n entries through its raw pointer)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {t.dtype}")
+    if not t.is_cuda or t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name}: expected a tensor on the current GPU, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if t.numel() < n:
+        raise ValueError(f"{name}: holds {t.numel()} entries, needs at least {n}")
+    return t
 
 
 def _stream():
@@ -230,9 +248,10 @@ class Plan:
     def _vec(self, out=None):
         if out is None:
             out = torch.empty(self.slen, dtype=torch.float64, device="cuda")
-        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
-        assert out.numel() >= self.slen
-        return out
+        return _device_vec(out, self.slen, "out")
+
+    def _inp(self, x, name: str):
+        return _device_vec(x, self.slen, name)
 
     def initial_state(self, out=None):
         out = self._vec(out)
@@ -240,11 +259,13 @@ class Plan:
         return out
 
     def apply(self, x, level: int = 0, out=None):
+        self._inp(x, "x")
         out = self._vec(out)
         _check(_lib.ctm_apply(self._h, level, _ptr(x), _ptr(out), _stream()))
         return out
 
     def propagate(self, x, nsteps: int, level: int = 0, per_grid: bool = False, out=None):
+        self._inp(x, "x")
         out = self._vec(out)
         _check(_lib.ctm_propagate(self._h, level, nsteps, _ptr(x), _ptr(out), int(per_grid),
                                   _stream()))
@@ -258,6 +279,8 @@ class Plan:
     def solve(self, u0=None, out=None, check: bool = True):
         """The whole method; returns the packed component states at t1.
         With check=False returns (state, status) instead of raising."""
+        if u0 is not None:
+            self._inp(u0, "u0")
         out = self._vec(out)
         ws = self.workspace()
         st = _lib.ctm_solve(self._h, _ptr(ws), ws.numel(), _ptr(u0), _ptr(out), _stream())
@@ -267,24 +290,30 @@ class Plan:
         return out, st
 
     def gather(self, u, pts, out=None):
-        pts = pts.contiguous()
-        assert pts.dtype == torch.float64 and pts.is_cuda and pts.shape[1] == self.prob["d"]
+        self._inp(u, "u")
+        if pts.dim() != 2 or pts.shape[1] != self.prob["d"]:
+            raise ValueError(f"pts: expected shape (n, {self.prob['d']}), got {tuple(pts.shape)}")
+        _device_vec(pts, pts.numel(), "pts")
         if out is None:
             out = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+        _device_vec(out, pts.shape[0], "out")
         _check(_lib.ctm_gather(self._h, _ptr(u), _ptr(pts), pts.shape[0], _ptr(out), _stream()))
         return out
 
     def combine_project(self, u, out=None):
+        self._inp(u, "u")
         out = self._vec(out)
         _check(_lib.ctm_combine_project(self._h, _ptr(u), _ptr(out), _stream()))
         return out
 
     def hierarchize(self, u, out=None, inverse=False):
+        self._inp(u, "u")
         out = self._vec(out)
         _check(_lib.ctm_hierarchize(self._h, _ptr(u), _ptr(out), int(bool(inverse)), _stream()))
         return out
 
     def recombine(self, u, out=None):
+        self._inp(u, "u")
         out = self._vec(out)
         _check(_lib.ctm_recombine(self._h, _ptr(u), _ptr(out), _stream()))
         return out
@@ -301,7 +330,7 @@ class Plan:
                     chain_ms=st.chain_ms, chain_bytes=st.chain_bytes,
                     shapes=[dict(W=st.shape_w[i], K=st.shape_k[i], ms=st.shape_ms[i],
                                  launches=st.shape_launches[i], work=st.shape_work[i],
-                                 bytes=st.shape_bytes[i])
+                                 bytes=st.shape_bytes[i], dofsteps=st.shape_dofsteps[i])
                             for i in range(16) if st.shape_launches[i] or st.shape_work[i]])
 
     def grid_shape(self, g: int):

@@ -12,6 +12,68 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def state_errors(prob, u, ref, floor=1e-6):
+    """(whole-state relative L2, largest per-grid relative L2, largest
+    element error over the state's max norm). A grid's error is taken
+    relative to its own norm, or to `floor` times the largest grid norm when
+    its solution is smaller than that (grids on which the initial modes
+    vanish hold rounding noise only)."""
+    u = np.asarray(u, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    pu, pr = split(prob, u), split(prob, ref)
+    norms = [np.linalg.norm(r) for r in pr]
+    scale = floor * max(max(norms), 1e-300)
+    grid = max(np.linalg.norm(a - b) / max(n, scale) for a, b, n in zip(pu, pr, norms))
+    elem = np.abs(u - ref).max() / max(np.abs(ref).max(), 1e-300)
+    return rel_l2(u, ref), float(grid), float(elem)
+
+
+def assert_state_close(prob, u, ref, tol, what=""):
+    """The solve-level parity bar: whole state, every grid and every element
+    within tol (see state_errors)."""
+    glob, grid, elem = state_errors(prob, u, ref)
+    print(f"  {what} rel L2 {glob:.3e}, worst grid {grid:.3e}, worst element {elem:.3e} "
+          f"(bar {tol:.0e})", flush=True)
+    assert glob <= tol and grid <= tol and elem <= tol, (glob, grid, elem, tol)
+
+
+def _oracle_part(prob, sel):
+    return sel, solve.component_states(prob, sel)
+
+
+def oracle_states(prob, workers=None):
+    """Every component state at T from the oracle; large workloads spread
+    the grids over host processes (spawned, so the GPU context of the test
+    process is not inherited)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    gl = solve.grid_list(prob)
+    sizes = np.diff(solve.offsets(prob))
+    work = int(sizes.sum()) * prob["nsteps"]
+    if workers is None:
+        try:
+            ncpu = len(os.sched_getaffinity(0))
+        except AttributeError:
+            ncpu = os.cpu_count() or 1
+        workers = max(1, min(16, ncpu)) if work > 5e7 else 1
+    if workers == 1:
+        return solve.component_states(prob)
+    bins = [[] for _ in range(workers)]
+    load = [0] * workers
+    for g in sorted(range(len(gl)), key=lambda g: -sizes[g]):
+        b = load.index(min(load))
+        bins[b].append(g)
+        load[b] += int(sizes[g])
+    bins = [b for b in bins if b]
+    states = [None] * len(gl)
+    with cf.ProcessPoolExecutor(len(bins), mp_context=mp.get_context("spawn")) as ex:
+        for sel, st in ex.map(_oracle_part, [prob] * len(bins), bins):
+            for g, x in zip(sel, st):
+                states[g] = x
+    return states
+
+
 def split(prob, packed):
     """Packed vector -> list of per-grid arrays (canonical order)."""
     off = solve.offsets(prob)
@@ -69,5 +131,5 @@ def oracle_mgrit_history(prob, nit, grid_sel=None):
     return hist
 
 
-__all__ = ["rel_l2", "split", "oracle_apply", "oracle_abs_apply", "oracle_propagate",
+__all__ = ["rel_l2", "split", "state_errors", "assert_state_close", "oracle_states", "oracle_apply", "oracle_abs_apply", "oracle_propagate",
            "oracle_initial", "oracle_mgrit_history", "combine", "index_set", "solve"]

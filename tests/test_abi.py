@@ -130,3 +130,34 @@ def test_shape_entry_points_reject_null_plan():
     rep = ctm.TuneReport()
     assert lib.ctm_autotune(None, None, 0, None, 0, 1, ctypes.byref(rep), None) == 1
     assert "NULL" in lib.ctm_last_error().decode()
+
+
+def test_stats_struct_layout_matches_c(tmp_path):
+    fields = [f for f, _ in ctm.Stats._fields_]
+    src = tmp_path / "stats.c"
+    body = "\n".join(f'  printf("{f} %zu\\n", offsetof(ctm_stats, {f}));' for f in fields)
+    src.write_text(f'#include <stdio.h>\n#include <stddef.h>\n#include "ctm.h"\n'
+                   f'int main(void) {{\n{body}\n  printf("size %zu\\n", sizeof(ctm_stats));\n'
+                   f'  return 0;\n}}\n')
+    exe = tmp_path / "stats"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict(line.split() for line in out.splitlines())
+    for f in fields:
+        assert int(got[f]) == getattr(ctm.Stats, f).offset, f
+    assert int(got["size"]) == ctypes.sizeof(ctm.Stats)
+
+
+@pytest.mark.parametrize("make_bad,err", [
+    (lambda torch: [0.0] * 8, TypeError),
+    (lambda torch: torch.zeros(8, dtype=torch.float32), TypeError),
+    (lambda torch: torch.zeros(8, dtype=torch.float64), ValueError),          # host memory
+])
+def test_device_vector_guard_rejects_bad_inputs(make_bad, err):
+    # every tensor handed to the library goes through this guard before its
+    # raw pointer reaches a kernel; on the host the checks run up to the
+    # device test
+    import torch
+    with pytest.raises(err):
+        ctm._device_vec(make_bad(torch), 8, "x")

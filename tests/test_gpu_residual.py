@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 from paper_2509_22156_amd import ctm  # noqa: E402
 from workloads import make  # noqa: E402
 
-from helpers import rel_l2, solve  # noqa: E402
+from helpers import assert_state_close, rel_l2, solve  # noqa: E402
 
 
 def _say(msg):
@@ -49,7 +49,7 @@ def test_residual_mode_reaches_sequential_solution(name, relax):
     # two Krylov iterations per step: the work per solve is bounded
     assert st["krylov_max"] <= p["krylov_maxit"]
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-11, rel_l2(u, ref)
+    assert_state_close(p, u, ref, 1e-11)
 
 
 @pytest.mark.parametrize("name", ["heat3d", "ou4d", "fp_lin4d"])
@@ -65,7 +65,7 @@ def test_residual_mode_mixed_precision(name):
     st = plan.stats()
     assert st["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-8, rel_l2(u, ref)
+    assert_state_close(p, u, ref, 1e-8)
 
 
 def test_residual_mode_paper_settings_oscillator():
@@ -103,7 +103,7 @@ def test_residual_mode_streaming_grids(relax):
     assert any(s["K"] == 0 for s in st["shapes"])
     assert st["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-11, rel_l2(u, ref)
+    assert_state_close(p, u, ref, 1e-11)
 
 
 @pytest.mark.parametrize("tol,bar", [(1e-10, 1e-9), (1e-4, 1e-3)])

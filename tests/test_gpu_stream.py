@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 from paper_2509_22156_amd import ctm  # noqa: E402
 from workloads import make, random_vectors  # noqa: E402
 
-from helpers import (combine, oracle_abs_apply, oracle_apply, oracle_mgrit_history,  # noqa: E402
+from helpers import (assert_state_close, combine, oracle_abs_apply, oracle_apply, oracle_mgrit_history,  # noqa: E402
                      oracle_propagate, rel_l2, solve, split)
 
 
@@ -78,7 +78,7 @@ def test_streaming_solve_fp64(kw):
     u = plan.solve().cpu().numpy()
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-11
+    assert_state_close(p, u, ref, 1e-11)
 
 
 @pytest.mark.parametrize("relax", ["FCF", "F"])
@@ -104,7 +104,7 @@ def test_streaming_solve_mixed():
     u = plan.solve().cpu().numpy()
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-8
+    assert_state_close(p, u, ref, 1e-8)
 
 
 @pytest.mark.parametrize("name,kw", [("ou4d", dict(d=2, n=10, nsteps=16, t1=0.1)),
@@ -120,7 +120,7 @@ def test_streaming_other_operators(name, kw):
     assert plan.stats()["status_flags"] == 0
     assert any(s["K"] == 0 for s in plan.stats()["shapes"])
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-11
+    assert_state_close(p, u, ref, 1e-11)
 
 
 @pytest.mark.parametrize("kw", [dict(mgrit_levels=1), dict(), dict(krylov="bicgstab"),
@@ -140,9 +140,9 @@ def test_streaming_wide_against_narrow(kw):
         assert st["status_flags"] == 0
         assert st["krylov_iterations"] > 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(out[0], ref) <= 1e-11
-    assert rel_l2(out[ALL], ref) <= 1e-11
-    assert rel_l2(out[ALL], out[0]) <= 1e-11
+    assert_state_close(p, out[0], ref, 1e-11)
+    assert_state_close(p, out[ALL], ref, 1e-11)
+    assert_state_close(p, out[ALL], out[0], 1e-11)
 
 
 def test_streaming_wide_drift_oscillator():
@@ -155,7 +155,7 @@ def test_streaming_wide_drift_oscillator():
     u = plan.solve().cpu().numpy()
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-11
+    assert_state_close(p, u, ref, 1e-11)
 
 
 def test_streaming_wide_noconv_flag():
@@ -187,7 +187,7 @@ def test_streaming_three_dimensional(kw):
         st = plan.stats()
         assert st["status_flags"] == 0
         assert any(s["K"] == 0 for s in st["shapes"])
-        assert rel_l2(u, ref) <= 1e-11, wide
+        assert_state_close(p, u, ref, 1e-11)
 
 
 @pytest.mark.parametrize("krylov", ["cg", "bicgstab"])
@@ -205,8 +205,8 @@ def test_streaming_wide_many_tasks(krylov):
         plan.set_wide(wide)
         out[wide] = plan.solve().cpu().numpy()
         assert plan.stats()["status_flags"] == 0
-        assert rel_l2(out[wide], ref) <= 1e-11, wide
-    assert rel_l2(out[ALL], out[0]) <= 1e-11
+        assert_state_close(p, out[wide], ref, 1e-11)
+    assert_state_close(p, out[ALL], out[0], 1e-11)
 
 
 @pytest.mark.parametrize("tight", [False, True])
@@ -227,7 +227,7 @@ def test_streaming_paper_size_oscillator(tight):
     u = plan.solve().cpu().numpy()
     assert plan.stats()["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= (1e-10 if tight else 5e-8)
+    assert_state_close(p, u, ref, (1e-10 if tight else 5e-8))
 
 
 @pytest.mark.parametrize("name,kw", [("varcoef6d", dict(d=2, n=10, nsteps=256, t1=0.01, cf=2)),
@@ -245,4 +245,4 @@ def test_streaming_many_tasks_with_tables(name, kw):
     assert plan.stats()["status_flags"] == 0
     assert any(s["K"] == 0 for s in plan.stats()["shapes"])
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-11
+    assert_state_close(p, u, ref, 1e-11)

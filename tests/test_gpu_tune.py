@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 from paper_2509_22156_amd import ctm  # noqa: E402
 from workloads import make, metric_settings  # noqa: E402
 
-from helpers import rel_l2, solve  # noqa: E402
+from helpers import assert_state_close, rel_l2, solve  # noqa: E402
 
 WAVES = (1, 2, 4, 8, 16)
 
@@ -73,7 +73,7 @@ def test_other_shapes_same_solution(name, prec):
     st = plan.stats()
     ref = solve.packed(solve.component_states(p))
     assert st["status_flags"] == 0
-    assert rel_l2(u, ref) <= (1e-11 if prec == "fp64" else 1e-8)
+    assert_state_close(p, u, ref, (1e-11 if prec == "fp64" else 1e-8))
 
 
 def test_set_grid_shape_rejects_invalid():
@@ -114,7 +114,7 @@ def test_autotune_keeps_parity(name):
     st = plan.stats()
     ref = solve.packed(solve.component_states(p))
     assert st["status_flags"] == 0
-    assert rel_l2(u, ref) <= 1e-8
+    assert_state_close(p, u, ref, 1e-8)
 
 
 def test_autotune_full_heat3d_measurement_settings():
@@ -130,4 +130,4 @@ def test_autotune_full_heat3d_measurement_settings():
     st = plan.stats()
     assert st["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
-    assert rel_l2(u, ref) <= 1e-8
+    assert_state_close(p, u, ref, 1e-8)

@@ -95,3 +95,30 @@ def test_discrete_density_moments_approach_exact():
         mean = (X * u[:, None]).sum(axis=0) * h * h / mass
         errs.append(np.abs(mean - m_ex).max())
     assert errs[2] < 0.7 * errs[1] < 0.49 * errs[0] and errs[2] < 0.05, errs
+
+
+def test_density_closed_forms():
+    # the Gaussian density: its peak value is 1/sqrt((2 pi)^d det C); with a
+    # diagonal covariance it is the product of the 1-D normal densities
+    # (scipy.stats.norm, an independent routine); it integrates to one and
+    # reproduces its mean and covariance under quadrature
+    from scipy.stats import norm
+    mean = np.array([0.7, -1.3])
+    cov = np.array([[0.5, 0.2], [0.2, 0.3]])
+    peak = sde.density(mean[None, :], mean, cov)[0]
+    assert peak == pytest.approx(1.0 / np.sqrt((2 * np.pi) ** 2 * np.linalg.det(cov)), rel=1e-14)
+    diag = np.diag([0.4, 0.9])
+    X = np.random.default_rng(5).normal(size=(50, 2))
+    want = norm.pdf(X[:, 0], mean[0], np.sqrt(0.4)) * norm.pdf(X[:, 1], mean[1], np.sqrt(0.9))
+    np.testing.assert_allclose(sde.density(X, mean, diag), want, rtol=1e-13)
+    h = 0.02
+    g0 = np.arange(mean[0] - 8, mean[0] + 8, h)
+    g1 = np.arange(mean[1] - 8, mean[1] + 8, h)
+    G = np.stack(np.meshgrid(g0, g1, indexing="ij"), axis=-1).reshape(-1, 2)
+    w = sde.density(G, mean, cov) * h * h
+    assert w.sum() == pytest.approx(1.0, abs=1e-10)
+    m = (G * w[:, None]).sum(axis=0)
+    np.testing.assert_allclose(m, mean, atol=1e-9)
+    Z = G - m
+    c = (Z[:, :, None] * Z[:, None, :] * w[:, None, None]).sum(axis=0)
+    np.testing.assert_allclose(c, cov, atol=1e-9)

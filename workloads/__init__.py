@@ -236,18 +236,32 @@ def retabulate(p: dict, seed: int = 0) -> dict:
     return p
 
 
-def metric_settings(prec: str) -> dict:
-    """Solver tolerances of the throughput measurement: the final state
-    within 1e-8 relative L2 of the FP64 oracle. Mixed: FP64-refined implicit
-    steps to 1e-10 relative residual around FP32 inner solves to 1e-6; FP64:
-    Krylov to 1e-10. Both: MGRIT C-point residual to 1e-9, and the implicit
-    steps of the coarse MGRIT levels to 1e-3 (they only steer the
-    correction, the fixed point is the fine-level one)."""
+# Workloads whose measurement needs tighter solver tolerances: in six
+# dimensions the combination sums 1,709 grids with coefficients up to 10 in
+# magnitude (sum of |c| = 7,183), so an error in the component states grows
+# by about two orders of magnitude in the combined solution at the gather
+# points, and the states must be solved well below 1e-10 for the gather to
+# stay within 1e-8 of the oracle.
+_TIGHT = {"varcoef6d": dict(tol=1e-12, mgrit_tol=1e-13)}
+
+
+def metric_settings(prec: str, name: str | None = None) -> dict:
+    """Solver tolerances of the throughput measurement: the final state and
+    the combination at the gather points within 1e-8 relative L2 of the FP64
+    oracle. Mixed: FP64-refined implicit steps to 1e-10 relative residual
+    around FP32 inner solves to 1e-6; FP64: Krylov to 1e-10. Both: MGRIT
+    C-point residual to 1e-9, and the implicit steps of the coarse MGRIT
+    levels to 1e-3 (they only steer the correction, the fixed point is the
+    fine-level one). The 6-D workload (`name`) solves its fine steps to
+    1e-12 and MGRIT to 1e-13 (see _TIGHT)."""
+    tight = _TIGHT.get(name, {})
+    tol = tight.get("tol", 1e-10)
+    mtol = tight.get("mgrit_tol", 1e-9)
     if prec == "mixed":
-        return dict(prec="mixed", refine_tol=1e-10, inner_tol=1e-6, refine_maxit=12,
-                    mgrit_tol=1e-9, krylov_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64,
+        return dict(prec="mixed", refine_tol=tol, inner_tol=1e-6, refine_maxit=12,
+                    mgrit_tol=mtol, krylov_tol=1e-13, krylov_maxit=20000, mgrit_maxit=64,
                     coarse_tol=1e-3)
-    return dict(prec="fp64", krylov_tol=1e-10, mgrit_tol=1e-9, krylov_maxit=20000,
+    return dict(prec="fp64", krylov_tol=tol, mgrit_tol=mtol, krylov_maxit=20000,
                 mgrit_maxit=64, coarse_tol=1e-3)
 
 
