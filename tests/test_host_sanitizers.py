@@ -19,7 +19,10 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
-FLAGS = ["-std=c++17", "-D__HIP_PLATFORM_AMD__", "-Wno-unused-result", "-g", "-O1",
+# the host compiler builds the file's host side only: the two HIP spellings
+# that only the HIP compiler knows get their host meaning
+FLAGS = ["-std=c++17", "-D__HIP_PLATFORM_AMD__", "-D__align__(n)=__attribute__((aligned(n)))",
+         "-DHIP_SYMBOL(x)=(&(x))", "-Wno-unused-result", "-g", "-O1",
          "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
          "-fno-sanitize-recover=undefined", "-I", os.path.join(ROCM, "include"),
          "-I", os.path.join(ROOT, "include"),
@@ -46,7 +49,9 @@ def _build(tmp_path):
 
 
 def _run(exe):
+    supp = os.path.join(ROOT, "tests", "asan", "lsan.supp")
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               LSAN_OPTIONS=f"suppressions={supp}:print_suppressions=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
     print(r.stdout[-4000:])
