@@ -239,6 +239,27 @@ ctm_status ctm_propagate(ctm_plan* plan, int level, long long nsteps, const doub
 ctm_status ctm_solve(ctm_plan* plan, void* ws, size_t ws_bytes, const double* u0,
                      double* u_final, ctm_stream s);
 
+/* Size of the workspace ctm_solve_noalloc uses: a static array in the
+ * library's device code, held by every device the library runs on until the
+ * process ends (256 MiB). */
+#define CTM_NOALLOC_WORKSPACE_BYTES (256ull << 20)
+
+/* ctm_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid hipMalloc): the same method and kernels, on the library's static
+ * workspace instead of a caller buffer, with no hipMalloc, hipFree, stream or
+ * event creation inside the call. Requirements, each checked (CTM_ERR_INVALID
+ * with a message otherwise): ctm_plan_workspace_bytes(plan) <=
+ * CTM_NOALLOC_WORKSPACE_BYTES; the plan's device is current; its launch tables
+ * exist -- they are built by ctm_plan_create and by every ctm_solve, and
+ * ctm_plan_set_grid_shape / ctm_autotune discard them until the next
+ * ctm_solve. u0, u_final and s as for ctm_solve; ctm_set_timing is ignored
+ * (no per-launch events). Every call on one device shares the one workspace:
+ * calls that overlap on a device (other streams or host threads) race. The
+ * workspace keeps the last call's contents; the solve initialises everything
+ * it reads. Synchronises s. */
+ctm_status ctm_solve_noalloc(ctm_plan* plan, const double* u0, double* u_final, ctm_stream s);
+
 /* Combination at arbitrary points (Section 2.1.1): out[j] = sum_g coef_g
  * (I_g u_g)(pts[j]), I_g the d-linear interpolant on grid g with zero
  * boundary values; pts is device [npts][d] row-major. Async. */

@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -815,9 +816,11 @@ void reset_stats(ctm_plan* P) {
   P->events_used = 0;
 }
 
+// (a fill kernel rather than hipMemsetAsync: the counters are 8-byte words,
+// and all-zero bits are a zero of either type)
 ctm_status reset_device_stats(ctm_plan* P, hipStream_t s) {
-  CTM_HIP(hipMemsetAsync(P->dcounters, 0, kStatSlots * CNT_N * sizeof(unsigned long long), s));
-  CTM_HIP(hipMemsetAsync(P->dsync, 0, 2 * sizeof(double), s));
+  CTM_HIP(launch_fill_zero(reinterpret_cast<double*>(P->dcounters), (long long)kStatSlots * CNT_N, s));
+  CTM_HIP(launch_fill_zero(P->dsync, 2, s));
   return CTM_OK;
 }
 
@@ -1316,6 +1319,131 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   return fail(CTM_ERR_NOCONV, "MGRIT reached mgrit_maxit");
 }
 
+// ------------------------------------------------ allocation-free solve
+// The workspace of ctm_solve_noalloc: one array in the library's device
+// code, CTM_NOALLOC_WORKSPACE_BYTES long, held by every device the library
+// runs on until the process ends. Host code never passes its name to a
+// kernel or copy (on the host the name is only a stand-in); it uses the
+// device address hipGetSymbolAddress returns, one per device, looked up once
+// with that device current.
+static __device__ __align__(256) unsigned char scratch[CTM_NOALLOC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the array on device dev (the current device), looked up
+// on first use; nullptr if the lookup fails.
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Task sets a solve launches: the level-0 intervals, the intervals of every
+// intermediate MGRIT level, and one task per grid.
+std::vector<long long> solve_task_counts(const ctm_plan* P) {
+  const ctm_problem& p = P->prob;
+  std::vector<long long> m{1};
+  if (p.mgrit_levels > 1) {
+    long long n = p.nsteps / p.nrecomb;
+    for (int l = 0; l < p.mgrit_levels - 1; ++l) {
+      m.push_back(n / p.mgrit_cf);
+      n /= p.mgrit_cf;
+    }
+  }
+  return m;
+}
+
+constexpr size_t kSyncEvents = 4;  // fork/join events one phase uses at most
+
+// Builds what ctm_solve otherwise creates on first use: the task sets, the
+// side streams, the fork/join and per-iteration events, and the node map of
+// the hierarchical basis when there are recombination steps.
+ctm_status prepare_solve(ctm_plan* P) {
+  ctm_status st;
+  for (long long M : solve_task_counts(P)) {
+    TaskSet* ts = nullptr;
+    if ((st = tasks_for(P, M, &ts)) != CTM_OK) return st;
+  }
+  for (int l = 1; l <= ctm_plan::kSideStreams; ++l) {
+    hipStream_t cs = nullptr;
+    if ((st = lane_stream(P, l, nullptr, &cs)) != CTM_OK) return st;
+  }
+  size_t used = 0;
+  while (P->sync_events.size() < kSyncEvents)
+    if (!take_event(P, used, P->sync_events, false)) return fail(CTM_ERR_HIP, "event creation failed");
+  while ((int)P->it_events.size() <= P->prob.mgrit_maxit) {
+    hipEvent_t e = nullptr;
+    CTM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    P->it_events.push_back(e);
+  }
+  if (P->prob.nrecomb > 1 && (st = ensure_hier(P)) != CTM_OK) return st;
+  return CTM_OK;
+}
+
+// Whether a solve would find everything prepare_solve builds.
+bool solve_prepared(const ctm_plan* P) {
+  for (long long M : solve_task_counts(P))
+    if (!P->tsets.count(M)) return false;
+  for (auto s : P->cstreams)
+    if (!s) return false;
+  if (P->sync_events.size() < kSyncEvents) return false;
+  if ((int)P->it_events.size() <= P->prob.mgrit_maxit) return false;
+  if (P->prob.nrecomb > 1 && !P->dhnode) return false;
+  return true;
+}
+
+// The problem's initial value on every grid.
+hipError_t initial_state(ctm_plan* P, double* u0, hipStream_t s) {
+  if (P->prob.manufactured == CTM_MMS_HEAT)
+    return launch_mms_initial(P->dgrids, P->G, P->maxpts, P->prob.t0, u0, s);
+  return launch_initial_state(P->dgrids, P->G, P->maxpts, P->n, (int)P->icw.size(), P->dicw,
+                              P->dicf, u0, s);
+}
+
+// The body of ctm_solve on a given workspace.
+ctm_status solve_on(ctm_plan* P, void* ws, size_t ws_bytes, const double* u0, double* u_final,
+                    hipStream_t hs) {
+  Layout lay = make_layout(P, static_cast<char*>(ws));
+  if (ws_bytes < lay.bytes) return fail(CTM_ERR_NOMEM, "workspace smaller than ctm_plan_workspace_bytes");
+  reset_stats(P);
+  ctm_status st = reset_device_stats(P, hs);
+  if (st != CTM_OK) return st;
+  if (u0) {
+    CTM_HIP(hipMemcpyAsync(lay.X, u0, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  } else {
+    CTM_HIP(initial_state(P, lay.X, hs));
+  }
+  ctm_status result = CTM_OK;
+  const double dt0 = (P->prob.t1 - P->prob.t0) / (double)P->prob.nsteps;
+  const long long Nb = P->prob.nsteps / P->prob.nrecomb;
+  for (int b = 0; b < P->prob.nrecomb; ++b) {
+    if (b > 0 && (st = recombine(P, lay.Y, lay.X, hs)) != CTM_OK) return st;
+    P->block_t0 = P->prob.t0 + (double)(b * Nb) * dt0;
+    st = mgrit_block(P, lay, hs);
+    // the caller's stream waits for the side lanes whatever happened (an
+    // error can leave a phase running on them)
+    const ctm_status js = join_lanes(P, hs);
+    if (st == CTM_OK && js != CTM_OK) st = js;
+    P->stats.blocks += 1;
+    if (st == CTM_ERR_NOCONV) {
+      result = st;
+    } else if (st != CTM_OK) {
+      return st;
+    }
+  }
+  P->block_t0 = P->prob.t0;
+  CTM_HIP(hipMemcpyAsync(u_final, lay.Y, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  if ((st = collect_device_stats(P, hs)) != CTM_OK) return st;
+  if (result != CTM_OK) return result;
+  return status_from_flags(P->stats.status_flags);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1610,6 +1738,11 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   CTM_HIPC(hipMemcpy(P->didentity, ident.data(), P->G * sizeof(int2), hipMemcpyHostToDevice));
 #undef CTM_HIPC
   reset_stats(P);
+  if ((st = prepare_solve(P)) != CTM_OK) {
+    delete P;
+    return st;
+  }
+  scratch_address(P->device);  // set-up of the allocation-free entry point
   *out = P;
   return CTM_OK;
 }
@@ -1647,13 +1780,6 @@ ctm_status ctm_plan_workspace_bytes(const ctm_plan* P, size_t* bytes) {
   return CTM_OK;
 }
 
-// The problem's initial value on every grid.
-hipError_t initial_state(ctm_plan* P, double* u0, hipStream_t s) {
-  if (P->prob.manufactured == CTM_MMS_HEAT)
-    return launch_mms_initial(P->dgrids, P->G, P->maxpts, P->prob.t0, u0, s);
-  return launch_initial_state(P->dgrids, P->G, P->maxpts, P->n, (int)P->icw.size(), P->dicw,
-                              P->dicf, u0, s);
-}
 
 ctm_status ctm_initial_state(ctm_plan* P, double* u0, ctm_stream s) {
   if (!P || !u0) return fail(CTM_ERR_INVALID, "NULL argument");
@@ -1709,40 +1835,33 @@ ctm_status ctm_propagate(ctm_plan* P, int level, long long nsteps, const double*
 ctm_status ctm_solve(ctm_plan* P, void* ws, size_t ws_bytes, const double* u0, double* u_final,
                      ctm_stream s) {
   if (!P || !ws || !u_final) return fail(CTM_ERR_INVALID, "NULL argument");
-  Layout lay = make_layout(P, static_cast<char*>(ws));
-  if (ws_bytes < lay.bytes) return fail(CTM_ERR_NOMEM, "workspace smaller than ctm_plan_workspace_bytes");
-  hipStream_t hs = (hipStream_t)s;
-  reset_stats(P);
-  ctm_status st = reset_device_stats(P, hs);
-  if (st != CTM_OK) return st;
-  if (u0) {
-    CTM_HIP(hipMemcpyAsync(lay.X, u0, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
-  } else {
-    CTM_HIP(initial_state(P, lay.X, hs));
-  }
-  ctm_status result = CTM_OK;
-  const double dt0 = (P->prob.t1 - P->prob.t0) / (double)P->prob.nsteps;
-  const long long Nb = P->prob.nsteps / P->prob.nrecomb;
-  for (int b = 0; b < P->prob.nrecomb; ++b) {
-    if (b > 0 && (st = recombine(P, lay.Y, lay.X, hs)) != CTM_OK) return st;
-    P->block_t0 = P->prob.t0 + (double)(b * Nb) * dt0;
-    st = mgrit_block(P, lay, hs);
-    // the caller's stream waits for the side lanes whatever happened (an
-    // error can leave a phase running on them)
-    const ctm_status js = join_lanes(P, hs);
-    if (st == CTM_OK && js != CTM_OK) st = js;
-    P->stats.blocks += 1;
-    if (st == CTM_ERR_NOCONV) {
-      result = st;
-    } else if (st != CTM_OK) {
-      return st;
-    }
-  }
-  P->block_t0 = P->prob.t0;
-  CTM_HIP(hipMemcpyAsync(u_final, lay.Y, P->slen * sizeof(double), hipMemcpyDeviceToDevice, hs));
-  if ((st = collect_device_stats(P, hs)) != CTM_OK) return st;
-  if (result != CTM_OK) return result;
-  return status_from_flags(P->stats.status_flags);
+  return solve_on(P, ws, ws_bytes, u0, u_final, (hipStream_t)s);
+}
+
+ctm_status ctm_solve_noalloc(ctm_plan* P, const double* u0, double* u_final, ctm_stream s) {
+  if (!P || !u_final) return fail(CTM_ERR_INVALID, "NULL argument");
+  const size_t need = make_layout(P, nullptr).bytes;
+  if (need > (size_t)CTM_NOALLOC_WORKSPACE_BYTES)
+    return fail(CTM_ERR_INVALID, "the plan's workspace (" + std::to_string(need) +
+                                     " bytes) exceeds the library's static one (" +
+                                     std::to_string((size_t)CTM_NOALLOC_WORKSPACE_BYTES) + " bytes)");
+  if (!solve_prepared(P))
+    return fail(CTM_ERR_INVALID,
+                "the plan's launch tables changed since its last allocating call "
+                "(ctm_plan_set_grid_shape, ctm_autotune): call ctm_solve once first");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != P->device)
+    return fail(CTM_ERR_INVALID, "the plan's device is not the current device");
+  void* ws = scratch_address(P->device);
+  if (!ws) return fail(CTM_ERR_HIP, "the static workspace has no device address on this device");
+  // per-launch timing would create events: off for this call
+  struct TimingOff {
+    ctm_plan* P;
+    bool was;
+    ~TimingOff() { P->timing = was; }
+  } timing_off{P, P->timing};
+  P->timing = false;
+  return solve_on(P, ws, need, u0, u_final, (hipStream_t)s);
 }
 
 ctm_status ctm_gather(ctm_plan* P, const double* u, const double* pts, long long npts, double* out,

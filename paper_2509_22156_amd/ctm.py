@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libctm.so")
 
 MAXD = 8
 MAX_HISTORY = 256
+NOALLOC_WORKSPACE_BYTES = 256 << 20  # CTM_NOALLOC_WORKSPACE_BYTES of ctm.h
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE = range(7)
 _OPS = {"heat": 0, "varcoef": 1, "ou": 2, "cme": 3, "drift": 4}
@@ -96,6 +97,7 @@ def _load():
         "ctm_apply": [P, i, P, P, P],
         "ctm_propagate": [P, i, ll, P, P, i, P],
         "ctm_solve": [P, P, sz, P, P, P],
+        "ctm_solve_noalloc": [P, P, P, P],
         "ctm_gather": [P, P, P, ll, P, P],
         "ctm_combine_project": [P, P, P, P],
         "ctm_hierarchize": [P, P, P, i, P],
@@ -289,6 +291,18 @@ class Plan:
             return out
         return out, st
 
+    def solve_noalloc(self, u0=None, out=None, check: bool = True):
+        """The whole method on the library's static workspace
+        (ctm_solve_noalloc): no device allocation inside the call."""
+        if u0 is not None:
+            self._inp(u0, "u0")
+        out = self._vec(out)
+        st = _lib.ctm_solve_noalloc(self._h, _ptr(u0), _ptr(out), _stream())
+        if check:
+            _check(st)
+            return out
+        return out, st
+
     def gather(self, u, pts, out=None):
         self._inp(u, "u")
         if pts.dim() != 2 or pts.shape[1] != self.prob["d"]:
@@ -366,7 +380,8 @@ def exported_symbols():
     """Names of the entry points declared in include/ctm.h."""
     return ["ctm_problem_defaults", "ctm_plan_create", "ctm_plan_destroy", "ctm_plan_grids",
             "ctm_plan_grid_info", "ctm_plan_state_len", "ctm_plan_workspace_bytes",
-            "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_gather",
+            "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_solve_noalloc",
+            "ctm_gather",
             "ctm_combine_project", "ctm_hierarchize", "ctm_recombine", "ctm_get_stats", "ctm_set_timing", "ctm_plan_grid_shape",
             "ctm_plan_set_grid_shape", "ctm_plan_set_wide", "ctm_autotune", "ctm_status_string",
             "ctm_last_error"]
