@@ -101,9 +101,10 @@ def flops_per_iteration(d: int, krylov: str) -> int:
 
 
 def measured_traffic(workload: str, cls_key: str):
-    """Calibrated HBM bytes per launch of a chain-kernel size class from the
-    committed hardware-counter runs of this workload, or None once the
-    kernel sources differ from the ones the counters were taken on."""
+    """Calibrated HBM bytes per launch of a chain-kernel size class and
+    precision ("W4K4/mixed") from the committed hardware-counter runs of this
+    workload, or None once the kernel sources differ from the ones the
+    counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "chain_kernel_traffic.json")
     if not os.path.exists(path):
@@ -456,7 +457,10 @@ def _roofline(shapes, d, krylov, prec, copy_gbps):
     kernel with the most device time. Its algorithmic HBM bytes are 16 B per
     unknown and implicit step (read the previous state, write the new one);
     the FP32/FP64 flops of its Krylov iterations are reported beside."""
-    (dw, dk), dom = max(shapes.items(), key=lambda kv: kv[1]["ms"])
+    # on-chip size classes only (K > 0): not the streaming solvers, nor the
+    # FP64 coarse-level launches of a mixed plan, which are reported apart
+    (dw, dk), dom = max(((k, v) for k, v in shapes.items() if k[1] > 0),
+                        key=lambda kv: kv[1]["ms"])
     dom_s = dom["ms"] / 1e3
     nl = max(dom["launches"], 1)
     alg_bytes = STEP_BYTES_PER_DOF * dom["dofsteps"]
@@ -487,8 +491,72 @@ def _roofline(shapes, d, krylov, prec, copy_gbps):
                          "note": "vector peak; the on-chip Krylov iteration is bound by "
                                  "latency (occupancy, barriers, reductions)"},
         "copy_GBps": copy_gbps,
-        "all_classes": {f"W{w}K{k}": v for (w, k), v in sorted(shapes.items())},
+        "all_classes": {("fp64_coarse_levels" if (w, k) == (0, 0) else f"W{w}K{k}"): v
+                        for (w, k), v in sorted(shapes.items())},
     }
+
+
+def summarize_traffic(workload: str, fetch_dir: str, write_dir: str, out_path: str):
+    """Calibrated HBM bytes per launch of every chain-kernel size class from
+    two rocprofv3 counter runs of `bench.py --copy-calibration` (FETCH_SIZE,
+    then WRITE_SIZE; KiB per dispatch). The run ends with a plain copy of a
+    known size, which gives the factor from each counter to bytes. Writes the
+    record `measured_traffic` reads, keyed by the kernel sources' hash."""
+    import csv
+    import hashlib
+    import re
+    sources = ["paper_2509_22156_amd/csrc/chain_kernel.hpp",
+               "paper_2509_22156_amd/csrc/line_layout.hpp",
+               "paper_2509_22156_amd/csrc/device_common.hpp",
+               "paper_2509_22156_amd/csrc/ctm_internal.h"]
+    copy_bytes = 32 * 2 ** 20 * 8
+
+    def per_dispatch(d, counter):
+        rows = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] != counter:
+                continue
+            key = int(r["Dispatch_Id"])
+            rows.setdefault(key, [r["Kernel_Name"], 0.0])
+            rows[key][1] += float(r["Counter_Value"])
+        return [rows[k] for k in sorted(rows)]
+
+    def classes(rows):
+        acc = {}
+        for name, kib in rows:
+            m = re.search(r"chain_kernel<\d+, \d+, (true|false), \d+, (\d+), (\d+)>", name)
+            if m:
+                prec = "mixed" if m.group(1) == "true" else "fp64"
+                a = acc.setdefault(f"W{m.group(2)}K{m.group(3)}/{prec}", [0.0, 0])
+                a[0] += kib
+                a[1] += 1
+        return acc
+
+    def copy_kib(rows):
+        # the calibration copy is the last dispatch of the run
+        return rows[-1][1]
+    fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = per_dispatch(write_dir, "WRITE_SIZE")
+    rf = copy_bytes / (copy_kib(fetch) * 1024.0)
+    wf = copy_bytes / (copy_kib(write) * 1024.0)
+    cf, cw = classes(fetch), classes(write)
+    rec_classes = {}
+    for k in sorted(cf):
+        n = cf[k][1]
+        rec_classes[k] = {"dispatches": n,
+                          "fetch_kib_per_launch": cf[k][0] / n,
+                          "write_kib_per_launch": cw[k][0] / cw[k][1],
+                          "bytes_per_launch": (cf[k][0] / n * rf + cw[k][0] / cw[k][1] * wf) * 1024.0}
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    rec = {"workload": workload, "source_sha256": h.hexdigest(), "sources": sources,
+           "read_factor": rf, "write_factor": wf, "copy_bytes": copy_bytes,
+           "classes": rec_classes}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
 
 
 def main(argv=None):
@@ -513,7 +581,17 @@ def main(argv=None):
                     help="take the launch shapes from this JSON file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 256 MiB device copy (hardware-counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="instead of the metric: summarise two rocprofv3 counter runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of --copy-calibration into "
+                         "profiles/chain_kernel_traffic.json")
     args = ap.parse_args(argv)
+
+    if args.traffic_from:
+        rec = summarize_traffic(args.workload, *args.traffic_from,
+                                os.path.join(ROOT, "profiles", "chain_kernel_traffic.json"))
+        print(json.dumps(rec))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -590,7 +668,7 @@ def main(argv=None):
     value = dof_steps / (elapsed / args.steps)
     copy_gbps = copy_bandwidth(torch)  # measured after the timed steps
     (dw, dk), roofline = _roofline(shapes, prob["d"], prob["krylov"], prob["prec"], copy_gbps)
-    roofline["traffic"] = measured_traffic(args.workload, f"W{dw}K{dk}")
+    roofline["traffic"] = measured_traffic(args.workload, f"W{dw}K{dk}/{prob['prec']}")
     u_mixed = u.cpu().numpy()
     vals_mixed = vals.cpu().numpy()
     log(f"mixed MGRIT: {ms_per_step:.2f} ms/step, {value:.3e} DoF*steps/s, dominant W{dw}K{dk} "

@@ -171,7 +171,10 @@ typedef struct {
      work-group, unknowns per lane, timed duration, launches, Krylov work.
      Grids on the streaming solver report unknowns per lane 0, with 16 waves
      (one 1,024-thread work-group per task) or 4 (the wide solver, many
-     256-thread work-groups per task; a launch is its whole chain) */
+     256-thread work-groups per task; a launch is its whole chain). In a
+     mixed plan the on-chip launches that run in FP64 (the coarse MGRIT
+     levels of the operators with per-line coefficients) are reported
+     together with 0 waves and 0 unknowns per lane. */
   int shape_w[16], shape_k[16];
   double shape_ms[16];
   long long shape_launches[16];

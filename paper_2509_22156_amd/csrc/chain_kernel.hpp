@@ -359,6 +359,9 @@ __device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
 
 // One implicit step as a single FP32 solve from zero (mixed path, loose
 // coarse-level tolerance): x <- (I + dt L)^-1 v to relative tolerance itol.
+// (Starting from the state one step earlier instead cut the FP32 Krylov
+// iterations of the 6-D workload by a quarter but raised its MGRIT
+// iterations from 11 to 15: the coarse corrections were worse.)
 template <int OPC, int SOLVER, int W, int K>
 __device__ __forceinline__ void step_single32(const Solver<OPC, float, K>& S32, RedRing& ring,
                                               const double (&v)[K], float itol2, int maxit,
@@ -464,6 +467,23 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
   double res_max = 0.0;  // residual mode: largest squared residual of the task's steps
 
+  // initial guess of step j: the given one (a previous iterate at this time
+  // point: guess for j < nsteps, guess_fin for the last step), else the state
+  // one step earlier. The FP64 kernels of the operators with per-line
+  // coefficients load given guesses one step ahead, so that their memory
+  // latency hides behind the solve of the step before (measured: 6% off the
+  // 6-D FP64 solve; the heat and mixed kernels lose a wave of occupancy to
+  // the extra registers, or gain nothing, and load at the step).
+  constexpr bool kPrefetch = !MIXED && OPC != OPC_HEAT;
+  auto guess_of = [&](int j) -> const VecRef& { return j == a.nsteps ? a.guess_fin : a.guess; };
+  auto guess_at = [&](int j) {
+    const VecRef& r = guess_of(j);
+    return vec_at(r, r.a * q + r.b + (j == a.nsteps ? 0 : j), a.slen, off);
+  };
+  double gnext[K];
+  if constexpr (kPrefetch) {
+    if (guess_of(1).base) gload<K>(L, guess_at(1), gnext);
+  }
   for (int j = 1; j <= a.nsteps; ++j) {
     // heat (few registers in use): the forcing of this step is loaded
     // before the solve, so that its latency hides behind it
@@ -471,16 +491,22 @@ __global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) 
     double f[K];
     if (kEarly && a.forcing.base)
       gload<K>(L, vec_at(a.forcing, a.forcing.a * q + a.forcing.b + j, a.slen, off), f);
-    // initial guess: the given one (a previous iterate at this time point),
-    // else the state one step earlier
     double x[K];
     const bool last = (j == a.nsteps);
-    const VecRef gr = last ? a.guess_fin : a.guess;
+    const VecRef& gr = guess_of(j);
     if (gr.base) {
-      gload<K>(L, vec_at(gr, gr.a * q + gr.b + (last ? 0 : j), a.slen, off), x);
+      if constexpr (kPrefetch) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = gnext[k];
+      } else {
+        gload<K>(L, guess_at(j), x);
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) x[k] = v[k];
+    }
+    if constexpr (kPrefetch) {
+      if (!last && guess_of(j + 1).base) gload<K>(L, guess_at(j + 1), gnext);
     }
     // manufactured heat problem: the step solves (I + dt L) x = v + dt f(t_j)
     if constexpr (FORCED) {

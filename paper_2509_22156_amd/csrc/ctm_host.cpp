@@ -535,17 +535,30 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false,
   return a;
 }
 
+// Whether the coarse MGRIT levels of a mixed plan run the FP64 kernels: for
+// the operators with per-line coefficients, whose mixed kernels hold both
+// precisions' coefficients and run one wave per SIMD against two for FP64,
+// when the coarse tolerance is loose (the coarse steps only steer the
+// correction; warm-started FP64 steps meet 1e-3 in about one iteration).
+// Measured on the 6-D workload: 1.46 -> 1.23 s per mixed solve, with 10
+// MGRIT iterations instead of 11; on the 3-D heat workload (low-register
+// kernels) the single FP32 coarse solves stay faster.
+bool coarse_in_fp64(const ctm_plan* P) {
+  return P->mixed && P->opc != OPC_HEAT && P->prob.coarse_tol >= 1e-5 && !P->prob.residual_mode;
+}
+
 // Arguments of a chain on MGRIT level l >= 1: the coarse tolerance, when set,
 // replaces the level-0 one. In the mixed path a tolerance that FP32 reaches
-// by itself (>= 1e-5) makes each coarse step a single FP32 solve; otherwise
-// the inner FP32 target follows it.
+// by itself (>= 1e-5) makes each coarse step a single FP32 solve (heat) or an
+// FP64 solve (coarse_in_fp64); otherwise the inner FP32 target follows it.
 ChainArgs coarse_args(ctm_plan* P, int level, int nsteps) {
-  ChainArgs a = base_args(P, level, nsteps, false, true);
+  const bool c64 = coarse_in_fp64(P);
+  ChainArgs a = base_args(P, level, nsteps, c64, true);
   const double ct = P->prob.coarse_tol;
   if (ct > 0 && !a.resmode) {
     a.tol = ct;
     a.inner_tol = std::max(P->prob.inner_tol, 0.25 * ct);
-    if (P->mixed && ct >= 1e-5) {
+    if (P->mixed && ct >= 1e-5 && !c64) {
       a.single32 = 1;
       a.inner_tol = ct;
     }
@@ -672,7 +685,10 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   c.tasks = tasks + offset;
   if (a.res2) c.res2 = a.res2 + offset;
   const bool wide = use_wide(P, shape, count);
-  const int slot = wide ? kWideSlot : shape;  // statistics slot
+  // statistics slot: the size class, the wide solver, or the FP64 launches
+  // of a mixed plan
+  const int slot = wide ? kWideSlot
+                        : (P->mixed && !mixed && shape != kStreamShape) ? kCoarse64Slot : shape;
   c.counters = P->dcounters + (size_t)slot * CNT_N;
   c.pcrmax = (shape == kStreamShape) ? 0 : P->pcr_of[shape];
   const size_t smem = (shape == kStreamShape)
@@ -840,7 +856,10 @@ void fold_counters(const ctm_plan* P, const unsigned long long* c, ctm_stats* st
     st->shape_dofsteps[s] = (long long)k[CNT_DOFSTEPS];
     // streaming: K = 0, and W = 16 (1,024 threads per task) or the wide
     // solver's kWW waves per work-group
-    st->shape_w[s] = (s == kStreamShape) ? 16 : (s == kWideSlot) ? kWW : kShapes[s].W;
+    st->shape_w[s] = (s == kStreamShape)   ? 16
+                     : (s == kWideSlot)    ? kWW
+                     : (s == kCoarse64Slot) ? 0
+                                            : kShapes[s].W;
     st->shape_k[s] = (s >= kStreamShape) ? 0 : kShapes[s].K;
   }
   (void)P;
@@ -981,7 +1000,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
     a.fin = vref(E, 0, lay.N[l]);
     TaskSet* single = nullptr;
     if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
-    return run_chain(P, a, *single, s, false, !open_last, !open_last);
+    return run_chain(P, a, *single, s, coarse_in_fp64(P), !open_last, !open_last);
   }
   const long long M = lay.N[l] / c;
   TaskSet* tasks = nullptr;
@@ -997,7 +1016,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
     fc.forcing = vref(G, c, 0);
     fc.inter = vref(E, c, 0);
     fc.fin = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fc, *tasks, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fc, *tasks, s, coarse_in_fp64(P))) != CTM_OK) return st;
     ChainArgs fr = coarse_args(P, l, (int)c);
     fr.start = vref(Cn, 1, 0);
     fr.start_wb = vref(E, c, 0);
@@ -1005,7 +1024,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s, coarse_in_fp64(P))) != CTM_OK) return st;
     csrc = Cn;
     ca = 1;
   } else {
@@ -1015,7 +1034,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(E, c, c);
-    if ((st = run_chain(P, fr, *tasks, s)) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s, coarse_in_fp64(P))) != CTM_OK) return st;
     csrc = E;
     ca = c;
   }
@@ -1028,7 +1047,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
   fi.forcing = vref(G, c, 0);
   fi.inter = vref(E, c, 0);
   fi.fin = vref(E, c, c - 1);
-  return run_chain(P, fi, *tasks, s);
+  return run_chain(P, fi, *tasks, s, coarse_in_fp64(P));
 }
 
 // Node map of the hierarchical basis: every unknown named by its node on

@@ -124,7 +124,10 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kStreamShape = kNumShapes;
 // Statistics slot of the wide streaming solver (after the size classes).
 constexpr int kWideSlot = kNumShapes + 1;
-constexpr int kStatSlots = kNumShapes + 2;
+// Statistics slot of the on-chip launches that run in FP64 inside a mixed
+// plan (its coarse MGRIT levels, all size classes together).
+constexpr int kCoarse64Slot = kNumShapes + 2;
+constexpr int kStatSlots = kNumShapes + 3;
 static_assert(kStatSlots <= 16, "ctm_stats keeps 16 shape slots");
 
 hipError_t launch_chain(int opc, int solver, bool mixed, int shape, const ChainArgs& a,

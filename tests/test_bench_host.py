@@ -78,7 +78,7 @@ def test_traffic_record_follows_its_sources():
     wl = rec["workload"]
     for cls, c in rec["classes"].items():
         assert bench.measured_traffic(wl, cls) == (c["bytes_per_launch"] if fresh else None)
-    assert bench.measured_traffic(wl, "W99K4") is None
+    assert bench.measured_traffic(wl, "W99K4/mixed") is None
     assert bench.measured_traffic("no-such-workload", next(iter(rec["classes"]))) is None
 
 
