@@ -74,9 +74,11 @@ typedef enum {
                          deaths -h at rate gamma_i x/h (Section 4.3) */
   CTM_OP_DRIFT = 4    /* Fokker-Planck of the linear SDE dX = theta X dt + sigma dW with a
                          full drift matrix (Section 4.4): L u = sum_i d_i((theta x)_i u)
-                         - 1/2 sum_i H_ii d_ii u, H diagonal; central diffusion and
-                         donor-cell fluxes with the face velocity (theta x)_i taken at the
-                         face (x_i shifted by -/+ h_i/2, the other coordinates at the node) */
+                         - 1/2 sum_i H_ii d_ii u, H diagonal; second-order finite
+                         differences (Section 4.4.1): central diffusion and central face
+                         fluxes w (u_j + u_{j+1})/2 with the face velocity w = (theta x)_i
+                         taken at the face (x_i shifted by -/+ h_i/2, the other coordinates
+                         at the node) */
 } ctm_op_kind;
 
 /* Manufactured-solution problems (Section 4.2): CTM_MMS_HEAT is the heat

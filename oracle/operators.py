@@ -23,10 +23,12 @@ Operator kinds (u_t + L u = 0 in all workloads):
   drift    Fokker-Planck operator of the linear SDE dX = theta X dt + sigma dW
            with a full drift matrix theta (Section 4.4): u_t = -sum_i
            d_i((theta x)_i u) + (1/2) sum_i H_ii d_ii u with H = 2 sigma D
-           sigma^T diagonal (as in both systems of Section 4.4). Same
-           discretisation as ou: central diffusion, donor-cell face fluxes
-           with the face velocity w = (theta x)_i taken at the face (x_i
-           shifted by -/+ h_i/2, the other coordinates at the node).
+           sigma^T diagonal (as in both systems of Section 4.4). Second-order
+           finite differences, as Section 4.4.1 states for these systems:
+           central diffusion, and the drift in conservative flux form with
+           central face fluxes F_{j+1/2} = w_{j+1/2} (u_j + u_{j+1}) / 2, the
+           face velocity w = (theta x)_i taken at the face (x_i shifted by
+           -/+ h_i/2, the other coordinates at the node).
   cme      master-equation generator of independent immigration-death
            species (Section 4.3, master equation with propensities k_i and
            gamma_i x_i) on the lattice embedding with node spacing h: births
@@ -39,10 +41,11 @@ heat at amp = 0, is symmetric, and is second-order consistent with
 -div(a grad u) for a smooth u; ou and cme have zero column sums (exactly for
 cme, away from boundary-adjacent columns for ou), the M-matrix sign pattern,
 and the expected consistency order; the cme chain at h = 1 reproduces
-Poisson marginals (tests/test_oracle_propagate.py); drift equals ou exactly
-for theta = -diag(theta_i), H = sigma^2 I, has zero column sums away from
-the boundary and the M-matrix sign pattern, and is first-order consistent
-with the continuous operator for a full theta.
+Poisson marginals (tests/test_oracle_propagate.py); drift has zero column
+sums away from the boundary (the central fluxes conserve mass), is the heat
+operator times H/2 for theta = 0, is second-order consistent with the
+continuous operator for a full theta, and its drift part is skew in the
+interior for a constant velocity (tests/test_oracle_sde.py).
 """
 from __future__ import annotations
 
@@ -91,9 +94,10 @@ def couplings(prob, l, i: int, X: np.ndarray):
         wc = X @ th[i]  # (theta x)_i at the node
         w_up = wc + th[i, i] * 0.5 * h
         w_dn = wc - th[i, i] * 0.5 * h
-        diag = (np.maximum(w_up, 0.0) - np.minimum(w_dn, 0.0)) / h + H / h ** 2
-        upper = np.minimum(w_up, 0.0) / h - 0.5 * H / h ** 2
-        lower = -np.maximum(w_dn, 0.0) / h - 0.5 * H / h ** 2
+        # (F_{j+1/2} - F_{j-1/2}) / h with F = w (u_j + u_{j+1}) / 2
+        diag = 0.5 * (w_up - w_dn) / h + H / h ** 2
+        upper = 0.5 * w_up / h - 0.5 * H / h ** 2
+        lower = -0.5 * w_dn / h - 0.5 * H / h ** 2
         return diag, lower, upper
     if op == "cme":
         k = prob["k"][i]

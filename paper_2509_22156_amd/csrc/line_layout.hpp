@@ -151,7 +151,9 @@ struct LineOp<OPC_VAR, T, K> {
   T qlo[MAXD - 1], qup[MAXD - 1];
   const T* oc;
 };
-// DRIFT: the face velocity along a non-stiff axis a at unknown k is
+// DRIFT: second-order central differences (conservative central face
+// fluxes w (u_j + u_{j+1}) / 2, central diffusion). The face velocity along a
+// non-stiff axis a at unknown k is
 // base[m] + theta[a][s] x_s(k) -/+ theta[a][a] h_a / 2, so a lane keeps
 // base[m] (the contribution of its fixed coordinates) and computes the
 // neighbour couplings in the apply; the stiff-axis and diagonal couplings
@@ -221,9 +223,9 @@ __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L,
       const T xs = O.xs0 + (T)k * hs;
       const T wc = bs + tss * xs;
       const T wup = wc + tss * (T)0.5 * hs, wdn = wc - tss * (T)0.5 * hs;
-      T dg = (max(wup, (T)0) - min(wdn, (T)0)) / hs + Hs / (hs * hs);
-      const T up = min(wup, (T)0) / hs - (T)0.5 * Hs / (hs * hs);
-      const T lo = -max(wdn, (T)0) / hs - (T)0.5 * Hs / (hs * hs);
+      T dg = (T)0.5 * (wup - wdn) / hs + Hs / (hs * hs);
+      const T up = (T)0.5 * wup / hs - (T)0.5 * Hs / (hs * hs);
+      const T lo = (T)-0.5 * wdn / hs - (T)0.5 * Hs / (hs * hs);
 #pragma unroll
       for (int m = 0; m < MAXD - 1; ++m) {
         if (m < d - 1) {
@@ -231,7 +233,7 @@ __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L,
           const T ha = (T)g.h[a], taa = tab[a * d + a];
           const T w0 = O.base[m] + tab[a * d + s] * xs;
           const T wu = w0 + taa * (T)0.5 * ha, wd = w0 - taa * (T)0.5 * ha;
-          dg += (max(wu, (T)0) - min(wd, (T)0)) / ha + tab[d * d + a] / (ha * ha);
+          dg += (T)0.5 * (wu - wd) / ha + tab[d * d + a] / (ha * ha);
         }
       }
       O.diag[k] = v ? (T)1 + O.dt * dg : (T)1;
@@ -399,17 +401,17 @@ __device__ __forceinline__ void line_apply(const GridDev& g, const Lane<K>& L,
       const T* plo = xl + (((L.nb >> (2 * m)) & 1u) ? L.tid - off : ghost);
       const T* phi = xl + (((L.nb >> (2 * m + 1)) & 1u) ? L.tid + off : ghost);
       if constexpr (OPC == OPC_DRIFT) {
-        // donor-cell couplings from the face velocities of this unknown
+        // central-flux couplings from the face velocities of this unknown
         const int d = g.d, a = g.oax[m], s = g.sax;
         const T ha = (T)g.h[a], hs = (T)g.h[s];
         const T tas = O.tab[a * d + s], half = O.tab[a * d + a] * (T)0.5 * ha;
-        const T ih = O.dt / ha;
+        const T ih = (T)0.5 * O.dt / ha;
         const T dH = (T)0.5 * O.dt * O.tab[d * d + a] / (ha * ha);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const T w0 = O.base[m] + tas * (O.xs0 + (T)k * hs);
-          const T clo = -ih * max(w0 - half, (T)0) - dH;
-          const T chi = ih * min(w0 + half, (T)0) - dH;
+          const T clo = -ih * (w0 - half) - dH;
+          const T chi = ih * (w0 + half) - dH;
           acc[k] += clo * plo[k * PITCH];
           acc[k] += chi * phi[k * PITCH];
         }

@@ -94,10 +94,11 @@ __device__ __forceinline__ void point_coef(const GridDev& g, const double* tl, d
       // sweeps are VALU-bound on this operator; 1/h is uniform per grid)
       const double h = g.h[i], half = tl[i * d + i] * 0.5 * h, H = tl[d * d + i];
       const double ih = 1.0 / h, ih2 = g.ih2[i];
+      // central face fluxes w (u_j + u_{j+1}) / 2 (second order)
       const double wu = w + half, wd = w - half;
-      diag += dt * ((fmax(wu, 0.0) - fmin(wd, 0.0)) * ih + H * ih2);
-      up = dt * (fmin(wu, 0.0) * ih - 0.5 * H * ih2);
-      lo = dt * (-fmax(wd, 0.0) * ih - 0.5 * H * ih2);
+      diag += dt * (0.5 * (wu - wd) * ih + H * ih2);
+      up = dt * (0.5 * wu * ih - 0.5 * H * ih2);
+      lo = dt * (-0.5 * wd * ih - 0.5 * H * ih2);
     }
     c.lo[i] = (j > 0) ? lo : 0.0;
     c.up[i] = (j < n - 1) ? up : 0.0;

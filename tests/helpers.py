@@ -1,8 +1,12 @@
 """Shared helpers of the GPU parity tests: run the oracle and the HIP path
 on the same seeded problem and compare."""
+import os
+
 import numpy as np
 
-from oracle import combine, grids, index_set, operators, propagate, solve
+from oracle import combine, grids, index_set, operators, propagate, sde, solve
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def rel_l2(a, b):
@@ -131,5 +135,32 @@ def oracle_mgrit_history(prob, nit, grid_sel=None):
     return hist
 
 
+def table3_figures():
+    """Table 3 of Section 4.4.1: scheme -> maximum error at the origin."""
+    rows = {}
+    with open(os.path.join(GOLD, "table3_oscillator_origin.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                rows[k] = float(v)
+    return rows
+
+
+def origin_errors(series, coef, every, dt):
+    """|u^(c)(0, t) - p(0, t)| at the sampled times of a stored origin series
+    of the 2-D oscillator (the origin is a node of every component grid, so
+    the combination there is the coefficient sum of the grid values)."""
+    from workloads import make
+    p = make("fp_osc2d")
+    th, H = np.asarray(p["drift"]), np.diag(p["diffusion"])
+    comb = np.asarray(coef) @ np.asarray(series)
+    out = np.empty(comb.shape[0])
+    for k in range(comb.shape[0]):
+        m, C = sde.moments(th, H, p["mean0"], np.diag(p["var0"]), k * every * dt)
+        out[k] = abs(comb[k] - sde.density(np.zeros((1, 2)), m, C)[0])
+    return out
+
+
 __all__ = ["rel_l2", "split", "state_errors", "assert_state_close", "oracle_states", "oracle_apply", "oracle_abs_apply", "oracle_propagate",
-           "oracle_initial", "oracle_mgrit_history", "combine", "index_set", "solve"]
+           "oracle_initial", "oracle_mgrit_history", "table3_figures",
+           "origin_errors", "GOLD", "combine", "index_set", "solve"]

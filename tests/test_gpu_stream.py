@@ -110,7 +110,7 @@ def test_streaming_solve_mixed():
 @pytest.mark.parametrize("name,kw", [("ou4d", dict(d=2, n=10, nsteps=16, t1=0.1)),
                                      ("cme5d", dict(d=2, n=10, hi=[1024.0] * 2, nsteps=16, t1=0.1)),
                                      ("varcoef6d", dict(d=2, n=10, nsteps=16, t1=0.01, cf=4)),
-                                     ("fp_osc2d", dict(n=12, L0=3, nsteps=16))])
+                                     ("fp_osc2d", dict(n=12, L0=3, nsteps=16, t1=0.08))])
 def test_streaming_other_operators(name, kw):
     p = make(name, **kw)
     p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100)
@@ -147,7 +147,7 @@ def test_streaming_wide_against_narrow(kw):
 
 def test_streaming_wide_drift_oscillator():
     # the full-drift operator (BiCGStab) with every streaming launch wide
-    p = make("fp_osc2d", n=12, L0=3, nsteps=16)
+    p = make("fp_osc2d", n=12, L0=3, nsteps=16, t1=0.08)
     p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=100)
     _say("streaming wide fp_osc2d")
     plan = ctm.Plan(p)
@@ -246,3 +246,19 @@ def test_streaming_many_tasks_with_tables(name, kw):
     assert any(s["K"] == 0 for s in plan.stats()["shapes"])
     ref = solve.packed(solve.component_states(p))
     assert_state_close(p, u, ref, 1e-11)
+
+
+def test_drift_beyond_the_solver_reports_noconv():
+    # the oscillator's step is dt = 0.005 (Section 4.4.1); at 16 times that
+    # step (coarse step 0.16) the central fluxes of the rotating drift give
+    # the mid-size grids a spectrum far off the real axis, where BiCGStab with
+    # the line preconditioner stagnates: the solve must end with that
+    # reported (no convergence, or a breakdown once MGRIT has diverged)
+    p = make("fp_osc2d", n=12, L0=3, nsteps=16)
+    p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-13, mgrit_maxit=4, krylov_maxit=200)
+    _say("drift at 16x the paper's step")
+    plan = ctm.Plan(p)
+    _, st = plan.solve(check=False)
+    flags = plan.stats()["status_flags"]
+    assert st in (ctm.ERR_NOCONV, ctm.ERR_BREAKDOWN)
+    assert flags & (1 << ctm.ERR_NOCONV)

@@ -1,9 +1,13 @@
 """Pins of the full-drift Fokker-Planck operator and the exact Gaussian law
 of the linear SDE (Section 4.4)."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
 from oracle import grids, operators, propagate, sde
+from helpers import GOLD, origin_errors, table3_figures
 from workloads import make
 
 
@@ -17,29 +21,69 @@ def _drift_from_ou(p):
 
 
 @pytest.mark.parametrize("l", [(4, 3), (3, 2, 3)])
-def test_drift_equals_ou_for_diagonal_theta(l):
+def test_upwind_ou_is_central_drift_plus_numerical_diffusion(l):
+    # with theta = -diag(theta_i) and H = sigma^2 I the drift operator has the
+    # OU operator's diffusion, and the donor-cell fluxes of OU differ from its
+    # central fluxes by exactly a second difference with the face weights
+    # |w_{j+1/2}| / (2 h) (upwinding adds the diffusion |w| h / 2); the
+    # difference is assembled here from the face velocities alone
     p = make("ou4d", d=len(l), n=5)
     q = _drift_from_ou(p)
     A = operators.matrix(p, l).toarray()
     B = operators.matrix(q, l).toarray()
-    assert np.abs(A - B).max() <= 1e-12 * np.abs(A).max()
+    X = grids.coordinates(p, l)
+    shp = grids.shape(p, l)
+    idx = np.arange(X.shape[0]).reshape(shp)
+    N = np.zeros_like(A)
+    for i in range(len(l)):
+        h = (p["hi"][i] - p["lo"][i]) / 2 ** l[i]
+        th = p["theta"][i]
+        for j in range(X.shape[0]):
+            nu_up = abs(th * (X[j, i] + 0.5 * h)) / (2 * h)
+            nu_dn = abs(th * (X[j, i] - 0.5 * h)) / (2 * h)
+            N[j, j] += nu_up + nu_dn
+            pos = np.unravel_index(j, shp)
+            if pos[i] + 1 < shp[i]:
+                up = list(pos)
+                up[i] += 1
+                N[j, idx[tuple(up)]] -= nu_up
+            if pos[i] > 0:
+                dn = list(pos)
+                dn[i] -= 1
+                N[j, idx[tuple(dn)]] -= nu_dn
+    assert np.abs(A - B - N).max() <= 1e-12 * np.abs(A).max()
+
+
+def test_drift_without_velocity_is_scaled_heat():
+    p = make("fp_lin4d", d=2, n=5)
+    p["drift"] = [[0.0, 0.0], [0.0, 0.0]]
+    p["diffusion"] = [0.6, 0.6]
+    q = dict(p, op="heat")
+    A = operators.matrix(p, (4, 3)).toarray()
+    B = operators.matrix(q, (4, 3)).toarray()
+    assert np.abs(A - 0.3 * B).max() <= 1e-13 * np.abs(A).max()
 
 
 @pytest.mark.parametrize("name,l", [("fp_osc2d", (5, 4)), ("fp_lin4d", (3, 2, 3, 2))])
-def test_drift_conservation_and_sign_pattern(name, l):
+def test_drift_conservation_and_skew_transport(name, l):
     p = make(name)
     A = operators.matrix(p, l).toarray()
-    off = A - np.diag(np.diag(A))
-    assert (off <= 1e-14).all() and (np.diag(A) >= -1e-14).all()
     # columns away from the boundary sum to zero (mass is conserved inside)
     shp = grids.shape(p, l)
     idx = np.arange(A.shape[0]).reshape(shp)
     inner = idx[tuple(slice(1, -1) for _ in shp)].reshape(-1)
     assert np.abs(A[:, inner].sum(axis=0)).max() <= 1e-10 * np.abs(A).max()
+    # without diffusion, central fluxes couple neighbours antisymmetrically:
+    # A + A^T is diagonal
+    q = dict(p, diffusion=[0.0] * p["d"])
+    T = operators.matrix(q, l).toarray()
+    S = T + T.T
+    assert np.abs(S - np.diag(np.diag(S))).max() <= 1e-12 * np.abs(T).max()
 
 
-def test_drift_first_order_consistency():
-    # L f against the continuous operator for a smooth f with a full theta
+def test_drift_second_order_consistency():
+    # L f against the continuous operator for a smooth f with a full theta:
+    # the error falls by about four when h halves
     p = make("fp_lin4d", d=4)
     th = np.asarray(p["drift"])
     H = np.asarray(p["diffusion"])
@@ -55,7 +99,7 @@ def test_drift_first_order_consistency():
         cont = f * div - 0.5 * f * lap
         mask = np.all(np.abs(X) < 3.0, axis=1)
         errs.append(np.abs(operators.matrix(p, l) @ f - cont)[mask].max())
-    assert errs[1] < 0.65 * errs[0], errs
+    assert errs[1] < 0.3 * errs[0], errs
 
 
 @pytest.mark.parametrize("name", ["fp_osc2d", "fp_lin4d"])
@@ -122,3 +166,31 @@ def test_density_closed_forms():
     Z = G - m
     c = (Z[:, :, None] * Z[:, None, :] * w[:, None, None]).sum(axis=0)
     np.testing.assert_allclose(c, cov, atol=1e-9)
+
+
+def test_oscillator_origin_error_matches_table3():
+    # Section 4.4.1, Table 3: the time-sequential combination technique on
+    # L = 14, L0 = 6 with dt = 0.005 to T = 100 misses the exact density at
+    # the origin by at most 0.00089 over time. The stored series is the
+    # oracle's (tests/golden/osc2d_origin.py); the oracle as it stands
+    # reproduces its first 2,000 steps on every grid (the operators and the
+    # start are time-invariant, so the rest of the march follows), and the
+    # stored combination's maximum error matches the printed figure within
+    # 10%; a donor-cell flux, a sign or index slip in the drift or a wrong
+    # coefficient moves it far outside. Combining also beats every component
+    # grid on its own.
+    sys.path.insert(0, GOLD)
+    import osc2d_origin as gen
+    z = np.load(os.path.join(GOLD, "osc2d_origin.npz"))
+    every, dt = int(z["every"]), float(z["dt"])
+    assert every == gen.EVERY and dt == gen.DT and z["series"].shape[1] == gen.NSTEPS // every + 1
+    levels, coef, fresh = gen.compute(workers=min(7, os.cpu_count() or 1), nsteps=2000)
+    np.testing.assert_array_equal(levels, z["levels"])
+    np.testing.assert_array_equal(coef, z["coef"])
+    np.testing.assert_allclose(fresh, z["series"][:, :fresh.shape[1]], rtol=1e-12, atol=1e-15)
+    err = origin_errors(z["series"], z["coef"], every, dt)
+    paper = table3_figures()["CT"]
+    assert abs(err.max() - paper) <= 0.1 * paper, err.max()
+    for g in range(len(coef)):
+        own = origin_errors(z["series"][g:g + 1], [1.0], every, dt)
+        assert err.max() < own.max()
