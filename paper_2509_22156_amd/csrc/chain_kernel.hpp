@@ -393,8 +393,21 @@ __device__ __forceinline__ void step_single32(const Solver<OPC, float, K>& S32, 
 // largest over that and the initial residuals of its other steps.
 enum { MODE_PLAIN = 0, MODE_FORCED = 1, MODE_RESIDUAL = 2 };
 
+// Waves per SIMD the compiler must leave room for. gfx950 gives a SIMD 512
+// vector registers per lane: a kernel over 256 runs one wave per SIMD, and
+// the chain kernels, bound by the latency of their reductions and barriers,
+// then idle. The mixed K = 4 kernels of the variable-coefficient operator
+// need a little over 256 (they hold the FP64 and the FP32 line operator:
+// about 290); held to 256 they spill under 40 registers and run two waves
+// per SIMD, measured 25% off the mixed 6-D solve. Held to three waves (168)
+// they spill over 120 registers and run 65% slower.
+template <int OPC, bool MIXED, int W, int K>
+constexpr int chain_min_waves() { return (OPC == OPC_VAR && K == 4 && MIXED) ? 2 : 1; }
+
 template <int OPC, int SOLVER, bool MIXED, int MODE, int W, int K>
-__global__ void __launch_bounds__(64 * W) chain_kernel(ChainArgs a, int tabmax) {
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(chain_min_waves<OPC, MIXED, W, K>())))
+    chain_kernel(ChainArgs a, int tabmax) {
   constexpr bool FORCED = (MODE == MODE_FORCED);
   constexpr bool RES = (MODE == MODE_RESIDUAL);
   constexpr int BS = 64 * W;
