@@ -329,21 +329,48 @@ ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lan
  * the one-work-group kernel. */
 ctm_status ctm_plan_set_wide(ctm_plan* plan, int max_tasks);
 
+/* Schedule of the MGRIT phases (Algorithm 2: relaxation, restriction,
+ * coarse solve, correction) over the size classes. A plan runs its size
+ * classes on up to four streams: the caller's and three of its own.
+ *   CTM_SCHED_JOINED: every phase of all classes is joined back into the
+ *     caller's stream before the next phase starts.
+ *   CTM_SCHED_PER_CLASS: with FCF-relaxation, each class runs its phases
+ *     (coarse levels included) one after another on its own stream, joined
+ *     only for the convergence test of each iteration; a class that ends a
+ *     phase early starts its next one while the others still work.
+ *   CTM_SCHED_AUTO (default): per class with two MGRIT levels, joined with
+ *     three or more.
+ * Every class reads only what it wrote itself, so the results do not depend
+ * on the schedule. F-relaxation always joins. */
+typedef enum {
+  CTM_SCHED_AUTO = 0,
+  CTM_SCHED_JOINED = 1,
+  CTM_SCHED_PER_CLASS = 2
+} ctm_schedule;
+
+/* Select the schedule (a ctm_schedule value; anything else is
+ * CTM_ERR_INVALID). Takes effect at the next solve. */
+ctm_status ctm_plan_set_schedule(ctm_plan* plan, int schedule);
+
 typedef struct {
   int classes;       /* anisotropy classes with more than one candidate shape */
   int trials;        /* timed trial solves run */
   int changed;       /* classes whose shape differs from the plan's default */
   double ms_default; /* trial time with the shapes the plan started with */
-  double ms_tuned;   /* trial time with the chosen shapes */
+  double ms_tuned;   /* trial time with the chosen shapes and schedule */
   double tune_ms;    /* wall time of the whole tuning */
+  int schedule;      /* the plan's schedule after tuning (ctm_schedule) */
 } ctm_tune_report;
 
-/* Autotuner of the launch shapes. The on-chip grids fall into anisotropy
- * classes: equal stiff-axis line length and number of lines, hence the same
- * candidate shapes (per_lane 4 or 8, each with the fewest waves that hold
- * the lines). For each class with two candidates, in decreasing order of
- * its unknowns, the other candidate is tried and kept when it shortens the
- * trial by more than 2%. A trial is ctm_solve from the problem's initial
+/* Autotuner of the launch shapes and the schedule. The on-chip grids fall
+ * into anisotropy classes: equal stiff-axis line length and number of lines,
+ * hence the same candidate shapes (per_lane 4 or 8, each with the fewest
+ * waves that hold the lines). For each class with two candidates, in
+ * decreasing order of its unknowns, the other candidate is tried and kept
+ * when it shortens the trial by more than 2%. Then, for FCF-relaxation with
+ * two or more MGRIT levels, the schedule other than the one in effect
+ * (CTM_SCHED_JOINED or CTM_SCHED_PER_CLASS) is tried and kept on the same
+ * rule. A trial is ctm_solve from the problem's initial
  * value, capped at trial_iterations MGRIT iterations per block when
  * trial_iterations > 0 (0 = run to convergence); each configuration runs
  * `repeats` >= 1 times and its fastest run counts. ws (ctm_plan_workspace_bytes)

@@ -121,6 +121,9 @@ struct ctm_plan {
   // Fixed per plan, so that consecutive phases of one class need no
   // cross-stream synchronisation.
   int lane_of[kNumShapes + 1] = {};
+  // MGRIT phase schedule (ctm_plan_set_schedule): CTM_SCHED_AUTO, _JOINED
+  // or _PER_CLASS
+  int sched = CTM_SCHED_AUTO;
   // cyclic-reduction steps of the line preconditioner each size class's LDS
   // table must hold: the largest log2(lanes per line) over its grids
   int pcr_of[kNumShapes] = {};
@@ -983,14 +986,17 @@ ctm_status fork_lanes(ctm_plan* P, hipStream_t s) {
 
 // One MGRIT cycle on level l >= 1 for the residual equation. On the last
 // level, e_m for m >= 1 is written and e_0 (= 0, cleared once per block) is
-// left alone; with open_last the last level's chain runs per size class on
-// the lanes forked before, without a join (the readers of its output run on
-// the same lanes). Every other phase is forked from and joined back into s.
-// The first residual vector r_0 of every level is cleared once per block.
-ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last) {
+// left alone. per_class: every phase, fill and correction runs per size
+// class on the lanes forked before, without a join (each reads only what its
+// own class wrote); otherwise every phase is forked from and joined back
+// into s. The first residual vector r_0 of every level is cleared once per
+// block.
+ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool per_class) {
   const long long c = lay.c;
   double* G = lay.R[l];
   double* E = lay.E[l];
+  const bool c64 = coarse_in_fp64(P);
+  const bool fj = !per_class;  // fork and join around each phase
   ctm_status st;
   if (l == lay.L - 1) {
     ChainArgs a = coarse_args(P, l, (int)lay.N[l]);
@@ -1000,23 +1006,34 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
     a.fin = vref(E, 0, lay.N[l]);
     TaskSet* single = nullptr;
     if ((st = tasks_for(P, 1, &single)) != CTM_OK) return st;
-    return run_chain(P, a, *single, s, coarse_in_fp64(P), !open_last, !open_last);
+    return run_chain(P, a, *single, s, c64, fj, fj);
   }
   const long long M = lay.N[l] / c;
   TaskSet* tasks = nullptr;
   if ((st = tasks_for(P, M, &tasks)) != CTM_OK) return st;
-  CTM_HIP(launch_fill_zero(E, (lay.N[l] + 1) * P->slen, s, P->skip));
+  // dst = x + y over nvec vectors: whole vectors on s, or per class
+  auto add = [&](VecRef dst, VecRef x, VecRef y, long long nvec) -> ctm_status {
+    if (per_class) return class_vec_add(P, dst, x, y, nvec, s);
+    if (!x.base && !y.base) {
+      CTM_HIP(launch_fill_zero(dst.base + dst.b * P->slen, nvec * P->slen, s, P->skip));
+    } else {
+      CTM_HIP(launch_vec_add(dst, x, y, (int)nvec, P->slen, s, P->skip));
+    }
+    return CTM_OK;
+  };
+  const VecRef none = vref(nullptr, 0, 0);
+  if ((st = add(vref(E, 1, 0), none, none, lay.N[l] + 1)) != CTM_OK) return st;
   double* csrc;
   long long ca;
   if (P->prob.relax == CTM_RELAX_FCF) {
     double* Cn = lay.Cn[l];
-    CTM_HIP(launch_fill_zero(Cn, P->slen, s, P->skip));
+    if ((st = add(vref(Cn, 1, 0), none, none, 1)) != CTM_OK) return st;
     ChainArgs fc = coarse_args(P, l, (int)c);
     fc.start = vref(E, c, 0);
     fc.forcing = vref(G, c, 0);
     fc.inter = vref(E, c, 0);
     fc.fin = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fc, *tasks, s, coarse_in_fp64(P))) != CTM_OK) return st;
+    if ((st = run_chain(P, fc, *tasks, s, c64, fj, fj)) != CTM_OK) return st;
     ChainArgs fr = coarse_args(P, l, (int)c);
     fr.start = vref(Cn, 1, 0);
     fr.start_wb = vref(E, c, 0);
@@ -1024,7 +1041,7 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(Cn, 1, 1);
-    if ((st = run_chain(P, fr, *tasks, s, coarse_in_fp64(P))) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s, c64, fj, fj)) != CTM_OK) return st;
     csrc = Cn;
     ca = 1;
   } else {
@@ -1034,20 +1051,20 @@ ctm_status cycle(ctm_plan* P, Layout& lay, int l, hipStream_t s, bool open_last)
     fr.inter = vref(E, c, 0);
     fr.fin = vref(lay.R[l + 1], 1, 1);
     fr.target = vref(E, c, c);
-    if ((st = run_chain(P, fr, *tasks, s, coarse_in_fp64(P))) != CTM_OK) return st;
+    if ((st = run_chain(P, fr, *tasks, s, c64, fj, fj)) != CTM_OK) return st;
     csrc = E;
     ca = c;
   }
-  if ((st = cycle(P, lay, l + 1, s, false)) != CTM_OK) return st;
+  if ((st = cycle(P, lay, l + 1, s, per_class)) != CTM_OK) return st;
   // correction at the C-points, then F-relaxation (ideal interpolation)
-  CTM_HIP(launch_vec_add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0), (int)(M + 1),
-                         P->slen, s, P->skip));
+  if ((st = add(vref(E, c, 0), vref(csrc, ca, 0), vref(lay.E[l + 1], 1, 0), M + 1)) != CTM_OK)
+    return st;
   ChainArgs fi = coarse_args(P, l, (int)(c - 1));
   fi.start = vref(E, c, 0);
   fi.forcing = vref(G, c, 0);
   fi.inter = vref(E, c, 0);
   fi.fin = vref(E, c, c - 1);
-  return run_chain(P, fi, *tasks, s, coarse_in_fp64(P));
+  return run_chain(P, fi, *tasks, s, c64, fj, fj);
 }
 
 // Node map of the hierarchical basis: every unknown named by its node on
@@ -1238,12 +1255,13 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
   // the correction follow each other on the class's lane without
   // cross-stream synchronisation; only the convergence test joins all lanes.
   bool open = false;  // side streams hold work not yet joined into s
-  // two levels: every phase per class without joins (measured faster on
-  // heat3d); three or more: each phase joined (measured faster on ou4d,
-  // where the slowest class's relaxation then has the machine to itself
-  // at the end of each phase instead of sharing it with the next phase of
-  // the other classes)
-  const bool per_class = (lay.L == 2);
+  // the schedule (CTM_SCHED_AUTO): two levels run every phase per class
+  // without joins (measured faster on heat3d); three or more join each phase
+  // (measured faster on ou4d, where the slowest class's relaxation then has
+  // the machine to itself at the end of each phase instead of sharing it
+  // with the next phase of the other classes)
+  const bool per_class = P->sched == CTM_SCHED_AUTO ? (lay.L == 2)
+                                                     : (P->sched == CTM_SCHED_PER_CLASS);
   for (int it = 1; it <= maxit; ++it) {
     // when the residuals seen so far predict that iteration it - 1 meets the
     // tolerance (geometric decrease), wait for its test before queueing more
@@ -1945,6 +1963,15 @@ ctm_status ctm_plan_set_wide(ctm_plan* P, int max_tasks) {
   return CTM_OK;
 }
 
+ctm_status ctm_plan_set_schedule(ctm_plan* P, int schedule) {
+  if (!P) return fail(CTM_ERR_INVALID, "plan is NULL");
+  if (schedule != CTM_SCHED_AUTO && schedule != CTM_SCHED_JOINED &&
+      schedule != CTM_SCHED_PER_CLASS)
+    return fail(CTM_ERR_INVALID, "unknown schedule");
+  P->sched = schedule;
+  return CTM_OK;
+}
+
 ctm_status ctm_autotune(ctm_plan* P, void* ws, size_t ws_bytes, double* u_scratch,
                         int trial_iterations, int repeats, ctm_tune_report* report,
                         ctm_stream s) {
@@ -2017,13 +2044,29 @@ ctm_status ctm_autotune(ctm_plan* P, void* ws, size_t ws_bytes, double* u_scratc
       for (int g : tc.grids) set_shape(P, g, now);
     }
   }
+  // the schedule: the explicit one not in effect, kept on the same rule
+  const int sched0 = P->sched;
+  if (st == CTM_OK && P->prob.mgrit_levels > 1 && P->prob.relax == CTM_RELAX_FCF) {
+    const bool pc_now = (sched0 == CTM_SCHED_AUTO) ? (P->prob.mgrit_levels == 2)
+                                                    : (sched0 == CTM_SCHED_PER_CLASS);
+    P->sched = pc_now ? CTM_SCHED_JOINED : CTM_SCHED_PER_CLASS;
+    double t = 0.0;
+    st = trial(&t);
+    if (st == CTM_OK && t < 0.98 * cur) {
+      cur = t;
+    } else {
+      P->sched = sched0;
+    }
+  }
   P->timing = timing;
   P->prob.mgrit_maxit = maxit;
   if (st != CTM_OK) {
     for (int g = 0; g < P->G; ++g) set_shape(P, g, initial[g]);
+    P->sched = sched0;
     return st;
   }
   rep.ms_tuned = cur;
+  rep.schedule = P->sched;
   for (const TuneClass& tc : classes)
     if (P->gshape[tc.grids[0]] != initial[tc.grids[0]]) rep.changed += 1;
   rep.tune_ms = std::chrono::duration<double, std::milli>(clock::now() - t_start).count();

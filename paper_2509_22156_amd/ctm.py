@@ -20,6 +20,7 @@ MAX_HISTORY = 256
 NOALLOC_WORKSPACE_BYTES = 256 << 20  # CTM_NOALLOC_WORKSPACE_BYTES of ctm.h
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE = range(7)
+SCHED_AUTO, SCHED_JOINED, SCHED_PER_CLASS = range(3)
 _OPS = {"heat": 0, "varcoef": 1, "ou": 2, "cme": 3, "drift": 4}
 _KRYLOV = {"auto": 0, "cg": 1, "bicgstab": 2}
 _PREC = {"fp64": 0, "mixed": 1}
@@ -69,7 +70,7 @@ class Stats(ctypes.Structure):
 class TuneReport(ctypes.Structure):
     _fields_ = [("classes", ctypes.c_int), ("trials", ctypes.c_int), ("changed", ctypes.c_int),
                 ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double),
-                ("tune_ms", ctypes.c_double)]
+                ("tune_ms", ctypes.c_double), ("schedule", ctypes.c_int)]
 
 
 class CtmError(RuntimeError):
@@ -107,6 +108,7 @@ def _load():
         "ctm_plan_grid_shape": [P, i, ctypes.POINTER(i), ctypes.POINTER(i)],
         "ctm_plan_set_grid_shape": [P, i, i, i],
         "ctm_plan_set_wide": [P, i],
+        "ctm_plan_set_schedule": [P, i],
         "ctm_autotune": [P, P, sz, P, i, i, ctypes.POINTER(TuneReport), P],
     }
     for name, args in sigs.items():
@@ -362,9 +364,14 @@ class Plan:
         (many work-groups per task) solver; 0 disables it (default: every launch)."""
         _check(_lib.ctm_plan_set_wide(self._h, max_tasks))
 
+    def set_schedule(self, schedule: int):
+        """MGRIT phase schedule: SCHED_AUTO, SCHED_JOINED or SCHED_PER_CLASS
+        (ctm_plan_set_schedule)."""
+        _check(_lib.ctm_plan_set_schedule(self._h, int(schedule)))
+
     def autotune(self, trial_iterations: int = 0, repeats: int = 2) -> dict:
-        """Choose the launch shape of every anisotropy class by timed trial
-        solves (ctm_autotune); returns its report."""
+        """Choose the launch shape of every anisotropy class and the MGRIT
+        schedule by timed trial solves (ctm_autotune); returns its report."""
         ws = self.workspace()
         u = self._vec()
         rep = TuneReport()
@@ -383,5 +390,5 @@ def exported_symbols():
             "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_solve_noalloc",
             "ctm_gather",
             "ctm_combine_project", "ctm_hierarchize", "ctm_recombine", "ctm_get_stats", "ctm_set_timing", "ctm_plan_grid_shape",
-            "ctm_plan_set_grid_shape", "ctm_plan_set_wide", "ctm_autotune", "ctm_status_string",
+            "ctm_plan_set_grid_shape", "ctm_plan_set_wide", "ctm_plan_set_schedule", "ctm_autotune", "ctm_status_string",
             "ctm_last_error"]

@@ -127,6 +127,7 @@ def test_shape_entry_points_reject_null_plan():
     assert lib.ctm_plan_grid_shape(None, 0, ctypes.byref(w), ctypes.byref(k)) == 1
     assert lib.ctm_plan_set_grid_shape(None, 0, 1, 4) == 1
     assert lib.ctm_plan_set_wide(None, 4) == 1
+    assert lib.ctm_plan_set_schedule(None, ctm.SCHED_JOINED) == 1
     rep = ctm.TuneReport()
     assert lib.ctm_autotune(None, None, 0, None, 0, 1, ctypes.byref(rep), None) == 1
     assert "NULL" in lib.ctm_last_error().decode()

@@ -1,7 +1,8 @@
-"""Launch shapes and their autotuner (through the C ABI): every admissible
-shape of a grid gives the oracle's solution to the usual bars, invalid
-shapes are rejected, and the autotuned plan keeps parity, also at the size
-and settings of the 3-D heat measurement."""
+"""Launch shapes, schedules and their autotuner (through the C ABI): every
+admissible shape of a grid gives the oracle's solution to the usual bars,
+both MGRIT schedules give the same bits, invalid settings are rejected, and
+the autotuned plan keeps parity, also at the size and settings of the 3-D
+heat measurement."""
 import sys
 
 import pytest
@@ -104,7 +105,9 @@ def test_autotune_keeps_parity(name):
     plan = ctm.Plan(p)
     rep = plan.autotune(trial_iterations=2, repeats=1)
     assert rep["classes"] >= 1
-    assert rep["trials"] == 1 + rep["classes"]
+    # the default shapes, one trial per class, one for the other schedule
+    assert rep["trials"] == 2 + rep["classes"]
+    assert rep["schedule"] in (ctm.SCHED_AUTO, ctm.SCHED_JOINED, ctm.SCHED_PER_CLASS)
     assert 0 < rep["ms_tuned"] <= rep["ms_default"]
     assert 0 <= rep["changed"] <= rep["classes"]
     for g in range(plan.G):
@@ -125,9 +128,38 @@ def test_autotune_full_heat3d_measurement_settings():
     plan = ctm.Plan(p)
     rep = plan.autotune(trial_iterations=3, repeats=1)
     _say(f"report {rep}")
-    assert rep["trials"] == 1 + rep["classes"]
+    assert rep["trials"] == 2 + rep["classes"]
     u = plan.solve().cpu().numpy()
     st = plan.stats()
     assert st["status_flags"] == 0
     ref = solve.packed(solve.component_states(p))
     assert_state_close(p, u, ref, 1e-8)
+
+
+@pytest.mark.parametrize("name,prec,levels", [("heat3d", "mixed", 2), ("ou4d", "fp64", 3),
+                                              ("ou4d", "mixed", 3), ("varcoef6d", "mixed", 3)])
+def test_schedules_give_identical_results(name, prec, levels):
+    # joined phases and per-class lanes run the same kernels on the same
+    # data: the states agree bit for bit, and both meet the oracle
+    p = _settings(_small(name), prec)
+    p["mgrit_levels"] = levels
+    _say(f"schedules {name} {prec} levels={levels}")
+    out, its = {}, {}
+    for sched in (ctm.SCHED_JOINED, ctm.SCHED_PER_CLASS):
+        plan = ctm.Plan(p)
+        plan.set_schedule(sched)
+        out[sched] = plan.solve().cpu().numpy()
+        st = plan.stats()
+        assert st["status_flags"] == 0
+        its[sched] = st["mgrit_iterations"]
+    assert its[ctm.SCHED_JOINED] == its[ctm.SCHED_PER_CLASS]
+    assert (out[ctm.SCHED_JOINED] == out[ctm.SCHED_PER_CLASS]).all()
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, out[ctm.SCHED_PER_CLASS], ref, 1e-11 if prec == "fp64" else 1e-8)
+
+
+def test_set_schedule_rejects_unknown():
+    plan = ctm.Plan(_settings(_small("heat3d"), "fp64"))
+    for bad in (-1, 3):
+        with pytest.raises(ctm.CtmError, match="unknown schedule"):
+            plan.set_schedule(bad)
