@@ -18,9 +18,12 @@ step:
              positions, N - P w of size w + 1 first and the rest of size
              w = floor(N / P).
   overlap    with gamma = m / 2 each disjoint subdomain is extended by
-             round(gamma w) positions on each side of the curve (clipped at
-             its ends), so that interior points lie in m + 1 subdomains.
-             R_i is the injection onto the extended subdomain.
+             floor(gamma w) positions on each side of the curve (clipped at
+             its ends); for gamma = 1/2 the points within floor(w / 2) of an
+             interior subdomain boundary lie in two extended subdomains (all
+             points when w is even, all but one per subdomain when it is
+             odd), and subdomains two apart never overlap. R_i is the
+             injection onto the extended subdomain.
   weights    D_i = omega_i I, omega_i = 1 / (the largest number of extended
              subdomains holding a point of the disjoint subdomain i).
   coarse     each disjoint subdomain is cut into q consecutive blocks (sizes
@@ -36,7 +39,7 @@ Library primitives: numpy's dense inverse and products.
 Pinned by tests/test_oracle_schwarz.py: the curve visits every lattice point
 once and consecutive points are lattice neighbours (the Hilbert property,
 d = 1..4); partition sizes and counts as Section 2.1.2 states; overlap
-multiplicity m + 1 inside the curve; F A F = F; C_bal equals A^-1 exactly
+multiplicity two near interior boundaries and never above two; F A F = F; C_bal equals A^-1 exactly
 for one subdomain and when the coarse space holds every point; C_bal is
 symmetric positive definite for a symmetric positive definite A; the
 preconditioned CG of oracle.krylov reaches the direct solution in fewer
@@ -124,7 +127,7 @@ class Decomposition:
         starts = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
         self.P = P
         self.disjoint = [(int(starts[i]), int(starts[i + 1])) for i in range(P)]
-        ov = int(round(gamma * w)) if P > 1 else 0
+        ov = int(math.floor(gamma * w)) if P > 1 else 0
         self.extended = [(max(0, a - ov), min(N, b + ov)) for a, b in self.disjoint]
         mult = np.zeros(N, dtype=int)
         for a, b in self.extended:

@@ -44,8 +44,9 @@ def test_curve_order_of_an_anisotropic_grid():
 @pytest.mark.parametrize("N_l,S", [((5, 4), 3), ((4, 4), 4), ((6, 3), 4), ((3, 3, 3), 5)])
 def test_partition_sizes_and_overlap(N_l, S):
     # Section 2.1.2: P = ceil(N / 2^S) subdomains, N - P w of them of size
-    # w + 1 and the others of size w = floor(N / P); with gamma = 1/2 every
-    # point away from the curve's ends lies in two extended subdomains
+    # w + 1 and the others of size w = floor(N / P); with gamma = 1/2 the
+    # points within floor(w / 2) of an interior boundary lie in two extended
+    # subdomains, no point in more, and subdomains two apart are disjoint
     p = make("heat2d") if len(N_l) == 2 else make("heat3d")
     dec = schwarz.Decomposition(p, N_l, S)
     N = dec.N
@@ -55,11 +56,16 @@ def test_partition_sizes_and_overlap(N_l, S):
     w = N // P
     assert sizes.count(w + 1) == N - P * w and sizes.count(w) == P - (N - P * w)
     assert sum(sizes) == N
+    assert dec.multiplicity.max() <= 2 and dec.multiplicity.min() >= 1
     if P > 1:
-        ov = round(0.5 * w)
-        inner = dec.multiplicity[ov:N - ov]
-        assert inner.min() >= 2 and inner.max() <= 3
-        assert all(abs(om - 0.5) < 1e-15 or abs(om - 1 / 3) < 1e-15 for om in dec.omega)
+        ov = w // 2
+        for a, _ in dec.disjoint[1:]:
+            assert (dec.multiplicity[a - ov:a + ov] == 2).all()
+        assert all(om == 0.5 for om in dec.omega)
+        for (a0, b0), (a2, b2) in zip(dec.extended, dec.extended[2:]):
+            assert b0 <= a2
+        if w % 2 == 0:
+            assert (dec.multiplicity == 2).sum() == N - 2 * ov
     # coarse blocks partition the curve
     cov = np.zeros(N, dtype=int)
     for a, b in dec.blocks:
