@@ -93,6 +93,25 @@ typedef enum { CTM_PREC_FP64 = 0, CTM_PREC_MIXED = 1 } ctm_precision;
 typedef enum { CTM_KRYLOV_AUTO = 0, CTM_KRYLOV_CG = 1, CTM_KRYLOV_BICGSTAB = 2 } ctm_krylov;
 typedef enum { CTM_RELAX_F = 0, CTM_RELAX_FCF = 1 } ctm_relax;
 
+/* Preconditioner of the implicit-step Krylov solves.
+ *   CTM_PRECOND_LINE: exact solves of the lines along each grid's stiffest
+ *     axis (the on-chip and streaming solvers' block preconditioner).
+ *   CTM_PRECOND_SCHWARZ: the two-level overlapping Schwarz preconditioner of
+ *     Section 2.1.2. The unknowns of a grid are ordered along a Hilbert
+ *     curve (virtual nodes make the grid isotropic), split into
+ *     P = ceil(N / 2^S) disjoint subdomains of consecutive curve positions
+ *     (sizes w = floor(N / P) and w + 1, the larger first), each extended by
+ *     floor(w / 2) positions on either side (overlap gamma = 1/2) and weighted
+ *     by 1/2 (1 for P = 1); the coarse space has one constant per block of
+ *     each disjoint subdomain cut into q = 2^(S-4) consecutive blocks (at
+ *     least 1); subdomain and coarse problems are the Galerkin restrictions
+ *     of the step matrix A = I + dt L, solved exactly by dense inverses the
+ *     plan computes on the device for every MGRIT level. With CG the
+ *     balanced form G^T C1 G + F (G = I - A F) is used, with BiCGStab the
+ *     additive form C1 + F (Section 4.1). Every grid then runs on the
+ *     streaming solver (FP64, one work-group of 1,024 threads per task). */
+typedef enum { CTM_PRECOND_LINE = 0, CTM_PRECOND_SCHWARZ = 1 } ctm_precond;
+
 typedef struct {
   int d;         /* 1..CTM_MAXD */
   int level_n;   /* sparse-grid level n (the paper's L) */
@@ -151,6 +170,9 @@ typedef struct {
                          FP32 noise floor); streaming grids step in FP64. Needs MGRIT (two
                          or more levels), warm_start and no manufactured forcing;
                          krylov_tol, coarse_tol and refine_tol are unused. */
+  ctm_precond precond; /* CTM_PRECOND_LINE (the default) or CTM_PRECOND_SCHWARZ */
+  int schwarz_s;       /* CTM_PRECOND_SCHWARZ: subdomains of about 2^S unknowns, 2 <= S <= 6
+                          (default 5); a grid may have at most 1,024 coarse blocks */
 } ctm_problem;
 
 typedef struct {
@@ -188,7 +210,8 @@ typedef struct {
 } ctm_stats;
 
 /* Fill *p with the paper's solver defaults (Section 4.1): two-level MGRIT,
- * c = 2, FCF, tolerances 1e-8, CG, FP64, L0 = 1, s = 1, and the unit box. */
+ * c = 2, FCF, tolerances 1e-8, CG, FP64, L0 = 1, s = 1, and the unit box;
+ * the line preconditioner (schwarz_s = 5 for CTM_PRECOND_SCHWARZ). */
 ctm_status ctm_problem_defaults(ctm_problem* p);
 
 /* Validate *p, enumerate the component grids (Section 2.1.1, combination
@@ -223,6 +246,15 @@ ctm_status ctm_initial_state(ctm_plan* plan, double* u0_out, ctm_stream s);
  * (the system matrix of one backward-Euler step, Section 2). FP64. x and y
  * are packed vectors and must not overlap. Async. */
 ctm_status ctm_apply(ctm_plan* plan, int level, const double* x, double* y, ctm_stream s);
+
+/* y = C x on every grid with the Schwarz preconditioner C of MGRIT level
+ * `level` (Section 2.1.2: the balanced form for CG, the additive form for
+ * BiCGStab; see CTM_PRECOND_SCHWARZ). FP64. x and y are packed vectors and
+ * must not overlap. Needs a plan with precond = CTM_PRECOND_SCHWARZ
+ * (CTM_ERR_INVALID otherwise). Allocates its scratch and returns after the
+ * result is complete (the stream is synchronised). */
+ctm_status ctm_precond_apply(ctm_plan* plan, int level, const double* x, double* y,
+                             ctm_stream s);
 
 /* y = Phi_level^nsteps x on every grid: nsteps backward-Euler steps of size
  * dt_level, all grids in one batched launch (time-sequential stepping,

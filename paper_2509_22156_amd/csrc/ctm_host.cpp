@@ -167,6 +167,17 @@ struct ctm_plan {
   double* dhcoef = nullptr; // [slen] combination coefficient of the entry's grid
   double* dhsg = nullptr;   // [hnodes] combined surpluses
   std::vector<hipEvent_t> sync_events;    // fork/join events
+  // two-level Schwarz preconditioner (precond = CTM_PRECOND_SCHWARZ): grid
+  // and subdomain records, index arrays, the owner grid of every subdomain,
+  // and per MGRIT level the dense local and coarse inverses
+  bool schwarz = false;
+  SchwarzGrid* dsch_grid = nullptr;
+  SchwarzSub* dsch_sub = nullptr;
+  int* dsch_ints = nullptr;
+  int* dsch_subgrid = nullptr;
+  std::vector<double*> dsch_linv, dsch_cinv;
+  long long sch_nsub = 0;
+  int sch_nmax = 0, sch_nbmax = 0;
   ctm_stats stats;
   bool timing = false;
   std::vector<hipEvent_t> events;  // pairs (start, stop) per timed launch
@@ -202,6 +213,12 @@ struct ctm_plan {
     for (auto e : sync_events) hipEventDestroy(e);
     for (auto s : cstreams)
       if (s) hipStreamDestroy(s);
+    hipFree(dsch_grid);
+    hipFree(dsch_sub);
+    hipFree(dsch_ints);
+    hipFree(dsch_subgrid);
+    for (auto p : dsch_linv) hipFree(p);
+    for (auto p : dsch_cinv) hipFree(p);
   }
 };
 
@@ -337,6 +354,15 @@ ctm_status validate(const ctm_problem* p) {
     return fail(CTM_ERR_INVALID,
                 "residual_mode needs MGRIT (two or more levels), warm_start and no manufactured "
                 "forcing");
+  if (as_int(&p->precond) != CTM_PRECOND_LINE && as_int(&p->precond) != CTM_PRECOND_SCHWARZ)
+    return fail(CTM_ERR_INVALID, "unknown preconditioner");
+  if (p->precond == CTM_PRECOND_SCHWARZ) {
+    if (p->schwarz_s < kSchwarzMinS || p->schwarz_s > kSchwarzMaxS)
+      return fail(CTM_ERR_INVALID, "schwarz_s must be in 2..6");
+    if (p->manufactured != CTM_MMS_NONE)
+      return fail(CTM_ERR_INVALID, "the Schwarz preconditioner runs every grid on the streaming "
+                                   "solver, which has no manufactured forcing");
+  }
   if (p->op == CTM_OP_DRIFT) {
     for (int i = 0; i < p->d; ++i)
       if (!(p->diffusion[i] >= 0) || !std::isfinite(p->diffusion[i]))
@@ -505,6 +531,21 @@ void set_shape(ctm_plan* P, int g, int sh) {
   assign_lanes(P);
 }
 
+// The Schwarz preconditioner of MGRIT level `level` (empty without it).
+SchwarzView schwarz_view(const ctm_plan* P, int level) {
+  SchwarzView v;
+  std::memset(&v, 0, sizeof(v));
+  if (!P->schwarz || level < 0 || level >= (int)P->dsch_linv.size()) return v;
+  v.grid = P->dsch_grid;
+  v.sub = P->dsch_sub;
+  v.ints = P->dsch_ints;
+  v.linv = P->dsch_linv[level];
+  v.cinv = P->dsch_cinv[level];
+  v.balanced = (P->solver == SOLV_CG) ? 1 : 0;
+  v.nbmax = P->sch_nbmax;
+  return v;
+}
+
 // mgrit: arguments of an MGRIT relaxation or coarse chain (residual mode
 // applies there only; plain time stepping always solves to tolerance).
 ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false,
@@ -524,6 +565,7 @@ ChainArgs base_args(ctm_plan* P, int level, int nsteps, bool fp64_only = false,
   a.inner_tol = P->prob.inner_tol;
   a.status = reinterpret_cast<int*>(P->dsync + 1);
   a.skip = P->skip;
+  a.sch = schwarz_view(P, level);
   if (mgrit && P->prob.residual_mode) {  // fixed-count steps on every level
     a.resmode = 1;
     a.tol = 0.0;
@@ -600,7 +642,7 @@ hipEvent_t take_event(ctm_plan* P, size_t& used, std::vector<hipEvent_t>& pool, 
 
 // Whether a launch range runs on the wide streaming solver.
 bool use_wide(const ctm_plan* P, int shape, long long count) {
-  return shape == kStreamShape && count > 0 && count <= P->wide_max_tasks &&
+  return shape == kStreamShape && !P->schwarz && count > 0 && count <= P->wide_max_tasks &&
          count <= P->wide_cap &&
          (size_t)P->tabmax * sizeof(double) + kWideStaticLds <= 65536;
 }
@@ -1528,6 +1570,8 @@ ctm_status ctm_problem_defaults(ctm_problem* p) {
   p->inner_tol = 1e-5;
   p->refine_maxit = 10;
   p->warm_start = 1;
+  p->precond = CTM_PRECOND_LINE;
+  p->schwarz_s = 5;
   return CTM_OK;
 }
 
@@ -1671,13 +1715,15 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   P->shape = pick_shape(P->hdev);
   P->gshape.resize(P->G);
   int nstream = 0, maxstream = 0;
+  P->schwarz = (prob->precond == CTM_PRECOND_SCHWARZ);
   for (int g = 0; g < P->G; ++g) {
-    const int sh = grid_shape_fitting(P, P->hdev[g]);
+    // the Schwarz preconditioner lives in the streaming solver only
+    const int sh = P->schwarz ? -1 : grid_shape_fitting(P, P->hdev[g]);
     P->gshape[g] = sh >= 0 ? sh : kStreamShape;
     if (sh < 0) {
       ++nstream;
       maxstream = std::max(maxstream, P->hdev[g].npts);
-      if (P->hdev[g].ns > 1024) {
+      if (!P->schwarz && P->hdev[g].ns > 1024) {
         delete P;
         return fail(CTM_ERR_INVALID, "a component grid has lines longer than 1024 unknowns");
       }
@@ -1773,6 +1819,59 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   for (int g = 0; g < P->G; ++g) ident[g] = make_int2(g, 0);
   CTM_HIPC(hipMalloc(&P->didentity, P->G * sizeof(int2)));
   CTM_HIPC(hipMemcpy(P->didentity, ident.data(), P->G * sizeof(int2), hipMemcpyHostToDevice));
+  if (P->schwarz) {
+    std::vector<SchwarzGrid> sgs(P->G);
+    std::vector<SchwarzSub> subs;
+    std::vector<int> ints, subgrid;
+    long long linv_len = 0, cinv_len = 0;
+    for (int g = 0; g < P->G; ++g) {
+      std::string msg;
+      std::memset(&sgs[g], 0, sizeof(SchwarzGrid));
+      if (!schwarz_decompose(P->hdev[g], prob->schwarz_s, sgs[g], subs, ints, linv_len, cinv_len,
+                             msg))
+        return cleanup(fail(CTM_ERR_INVALID, msg));
+      subgrid.resize(subs.size(), g);
+      P->sch_nmax = std::max(P->sch_nmax, sgs[g].nmax);
+      P->sch_nbmax = std::max(P->sch_nbmax, sgs[g].nblk);
+    }
+    P->sch_nsub = (long long)subs.size();
+    CTM_HIPC(hipMalloc(&P->dsch_grid, P->G * sizeof(SchwarzGrid)));
+    CTM_HIPC(hipMemcpy(P->dsch_grid, sgs.data(), P->G * sizeof(SchwarzGrid),
+                       hipMemcpyHostToDevice));
+    CTM_HIPC(hipMalloc(&P->dsch_sub, subs.size() * sizeof(SchwarzSub)));
+    CTM_HIPC(hipMemcpy(P->dsch_sub, subs.data(), subs.size() * sizeof(SchwarzSub),
+                       hipMemcpyHostToDevice));
+    CTM_HIPC(hipMalloc(&P->dsch_ints, ints.size() * sizeof(int)));
+    CTM_HIPC(hipMemcpy(P->dsch_ints, ints.data(), ints.size() * sizeof(int),
+                       hipMemcpyHostToDevice));
+    CTM_HIPC(hipMalloc(&P->dsch_subgrid, subgrid.size() * sizeof(int)));
+    CTM_HIPC(hipMemcpy(P->dsch_subgrid, subgrid.data(), subgrid.size() * sizeof(int),
+                       hipMemcpyHostToDevice));
+    // the inverses of every MGRIT level (step dt c^level)
+    const int levels = std::max(1, prob->mgrit_levels);
+    int* dstat = reinterpret_cast<int*>(P->dsync + 1);
+    for (int l = 0; l < levels; ++l) {
+      double* li = nullptr;
+      double* ci = nullptr;
+      if (hipMalloc(&li, std::max<long long>(1, linv_len) * sizeof(double)) != hipSuccess ||
+          hipMalloc(&ci, std::max<long long>(1, cinv_len) * sizeof(double)) != hipSuccess) {
+        hipFree(li);
+        hipFree(ci);
+        return cleanup(fail(CTM_ERR_NOMEM, "Schwarz preconditioner allocation failed"));
+      }
+      P->dsch_linv.push_back(li);
+      P->dsch_cinv.push_back(ci);
+      const SchwarzView v = schwarz_view(P, l);
+      CTM_HIPC(launch_schwarz_setup(P->opc, P->d, P->dgrids, P->G, P->dtab, prob->amp,
+                                    level_dt(P, l), P->tabmax, v, li, ci, P->dsch_subgrid,
+                                    P->sch_nsub, P->sch_nmax, dstat, nullptr));
+    }
+    CTM_HIPC(hipDeviceSynchronize());
+    int flags = 0;
+    CTM_HIPC(hipMemcpy(&flags, dstat, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags) return cleanup(fail(CTM_ERR_BREAKDOWN, "Schwarz preconditioner: singular "
+                                                      "subdomain or coarse matrix"));
+  }
 #undef CTM_HIPC
   reset_stats(P);
   if ((st = prepare_solve(P)) != CTM_OK) {
@@ -1837,11 +1936,35 @@ ctm_status ctm_apply(ctm_plan* P, int level, const double* x, double* y, ctm_str
   return CTM_OK;
 }
 
+ctm_status ctm_precond_apply(ctm_plan* P, int level, const double* x, double* y,
+                             ctm_stream s) {
+  if (!P || !x || !y) return fail(CTM_ERR_INVALID, "NULL argument");
+  if (!P->schwarz) return fail(CTM_ERR_INVALID, "the plan has no Schwarz preconditioner");
+  if (level < 0 || level >= (int)P->dsch_linv.size())
+    return fail(CTM_ERR_INVALID, "level out of range (the plan's MGRIT levels)");
+  if (x == y) return fail(CTM_ERR_INVALID, "x and y must not overlap");
+  hipStream_t hs = (hipStream_t)s;
+  const long long ss = ((long long)P->maxpts + 63) / 64 * 64;
+  double* scratch = nullptr;
+  if (hipMalloc(&scratch, (size_t)P->G * kStreamVectors * (size_t)ss * sizeof(double)) !=
+      hipSuccess)
+    return fail(CTM_ERR_NOMEM, "preconditioner scratch allocation failed");
+  hipError_t e = launch_schwarz_apply(P->opc, P->solver, P->d, P->dgrids, P->G, P->dtab,
+                                      P->prob.amp, level_dt(P, level), P->tabmax,
+                                      schwarz_view(P, level), x, y, scratch, ss, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  hipFree(scratch);
+  if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("preconditioner: ") + hipGetErrorString(e));
+  return CTM_OK;
+}
+
 ctm_status ctm_propagate(ctm_plan* P, int level, long long nsteps, const double* x, double* y,
                          int per_grid, ctm_stream s) {
   if (!P || !x || !y) return fail(CTM_ERR_INVALID, "NULL argument");
   if (level < 0 || level > 16 || nsteps < 0 || nsteps > (1LL << 30))
     return fail(CTM_ERR_INVALID, "level or nsteps out of range");
+  if (P->schwarz && level >= (int)P->dsch_linv.size())
+    return fail(CTM_ERR_INVALID, "the Schwarz preconditioner is built for the plan's MGRIT levels");
   hipStream_t hs = (hipStream_t)s;
   reset_stats(P);
   ctm_status st = reset_device_stats(P, hs);

@@ -1,6 +1,9 @@
 // Internal structures shared by the host driver and the HIP kernels.
 #pragma once
 
+#include <string>
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -60,6 +63,42 @@ struct VecRef {
   long long a, b;
 };
 
+// Two-level overlapping Schwarz preconditioner (Section 2.1.2) of one grid:
+// its subdomain records and index arrays (offsets into SchwarzView::ints),
+// and its coarse inverse (offset into a level's coarse buffer).
+struct SchwarzGrid {
+  long long sub0;  // first subdomain record of the grid
+  long long cord;  // curve order: grid point at each curve position (npts ints)
+  long long cblk;  // coarse block of every grid point (npts ints)
+  long long bst;   // first curve position of each coarse block (nblk + 1 ints)
+  long long cinv;  // A_0^-1, nblk x nblk column-major (doubles)
+  int nsub;        // subdomains P
+  int nblk;        // coarse blocks
+  int nmax;        // largest extended subdomain
+  int pad_;
+};
+struct SchwarzSub {
+  long long idx;   // grid points of the extended subdomain, curve order (n ints)
+  long long srt;   // (point, local row) pairs sorted by point (2 n ints)
+  long long inv;   // (R_i A R_i^T)^-1, n x n column-major (doubles, in a level's buffer)
+  int n;           // unknowns of the extended subdomain
+  int pad_;
+  double omega;    // weight D_i = omega_i I
+};
+// What a launch needs of the preconditioner; grid == nullptr: the line
+// preconditioner instead.
+struct SchwarzView {
+  const SchwarzGrid* grid;  // [G]
+  const SchwarzSub* sub;
+  const int* ints;
+  const double* linv;       // local inverses of the launch's MGRIT level
+  const double* cinv;       // coarse inverses of the launch's MGRIT level
+  int balanced;             // 1: G^T C1 G + F (CG); 0: C1 + F (BiCGStab)
+  int nbmax;                // largest coarse block count (LDS of a launch)
+};
+constexpr int kSchwarzMaxBlocks = 1024;
+constexpr int kSchwarzMinS = 2, kSchwarzMaxS = 6;
+
 // Arguments of one launch of the chain kernel. A task (g, q) takes grid g,
 // loads the start vector of index start.a*q + start.b, applies `nsteps`
 // implicit steps v <- Phi(v) + forcing_j and stores according to the roles.
@@ -97,6 +136,7 @@ struct ChainArgs {
                             // work queued past the converged iteration)
   int pcrmax;               // cyclic-reduction steps the LDS of the launch holds per lane
                             // (at least log2 of the lanes per line of every grid of it)
+  SchwarzView sch;          // streaming launches: the Schwarz preconditioner, if chosen
 };
 
 enum {
@@ -314,5 +354,34 @@ hipError_t launch_class_vec_add(const int2* tasks, int ntasks, const GridDev* gr
                                 const double* skip);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s,
                             const double* skip = nullptr);
+
+// ------------------------------------------------ Schwarz preconditioner
+// Host decomposition of one grid (Section 2.1.2): Hilbert-curve order of
+// the unknowns with virtual nodes, disjoint partition, overlap, weights and
+// coarse blocks. Appends the grid's subdomain records and index arrays to
+// `subs` / `ints` and fills `sg` (offsets into those; `sg.cinv` and the
+// records' `inv` are offsets into the per-level inverse buffers, advanced in
+// `linv_len` / `cinv_len`). Returns false (and a message) when the grid
+// exceeds the preconditioner's limits.
+bool schwarz_decompose(const GridDev& gd, int S, SchwarzGrid& sg, std::vector<SchwarzSub>& subs,
+                       std::vector<int>& ints, long long& linv_len, long long& cinv_len,
+                       std::string& msg);
+// Device set-up of one MGRIT level (step dt): the dense local matrices
+// R_i A R_i^T of every subdomain (records subs[0..nsub_total), owner grid
+// sub_grid[i]) into linv, the coarse matrices R_0 A R_0^T of every grid into
+// cinv, then both inverted in place (Gauss-Jordan with partial pivoting);
+// *status gets the breakdown bit for a singular pivot.
+hipError_t launch_schwarz_setup(int opc, int d, const GridDev* grids, int G, const double* tab64,
+                                double amp, double dt, int tabmax, const SchwarzView& v,
+                                double* linv, double* cinv, const int* sub_grid,
+                                long long nsub_total, int nmax_sub, int* status,
+                                hipStream_t s);
+// y = C x on every grid (one work-group per grid) with the Schwarz
+// preconditioner of the view's level; scratch holds kStreamVectors vectors
+// of ss doubles per grid.
+hipError_t launch_schwarz_apply(int opc, int solver, int d, const GridDev* grids, int G,
+                                const double* tab64, double amp, double dt, int tabmax,
+                                const SchwarzView& v, const double* x, double* y,
+                                double* scratch, long long ss, hipStream_t s);
 
 }  // namespace ctm

@@ -420,11 +420,136 @@ __device__ double stream_linepre_apply(const GridDev& g, const double* sv, long 
   return acc;
 }
 
+// ------------------------------------------------ Schwarz preconditioner
+// The two-level overlapping Schwarz preconditioner of Section 2.1.2 on one
+// task's grid (dense subdomain and coarse inverses computed at plan set-up,
+// column-major, so that the threads of consecutive rows read consecutive
+// addresses). cw: 3 * nbmax doubles of LDS.
+
+// z (+)= C1 y: z_Omega_i += omega_i (R_i A R_i^T)^-1 y_Omega_i. The
+// subdomains of one parity are disjoint (the overlap is at most half a
+// subdomain), so each parity is one pass without write conflicts; the rows
+// of a pass are spread over the work-group, nmax per subdomain. z must be
+// set (zero) and y complete on entry; ends with a barrier.
+__device__ __forceinline__ void schwarz_local(const SchwarzView& v, const SchwarzGrid& sg,
+                                              const double* y, double* z) {
+  const int nm = sg.nmax;
+#pragma unroll 1
+  for (int par = 0; par < 2; ++par) {
+    const int nsp = (sg.nsub - par + 1) / 2;  // subdomains of this parity
+    const long long rows = (long long)nsp * nm;
+    for (long long f = threadIdx.x; f < rows; f += kStreamThreads) {
+      const int k = par + 2 * (int)(f / nm);
+      const int r = (int)(f % nm);
+      const SchwarzSub& sb = v.sub[sg.sub0 + k];
+      if (r >= sb.n) continue;
+      const int* idx = v.ints + sb.idx;
+      const double* M = v.linv + sb.inv;
+      const int n = sb.n;
+      double acc = 0.0;
+#pragma unroll 4
+      for (int c = 0; c < n; ++c) acc += M[(long long)c * n + r] * y[idx[c]];
+      z[idx[r]] += sb.omega * acc;
+    }
+    __syncthreads();
+  }
+}
+
+// wc[a] = (A_0^-1 R_0 y)_a in LDS (sums holds R_0 y on the way). y
+// complete on entry; ends with a barrier.
+__device__ __forceinline__ void schwarz_coarse(const SchwarzView& v, const SchwarzGrid& sg,
+                                               const double* y, double* sums, double* wc) {
+  const int nb = sg.nblk;
+  const int* cord = v.ints + sg.cord;
+  const int* bst = v.ints + sg.bst;
+  for (int a = threadIdx.x; a < nb; a += kStreamThreads) {
+    double sum = 0.0;
+    for (int pos = bst[a]; pos < bst[a + 1]; ++pos) sum += y[cord[pos]];
+    sums[a] = sum;
+  }
+  __syncthreads();
+  const double* Mi = v.cinv + sg.cinv;
+  for (int a = threadIdx.x; a < nb; a += kStreamThreads) {
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += Mi[(long long)b * nb + a] * sums[b];
+    wc[a] = acc;
+  }
+  __syncthreads();
+}
+
+// z = C r: balanced G^T C1 G r + F r (G = I - A F; A symmetric, so G^T =
+// I - F A) or additive C1 r + F r. Returns this thread's part of
+// sum w[p] z[p] when w is given; ends with a barrier. The balanced form uses
+// three scratch vectors of the task (the line preconditioner's factor
+// slots, unused with this preconditioner). Out of line: the Krylov loops
+// that call it stay small enough to be inlined into the kernel.
+template <int OPC, int D>
+__device__ __noinline__ double schwarz_apply(const GridDev& g, const double* tl, double dt,
+                                             double amp, const SchwarzView& v,
+                                             const SchwarzGrid& sg, double* cw, double* sv,
+                                             long long ss, const double* r, double* z,
+                                             const double* w) {
+  const int np = g.npts;
+  const int* cblk = v.ints + sg.cblk;
+  double* c0 = cw;                  // A_0^-1 R_0 r
+  double* c1 = cw + v.nbmax;        // block sums of a coarse solve
+  double* c2 = cw + 2 * v.nbmax;    // A_0^-1 R_0 A C1 G r (balanced)
+  double acc = 0.0;
+  if (v.balanced) {
+    double* T = sv + SV_FM * ss;   // F r
+    double* U = sv + SV_FID * ss;  // G r = r - A F r
+    double* Y = sv + SV_FCU * ss;  // A C1 G r
+    schwarz_coarse(v, sg, r, c1, c0);
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) T[p] = c0[cblk[p]];
+    __syncthreads();
+    stream_apply<OPC, D>(g, tl, dt, amp, T, U, nullptr);
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      U[p] = r[p] - U[p];
+      z[p] = 0.0;
+    }
+    __syncthreads();
+    schwarz_local(v, sg, U, z);
+    stream_apply<OPC, D>(g, tl, dt, amp, z, Y, nullptr);
+    __syncthreads();
+    schwarz_coarse(v, sg, Y, c1, c2);  // A_0^-1 R_0 A C1 G r; c0 (for F r) stays
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      const int b = cblk[p];
+      const double zp = z[p] - c2[b] + c0[b];
+      z[p] = zp;
+      if (w) acc += w[p] * zp;
+    }
+  } else {
+    schwarz_coarse(v, sg, r, c1, c0);
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) z[p] = 0.0;
+    __syncthreads();
+    schwarz_local(v, sg, r, z);
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      const double zp = z[p] + c0[cblk[p]];
+      z[p] = zp;
+      if (w) acc += w[p] * zp;
+    }
+  }
+  __syncthreads();
+  return acc;
+}
+
+// The task's preconditioner: Schwarz when the launch carries it (sg), else
+// the line-block solve. Same contract as stream_linepre_apply.
+template <int OPC, int D>
+__device__ __forceinline__ double stream_precond(const GridDev& g, const double* tl,
+                                                 const ChainArgs& a, const SchwarzGrid* sg,
+                                                 double* cw, double* sv, long long ss,
+                                                 const double* r, double* z, const double* w) {
+  if (sg) return schwarz_apply<OPC, D>(g, tl, a.dt, a.amp, a.sch, *sg, cw, sv, ss, r, z, w);
+  return stream_linepre_apply<D>(g, sv, ss, r, z, w);
+}
+
 // One implicit step: x <- (I + dt L)^-1 b, x holding the initial guess.
 // Preconditioned CG (symmetric operators).
 template <int OPC, int D>
 __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a, double* sv,
-                         long long ss, RedRing& ring, double tol2, int* flag, double* rr0) {
+                         long long ss, RedRing& ring, double tol2, int* flag, double* rr0,
+                         const SchwarzGrid* sg, double* cw) {
   double* X = sv + SV_X * ss;
   double* B = sv + SV_B * ss;
   double* R = sv + SV_R * ss;
@@ -448,7 +573,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
   }
   *rr0 = s0[0];  // the initial residual (residual mode's F-step norm)
   if (s0[0] <= tol2 * bb) return 0;
-  double rz1[1] = {stream_linepre_apply<D>(g, sv, ss, R, Z, R)};
+  double rz1[1] = {stream_precond<OPC, D>(g, tl, a, sg, cw, sv, ss, R, Z, R)};
   block_sum<kStreamW, 1, double>(rz1, ring);
   double rz = rz1[0];
   for (int p = threadIdx.x; p < np; p += kStreamThreads) P[p] = Z[p];
@@ -474,7 +599,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
       return it;
     }
     if (s1[0] <= tol2 * bb) return it;
-    double rzn[1] = {stream_linepre_apply<D>(g, sv, ss, R, Z, R)};
+    double rzn[1] = {stream_precond<OPC, D>(g, tl, a, sg, cw, sv, ss, R, Z, R)};
     block_sum<kStreamW, 1, double>(rzn, ring);
     const double beta = rzn[0] / rz;
     rz = rzn[0];
@@ -491,7 +616,7 @@ __device__ int stream_cg(const GridDev& g, const double* tl, const ChainArgs& a,
 template <int OPC, int D>
 __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainArgs& a,
                                double* sv, long long ss, RedRing& ring, double tol2,
-                               int* flag, double* rr0) {
+                               int* flag, double* rr0, const SchwarzGrid* sg, double* cw) {
   double* X = sv + SV_X * ss;
   double* B = sv + SV_B * ss;
   double* R = sv + SV_R * ss;
@@ -522,7 +647,7 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
   if (s0[0] <= tol2 * bb) return 0;
   double rho = s0[0];
   for (int it = 1; it <= a.maxit; ++it) {
-    stream_linepre_apply<D>(g, sv, ss, P, H, nullptr);
+    stream_precond<OPC, D>(g, tl, a, sg, cw, sv, ss, P, H, nullptr);
     double s2[1] = {stream_apply<OPC, D>(g, tl, a.dt, a.amp, H, V, RH)};
     block_sum<kStreamW, 1, double>(s2, ring);
     if (!(s2[0] != 0.0) || !(s2[0] == s2[0])) {
@@ -535,7 +660,7 @@ __device__ int stream_bicgstab(const GridDev& g, const double* tl, const ChainAr
       S[p] = R[p] - alpha * V[p];
     }
     __syncthreads();  // S complete before the preconditioner reads whole lines
-    stream_linepre_apply<D>(g, sv, ss, S, H, nullptr);
+    stream_precond<OPC, D>(g, tl, a, sg, cw, sv, ss, S, H, nullptr);
     double s3[3] = {0.0, 0.0, 0.0};  // (t, s), (t, t), (s, s)
     for (int p = threadIdx.x; p < np; p += kStreamThreads) {
       PointCoef<OPC, D> c;
@@ -610,7 +735,6 @@ __global__ void __launch_bounds__(kStreamThreads)
   const GridDev& g = gs;
   load_tables<OPC, double, kStreamThreads>(g, a.tab64, a.dt, tl);
   __syncthreads();
-  (void)tabmax;
   double* sv = scratch + (long long)blockIdx.x * SV_N * ss;
   double* X = sv + SV_X * ss;
   double* B = sv + SV_B * ss;
@@ -624,9 +748,12 @@ __global__ void __launch_bounds__(kStreamThreads)
     B[p] = v;
     if (wb) wb[p] = v;
   }
-  // the preconditioner's factors, once per chain (each lane later reads only
+  // the Schwarz preconditioner (its LDS after the tables), or the line
+  // preconditioner's factors, once per chain (each lane later reads only
   // what it wrote here)
-  stream_linepre_setup<OPC, D>(g, tl, a.dt, a.amp, sv, ss, sv + SV_S * ss);
+  const SchwarzGrid* sg = a.sch.grid ? a.sch.grid + task.x : nullptr;
+  double* cw = tl + tabmax;
+  if (!sg) stream_linepre_setup<OPC, D>(g, tl, a.dt, a.amp, sv, ss, sv + SV_S * ss);
   __syncthreads();
   RedRing ring{red, 0};
   int flag = 0;
@@ -664,9 +791,9 @@ __global__ void __launch_bounds__(kStreamThreads)
     int it;
     double r0 = 0.0;
     if constexpr (SOLVER == SOLV_CG)
-      it = stream_cg<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag, &r0);
+      it = stream_cg<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag, &r0, sg, cw);
     else
-      it = stream_bicgstab<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag, &r0);
+      it = stream_bicgstab<OPC, D>(g, tl, a, sv, ss, ring, tol2, &flag, &r0, sg, cw);
     if (res) {
       flag &= ~(FLAG_NOCONV | FLAG_BREAKDOWN);
       res_max = r0 > res_max ? r0 : res_max;
@@ -713,7 +840,9 @@ template <int OPC, int SOLVER, int D>
 hipError_t launch_stream_t(const ChainArgs& a, int ntasks, int tabmax, double* scratch,
                            long long ss, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-  const size_t smem = (size_t)tabmax * sizeof(double);
+  // the coefficient tables, then the Schwarz preconditioner's coarse vectors
+  const size_t smem =
+      ((size_t)tabmax + (a.sch.grid ? 3 * (size_t)a.sch.nbmax : 0)) * sizeof(double);
   hipLaunchKernelGGL((stream_kernel<OPC, SOLVER, D>), dim3(ntasks), dim3(kStreamThreads), smem, s,
                      a, tabmax, scratch, ss);
   return hipGetLastError();

@@ -25,6 +25,7 @@ _OPS = {"heat": 0, "varcoef": 1, "ou": 2, "cme": 3, "drift": 4}
 _KRYLOV = {"auto": 0, "cg": 1, "bicgstab": 2}
 _PREC = {"fp64": 0, "mixed": 1}
 _RELAX = {"F": 0, "FCF": 1}
+_PRECOND = {"line": 0, "schwarz": 1}
 
 
 class Problem(ctypes.Structure):
@@ -47,6 +48,7 @@ class Problem(ctypes.Structure):
         ("manufactured", ctypes.c_int),
         ("drift", ctypes.c_double * (MAXD * MAXD)), ("diffusion", ctypes.c_double * MAXD),
         ("residual_mode", ctypes.c_int),
+        ("precond", ctypes.c_int), ("schwarz_s", ctypes.c_int),
     ]
 
 
@@ -96,6 +98,7 @@ def _load():
         "ctm_plan_workspace_bytes": [P, ctypes.POINTER(sz)],
         "ctm_initial_state": [P, P, P],
         "ctm_apply": [P, i, P, P, P],
+        "ctm_precond_apply": [P, i, P, P, P],
         "ctm_propagate": [P, i, ll, P, P, i, P],
         "ctm_solve": [P, P, sz, P, P, P],
         "ctm_solve_noalloc": [P, P, P, P],
@@ -199,6 +202,8 @@ def problem_struct(prob: dict):
     s.warm_start = int(prob.get("warm_start", 1))
     s.manufactured = 1 if prob.get("manufactured") == "heat" else 0
     s.residual_mode = int(prob.get("residual_mode", 0))
+    s.precond = _PRECOND[prob.get("precond", "line")]
+    s.schwarz_s = int(prob.get("schwarz_s", 5))
     if prob["op"] == "drift":
         th = np.asarray(prob["drift"], dtype=np.float64)
         for i in range(d):
@@ -266,6 +271,13 @@ class Plan:
         self._inp(x, "x")
         out = self._vec(out)
         _check(_lib.ctm_apply(self._h, level, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def precond_apply(self, x, level: int = 0, out=None):
+        """y = C x with the plan's Schwarz preconditioner (ctm_precond_apply)."""
+        self._inp(x, "x")
+        out = self._vec(out)
+        _check(_lib.ctm_precond_apply(self._h, level, _ptr(x), _ptr(out), _stream()))
         return out
 
     def propagate(self, x, nsteps: int, level: int = 0, per_grid: bool = False, out=None):
@@ -387,7 +399,7 @@ def exported_symbols():
     """Names of the entry points declared in include/ctm.h."""
     return ["ctm_problem_defaults", "ctm_plan_create", "ctm_plan_destroy", "ctm_plan_grids",
             "ctm_plan_grid_info", "ctm_plan_state_len", "ctm_plan_workspace_bytes",
-            "ctm_initial_state", "ctm_apply", "ctm_propagate", "ctm_solve", "ctm_solve_noalloc",
+            "ctm_initial_state", "ctm_apply", "ctm_precond_apply", "ctm_propagate", "ctm_solve", "ctm_solve_noalloc",
             "ctm_gather",
             "ctm_combine_project", "ctm_hierarchize", "ctm_recombine", "ctm_get_stats", "ctm_set_timing", "ctm_plan_grid_shape",
             "ctm_plan_set_grid_shape", "ctm_plan_set_wide", "ctm_plan_set_schedule", "ctm_autotune", "ctm_status_string",

@@ -128,6 +128,9 @@ int main() {
   CHECK(ctm_gather(nullptr, nullptr, nullptr, 0, nullptr, nullptr) == CTM_ERR_INVALID, "gather(NULL)");
   CHECK(ctm_set_timing(nullptr, 1) == CTM_ERR_INVALID, "set_timing(NULL)");
   CHECK(ctm_plan_set_wide(nullptr, 1) == CTM_ERR_INVALID, "set_wide(NULL)");
+  CHECK(ctm_plan_set_schedule(nullptr, 1) == CTM_ERR_INVALID, "set_schedule(NULL)");
+  CHECK(ctm_precond_apply(nullptr, 0, nullptr, nullptr, nullptr) == CTM_ERR_INVALID,
+        "precond_apply(NULL)");
   CHECK(std::strlen(ctm_status_string((ctm_status)99)) > 0, "status string of an unknown code");
   std::printf("ok   NULL arguments\n");
 
@@ -161,6 +164,9 @@ int main() {
       {"17 initial terms", [](ctm_problem& p) { p.ic_terms = 17; }},
       {"residual mode on one level", [](ctm_problem& p) { p.residual_mode = 1; p.mgrit_levels = 1; }},
       {"mixed with refine_tol 0", [](ctm_problem& p) { p.prec = CTM_PREC_MIXED; p.refine_tol = 0; }},
+      {"unknown preconditioner", [](ctm_problem& p) { int v = 3; std::memcpy(&p.precond, &v, sizeof v); }},
+      {"Schwarz S = 1", [](ctm_problem& p) { p.precond = CTM_PRECOND_SCHWARZ; p.schwarz_s = 1; }},
+      {"Schwarz S = 7", [](ctm_problem& p) { p.precond = CTM_PRECOND_SCHWARZ; p.schwarz_s = 7; }},
   };
   for (const Bad& b : bad) {
     ctm_problem p = base(2, 5, CTM_OP_HEAT);

@@ -33,4 +33,10 @@ hipError_t launch_vec_add(VecRef, VecRef, VecRef, int, long long, hipStream_t, c
 hipError_t launch_class_vec_add(const int2*, int, const GridDev*, VecRef, VecRef, VecRef, int,
                                 long long, hipStream_t, const double*) CTM_STUB()
 hipError_t launch_fill_zero(double*, long long, hipStream_t, const double*) CTM_STUB()
+hipError_t launch_schwarz_setup(int, int, const GridDev*, int, const double*, double, double, int,
+                                const SchwarzView&, double*, double*, const int*, long long, int,
+                                int*, hipStream_t) CTM_STUB()
+hipError_t launch_schwarz_apply(int, int, int, const GridDev*, int, const double*, double, double,
+                                int, const SchwarzView&, const double*, double*, double*,
+                                long long, hipStream_t) CTM_STUB()
 }  // namespace ctm

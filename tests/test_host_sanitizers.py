@@ -1,4 +1,5 @@
-"""The plan and driver code of the library (csrc/ctm_host.cpp) built for the
+"""The plan and driver code of the library (csrc/ctm_host.cpp, and the
+Schwarz decomposition of csrc/schwarz_plan.cpp) built for the
 host with AddressSanitizer and UndefinedBehaviorSanitizer, linked with
 launcher stubs instead of the device kernels (tests/asan/stubs.cpp), and
 driven through the C ABI by tests/asan/driver.cpp: validation and rejection
@@ -34,6 +35,7 @@ def _build(tmp_path):
         pytest.skip("needs g++ and the HIP runtime library")
     exe = tmp_path / "host_driver"
     srcs = [os.path.join(ROOT, "paper_2509_22156_amd", "csrc", "ctm_host.cpp"),
+            os.path.join(ROOT, "paper_2509_22156_amd", "csrc", "schwarz_plan.cpp"),
             os.path.join(ROOT, "tests", "asan", "stubs.cpp"),
             os.path.join(ROOT, "tests", "asan", "driver.cpp")]
     objs = []
