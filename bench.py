@@ -452,6 +452,26 @@ def _heat3d(ctm, torch):
     return out
 
 
+def _schwarz(ctm, torch):
+    """The paper's spatial preconditioner (Section 2.1.2) beside the line
+    preconditioner on the 3-D heat workload in FP64 at the measurement's
+    tolerances: solve time, MGRIT and Krylov iterations. With Schwarz every
+    grid runs on the streaming solver (one 1,024-thread work-group per task,
+    vectors in HBM), balanced form with CG, subdomains of 2^5 unknowns."""
+    out = {}
+    for tag, kw in (("line", {}), ("schwarz_S5", dict(precond="schwarz", schwarz_s=5))):
+        p = workload_problem("heat3d", "fp64")
+        p.update(kw)
+        plan = ctm.Plan(p)
+        sec, _ = _timed(torch, lambda: plan.solve(), reps=2)
+        st = plan.stats()
+        out[tag] = {"seconds": sec, "mgrit_iterations": st["mgrit_iterations"],
+                    "krylov_iterations": st["krylov_iterations"],
+                    "krylov_per_solve": st["krylov_iterations"] / max(1, st["phi_solves"])}
+        del plan
+    return out
+
+
 def _roofline(shapes, d, krylov, prec, copy_gbps):
     """Roofline of the dominant kernel: the size class of the implicit-step
     kernel with the most device time. Its algorithmic HBM bytes are 16 B per
@@ -751,6 +771,8 @@ def main(argv=None):
         if args.workload != "heat3d":
             result["heat3d"] = _heat3d(ctm, torch)
             log(f"heat3d: {result['heat3d']}")
+        result["schwarz_vs_line"] = _schwarz(ctm, torch)
+        log(f"schwarz vs line: {result['schwarz_vs_line']}")
     if args.copy_calibration:
         src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

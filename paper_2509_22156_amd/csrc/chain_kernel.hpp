@@ -286,8 +286,8 @@ __device__ __forceinline__ void step_fp64(const Solver<OPC, double, K>& S, RedRi
 }
 
 // One implicit step by FP64 iterative refinement around FP32 Krylov solves.
-template <int OPC, int SOLVER, int W, int K>
-__device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
+template <int OPC, int SOLVER, int W, int K, class Apply64>
+__device__ __forceinline__ void step_mixed(const Apply64& apply64,
                                            const Solver<OPC, float, K>& S32, RedRing& ring,
                                            const double (&v)[K], double tol2, float itol2,
                                            int maxit, int refine_maxit, double (&x)[K],
@@ -298,7 +298,7 @@ __device__ __forceinline__ void step_mixed(const Solver<OPC, double, K>& S64,
   double bb = 0.0;
   for (; sweeps <= refine_maxit; ++sweeps) {
     double rq[K];
-    sapply<OPC, double, W, K>(S64, x, rq);
+    apply64(x, rq);
     double rr[2] = {0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -397,10 +397,11 @@ enum { MODE_PLAIN = 0, MODE_FORCED = 1, MODE_RESIDUAL = 2 };
 // vector registers per lane: a kernel over 256 runs one wave per SIMD, and
 // the chain kernels, bound by the latency of their reductions and barriers,
 // then idle. The mixed K = 4 kernels of the variable-coefficient operator
-// need a little over 256 (they hold the FP64 and the FP32 line operator:
-// about 290); held to 256 they spill under 40 registers and run two waves
-// per SIMD, measured 25% off the mixed 6-D solve. Held to three waves (168)
-// they spill over 120 registers and run 65% slower.
+// held the FP64 and the FP32 line operator in registers (about 290); with
+// most of the FP64 one parked in LDS they need about 190, and the bound
+// keeps them at two waves should that grow again (held to 256 before the
+// parking they spilled under 40 registers and ran 25% faster than at one
+// wave; held to three waves, 168, they spilled over 120 and ran 65% slower).
 template <int OPC, bool MIXED, int W, int K>
 constexpr int chain_min_waves() { return (OPC == OPC_VAR && K == 4 && MIXED) ? 2 : 1; }
 
@@ -412,7 +413,11 @@ __global__ void __launch_bounds__(64 * W)
   constexpr bool RES = (MODE == MODE_RESIDUAL);
   constexpr int BS = 64 * W;
   extern __shared__ __align__(16) unsigned char smem[];
-  const ChainSmem lay = chain_smem_layout(W, K, tabmax, MIXED, OPC == OPC_HEAT, a.pcrmax);
+  // mixed K = 4 variable-coefficient chains keep most of the FP64 line
+  // operator in LDS (parked after set-up, loaded for each FP64 residual): it
+  // would hold 30 more registers through the FP32 inner solves
+  constexpr bool PARK = MIXED && OPC == OPC_VAR && K == 4;
+  const ChainSmem lay = chain_smem_layout(W, K, tabmax, MIXED, OPC == OPC_HEAT, a.pcrmax, PARK);
   double* xl64 = reinterpret_cast<double*>(smem);
   double* ocv64 = reinterpret_cast<double*>(smem + lay.ocv);
   float* ocv32 = reinterpret_cast<float*>(ocv64 + MAXD);
@@ -445,6 +450,9 @@ __global__ void __launch_bounds__(64 * W)
   setup_lane<K>(g, L);
   LineOp<OPC, double, K> O64;
   lineop_setup<OPC, double, K>(g, L, a.dt, a.amp, tl64, ht64, ocv64, O64);
+  double* op64 = reinterpret_cast<double*>(smem + lay.op);
+  LineOpVarKeep<K> keep64;
+  if constexpr (PARK) lineop_park<K, BS>(O64, op64, keep64);
 
   const long long off = g.off;
   double v[K];
@@ -477,6 +485,17 @@ __global__ void __launch_bounds__(64 * W)
   if constexpr (OPC == OPC_HEAT && MIXED) __syncthreads();  // FP64 weights visible
   const Solver<OPC, double, K> S64{g, L, O64, M64, xl64};
   const Solver<OPC, float, K> S32{g, L, O32, M32, xl32};
+  // y = A x in FP64 (the parked operator is loaded for the apply only)
+  auto apply64 = [&](const double (&xin)[K], double (&yout)[K]) {
+    if constexpr (PARK) {
+      LineOp<OPC, double, K> Ol;
+      lineop_unpark<K, BS>(Ol, op64, keep64, ocv64);
+      const Solver<OPC, double, K> Sl{g, L, Ol, M64, xl64};
+      sapply<OPC, double, W, K>(Sl, xin, yout);
+    } else {
+      sapply<OPC, double, W, K>(S64, xin, yout);
+    }
+  };
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
   double res_max = 0.0;  // residual mode: largest squared residual of the task's steps
 
@@ -539,7 +558,7 @@ __global__ void __launch_bounds__(64 * W)
         // exact space-time residual at the C-point: rho = v - A target
         double tg[K], y[K];
         gload<K>(L, vec_at(a.target, a.target.a * q + a.target.b, a.slen, off), tg);
-        sapply<OPC, double, W, K>(S64, tg, y);
+        apply64(tg, y);
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = (k < L.nval) ? v[k] - y[k] : 0.0;
       } else {
@@ -550,7 +569,7 @@ __global__ void __launch_bounds__(64 * W)
         if constexpr (MIXED) {
           // x += d, A d = v - A x solved in FP32 by a.maxit iterations
           double rq[K];
-          sapply<OPC, double, W, K>(S64, x, rq);
+          apply64(x, rq);
           double rr[1] = {0.0};
           float r32[K], d32[K];
 #pragma unroll
@@ -599,8 +618,8 @@ __global__ void __launch_bounds__(64 * W)
           step_single32<OPC, SOLVER, W, K>(S32, ring, v, itol2, a.maxit, x, &flag, kr_sum,
                                            kr_max);
         else
-          step_mixed<OPC, SOLVER, W, K>(S64, S32, ring, v, tol2, itol2, a.maxit, a.refine_maxit,
-                                        x, &flag, kr_sum, kr_max, rf_sum, rf_max);
+          step_mixed<OPC, SOLVER, W, K>(apply64, S32, ring, v, tol2, itol2, a.maxit,
+                                        a.refine_maxit, x, &flag, kr_sum, kr_max, rf_sum, rf_max);
       } else {
         step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, gr.base != nullptr, x, &flag,
                                      kr_sum, kr_max);

@@ -127,6 +127,10 @@ struct ctm_plan {
   // cyclic-reduction steps of the line preconditioner each size class's LDS
   // table must hold: the largest log2(lanes per line) over its grids
   int pcr_of[kNumShapes] = {};
+  // coefficient-table doubles each size class's LDS must hold: the largest
+  // table of its grids (the plan-wide largest would cost LDS, and with it
+  // work-groups per CU, in classes whose grids have small tables)
+  int tab_of[kNumShapes] = {};
   // hierarchical basis (built on first use): node id of every unknown; per
   // node, the unknowns of all grids that share its basis function
   double block_t0 = 0.0;     // start time of the recombination block being solved
@@ -456,9 +460,15 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Whether grid gd's chain-kernel work-group fits the LDS in shape sh (its
 // line preconditioner's table grows with log2 of the lanes per line).
+// Whether a launch of shape sh keeps the FP64 line operator in LDS: the
+// mixed K = 4 chains of the variable-coefficient operator (chain kernel).
+bool parks_op(const ctm_plan* P, int sh, bool mixed) {
+  return mixed && P->opc == OPC_VAR && sh < kNumShapes && kShapes[sh].K == 4;
+}
+
 bool shape_fits(const ctm_plan* P, const GridDev& gd, int sh) {
   return chain_smem_bytes(sh, P->tabmax, P->mixed, P->opc == OPC_HEAT,
-                          pcr_steps(gd, kShapes[sh].K)) <= kMaxLdsBytes;
+                          pcr_steps(gd, kShapes[sh].K), parks_op(P, sh, P->mixed)) <= kMaxLdsBytes;
 }
 
 // The default shape of grid gd among those whose LDS fits, or -1 (streaming).
@@ -501,10 +511,13 @@ ctm_status tasks_for(ctm_plan* P, long long M, TaskSet** out) {
 // onto the lane (caller's stream or a side stream) with the fewest so far.
 // Also refreshes the classes' cyclic-reduction table sizes.
 void assign_lanes(ctm_plan* P) {
-  for (int s = 0; s < kNumShapes; ++s) P->pcr_of[s] = 0;
+  for (int s = 0; s < kNumShapes; ++s) P->pcr_of[s] = P->tab_of[s] = 0;
   for (int g = 0; g < P->G; ++g) {
     const int s = P->gshape[g];
-    if (s < kNumShapes) P->pcr_of[s] = std::max(P->pcr_of[s], pcr_steps(P->hdev[g], kShapes[s].K));
+    if (s < kNumShapes) {
+      P->pcr_of[s] = std::max(P->pcr_of[s], pcr_steps(P->hdev[g], kShapes[s].K));
+      P->tab_of[s] = std::max(P->tab_of[s], P->hdev[g].tabsz);
+    }
   }
   constexpr int nlanes = ctm_plan::kSideStreams + 1;
   double pts[kNumShapes + 1] = {};
@@ -738,7 +751,8 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   c.pcrmax = (shape == kStreamShape) ? 0 : P->pcr_of[shape];
   const size_t smem = (shape == kStreamShape)
                           ? 0
-                          : chain_smem_bytes(shape, P->tabmax, mixed, P->opc == OPC_HEAT, c.pcrmax);
+                          : chain_smem_bytes(shape, P->tab_of[shape], mixed, P->opc == OPC_HEAT,
+                                             c.pcrmax, parks_op(P, shape, mixed));
   // algorithmic bytes: every vector role of every task once
   P->stats.shape_bytes[slot] += 8.0 * points * chain_vectors_per_task(a);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -762,7 +776,7 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
                         P->stream_ss, s);
     }
   } else {
-    e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tabmax, s);
+    e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tab_of[shape], s);
   }
   if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("chain launch: ") + hipGetErrorString(e));
   if (P->timing) CTM_HIP(hipEventRecord(e1, s));

@@ -277,8 +277,14 @@ struct HeatTab {
 // row 0 the reciprocal reduced diagonal, rows 1 + 2r and 2 + 2r the factors
 // of step r, one column per thread.
 struct ChainSmem {
-  size_t x32, tab, heat, ocv, red, pre, total;  // byte offsets and total
+  size_t x32, tab, heat, ocv, red, pre, op, total;  // byte offsets and total
 };
+// Doubles per lane of the FP64 variable-coefficient line operator that a
+// mixed chain keeps in LDS: its faces (K + 1) and off-axis factors (qlo,
+// qup: MAXD - 1 each); the diagonal and the node sines stay in registers.
+// (Parking those as well measured no faster, even in eight-wave work-groups
+// whose LDS has room for them.)
+__host__ __device__ constexpr int parked_op_words(int K) { return K + 1 + 2 * (MAXD - 1); }
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 __host__ __device__ constexpr size_t heat_tab_bytes(int K, bool mixed) {
   return K == 4 ? align16(sizeof(HeatTab<double, 4>)) +
@@ -289,8 +295,10 @@ __host__ __device__ constexpr size_t heat_tab_bytes(int K, bool mixed) {
 constexpr size_t kOcvBytes = MAXD * sizeof(double) + MAXD * sizeof(float);
 // rows of the cyclic-reduction table for pcr steps (0: no table)
 __host__ __device__ constexpr int pcr_rows(int pcr) { return pcr < 0 ? 0 : 2 * pcr + 1; }
+// park: the FP64 line operator of a mixed variable-coefficient chain lives in
+// LDS (see the chain kernel), after the cyclic-reduction table.
 __host__ __device__ constexpr ChainSmem chain_smem_layout(int W, int K, int tabmax, bool mixed,
-                                                          bool heat, int pcr) {
+                                                          bool heat, int pcr, bool park = false) {
   const size_t elems = (size_t)K * lds_pitch(W);
   const size_t x32 = align16(elems * sizeof(double));
   const size_t tab = x32 + (mixed ? align16(elems * sizeof(float)) : 0);
@@ -301,10 +309,14 @@ __host__ __device__ constexpr ChainSmem chain_smem_layout(int W, int K, int tabm
   const size_t pre = red + 2u * 64u * sizeof(double);
   const size_t prebytes =
       heat ? 0 : align16((size_t)pcr_rows(pcr) * 64u * W * (mixed ? sizeof(float) : sizeof(double)));
-  return ChainSmem{x32, tab, hb, ocv, red, pre, pre + prebytes};
+  const size_t op = pre + prebytes;
+  const size_t opbytes = park ? align16((size_t)parked_op_words(K) * 64u * W * sizeof(double)) : 0;
+  return ChainSmem{x32, tab, hb, ocv, red, pre, op, op + opbytes};
 }
-inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed, bool heat, int pcr) {
-  return chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, mixed, heat, pcr).total;
+inline size_t chain_smem_bytes(int shape, int tabmax, bool mixed, bool heat, int pcr,
+                               bool park = false) {
+  return chain_smem_layout(kShapes[shape].W, kShapes[shape].K, tabmax, mixed, heat, pcr, park)
+      .total;
 }
 
 // Auxiliary kernels (aux_kernels.hip).

@@ -325,6 +325,54 @@ __device__ __forceinline__ void lineop_setup(const GridDev& g, const Lane<K>& L,
   }
 }
 
+// The FP64 variable-coefficient line operator of a mixed chain, partly
+// parked in LDS: the faces and the off-axis factors (parked_op_words(K) per
+// lane) go to LDS, field-major with lane-consecutive slots (word e of
+// thread t at lds[e * BS + t]: every wave access is conflict-free); the
+// diagonal and the node sines stay in registers (LineOpVarKeep). The chain
+// keeps it that way through the FP32 inner solves and loads the parked part
+// back for each FP64 residual.
+template <int K>
+struct LineOpVarKeep {
+  double diag[K];
+  double snj[K];
+};
+template <int K, int BS>
+__device__ __forceinline__ void lineop_park(const LineOp<OPC_VAR, double, K>& O, double* lds,
+                                            LineOpVarKeep<K>& keep) {
+  const int t = threadIdx.x;
+  int e = 0;
+#pragma unroll
+  for (int k = 0; k <= K; ++k) lds[(e++) * BS + t] = O.face[k];
+#pragma unroll
+  for (int m = 0; m < MAXD - 1; ++m) lds[(e++) * BS + t] = O.qlo[m];
+#pragma unroll
+  for (int m = 0; m < MAXD - 1; ++m) lds[(e++) * BS + t] = O.qup[m];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    keep.diag[k] = O.diag[k];
+    keep.snj[k] = O.snj[k];
+  }
+}
+template <int K, int BS>
+__device__ __forceinline__ void lineop_unpark(LineOp<OPC_VAR, double, K>& O, const double* lds,
+                                              const LineOpVarKeep<K>& keep, const double* oc) {
+  const int t = threadIdx.x;
+  int e = 0;
+#pragma unroll
+  for (int k = 0; k <= K; ++k) O.face[k] = lds[(e++) * BS + t];
+#pragma unroll
+  for (int m = 0; m < MAXD - 1; ++m) O.qlo[m] = lds[(e++) * BS + t];
+#pragma unroll
+  for (int m = 0; m < MAXD - 1; ++m) O.qup[m] = lds[(e++) * BS + t];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    O.diag[k] = keep.diag[k];
+    O.snj[k] = keep.snj[k];
+  }
+  O.oc = oc;
+}
+
 template <int OPC, typename T, int K>
 __device__ __forceinline__ T op_diag(const LineOp<OPC, T, K>& O, int k) {
   if constexpr (OPC == OPC_HEAT) return O.h->diag;
