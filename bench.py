@@ -334,6 +334,16 @@ def _comparators(args, ctm, torch, oracle_u, dof_steps):
     return out
 
 
+def _copy_calibration(torch):
+    """A plain 256 MiB device copy, the last kernel of a counter run: its
+    FETCH_SIZE / WRITE_SIZE counts calibrate the kernels' ones."""
+    src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"read": src.numel() * 8, "write": dst.numel() * 8}
+
+
 def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
     """Measured device-to-device copy rate (GB/s, read + write bytes) of a
     plain 1 GiB copy: the practical HBM ceiling beside the 8 TB/s peak."""
@@ -639,7 +649,10 @@ def main(argv=None):
     if args.mms_sweep:
         return mms_sweep(ctm, torch)
     if args.streaming_only:
-        print(json.dumps(_streaming(ctm, torch)), flush=True)
+        out = _streaming(ctm, torch)
+        if args.copy_calibration:
+            out["copy_calibration_bytes"] = _copy_calibration(torch)
+        print(json.dumps(out), flush=True)
         return 0
     t0 = time.perf_counter()
     plan = ctm.Plan(prob)
@@ -774,11 +787,7 @@ def main(argv=None):
         result["schwarz_vs_line"] = _schwarz(ctm, torch)
         log(f"schwarz vs line: {result['schwarz_vs_line']}")
     if args.copy_calibration:
-        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        result["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        result["copy_calibration_bytes"] = _copy_calibration(torch)
 
     print(json.dumps(result), flush=True)
     return 0
