@@ -462,6 +462,30 @@ def _heat3d(ctm, torch):
     return out
 
 
+def _table3_ct(ctm, torch):
+    """Section 4.4.1's time-sequential combination run (Table 3, CT): the 2-D
+    oscillator on L = 14, L0 = 6 (seven grids, 177,415 unknowns per level),
+    20,000 backward-Euler steps of 0.005 to T = 100, FP64 BiCGStab with the
+    line preconditioner to 1e-10, every grid on the wide streaming solver.
+    One solve after a short warm-up; the paper's figure for the same scheme
+    is 1,326 s on 176 cores of its CPU cluster (context, not a target)."""
+    from workloads import make
+    p = make("fp_osc2d", n=14, L0=6, prec="fp64")
+    p.update(t1=100.0, nsteps=20000, mgrit_levels=1, krylov_tol=1e-10, krylov_maxit=20000)
+    plan = ctm.Plan(p)
+    u0 = plan.initial_state()
+    plan.propagate(u0, 40)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    st = plan.stats()
+    return {"seconds": sec, "steps": p["nsteps"], "value": plan.slen * p["nsteps"] / sec,
+            "krylov_iterations": st["krylov_iterations"],
+            "paper_ct_seconds_176_cores": 1326.0}
+
+
 def _schwarz(ctm, torch):
     """The paper's spatial preconditioner (Section 2.1.2) beside the line
     preconditioner on the 3-D heat workload in FP64 at the measurement's
@@ -786,6 +810,8 @@ def main(argv=None):
             log(f"heat3d: {result['heat3d']}")
         result["schwarz_vs_line"] = _schwarz(ctm, torch)
         log(f"schwarz vs line: {result['schwarz_vs_line']}")
+        result["table3_ct"] = _table3_ct(ctm, torch)
+        log(f"table 3 CT: {result['table3_ct']}")
     if args.copy_calibration:
         result["copy_calibration_bytes"] = _copy_calibration(torch)
 
