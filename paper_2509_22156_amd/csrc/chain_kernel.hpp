@@ -260,16 +260,45 @@ __device__ __forceinline__ double* vec_at(const VecRef& r, long long idx, long l
   return r.base + idx * slen + off;
 }
 
+// A lane's K values in HBM. A lane whose chunk holds fewer than K unknowns
+// reads (and writes back) its first unknown in the place of the missing
+// ones, so that the K accesses form one block without per-value branches:
+// the compiler made each predicated store wait for the previous one to
+// complete, a memory round trip per value, measured at up to a third of a
+// small task's life. Rewriting the first unknown with its own value is
+// harmless; idle lanes (no unknowns) touch nothing.
+// gload_raw leaves a copy of the first value in the slots past the chunk's
+// end and uses nothing it loads, so that a prefetch does not wait;
+// pad_zero then clears those slots where the values are consumed.
+template <int K>
+__device__ __forceinline__ void gload_raw(const Lane<K>& L, const double* src, double (&v)[K]) {
+  if (L.nval > 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = src[L.cbase + (long long)(k < L.nval ? k : 0) * L.cstep];
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+  }
+}
+template <int K>
+__device__ __forceinline__ void pad_zero(const Lane<K>& L, double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = k < L.nval ? v[k] : 0.0;
+}
 template <int K>
 __device__ __forceinline__ void gload(const Lane<K>& L, const double* src, double (&v)[K]) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = (k < L.nval) ? src[L.cbase + (long long)k * L.cstep] : 0.0;
+  gload_raw<K>(L, src, v);
+  pad_zero<K>(L, v);
 }
 template <int K>
 __device__ __forceinline__ void gstore(const Lane<K>& L, double* dst, const double (&v)[K]) {
+  if (L.nval > 0) {
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (k < L.nval) dst[L.cbase + (long long)k * L.cstep] = v[k];
+    for (int k = 0; k < K; ++k) {
+      const bool in = k < L.nval;
+      dst[L.cbase + (long long)(in ? k : 0) * L.cstep] = in ? v[k] : v[0];
+    }
+  }
 }
 
 // One implicit step in FP64: x <- (I + dt L)^-1 v (x: the initial guess;
@@ -402,12 +431,14 @@ enum { MODE_PLAIN = 0, MODE_FORCED = 1, MODE_RESIDUAL = 2 };
 // keeps them at two waves should that grow again (held to 256 before the
 // parking they spilled under 40 registers and ran 25% faster than at one
 // wave; held to three waves, 168, they spilled over 120 and ran 65% slower).
-template <int OPC, bool MIXED, int W, int K>
-constexpr int chain_min_waves() { return (OPC == OPC_VAR && K == 4 && MIXED) ? 2 : 1; }
+template <int OPC, bool MIXED, int MODE, int W, int K>
+constexpr int chain_min_waves() {
+  return (OPC == OPC_VAR && K == 4 && (MIXED || MODE != MODE_RESIDUAL)) ? 2 : 1;
+}
 
 template <int OPC, int SOLVER, bool MIXED, int MODE, int W, int K>
 __global__ void __launch_bounds__(64 * W)
-    __attribute__((amdgpu_waves_per_eu(chain_min_waves<OPC, MIXED, W, K>())))
+    __attribute__((amdgpu_waves_per_eu(chain_min_waves<OPC, MIXED, MODE, W, K>())))
     chain_kernel(ChainArgs a, int tabmax) {
   constexpr bool FORCED = (MODE == MODE_FORCED);
   constexpr bool RES = (MODE == MODE_RESIDUAL);
@@ -502,11 +533,12 @@ __global__ void __launch_bounds__(64 * W)
   // initial guess of step j: the given one (a previous iterate at this time
   // point: guess for j < nsteps, guess_fin for the last step), else the state
   // one step earlier. The FP64 kernels of the operators with per-line
-  // coefficients load given guesses one step ahead, so that their memory
-  // latency hides behind the solve of the step before (measured: 6% off the
-  // 6-D FP64 solve; the heat and mixed kernels lose a wave of occupancy to
-  // the extra registers, or gain nothing, and load at the step).
-  constexpr bool kPrefetch = !MIXED && OPC != OPC_HEAT;
+  // coefficients, and the mixed ones that park their FP64 operator, load
+  // given guesses one step ahead, so that their memory latency hides behind
+  // the solve of the step before (measured: 6% off the 6-D FP64 solve; the
+  // heat kernels and the other mixed ones lose a wave of occupancy to the
+  // extra registers, or gain nothing, and load at the step).
+  constexpr bool kPrefetch = (!MIXED && OPC != OPC_HEAT) || PARK;
   auto guess_of = [&](int j) -> const VecRef& { return j == a.nsteps ? a.guess_fin : a.guess; };
   auto guess_at = [&](int j) {
     const VecRef& r = guess_of(j);
@@ -514,9 +546,24 @@ __global__ void __launch_bounds__(64 * W)
   };
   double gnext[K];
   if constexpr (kPrefetch) {
-    if (guess_of(1).base) gload<K>(L, guess_at(1), gnext);
+    if (guess_of(1).base) gload_raw<K>(L, guess_at(1), gnext);
   }
   for (int j = 1; j <= a.nsteps; ++j) {
+    // The state after step j - 1 (still in v) is written to `inter` here, at
+    // the start of step j rather than at the end of step j - 1. A wait for a
+    // load also waits for every store issued before it, and the prefetched
+    // guess is waited for as soon as a step ends: stored there, the state
+    // cost a full write round trip per step. Stored after that wait and
+    // before the next prefetch, it completes during the solve. The kernels
+    // that load the guess at the step store first, so that the store and
+    // the load overlap.
+    const bool put = a.inter.base && j > 1;
+    auto put_prev = [&]() {
+      gstore<K>(L, vec_at(a.inter, a.inter.a * q + a.inter.b + (j - 1), a.slen, off), v);
+    };
+    if constexpr (!kPrefetch) {
+      if (put) put_prev();
+    }
     // heat (few registers in use): the forcing of this step is loaded
     // before the solve, so that its latency hides behind it
     constexpr bool kEarly = (OPC == OPC_HEAT);
@@ -530,6 +577,7 @@ __global__ void __launch_bounds__(64 * W)
       if constexpr (kPrefetch) {
 #pragma unroll
         for (int k = 0; k < K; ++k) x[k] = gnext[k];
+        pad_zero<K>(L, x);
       } else {
         gload<K>(L, guess_at(j), x);
       }
@@ -538,7 +586,13 @@ __global__ void __launch_bounds__(64 * W)
       for (int k = 0; k < K; ++k) x[k] = v[k];
     }
     if constexpr (kPrefetch) {
-      if (!last && guess_of(j + 1).base) gload<K>(L, guess_at(j + 1), gnext);
+      // the prefetched guess has arrived before the stores issue
+      // (s_waitcnt vmcnt(0), on every path): left to itself the compiler
+      // orders the copy of the guess after the stores, and its wait then
+      // includes theirs
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      if (put) put_prev();
+      if (!last && guess_of(j + 1).base) gload_raw<K>(L, guess_at(j + 1), gnext);
     }
     // manufactured heat problem: the step solves (I + dt L) x = v + dt f(t_j)
     if constexpr (FORCED) {
@@ -634,9 +688,33 @@ __global__ void __launch_bounds__(64 * W)
         for (int k = 0; k < K; ++k) v[k] = x[k];
       }
     }
-    if (a.inter.base && j < a.nsteps)
-      gstore<K>(L, vec_at(a.inter, a.inter.a * q + a.inter.b + j, a.slen, off), v);
   }
+
+  // statistics: counter i from lane i (the values are uniform over the
+  // work-group), so that the task ends with two atomic instructions rather
+  // than a chain of single-lane ones, each waiting for the one before; ahead
+  // of the final stores, whose data registers they would otherwise wait for
+  if (a.counters && threadIdx.x < CNT_N) {
+    const int t = threadIdx.x;
+    const unsigned long long npts = (unsigned long long)g.npts;
+    unsigned long long val = 0;
+    switch (t) {
+      case CNT_KRYLOV: val = (unsigned long long)kr_sum; break;
+      case CNT_KRYLOV_MAX: val = (unsigned long long)kr_max; break;
+      case CNT_REFINE: val = (unsigned long long)rf_sum; break;
+      case CNT_REFINE_MAX: val = (unsigned long long)rf_max; break;
+      case CNT_SOLVES: val = (unsigned long long)a.nsteps; break;
+      case CNT_WORK: val = (unsigned long long)kr_sum * npts; break;
+      case CNT_DOFSTEPS: val = (unsigned long long)a.nsteps * npts; break;
+      default: break;
+    }
+    if (t == CNT_KRYLOV_MAX || t == CNT_REFINE_MAX) {
+      if (MIXED || t == CNT_KRYLOV_MAX) atomicMax(&a.counters[t], val);
+    } else if (val != 0) {
+      atomicAdd(&a.counters[t], val);
+    }
+  }
+  if (threadIdx.x == 0 && flag && a.status) atomicOr(a.status, flag);
 
   if (a.fin.base) {
     double* dst = vec_at(a.fin, a.fin.a * q + a.fin.b, a.slen, off);
@@ -663,18 +741,6 @@ __global__ void __launch_bounds__(64 * W)
     }
   }
 
-  if (threadIdx.x == 0) {
-    if (a.counters) {
-      atomicAdd(&a.counters[CNT_KRYLOV], (unsigned long long)kr_sum);
-      atomicMax(&a.counters[CNT_KRYLOV_MAX], (unsigned long long)kr_max);
-      atomicAdd(&a.counters[CNT_REFINE], (unsigned long long)rf_sum);
-      atomicMax(&a.counters[CNT_REFINE_MAX], (unsigned long long)rf_max);
-      atomicAdd(&a.counters[CNT_SOLVES], (unsigned long long)a.nsteps);
-      atomicAdd(&a.counters[CNT_WORK], (unsigned long long)kr_sum * (unsigned long long)g.npts);
-      atomicAdd(&a.counters[CNT_DOFSTEPS], (unsigned long long)a.nsteps * (unsigned long long)g.npts);
-    }
-    if (flag && a.status) atomicOr(a.status, flag);
-  }
 }
 
 template <int OPC, int SOLVER>
