@@ -63,7 +63,8 @@ __device__ __forceinline__ void sapply(const Solver<OPC, T, K>& S, const T (&x)[
 template <int OPC, typename T, int W, int K>
 __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
                                           const T (&b)[K], bool x_zero, bool check_first,
-                                          T tol2, int maxit, int* flag, T* rr0 = nullptr) {
+                                          T tol2, int maxit, int* flag, T* rr0 = nullptr,
+                                          T* rel_end = nullptr) {
   T r[K], z[K], w[K], p[K], s[K];
   if (x_zero) {
 #pragma unroll
@@ -107,7 +108,10 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
     *flag |= FLAG_NONFINITE;
     return 0;
   }
-  if (red[2] <= tol2 * bb) return 0;
+  if (red[2] <= tol2 * bb) {
+    if (rel_end) *rel_end = red[2] / bb;
+    return 0;
+  }
   T gamma = red[0];
   T alpha = kdiv(gamma, red[1]);
 #pragma unroll
@@ -135,7 +139,10 @@ __device__ __forceinline__ int krylov_pcg(const Solver<OPC, T, K>& S, RedRing& r
       *flag |= FLAG_NONFINITE;
       return it;
     }
-    if (rd[2] <= tol2 * bb) return it;
+    if (rd[2] <= tol2 * bb) {
+      if (rel_end) *rel_end = rd[2] / bb;
+      return it;
+    }
     const T beta = kdiv(rd[0], gamma);
     const T den = rd[1] - beta * kdiv(rd[0], alpha);
     if (den == (T)0 || !finite_val(den)) {
@@ -248,9 +255,11 @@ __device__ __forceinline__ int krylov_pbicgstab(const Solver<OPC, T, K>& S, RedR
 template <int OPC, int SOLVER, typename T, int W, int K>
 __device__ __forceinline__ int krylov(const Solver<OPC, T, K>& S, RedRing& ring, T (&x)[K],
                                       const T (&b)[K], bool x_zero, T tol2, int maxit,
-                                      int* flag, bool check_first = false, T* rr0 = nullptr) {
+                                      int* flag, bool check_first = false, T* rr0 = nullptr,
+                                      T* rel_end = nullptr) {
   if constexpr (SOLVER == SOLV_CG)
-    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, check_first, tol2, maxit, flag, rr0);
+    return krylov_pcg<OPC, T, W, K>(S, ring, x, b, x_zero, check_first, tol2, maxit, flag, rr0,
+                                    rel_end);
   else
     return krylov_pbicgstab<OPC, T, W, K>(S, ring, x, b, x_zero, tol2, maxit, flag, rr0);
 }
@@ -315,13 +324,26 @@ __device__ __forceinline__ void step_fp64(const Solver<OPC, double, K>& S, RedRi
 }
 
 // One implicit step by FP64 iterative refinement around FP32 Krylov solves.
+// Bound on the gap between the true residual of an FP32 CG correction and
+// the recursive residual the CG recurrences carry, relative to the norm of
+// the right-hand side: the rounding of the right-hand side to FP32, of the
+// FP32 operator's coefficients, and of the recurrences over `it` iterations,
+// each a small multiple of the FP32 unit roundoff times ||A|| ||d|| (standard
+// rounding-error analysis of CG; ||d|| <= 1 since A = I + dt L with L
+// symmetric positive semi-definite, so A >= I), with a safety factor of 32.
+// `anorm` bounds ||A||_2 (Gershgorin).
+__device__ __forceinline__ double cg_gap_bound(int it, double anorm) {
+  return 32.0 * 5.9604644775390625e-08 * (double)(it + 3) * anorm;
+}
+
 template <int OPC, int SOLVER, int W, int K, class Apply64>
 __device__ __forceinline__ void step_mixed(const Apply64& apply64,
                                            const Solver<OPC, float, K>& S32, RedRing& ring,
                                            const double (&v)[K], double tol2, float itol2,
                                            int maxit, int refine_maxit, double (&x)[K],
                                            int* flag, long long& kr_sum, long long& kr_max,
-                                           long long& rf_sum, long long& rf_max) {
+                                           long long& rf_sum, long long& rf_max,
+                                           double anorm) {
   bool conv = false;
   int sweeps = 0, its = 0;
   double bb = 0.0;
@@ -369,8 +391,9 @@ __device__ __forceinline__ void step_mixed(const Apply64& apply64,
     t2 = t2 > (double)itol2 ? t2 : (double)itol2;
     t2 = t2 < 0.25 ? t2 : 0.25;
     int iflag = 0;
-    const int it =
-        krylov<OPC, SOLVER, float, W, K>(S32, ring, d32, r32, true, (float)t2, maxit, &iflag);
+    float rel = 1.0f;
+    const int it = krylov<OPC, SOLVER, float, W, K>(S32, ring, d32, r32, true, (float)t2, maxit,
+                                                    &iflag, false, nullptr, &rel);
     its += it;
     if (iflag & FLAG_NONFINITE) {
       *flag |= FLAG_NONFINITE;
@@ -378,6 +401,20 @@ __device__ __forceinline__ void step_mixed(const Apply64& apply64,
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) x[k] += nr * (double)d32[k];
+    // CG on a symmetric operator (anorm > 0): the FP64 residual after the
+    // correction is at most nr (sqrt(rel) + gap). Where that bound already
+    // meets the tolerance the step ends without computing it; the next
+    // step, and the MGRIT residual, start from FP64 residuals as always.
+    if constexpr (SOLVER == SOLV_CG) {
+      if (anorm > 0.0 && iflag == 0) {
+        const double est = nr * (sqrt((double)rel) + cg_gap_bound(it, anorm));
+        if (est * est <= tol2 * bb) {
+          ++sweeps;
+          conv = true;
+          break;
+        }
+      }
+    }
   }
   if (!conv) *flag |= FLAG_NOCONV;
   kr_sum += its;
@@ -528,6 +565,16 @@ __global__ void __launch_bounds__(64 * W)
     }
   };
   const float itol2 = (float)(a.inner_tol * a.inner_tol);
+  // ||I + dt L||_2 <= 1 + dt sum_i 4 a_max / h_i^2 (Gershgorin; a_max = 1 for
+  // the heat operator, 1 + |amp| for the variable coefficient) for the
+  // symmetric operators; 0 (no bound) for the others
+  double anorm = 0.0;
+  if constexpr (OPC == OPC_HEAT || OPC == OPC_VAR) {
+    const double amax = (OPC == OPC_VAR) ? 1.0 + fabs(a.amp) : 1.0;
+    double sum = 0.0;
+    for (int i = 0; i < g.d; ++i) sum += g.ih2[i];
+    anorm = 1.0 + a.dt * 4.0 * amax * sum;
+  }
   double res_max = 0.0;  // residual mode: largest squared residual of the task's steps
 
   // initial guess of step j: the given one (a previous iterate at this time
@@ -673,7 +720,8 @@ __global__ void __launch_bounds__(64 * W)
                                            kr_max);
         else
           step_mixed<OPC, SOLVER, W, K>(apply64, S32, ring, v, tol2, itol2, a.maxit,
-                                        a.refine_maxit, x, &flag, kr_sum, kr_max, rf_sum, rf_max);
+                                        a.refine_maxit, x, &flag, kr_sum, kr_max, rf_sum, rf_max,
+                                        anorm);
       } else {
         step_fp64<OPC, SOLVER, W, K>(S64, ring, v, tol2, a.maxit, gr.base != nullptr, x, &flag,
                                      kr_sum, kr_max);
