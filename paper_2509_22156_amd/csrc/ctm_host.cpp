@@ -111,6 +111,8 @@ struct ctm_plan {
   double* dnorm2 = nullptr;   // [G]
   double* hsync = nullptr;    // pinned mirror of dsync
   int2* didentity = nullptr;  // (g, 0) in canonical order
+  int2* dgstage = nullptr;    // gather stages: runs of grids [x, y) of one LDS stage
+  int ngstage = 0;
   std::vector<int> gshape;    // launch shape of each grid (size class)
   std::map<long long, TaskSet> tsets;  // M -> (g, q) tasks grouped by shape
   // side streams for concurrent size classes: with the caller's stream they
@@ -198,6 +200,7 @@ struct ctm_plan {
     hipFree(dsync);
     hipFree(dnorm2);
     hipFree(didentity);
+    hipFree(dgstage);
     hipFree(dhnode);
     hipFree(dhoff);
     hipFree(dhidx);
@@ -1833,6 +1836,25 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
   for (int g = 0; g < P->G; ++g) ident[g] = make_int2(g, 0);
   CTM_HIPC(hipMalloc(&P->didentity, P->G * sizeof(int2)));
   CTM_HIPC(hipMemcpy(P->didentity, ident.data(), P->G * sizeof(int2), hipMemcpyHostToDevice));
+  {
+    // gather stages: runs of consecutive grids, contiguous in the packed
+    // vector, whose unknowns fit one LDS stage (a larger grid alone)
+    std::vector<int2> st;
+    const long long cap = gather_stage_capacity();
+    for (int g = 0; g < P->G;) {
+      long long n = 0;
+      int e = g;
+      while (e < P->G && n + P->hdev[e].npts <= cap &&
+             (e == g || P->hdev[e].off == P->hdev[e - 1].off + P->hdev[e - 1].npts))
+        n += P->hdev[e++].npts;
+      if (e == g) e = g + 1;
+      st.push_back(make_int2(g, e));
+      g = e;
+    }
+    P->ngstage = (int)st.size();
+    CTM_HIPC(hipMalloc(&P->dgstage, st.size() * sizeof(int2)));
+    CTM_HIPC(hipMemcpy(P->dgstage, st.data(), st.size() * sizeof(int2), hipMemcpyHostToDevice));
+  }
   if (P->schwarz) {
     std::vector<SchwarzGrid> sgs(P->G);
     std::vector<SchwarzSub> subs;
@@ -2042,7 +2064,8 @@ ctm_status ctm_gather(ctm_plan* P, const double* u, const double* pts, long long
                       ctm_stream s) {
   if (!P || !u || (!pts && npts > 0) || (!out && npts > 0)) return fail(CTM_ERR_INVALID, "NULL argument");
   if (npts < 0) return fail(CTM_ERR_INVALID, "npts must be >= 0");
-  CTM_HIP(launch_gather(P->dgrids, P->G, u, pts, npts, out, (hipStream_t)s));
+  CTM_HIP(launch_gather(P->dgrids, P->dgstage, P->ngstage, P->d, u, pts, npts, out,
+                        (hipStream_t)s));
   return CTM_OK;
 }
 

@@ -328,8 +328,13 @@ hipError_t launch_mms_initial(const GridDev* grids, int G, int maxpts, double t,
 hipError_t launch_apply(int opc, int shape, const GridDev* grids, int G, const double* tab64,
                         double amp, double dt, int tabmax, const double* x, double* y,
                         hipStream_t s);
-hipError_t launch_gather(const GridDev* grids, int G, const double* u, const double* pts,
-                         long long npts, double* out, hipStream_t s);
+// Combination gather. stages: runs of consecutive grids [x, y) whose
+// unknowns fit gather_stage_capacity() doubles (a larger grid alone); d: the
+// plan's dimension.
+hipError_t launch_gather(const GridDev* grids, const int2* stages, int nstage, int d,
+                         const double* u, const double* pts, long long npts, double* out,
+                         hipStream_t s);
+int gather_stage_capacity();
 hipError_t launch_project(const GridDev* grids, const long long* offsets, int G, long long slen,
                           const double* u, double* out, hipStream_t s);
 // Hierarchical basis (Section 2.2.2): per-grid (de)hierarchization (one

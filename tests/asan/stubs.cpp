@@ -17,8 +17,9 @@ hipError_t launch_initial_state(const GridDev*, int, int, int, int, const double
 hipError_t launch_mms_initial(const GridDev*, int, int, double, double*, hipStream_t) CTM_STUB()
 hipError_t launch_apply(int, int, const GridDev*, int, const double*, double, double, int,
                         const double*, double*, hipStream_t) CTM_STUB()
-hipError_t launch_gather(const GridDev*, int, const double*, const double*, long long, double*,
-                         hipStream_t) CTM_STUB()
+hipError_t launch_gather(const GridDev*, const int2*, int, int, const double*, const double*,
+                         long long, double*, hipStream_t) CTM_STUB()
+int gather_stage_capacity() { return 4096; }
 hipError_t launch_project(const GridDev*, const long long*, int, long long, const double*, double*,
                           hipStream_t) CTM_STUB()
 hipError_t launch_hierarchize(const GridDev*, int, int, bool, bool, const double*, double*,
