@@ -276,3 +276,50 @@ def test_error_paths():
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     st = ctm.lib().ctm_solve(plan._h, ctm._ptr(small), 16, None, ctm._ptr(u), ctm._stream())
     assert st == ctm.ERR_NOMEM
+
+
+
+def _gather_stages(sizes, cap=4096):
+    """The gather's stage partition (runs of consecutive grids whose
+    unknowns fit cap values; a larger grid alone): (first, end) pairs."""
+    out, g = [], 0
+    while g < len(sizes):
+        n, e = 0, g
+        while e < len(sizes) and n + sizes[e] <= cap:
+            n += sizes[e]
+            e += 1
+        e = max(e, g + 1)
+        out.append((g, e))
+        g = e
+    return out
+
+
+@pytest.mark.parametrize("n,L0,kind", [(12, 4, "direct"), (11, 4, "shared")])
+def test_gather_staged_and_direct_grids(n, L0, kind):
+    # the oscillator's grids around one LDS stage of the gather (4,096
+    # values): level 12 has grids above it (read from HBM directly) beside
+    # ones staged alone, level 11 small ones that share a stage; points at
+    # nodes of the finest grids, on the boundary and inside
+    p = _fp64(make("fp_osc2d", n=n, L0=L0, nsteps=4))
+    gl = solve.grid_list(p)
+    sizes = [int(np.prod([2 ** li - 1 for li in l])) for (l, _, _) in gl]
+    stages = _gather_stages(sizes)
+    if kind == "direct":
+        assert any(sizes[a] > 4096 for a, _ in stages) and any(sizes[a] <= 4096 for a, _ in stages)
+    else:
+        assert any(e - a > 1 for a, e in stages)
+    _say(f"gather staged/direct n={n} L0={L0}: stages {stages}")
+    plan = ctm.Plan(p)
+    x = random_vectors(plan.slen, 1, seed=12)[0]
+    lo, hi = np.asarray(p["lo"], dtype=np.float64), np.asarray(p["hi"], dtype=np.float64)
+    rng = np.random.default_rng(12)
+    nodes = lo + (hi - lo) * rng.integers(0, 2 ** n + 1, size=(600, 2)) / 2.0 ** n
+    edge = lo + (hi - lo) * np.array([[0.0, 0.5], [1.0, 0.25], [0.5, 0.0], [0.75, 1.0],
+                                      [0.0, 0.0], [1.0, 1.0]])
+    pts = np.concatenate([nodes, edge, targets(p, 1400, seed=12)])
+    got = plan.gather(torch.from_numpy(x).cuda(), torch.from_numpy(pts).cuda()).cpu().numpy()
+    ref = combine.combine_at(p, gl, split(p, x), pts)
+    scale = sum(abs(c) for (_, _, c) in gl) * np.abs(x).max()
+    assert np.abs(got - ref).max() <= 1e-14 * scale
+    # the boundary carries zero values
+    assert np.abs(got[600:606]).max() <= 1e-14 * scale
