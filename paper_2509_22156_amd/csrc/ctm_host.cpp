@@ -1714,6 +1714,7 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     gd.sax = sax;
     gd.ns = gd.n[sax];
     gd.nlines = gd.npts / gd.ns;
+    gd.nseg = (gd.ns + kSegLen - 1) / kSegLen;
     int m = 0;
     for (int i = 0; i < d; ++i)
       if (i != sax) gd.oax[m++] = i;
@@ -1740,10 +1741,8 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     if (sh < 0) {
       ++nstream;
       maxstream = std::max(maxstream, P->hdev[g].npts);
-      if (!P->schwarz && P->hdev[g].ns > 1024) {
-        delete P;
-        return fail(CTM_ERR_INVALID, "a component grid has lines longer than 1024 unknowns");
-      }
+      // (lines longer than kSegLen unknowns: the line preconditioner
+      // works on segments of them)
     }
   }
   if (nstream) {
@@ -1765,9 +1764,10 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     for (int g = 0; g < P->G; ++g) {
       if (P->gshape[g] != kStreamShape) continue;
       const GridDev& gd = P->hdev[g];
+      const int seglen = gd.nseg > 1 ? kSegLen : gd.ns;
       int Lc = 1;
-      while (Lc < (gd.ns + kWideSK - 1) / kWideSK) Lc <<= 1;
-      const int waves = (gd.nlines + 64 / Lc - 1) / (64 / Lc);
+      while (Lc < (seglen + kWideSK - 1) / kWideSK) Lc <<= 1;
+      const int waves = (gd.nlines * gd.nseg + 64 / Lc - 1) / (64 / Lc);
       P->wide_lb = std::max(P->wide_lb, (waves + kWLW - 1) / kWLW);
       P->wide_pb = std::max(P->wide_pb, (gd.npts + kWP - 1) / kWP);
     }

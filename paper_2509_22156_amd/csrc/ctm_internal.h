@@ -49,11 +49,20 @@ struct GridDev {
   int sax;             // stiff axis (canonical index)
   int ns;              // unknowns along the stiff axis
   int nlines;          // npts / ns
-  int pad4_;
+  int nseg;            // streaming solvers: segments per line of the line preconditioner
+                       // (lines longer than kSegLen unknowns are cut into segments of
+                       // kSegLen, the last one shorter; 1 otherwise)
   int oax[MAXD];       // non-stiff axes, canonical indices, increasing
   int lstride[MAXD];   // line-index stride of oax[m]
   int cstride[MAXD];   // canonical point stride of canonical axis i (= stride[i])
 };
+
+// Longest line segment the streaming solvers' line preconditioner solves
+// exactly: 64 lanes of kSK = 16 unknowns (one wave). Longer lines are cut
+// into segments of this length, solved exactly each, with the couplings
+// between segments dropped from the preconditioner (block Jacobi over the
+// segments; the operator keeps them).
+constexpr int kSegLen = 1024;
 
 // A family of packed vectors indexed by time: vector index = a * q + b
 // (+ j for per-step roles); element (idx, grid g, point p) lives at

@@ -162,6 +162,7 @@ __device__ __forceinline__ double stream_apply(const GridDev& g, const double* t
 // back-substitution. No barrier inside: a lane reads and writes only its own
 // chunk, and neighbours come by cross-lane shuffles.
 constexpr int kSK = 16;
+static_assert(kSegLen == 64 * kSK, "a line segment is one wave of kSK-unknown chunks");
 
 struct SLane {
   int line, c, Lc, j0, nval;
@@ -170,26 +171,40 @@ struct SLane {
   int step;        // canonical stride along the stiff axis
 };
 
+// Unknowns of a line segment (the whole line when it is not cut) and the
+// segments of the task (lines x segments per line).
+__device__ __forceinline__ int stream_seg_len(const GridDev& g) {
+  return g.nseg > 1 ? kSegLen : g.ns;
+}
+__device__ __forceinline__ int stream_segments(const GridDev& g) { return g.nlines * g.nseg; }
+
 __device__ __forceinline__ int stream_line_rounds(const GridDev& g) {
-  const int Lc = pow2ceil((g.ns + kSK - 1) / kSK);
+  const int Lc = pow2ceil((stream_seg_len(g) + kSK - 1) / kSK);
   const int per_round = kStreamW * (64 / Lc);
-  return (g.nlines + per_round - 1) / per_round;
+  return (stream_segments(g) + per_round - 1) / per_round;
 }
 
 // Lane `lane` of wave `vwave` of the task: the wave holds 64 / Lc line
-// segments, lines vwave * (64 / Lc) + lane / Lc.
+// segments, segments vwave * (64 / Lc) + lane / Lc (segment s of line
+// s / nseg). The first chunk of a segment is lane c = 0 and its last has no
+// successor (nxt), so the line solve couples nothing across segments.
 template <int D>
 __device__ __forceinline__ void stream_lane_at(const GridDev& g, int vwave, int lane, SLane& L) {
-  const int Lc = pow2ceil((g.ns + kSK - 1) / kSK);
+  const int S = stream_seg_len(g);
+  const int Lc = pow2ceil((S + kSK - 1) / kSK);
   L.Lc = Lc;
   L.c = lane & (Lc - 1);
-  L.line = vwave * (64 / Lc) + lane / Lc;
-  L.j0 = L.c * kSK;
-  const bool live = L.line < g.nlines;
-  int nv = g.ns - L.j0;
+  const int seg = vwave * (64 / Lc) + lane / Lc;
+  const bool live = seg < stream_segments(g);
+  const int sg = live ? seg % g.nseg : 0;
+  L.line = live ? seg / g.nseg : g.nlines;
+  const int s0 = sg * S;                               // first unknown of the segment
+  const int s1 = s0 + S < g.ns ? s0 + S : g.ns;        // one past its last
+  L.j0 = s0 + L.c * kSK;
+  int nv = s1 - L.j0;
   nv = nv < 0 ? 0 : (nv > kSK ? kSK : nv);
   L.nval = live ? nv : 0;
-  L.nxt = live && (L.j0 + kSK < g.ns);
+  L.nxt = live && (L.j0 + kSK < s1);
   L.step = g.stride[g.sax];
   long long b = 0;
   const int rem = live ? L.line : 0;

@@ -38,8 +38,8 @@ __device__ __forceinline__ int wide_point_blocks(const GridDev& g) {
   return (g.npts + kWP - 1) / kWP;
 }
 __device__ __forceinline__ int wide_line_blocks(const GridDev& g) {
-  const int Lc = pow2ceil((g.ns + kSK - 1) / kSK);
-  const int waves = (g.nlines + (64 / Lc) - 1) / (64 / Lc);
+  const int Lc = pow2ceil((stream_seg_len(g) + kSK - 1) / kSK);
+  const int waves = (stream_segments(g) + (64 / Lc) - 1) / (64 / Lc);
   return (waves + kWLW - 1) / kWLW;
 }
 
@@ -278,7 +278,9 @@ struct WaveTile {
 __device__ __forceinline__ WaveTile wave_tile(const WideArgs& w, const GridDev& g,
                                               const SLane& L) {
   WaveTile T;
-  T.on = w.stage && (g.sax == g.d - 1);
+  // (lines cut into segments are read directly: a wave's segments need
+  // not be one contiguous range)
+  T.on = w.stage && (g.sax == g.d - 1) && g.nseg == 1;
   const int G = 64 / L.Lc;
   const int line0 = ((int)blockIdx.x * kWLW + (int)(threadIdx.x >> 6)) * G;
   const int gv = g.nlines - line0 < G ? g.nlines - line0 : G;

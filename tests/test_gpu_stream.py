@@ -262,3 +262,31 @@ def test_drift_beyond_the_solver_reports_noconv():
     flags = plan.stats()["status_flags"]
     assert st in (ctm.ERR_NOCONV, ctm.ERR_BREAKDOWN)
     assert flags & (1 << ctm.ERR_NOCONV)
+
+
+@pytest.mark.parametrize("n,wide", [(12, ALL), (12, 0), (13, ALL), (13, 0)])
+def test_lines_cut_into_segments(n, wide):
+    # levels 12 and 13: the grids (n - 1, 1) ... have lines of 2,047 and 4,095
+    # unknowns, longer than one wave's 1,024-unknown segment of the line
+    # preconditioner (two and four segments, the last shorter or full); the
+    # operator couples across the segments, the preconditioner does not, so
+    # the solution matches the oracle's direct solves as for any other grid,
+    # on the wide solver and on the one-work-group-per-system kernel
+    # (dt / h^2 about 50 and 200 on the finest axis: a condition number low
+    # enough for FP64 CG to reach the tolerances; at dt / h^2 ~ 2e4 the gap
+    # between the recursive and the true residual, eps times the condition
+    # number, keeps the MGRIT residual above 1e-13)
+    p = make("heat2d", n=n, nsteps=8, t1=1e-4)
+    p.update(prec="fp64", krylov_tol=1e-13, mgrit_tol=1e-12, mgrit_maxit=100, cf=2,
+             krylov_maxit=20000)
+    gl = solve.grid_list(p)
+    assert max(2 ** max(l) - 1 for (l, _, _) in gl) > 1024
+    _say(f"segmented lines n={n} wide={wide}")
+    plan = ctm.Plan(p)
+    plan.set_wide(wide)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    _say(f"  mgrit it={st['mgrit_iterations']} krylov={st['krylov_iterations']}")
+    assert st["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-11)
