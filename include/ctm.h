@@ -221,9 +221,9 @@ ctm_status ctm_problem_defaults(ctm_problem* p);
  * vectors in device memory the plan allocates). Rejects: d outside
  * 1..CTM_MAXD, n + d - 1 > 30, no grid with l >= L0, more than 65,535
  * grids, N not divisible by s * c^(levels-1), nonpositive tolerances, CG for
- * a non-symmetric operator, a grid with more than 2^20 unknowns, the
- * manufactured forcing on a streaming grid, residual mode outside its
- * conditions (ctm_problem.residual_mode), lattice box with hi - lo != 2^n.
+ * a non-symmetric operator, a grid with more than 2^20 unknowns, residual
+ * mode outside its conditions (ctm_problem.residual_mode), lattice box with
+ * hi - lo != 2^n.
  * On the streaming solver a line longer than 1,024 unknowns is cut into
  * segments of 1,024 for the line preconditioner (exact line solves per
  * segment, block Jacobi across them; the operator is unchanged, so only the

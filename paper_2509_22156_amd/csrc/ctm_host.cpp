@@ -1746,10 +1746,6 @@ ctm_status ctm_plan_create(const ctm_problem* prob, ctm_plan** out) {
     }
   }
   if (nstream) {
-    if (prob->manufactured != CTM_MMS_NONE) {
-      delete P;
-      return fail(CTM_ERR_INVALID, "the manufactured forcing needs every grid on chip");
-    }
     if ((size_t)P->tabmax * sizeof(double) > 65536) {
       delete P;
       return fail(CTM_ERR_INVALID, "coefficient tables of a streaming grid exceed 64 KiB");

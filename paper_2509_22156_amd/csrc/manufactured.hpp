@@ -66,4 +66,26 @@ __device__ __forceinline__ void mms_forcing(const GridDev& g, const Lane<K>& L, 
   }
 }
 
+// f(x_p, t) at canonical point p of grid g (axis d-1 fastest), for the
+// streaming solvers, which sweep points rather than lanes' chunks.
+template <int D>
+__device__ __forceinline__ double mms_point(const GridDev& g, int p, double t) {
+  double P = 1.0, C = 0.0, X2 = 0.0;
+  int rem = p;
+#pragma unroll
+  for (int i = D - 1; i >= 0; --i) {
+    if (i < g.d) {
+      const int j = rem % g.n[i];
+      rem /= g.n[i];
+      const double x = g.lo[i] + (double)(j + g.j0) * g.h[i];
+      double sn, cs;
+      sincospi(x, &sn, &cs);
+      C = C * sn + x * cs * P;
+      P *= sn;
+      X2 += x * x;
+    }
+  }
+  return mms_f(P, C, X2, g.d, t, exp(-t));
+}
+
 }  // namespace ctm

@@ -17,6 +17,7 @@
 #pragma once
 
 #include "line_layout.hpp"
+#include "manufactured.hpp"
 
 namespace ctm {
 
@@ -801,7 +802,14 @@ __global__ void __launch_bounds__(kStreamThreads)
     }
     const VecRef gr = last ? a.guess_fin : a.guess;
     const double* gx = gr.base ? at(gr, gr.a * q + gr.b + (last ? 0 : j)) : nullptr;
-    for (int p = threadIdx.x; p < np; p += kStreamThreads) X[p] = gx ? gx[p] : B[p];
+    // manufactured heat problem: the step solves (I + dt L) x = v + dt f(t_j)
+    // (the guess taken before the forcing is added, as on chip)
+    const bool mms = (OPC == OPC_HEAT) && a.fkind && !res;
+    const double tj = a.ft0 + (double)q * a.ftq + (double)j * a.dt;
+    for (int p = threadIdx.x; p < np; p += kStreamThreads) {
+      X[p] = gx ? gx[p] : B[p];
+      if (mms) B[p] += a.dt * mms_point<D>(g, p, tj);
+    }
     __syncthreads();
     int it;
     double r0 = 0.0;

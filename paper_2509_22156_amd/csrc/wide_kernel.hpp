@@ -573,6 +573,7 @@ __global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
                                              : nullptr;
   const bool rho = res && last && a.target.base;
   const double* tg = rho ? at(a.target, a.target.a * q + a.target.b) : nullptr;
+  const double tj = a.ft0 + (double)q * a.ftq + (double)j * a.dt;  // time of step j
   const VecRef gr = last ? a.guess_fin : a.guess;
   const double* gx = (!rho && gr.base) ? at(gr, gr.a * q + gr.b + (last ? 0 : j)) : nullptr;
   // (every load before the stores: the vectors may share a base)
@@ -584,6 +585,10 @@ __global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
     if (p >= g.npts) continue;
     const double b = (j == 1) ? (st ? st[p] : 0.0) : X[p] + (fp ? fp[p] : 0.0);
     double bb = b + (fj ? fj[p] : 0.0);
+    // manufactured heat problem: (I + dt L) x = v + dt f(t_j)
+    if constexpr (OPC == OPC_HEAT) {
+      if (a.fkind && !res) bb += a.dt * mms_point<D>(g, p, tj);
+    }
     if (rho) bb -= wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int i) { return tg[i]; });
     b0[k] = b;
     b1[k] = bb;

@@ -86,3 +86,23 @@ def test_mgrit_iterations_independent_of_dimension_and_level():
         its[(d, n)] = plan.stats()["mgrit_iterations"]
     _say(f"MGRIT iterations {its}")
     assert max(its.values()) <= 2 * min(its.values()), its
+
+
+@pytest.mark.parametrize("wide", [1 << 20, 0])
+def test_manufactured_on_streaming_grids(wide):
+    # 2-D level 12: the grids with lines of 2,047 unknowns run on the
+    # streaming solvers (their line preconditioner cut into segments),
+    # which add dt f(t_j) point by point; the wide solver and the
+    # one-work-group-per-system kernel (dt / h^2 about 1e3 on the finest
+    # axis, so that FP64 CG reaches the tolerances)
+    p = _fp64(d=2, n=12, nsteps=8, t1=2e-3)
+    p.update(mgrit_tol=1e-12, krylov_maxit=20000, cf=2)
+    _say(f"manufactured on streaming grids, wide={wide}")
+    plan = ctm.Plan(p)
+    plan.set_wide(wide)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    assert st["status_flags"] == 0
+    assert any(c["K"] == 0 for c in st["shapes"])  # a streaming class
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-11)
