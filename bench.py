@@ -192,7 +192,10 @@ def cpu_oracle_parallel(prob, pts, workers):
 
 
 # (d, n) cases of the manufactured heat family: two sparse-grid levels per d
-MMS_CASES = [(2, 7), (2, 9), (3, 7), (3, 9), (4, 6), (4, 8), (5, 6), (5, 8), (6, 5), (6, 7)]
+# (levels 11 and up in 2-D and 3-D have grids beyond the on-chip size: they
+# run on the streaming solvers, lines over 1,024 unknowns cut into segments)
+MMS_CASES = [(2, 7), (2, 9), (2, 11), (2, 13), (2, 15), (3, 7), (3, 9), (3, 11), (3, 13),
+             (4, 6), (4, 8), (4, 10), (5, 6), (5, 8), (6, 5), (6, 7)]
 
 
 def mms_sweep(ctm, torch):

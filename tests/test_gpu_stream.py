@@ -266,9 +266,10 @@ def test_drift_beyond_the_solver_reports_noconv():
 
 @pytest.mark.parametrize("n,wide", [(12, ALL), (12, 0), (13, ALL), (13, 0)])
 def test_lines_cut_into_segments(n, wide):
-    # levels 12 and 13: the grids (n - 1, 1) ... have lines of 2,047 and 4,095
-    # unknowns, longer than one wave's 1,024-unknown segment of the line
-    # preconditioner (two and four segments, the last shorter or full); the
+    # levels 12 and 13: the grids (n, 1), (n - 1, 1), ... have lines of up to
+    # 4,095 and 8,191 unknowns, longer than one wave's 1,024-unknown segment
+    # of the line preconditioner (two to eight segments, the last shorter or
+    # full); the
     # operator couples across the segments, the preconditioner does not, so
     # the solution matches the oracle's direct solves as for any other grid,
     # on the wide solver and on the one-work-group-per-system kernel
