@@ -1,6 +1,8 @@
 // Auxiliary kernels: initial value sampling, standalone stencil apply,
 // combination gather / combine-then-project, norms and vector updates of
 // the MGRIT driver, and the dispatch of the chain kernel instantiations.
+#include <algorithm>
+
 #include "line_layout.hpp"
 #include "manufactured.hpp"
 
@@ -557,31 +559,49 @@ hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, doub
   return hipGetLastError();
 }
 
-// out[0] = max over tasks t of sqrt(res2[t] / norm2[grid(t)]) (norm2 = 0 -> 1).
-__global__ void __launch_bounds__(256)
-    residual_max_kernel(const int2* __restrict__ tasks, int ntasks,
-                        const double* __restrict__ res2, const double* __restrict__ norm2,
-                        double* __restrict__ mg, double* __restrict__ host_mg, int it,
-                        double tol, const int* __restrict__ status) {
-  __shared__ double part[256];
-  double m = 0.0;
-  for (int t = threadIdx.x; t < ntasks; t += 256) {
-    const double n2 = norm2[tasks[t].x];
-    const double r = sqrt(res2[t] / (n2 > 0.0 ? n2 : 1.0));
-    m = (r > m || r != r) ? r : m;
-  }
-  part[threadIdx.x] = m;
+// The MGRIT residual test: max over tasks t of sqrt(res2[t] /
+// norm2[grid(t)]) (norm2 = 0 -> 1; NaN wins), in two passes: up to
+// kResBlocks work-groups each reduce a strided share of the tasks into
+// part[], then one work-group reduces part[] and records the iteration.
+// (One work-group over all tasks took 0.74 ms per iteration for the
+// 218,752 tasks of the 6-D workload, alone on the critical path.) The max
+// is exact, so the result does not depend on the split.
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__device__ __forceinline__ double block_max256(double m, double* sm) {
+  sm[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      const double a = part[threadIdx.x], b = part[threadIdx.x + w];
-      part[threadIdx.x] = (b > a || b != b) ? b : a;
-    }
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = nanmax(sm[threadIdx.x], sm[threadIdx.x + w]);
     __syncthreads();
   }
+  return sm[0];
+}
+
+__global__ void __launch_bounds__(256)
+    residual_part_kernel(const int2* __restrict__ tasks, int ntasks,
+                         const double* __restrict__ res2, const double* __restrict__ norm2,
+                         double* __restrict__ part) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < ntasks; t += gridDim.x * 256) {
+    const double n2 = norm2[tasks[t].x];
+    m = nanmax(m, sqrt(res2[t] / (n2 > 0.0 ? n2 : 1.0)));
+  }
+  const double r = block_max256(m, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256)
+    residual_max_kernel(const double* __restrict__ part, int nparts, double* __restrict__ mg,
+                        double* __restrict__ host_mg, int it, double tol,
+                        const int* __restrict__ status) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) m = nanmax(m, part[b]);
+  const double res = block_max256(m, sm);
   if (threadIdx.x == 0) {
     if (mg[0] == 0.0) {
-      const double res = part[0];
       mg[2 * it] = res;
       const bool nonfinite = (res != res) || ((*status >> CTM_ERR_NONFINITE) & 1);
       if (res <= tol || nonfinite) mg[0] = (double)it;
@@ -595,10 +615,13 @@ __global__ void __launch_bounds__(256)
 }
 
 hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
-                               const double* norm2, double* mg, double* host_mg, int it,
-                               double tol, const int* status, hipStream_t s) {
-  hipLaunchKernelGGL(residual_max_kernel, dim3(1), dim3(256), 0, s, tasks, ntasks, res2, norm2,
-                     mg, host_mg, it, tol, status);
+                               const double* norm2, double* part, double* mg, double* host_mg,
+                               int it, double tol, const int* status, hipStream_t s) {
+  const int nb = ntasks <= 0 ? 1 : std::min(kResBlocks, (ntasks + 255) / 256);
+  hipLaunchKernelGGL(residual_part_kernel, dim3(nb), dim3(256), 0, s, tasks, ntasks, res2, norm2,
+                     part);
+  hipLaunchKernelGGL(residual_max_kernel, dim3(1), dim3(256), 0, s, part, nb, mg, host_mg, it,
+                     tol, status);
   return hipGetLastError();
 }
 

@@ -964,6 +964,7 @@ struct Layout {
   double* X = nullptr;
   double* Y = nullptr;
   double* res2 = nullptr;
+  double* rpart = nullptr;  // partial maxima of the residual test
   size_t bytes = 0;
 };
 
@@ -1006,6 +1007,9 @@ Layout make_layout(const ctm_plan* P, char* base) {
   off += (size_t)maxtasks * sizeof(double);
   off = (off + 255) & ~size_t(255);
   lay.res2 = r2;
+  lay.rpart = base ? reinterpret_cast<double*>(base + off) : nullptr;
+  off += (size_t)kResBlocks * sizeof(double);
+  off = (off + 255) & ~size_t(255);
   lay.bytes = off;
   return lay;
 }
@@ -1369,8 +1373,9 @@ ctm_status mgrit_block(ctm_plan* P, Layout& lay, hipStream_t s) {
     if ((st = run_chain(P, fr, *tasks, s, false, !open, true)) != CTM_OK) return st;
     open = false;
     traj = (Tr != nullptr);
-    CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, P->dmg, P->hmg_dev, it,
-                                p.mgrit_tol, reinterpret_cast<const int*>(P->dsync + 1), s));
+    CTM_HIP(launch_residual_max(tasks->d, (int)nt, lay.res2, P->dnorm2, lay.rpart, P->dmg,
+                                P->hmg_dev, it, p.mgrit_tol,
+                                reinterpret_cast<const int*>(P->dsync + 1), s));
     CTM_HIP(hipEventRecord(P->it_events[it], s));
     mark(it);
     queued = it;

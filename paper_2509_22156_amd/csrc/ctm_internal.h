@@ -365,8 +365,10 @@ hipError_t launch_grid_norms2(const GridDev* grids, int G, const double* u, doub
 // non-finite bit. Always mg[2 it + 1] = mg[0]. host_mg (optional, mapped
 // pinned host memory) receives mg[2 it] and mg[2 it + 1] as well.
 hipError_t launch_residual_max(const int2* tasks, int ntasks, const double* res2,
-                               const double* norm2, double* mg, double* host_mg, int it,
-                               double tol, const int* status, hipStream_t s);
+                               const double* norm2, double* part, double* mg, double* host_mg,
+                               int it, double tol, const int* status, hipStream_t s);
+// partial maxima the residual test needs in the workspace (doubles)
+constexpr int kResBlocks = 256;
 // dst[(ad q + bd) slen + e] = x[(ax q + bx) slen + e] (+ y[(ay q + by) slen + e]),
 // q = 0..nvec-1, e = 0..slen-1; y.base may be null.
 // skip (optional): the launch does nothing once *skip != 0.

@@ -28,8 +28,8 @@ hipError_t launch_hier_combine(const int*, const int*, const double*, int, const
                                hipStream_t) CTM_STUB()
 hipError_t launch_hier_scatter(const int*, long long, const double*, double*, hipStream_t) CTM_STUB()
 hipError_t launch_grid_norms2(const GridDev*, int, const double*, double*, hipStream_t) CTM_STUB()
-hipError_t launch_residual_max(const int2*, int, const double*, const double*, double*, double*, int,
-                               double, const int*, hipStream_t) CTM_STUB()
+hipError_t launch_residual_max(const int2*, int, const double*, const double*, double*, double*,
+                               double*, int, double, const int*, hipStream_t) CTM_STUB()
 hipError_t launch_vec_add(VecRef, VecRef, VecRef, int, long long, hipStream_t, const double*) CTM_STUB()
 hipError_t launch_class_vec_add(const int2*, int, const GridDev*, VecRef, VecRef, VecRef, int,
                                 long long, hipStream_t, const double*) CTM_STUB()
