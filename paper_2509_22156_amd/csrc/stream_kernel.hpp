@@ -186,9 +186,12 @@ __device__ __forceinline__ int stream_line_rounds(const GridDev& g) {
 }
 
 // Lane `lane` of wave `vwave` of the task: the wave holds 64 / Lc line
-// segments, segments vwave * (64 / Lc) + lane / Lc (segment s of line
-// s / nseg). The first chunk of a segment is lane c = 0 and its last has no
-// successor (nxt), so the line solve couples nothing across segments.
+// segments, segments vwave * (64 / Lc) + lane / Lc. Segment index s is
+// segment s / nlines of line s % nlines (segment-major), so consecutive
+// indices are the same segment of neighbouring lines: neighbours in memory
+// where the stiff axis is not the fastest. The first chunk of a segment is
+// lane c = 0 and its last has no successor (nxt), so the line solve couples
+// nothing across segments.
 template <int D>
 __device__ __forceinline__ void stream_lane_at(const GridDev& g, int vwave, int lane, SLane& L) {
   const int S = stream_seg_len(g);
@@ -197,8 +200,8 @@ __device__ __forceinline__ void stream_lane_at(const GridDev& g, int vwave, int 
   L.c = lane & (Lc - 1);
   const int seg = vwave * (64 / Lc) + lane / Lc;
   const bool live = seg < stream_segments(g);
-  const int sg = live ? seg % g.nseg : 0;
-  L.line = live ? seg / g.nseg : g.nlines;
+  const int sg = live ? seg / g.nlines : 0;
+  L.line = live ? seg % g.nlines : g.nlines;
   const int s0 = sg * S;                               // first unknown of the segment
   const int s1 = s0 + S < g.ns ? s0 + S : g.ns;        // one past its last
   L.j0 = s0 + L.c * kSK;

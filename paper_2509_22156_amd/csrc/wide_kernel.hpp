@@ -43,6 +43,27 @@ __device__ __forceinline__ int wide_line_blocks(const GridDev& g) {
   return (waves + kWLW - 1) / kWLW;
 }
 
+// Virtual block of a line work-group. Work-groups are dealt to the eight
+// XCDs round robin, so consecutive blocks run on different XCDs, each with
+// its own L2. Where the stiff axis is not the fastest, consecutive virtual
+// waves hold neighbouring lines, which share 128-byte cache lines (16
+// doubles: the lines of m = 16 / (64 / Lc) waves); blocks b, b + 8, b + 16,
+// ... (one XCD) take such a run of m virtual blocks, so that a cache line
+// is brought into one L2 instead of m. A last run shorter than 8 m blocks
+// keeps the plain order (any bijection of the blocks is valid: the line
+// solves are independent).
+static_assert(kWLW == 1, "the run length counts one wave per line work-group");
+__device__ __forceinline__ int wide_line_vblock(const GridDev& g) {
+  const int b = (int)blockIdx.x;
+  const int Lc = pow2ceil((stream_seg_len(g) + kSK - 1) / kSK);
+  const int m = (g.sax == g.d - 1 || Lc < 8) ? 1 : Lc / 4;
+  const int span = 8 * m;
+  const int c0 = b - b % span;
+  if (m == 1 || c0 + span > wide_line_blocks(g)) return b;
+  const int r = b - c0;
+  return c0 + (r & 7) * m + (r >> 3);
+}
+
 struct WideSmem {
   double red[2 * 64];
   int flag;  // done broadcast (multi-wave work-groups)
@@ -232,11 +253,11 @@ __device__ __forceinline__ double wide_Ax(const GridDev& g, const double* tl, do
 }
 
 // ------------------------------------------------------- line helpers
-// Lane of this thread in the line layout (block b, wave w: virtual wave
-// b * kWLW + w of the task).
+// Lane of this thread in the line layout (wave w of the block: virtual wave
+// wide_line_vblock * kWLW + w of the task).
 template <int D>
 __device__ __forceinline__ void wide_lane(const GridDev& g, SLane& L) {
-  stream_lane_at<D>(g, (int)blockIdx.x * kWLW + (threadIdx.x >> 6), threadIdx.x & 63, L);
+  stream_lane_at<D>(g, wide_line_vblock(g) * kWLW + (threadIdx.x >> 6), threadIdx.x & 63, L);
 }
 // Point index of unknown k of the lane's chunk (< 2^20: a 32-bit offset).
 __device__ __forceinline__ unsigned lane_pt(const SLane& L, int k) {
@@ -282,7 +303,7 @@ __device__ __forceinline__ WaveTile wave_tile(const WideArgs& w, const GridDev& 
   // not be one contiguous range)
   T.on = w.stage && (g.sax == g.d - 1) && g.nseg == 1;
   const int G = 64 / L.Lc;
-  const int line0 = ((int)blockIdx.x * kWLW + (int)(threadIdx.x >> 6)) * G;
+  const int line0 = (wide_line_vblock(g) * kWLW + (int)(threadIdx.x >> 6)) * G;
   const int gv = g.nlines - line0 < G ? g.nlines - line0 : G;
   T.t0 = (unsigned)line0 * (unsigned)g.ns;
   T.n = gv * g.ns;
