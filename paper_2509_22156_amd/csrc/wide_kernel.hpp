@@ -43,25 +43,44 @@ __device__ __forceinline__ int wide_line_blocks(const GridDev& g) {
   return (waves + kWLW - 1) / kWLW;
 }
 
-// Virtual block of a line work-group. Work-groups are dealt to the eight
-// XCDs round robin, so consecutive blocks run on different XCDs, each with
-// its own L2. Where the stiff axis is not the fastest, consecutive virtual
-// waves hold neighbouring lines, which share 128-byte cache lines (16
-// doubles: the lines of m = 16 / (64 / Lc) waves); blocks b, b + 8, b + 16,
-// ... (one XCD) take such a run of m virtual blocks, so that a cache line
-// is brought into one L2 instead of m. A last run shorter than 8 m blocks
-// keeps the plain order (any bijection of the blocks is valid: the line
-// solves are independent).
-static_assert(kWLW == 1, "the run length counts one wave per line work-group");
+// Work-group placement. The dispatcher deals a launch's work-groups to the
+// eight XCDs round robin in linear order (y * gridDim.x + x), and each XCD
+// has its own L2. Left in that order, every task's blocks spread over all
+// eight, so the cache lines that neighbouring blocks share (stencil halos;
+// the neighbouring lines of a grid whose stiff axis is not the fastest) are
+// fetched into several L2s. Instead, the tasks of a launch are taken in
+// groups of eight: the eight gridDim.x-block rows of a group form one range
+// of linear ids, a multiple of eight long, whose ids on XCD k all become
+// blocks of task k of the group (block = position among them). A task then
+// runs on one XCD, and consecutive tasks (normally intervals of the same
+// grid, equal work) on different ones. A last group of fewer than eight
+// tasks keeps the plain order. Any bijection of (task, block) is valid: the
+// kernels depend on it only through the blocks' partial-sum slots, which
+// are indexed by the same mapped block.
+__device__ __forceinline__ bool wide_grouped() {
+  return blockIdx.y < (gridDim.y & ~7u);
+}
+__device__ __forceinline__ int wide_bx() {
+  if (!wide_grouped()) return (int)blockIdx.x;
+  return (int)(((blockIdx.y & 7u) * gridDim.x + blockIdx.x) >> 3);
+}
+__device__ __forceinline__ int wide_by() {
+  if (!wide_grouped()) return (int)blockIdx.y;
+  return (int)((blockIdx.y & ~7u) + (((blockIdx.y & 7u) * gridDim.x + blockIdx.x) & 7u));
+}
+
+// Virtual line block. In a last group of fewer than eight tasks (plain
+// order: a task's consecutive blocks on different XCDs) the blocks of a grid
+// whose stiff axis is not the fastest are regrouped, so that the blocks of
+// one XCD (b, b + 8, b + 16, ...) take q = nb / 8 consecutive virtual blocks:
+// neighbouring lines, which share cache lines. Blocks from 8 q on keep
+// their index.
 __device__ __forceinline__ int wide_line_vblock(const GridDev& g) {
-  const int b = (int)blockIdx.x;
-  const int Lc = pow2ceil((stream_seg_len(g) + kSK - 1) / kSK);
-  const int m = (g.sax == g.d - 1 || Lc < 8) ? 1 : Lc / 4;
-  const int span = 8 * m;
-  const int c0 = b - b % span;
-  if (m == 1 || c0 + span > wide_line_blocks(g)) return b;
-  const int r = b - c0;
-  return c0 + (r & 7) * m + (r >> 3);
+  const int b = wide_bx();
+  if (wide_grouped() || g.sax == g.d - 1) return b;
+  const int q = wide_line_blocks(g) >> 3;
+  if (b >= 8 * q) return b;
+  return (b & 7) * q + (b >> 3);
 }
 
 struct WideSmem {
@@ -84,7 +103,7 @@ __device__ __forceinline__ bool wide_begin(const WideArgs& w, WideSmem& sm, doub
                                            bool line, bool check_done, const GridDev*& gp,
                                            const double*& tl) {
   const ChainArgs& a = w.a;
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   const double skipv = a.skip ? *a.skip : 0.0;
   gp = &T->g;
   const GridDev& g = *gp;
@@ -92,7 +111,7 @@ __device__ __forceinline__ bool wide_begin(const WideArgs& w, WideSmem& sm, doub
   if constexpr (BT == 64) done = check_done ? T->done : 0;
   if (skipv != 0.0) return false;
   const int nb = line ? wide_line_blocks(g) : wide_point_blocks(g);
-  if ((int)blockIdx.x >= nb) return false;
+  if (wide_bx() >= nb) return false;
   if constexpr (BT > 64) {
     if (threadIdx.x == 0) sm.flag = check_done ? T->done : 0;
   }
@@ -108,14 +127,14 @@ __device__ __forceinline__ bool wide_begin(const WideArgs& w, WideSmem& sm, doub
 }
 
 __device__ __forceinline__ double* wide_sv(const WideArgs& w) {
-  return w.scratch + (long long)blockIdx.y * SV_N * w.ss;
+  return w.scratch + (long long)wide_by() * SV_N * w.ss;
 }
 // Scratch of the task holding this task's line factors.
 __device__ __forceinline__ const double* wide_fsv(const WideArgs& w) {
-  return w.scratch + (long long)w.st[blockIdx.y].fsrc * SV_N * w.ss;
+  return w.scratch + (long long)w.st[wide_by()].fsrc * SV_N * w.ss;
 }
 __device__ __forceinline__ double* wide_part(const WideArgs& w, int slot) {
-  return w.part + ((size_t)blockIdx.y * WS_N + slot) * w.maxblk;
+  return w.part + ((size_t)wide_by() * WS_N + slot) * w.maxblk;
 }
 
 // Store this work-group's partials of slots slot0 .. slot0 + NS - 1.
@@ -126,7 +145,7 @@ __device__ __forceinline__ void wide_put(const WideArgs& w, WideSmem& sm, int sl
   block_sum<BT / 64, NS, double>(v, ring);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) wide_part(w, slot0 + s)[blockIdx.x] = v[s];
+    for (int s = 0; s < NS; ++s) wide_part(w, slot0 + s)[wide_bx()] = v[s];
   }
 }
 
@@ -493,15 +512,15 @@ __global__ void __launch_bounds__(kWLT) wide_setup_kernel(WideArgs w) {
   // for the kernels that follow
   const ChainArgs& a = w.a;
   if (a.skip && *a.skip != 0.0) return;
-  const int2 task = a.tasks[blockIdx.y];
+  const int2 task = a.tasks[wide_by()];
   const GridDev& g = a.grids[task.x];
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   // the factors depend on the grid and the step only: the first task of the
   // launch on this grid computes them, the others read that task's copy
   // (one wave: the lanes scan the earlier tasks, a shuffle tree takes the
   // minimum)
-  int fsrc = (int)blockIdx.y;
-  for (int t = (int)threadIdx.x; t < (int)blockIdx.y; t += 64)
+  int fsrc = wide_by();
+  for (int t = (int)threadIdx.x; t < wide_by(); t += 64)
     if (a.tasks[t].x == task.x) {
       fsrc = t;
       break;
@@ -511,7 +530,7 @@ __global__ void __launch_bounds__(kWLT) wide_setup_kernel(WideArgs w) {
     const int o = __shfl_xor(fsrc, sh, 64);
     fsrc = o < fsrc ? o : fsrc;
   }
-  if (blockIdx.x == 0) {
+  if (wide_bx() == 0) {
     const int* src = reinterpret_cast<const int*>(&g);
     int* dst = reinterpret_cast<int*>(&T->g);
     for (int t = threadIdx.x; t < (int)(sizeof(GridDev) / sizeof(int)); t += kWLT) dst[t] = src[t];
@@ -520,7 +539,7 @@ __global__ void __launch_bounds__(kWLT) wide_setup_kernel(WideArgs w) {
       T->fsrc = fsrc;
     }
   }
-  if ((int)blockIdx.x >= wide_line_blocks(g) || fsrc != (int)blockIdx.y) return;
+  if (wide_bx() >= wide_line_blocks(g) || fsrc != wide_by()) return;
   if constexpr (OPC == OPC_SEP || OPC == OPC_VAR) {
     load_tables<OPC, double, kWLT>(g, a.tab64, a.dt, tl_lds);
     tl = tl_lds;
@@ -547,10 +566,10 @@ __global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
   if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, false, gp, tl)) return;
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
-  const int q = w.st[blockIdx.y].q;
+  const int q = w.st[wide_by()].q;
   const int j = w.j;
   const bool last = (j == a.nsteps), res = a.resmode != 0;
-  if (blockIdx.x == 0) {
+  if (wide_bx() == 0) {
     double rr0 = 0.0;
     if (j > 1 && res) {
       const int slot[1] = {WS_RR0}, nb[1] = {wide_point_blocks(g)};
@@ -559,7 +578,7 @@ __global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
       rr0 = v[0];
     }
     if (threadIdx.x == 0) {
-      WideTask* T = w.st + blockIdx.y;
+      WideTask* T = w.st + wide_by();
       if (j == 1) {
         T->kr_sum = T->kr_max = 0;
         T->res_max = 0.0;
@@ -601,7 +620,7 @@ __global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
   double b0[kWPT], b1[kWPT], xg[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     b0[k] = b1[k] = xg[k] = 0.0;
     if (p >= g.npts) continue;
     const double b = (j == 1) ? (st ? st[p] : 0.0) : X[p] + (fp ? fp[p] : 0.0);
@@ -617,7 +636,7 @@ __global__ void __launch_bounds__(kWT) wide_step_kernel(WideArgs w) {
   }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
     if (wb) wb[p] = b0[k];
     if (is) is[p] = b0[k];
@@ -645,7 +664,7 @@ __global__ void __launch_bounds__(kWT) wide_init_kernel(WideArgs w) {
   double rv[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     rv[k] = 0.0;
     if (p >= g.npts) continue;
     const double b = B[p];
@@ -656,7 +675,7 @@ __global__ void __launch_bounds__(kWT) wide_init_kernel(WideArgs w) {
   }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
     R[p] = rv[k];
     if constexpr (SOLVER == SOLV_BICG) {
@@ -679,7 +698,7 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
   if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   const double tol2 = a.tol * a.tol;
   const int i = w.i;
   double* sv = wide_sv(w);
@@ -738,7 +757,7 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_a_kernel(WideArgs w) {
     const double alpha = rho_o / Sm.rhv;
     const bool pend = (rho_n == 0.0 || omega == 0.0);
     const double beta = pend ? 0.0 : (rho_n / rho_o) * (alpha / omega);
-    if (pend && blockIdx.x == 0 && threadIdx.x == 0) T->pend = 1;
+    if (pend && wide_bx() == 0 && threadIdx.x == 0) T->pend = 1;
     // r = s - omega t, x += omega h; then p = r + beta (p - omega v)
     {
       double st[2][kSK];
@@ -783,7 +802,7 @@ __global__ void __launch_bounds__(kWT) wide_bicg_b_kernel(WideArgs w) {
   if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, true, gp, tl)) return;
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   const double* H = sv + SV_D * ss;
@@ -795,7 +814,7 @@ __global__ void __launch_bounds__(kWT) wide_bicg_b_kernel(WideArgs w) {
   double yv[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     yv[k] = 0.0;
     if (p >= g.npts) continue;
     const double y = wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int m) { return H[m]; });
@@ -814,7 +833,7 @@ __global__ void __launch_bounds__(kWT) wide_bicg_b_kernel(WideArgs w) {
   }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     if (p < g.npts) V[p] = yv[k];
   }
   wide_put<kWT, 1>(w, sm, WS_RHV, v);
@@ -827,7 +846,7 @@ __global__ void __launch_bounds__(kWLT) wide_bicg_c_kernel(WideArgs w) {
   WIDE_TILE;
   if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const GridDev& g = *gp;
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   double* sv = wide_sv(w);
   const long long ss = w.ss;
   double* X = sv + SV_X * ss;
@@ -889,7 +908,7 @@ __global__ void __launch_bounds__(kWT) wide_bicg_d_kernel(WideArgs w) {
   double tv[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     tv[k] = 0.0;
     if (p >= g.npts) continue;
     const double t = wide_Ax<OPC, D>(g, tl, a.dt, a.amp, p, [&](int m) { return H[m]; });
@@ -903,7 +922,7 @@ __global__ void __launch_bounds__(kWT) wide_bicg_d_kernel(WideArgs w) {
   }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     if (p < g.npts) Tv[p] = tv[k];
   }
   wide_put<kWT, 5>(w, sm, WS_D + 5 * (w.i & 1), v);
@@ -917,7 +936,7 @@ __global__ void __launch_bounds__(kWLT) wide_cg_a_kernel(WideArgs w) {
   WIDE_TILE;
   if (!wide_begin<OPC, kWLT>(w, sm, tl_lds, true, true, gp, tl)) return;
   const GridDev& g = *gp;
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   const double tol2 = w.a.tol * w.a.tol;
   double* sv = wide_sv(w);
   const long long ss = w.ss;
@@ -991,7 +1010,7 @@ __global__ void __launch_bounds__(kWT) wide_cg_b_kernel(WideArgs w) {
   double pvv[kWPT], yv[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     pvv[k] = yv[k] = 0.0;
     if (p >= g.npts) continue;
     auto pv = [&](int m) { return Z[m] + beta * Po[m]; };
@@ -1003,7 +1022,7 @@ __global__ void __launch_bounds__(kWT) wide_cg_b_kernel(WideArgs w) {
   }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
     Pn[p] = pvv[k];
     Q[p] = yv[k];
@@ -1017,7 +1036,7 @@ __global__ void __launch_bounds__(kWT) wide_cg_c_kernel(WideArgs w) {
   WIDE_SMEM;
   if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, true, gp, tl)) return;
   const GridDev& g = *gp;
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   const int i = w.i;
   const int slot[2] = {WS_PQ, WS_RZ + (i & 1)};
   const int nb[2] = {wide_point_blocks(g), wide_line_blocks(g)};
@@ -1039,7 +1058,7 @@ __global__ void __launch_bounds__(kWT) wide_cg_c_kernel(WideArgs w) {
   double xv[kWPT], rv[kWPT];
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     xv[k] = rv[k] = 0.0;
     if (p >= g.npts) continue;
     xv[k] = X[p] + alpha * Pn[p];
@@ -1049,7 +1068,7 @@ __global__ void __launch_bounds__(kWT) wide_cg_c_kernel(WideArgs w) {
   }
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts) continue;
     X[p] = xv[k];
     R[p] = rv[k];
@@ -1066,7 +1085,7 @@ __global__ void __launch_bounds__(kWT) wide_fin_kernel(WideArgs w) {
   if (!wide_begin<OPC, kWT>(w, sm, tl_lds, false, false, gp, tl)) return;
   const ChainArgs& a = w.a;
   const GridDev& g = *gp;
-  const int q = w.st[blockIdx.y].q;
+  const int q = w.st[wide_by()].q;
   const bool res = a.resmode != 0;
   const bool rho = res && a.target.base;  // the step kernel formed the residual
   double* sv = wide_sv(w);
@@ -1082,7 +1101,7 @@ __global__ void __launch_bounds__(kWT) wide_fin_kernel(WideArgs w) {
   double v[1] = {0.0};
 #pragma unroll
   for (int k = 0; k < kWPT; ++k) {
-    const int p = blockIdx.x * kWP + k * kWT + threadIdx.x;
+    const int p = wide_bx() * kWP + k * kWT + threadIdx.x;
     if (p >= g.npts || !dst) continue;
     double u = rho ? B[p] : X[p] + (fl ? fl[p] : 0.0);
     if (tg) u -= tg[p];
@@ -1107,7 +1126,7 @@ __global__ void __launch_bounds__(64) wide_finish_kernel(WideArgs w) {
   double v[2];
   wide_sums<2>(w, slot, nb, v);
   if (threadIdx.x != 0) return;
-  WideTask* T = w.st + blockIdx.y;
+  WideTask* T = w.st + wide_by();
   int flag = T->flag;
   long long kr_sum = T->kr_sum, kr_max = T->kr_max;
   double res_max = T->res_max;
@@ -1121,7 +1140,7 @@ __global__ void __launch_bounds__(64) wide_finish_kernel(WideArgs w) {
     kr_sum += it;
     kr_max = it > kr_max ? it : kr_max;
   }
-  if (a.target.base && a.res2) a.res2[blockIdx.y] = res ? fmax(v[0], res_max) : v[0];
+  if (a.target.base && a.res2) a.res2[wide_by()] = res ? fmax(v[0], res_max) : v[0];
   if (a.counters) {
     atomicAdd(&a.counters[CNT_KRYLOV], (unsigned long long)kr_sum);
     atomicMax(&a.counters[CNT_KRYLOV_MAX], (unsigned long long)kr_max);
@@ -1148,7 +1167,7 @@ __global__ void __launch_bounds__(64) wide_poll_kernel(WideArgs w) {
     const int nb[3] = {wide_point_blocks(g), wide_point_blocks(g), w.i > 1 ? nbr : 0};
     double v[3];
     wide_sums<3>(w, slot, nb, v);
-    WideTask* T = w.st + blockIdx.y;
+    WideTask* T = w.st + wide_by();
     int it, fl;
     const double tol2 = w.a.tol * w.a.tol;
     const bool stop = (w.i == 1) ? wide_test_init(v[0], v[1], tol2, it, fl)
@@ -1159,7 +1178,7 @@ __global__ void __launch_bounds__(64) wide_poll_kernel(WideArgs w) {
       busy = 1;
   }
   if (threadIdx.x == 0)
-    __hip_atomic_store(w.host_out + blockIdx.y, busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(w.host_out + wide_by(), busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 #undef WIDE_SMEM
