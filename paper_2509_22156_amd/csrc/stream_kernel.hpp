@@ -250,16 +250,18 @@ __device__ __forceinline__ void line_coef(const GridDev& g, const double* tl, do
 // unknown), FID = reciprocal pivots, FCU = upper couplings inside the
 // chunk, FPHI/FPSI = responses of the eliminated unknowns to the previous
 // and own interface unknown (slot kSK-1: the interface's couplings aL, cL).
-// ftmp is a scratch vector (the forward spike).
-template <int OPC, int D>
+// ftmp is a scratch vector (the forward spike). TF is the factors' storage
+// type (the arithmetic is FP64): double here, float in the wide solver,
+// whose slots then hold ss floats each.
+template <int OPC, int D, typename TF = double>
 __device__ __forceinline__ void linepre_setup_lane(const GridDev& g, const double* tl, double dt,
                                                    double amp, double* sv, long long ss,
                                                    double* ftmp, const SLane& L) {
-  double* FM = sv + SV_FM * ss;
-  double* FID = sv + SV_FID * ss;
-  double* FCU = sv + SV_FCU * ss;
-  double* FPHI = sv + SV_FPHI * ss;
-  double* FPSI = sv + SV_FPSI * ss;
+  TF* FM = reinterpret_cast<TF*>(sv + SV_FM * ss);
+  TF* FID = reinterpret_cast<TF*>(sv + SV_FID * ss);
+  TF* FCU = reinterpret_cast<TF*>(sv + SV_FCU * ss);
+  TF* FPHI = reinterpret_cast<TF*>(sv + SV_FPHI * ss);
+  TF* FPSI = reinterpret_cast<TF*>(sv + SV_FPSI * ss);
   {
     // forward over the eliminated unknowns k = 0..kSK-2
     double idp = 0.0, cp = 0.0, fp = 0.0;
@@ -284,9 +286,9 @@ __device__ __forceinline__ void linepre_setup_lane(const GridDev& g, const doubl
         f = -m * fp;
       }
       if (v) {
-        FM[p] = m;
-        FID[p] = id;
-        FCU[p] = (k < kSK - 2) ? c : 0.0;
+        FM[p] = (TF)m;
+        FID[p] = (TF)id;
+        FCU[p] = (TF)((k < kSK - 2) ? c : 0.0);
         ftmp[p] = f;
       }
       idp = id;
@@ -300,9 +302,9 @@ __device__ __forceinline__ void linepre_setup_lane(const GridDev& g, const doubl
       if (v) {
         double lo, dg, up;
         line_coef<OPC, D>(g, tl, dt, amp, (int)p, lo, dg, up);
-        FM[p] = dg;
-        FPHI[p] = lo;                  // aL (j0 + kSK - 1 > 0 always)
-        FPSI[p] = L.nxt ? up : 0.0;    // cL
+        FM[p] = (TF)dg;
+        FPHI[p] = (TF)lo;                      // aL (j0 + kSK - 1 > 0 always)
+        FPSI[p] = (TF)(L.nxt ? up : 0.0);      // cL
       }
     }
     // backward: phi = T^-1 (a_0 e_0), psi = T^-1 (c_{kSK-2} e_{kSK-2})
@@ -313,17 +315,17 @@ __device__ __forceinline__ void linepre_setup_lane(const GridDev& g, const doubl
       const long long p = L.base + (long long)(L.j0 + k) * L.step;
       double ph = 0.0, ps = 0.0;
       if (v) {
-        const double id = FID[p], f = ftmp[p];
+        const double id = (double)FID[p], f = ftmp[p];
         if (k == kSK - 2) {
           ph = f * id;
           ps = cp * id;  // c_{kSK-2}, from the forward pass
         } else {
-          const double cu = FCU[p];
+          const double cu = (double)FCU[p];
           ph = (f - cu * php) * id;
           ps = -cu * psp * id;
         }
-        FPHI[p] = ph;
-        FPSI[p] = ps;
+        FPHI[p] = (TF)ph;
+        FPSI[p] = (TF)ps;
       }
       php = ph;
       psp = ps;

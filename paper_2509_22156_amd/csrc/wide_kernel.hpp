@@ -293,6 +293,10 @@ __device__ __forceinline__ double ldo(const double* base, unsigned i) {
 __device__ __forceinline__ void sto(double* base, unsigned i, double v) {
   *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (size_t)(i * 8u)) = v;
 }
+__device__ __forceinline__ float ldo(const float* base, unsigned i) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) +
+                                         (size_t)(i * 4u));
+}
 
 // Line sweeps of a wave. Where the stiff axis is the grid's fastest axis
 // (stride 1), the wave's 64 / Lc lines are one contiguous range of at most
@@ -331,32 +335,34 @@ __device__ __forceinline__ WaveTile wave_tile(const WideArgs& w, const GridDev& 
 }
 
 // out[s][k] = vector s at unknown k of the lane's chunk (0 past nval).
-template <int NV>
+// TE: the vectors' element type (double; float for the line factors, which
+// then pass through the wave's tile region as floats).
+template <int NV, typename TE = double>
 __device__ __forceinline__ void line_gather(const WaveTile& T, const SLane& L,
-                                            const double* const (&v)[NV], double* tile,
-                                            double (&out)[NV][kSK]) {
+                                            const TE* const (&v)[NV], double* tile,
+                                            TE (&out)[NV][kSK]) {
   if (!T.on) {
 #pragma unroll
     for (int k = 0; k < kSK; ++k) {
       const bool ok = k < L.nval;
       const unsigned p = lane_pt(L, k);
 #pragma unroll
-      for (int s = 0; s < NV; ++s) out[s][k] = ok ? ldo(v[s], p) : 0.0;
+      for (int s = 0; s < NV; ++s) out[s][k] = ok ? ldo(v[s], p) : (TE)0;
     }
     return;
   }
-  double* tw = tile + (threadIdx.x >> 6) * (kTileVecs * kTilePad);
+  TE* tw = reinterpret_cast<TE*>(tile + (threadIdx.x >> 6) * (kTileVecs * kTilePad));
   const int lane = threadIdx.x & 63;
   // every global load first (one round trip), then the vectors pass
   // through the tile kTileVecs at a time (a small tile keeps more
   // work-groups resident per CU)
-  double tmp[NV][kSK];
+  TE tmp[NV][kSK];
 #pragma unroll
   for (int m = 0; m < kSK; ++m) {
     const int e = m * 64 + lane;
     const bool ok = e < T.n;
 #pragma unroll
-    for (int s = 0; s < NV; ++s) tmp[s][m] = ok ? ldo(v[s], T.t0 + (unsigned)e) : 0.0;
+    for (int s = 0; s < NV; ++s) tmp[s][m] = ok ? ldo(v[s], T.t0 + (unsigned)e) : (TE)0;
   }
 #pragma unroll
   for (int s0 = 0; s0 < NV; s0 += kTileVecs) {
@@ -375,7 +381,7 @@ __device__ __forceinline__ void line_gather(const WaveTile& T, const SLane& L,
       const bool ok = k < L.nval;
 #pragma unroll
       for (int s = s0; s < NV && s < s0 + kTileVecs; ++s)
-        out[s][k] = ok ? tw[(s - s0) * kTilePad + tpad(T.e0 + k)] : 0.0;
+        out[s][k] = ok ? tw[(s - s0) * kTilePad + tpad(T.e0 + k)] : (TE)0;
     }
     __syncthreads();  // the tile is reused by the next pass, gather or scatter
   }
@@ -423,19 +429,24 @@ __device__ __forceinline__ void line_scatter(const WaveTile& T, const SLane& L,
 
 // z = M^-1 r on the chunk of lane L in registers (r and z hold the chunk's
 // kSK unknowns; entries past nval are ignored / returned 0). The five factor
-// vectors are gathered in one pass.
+// vectors are gathered in one pass. They are stored in FP32 (half the bytes
+// and registers; the arithmetic stays FP64): M is then the exact line-block
+// solve up to a relative perturbation of the FP32 rounding, a fixed linear
+// operator, so the Krylov solve still converges to the FP64 tolerance; only
+// its iteration count can change.
 __device__ __forceinline__ void wide_pre(const double* fsv, long long ss, const WaveTile& T,
                                          const SLane& L, double* tile, const double (&r)[kSK],
                                          double (&z)[kSK]) {
-  const double* const fv[5] = {fsv + SV_FM * ss, fsv + SV_FID * ss, fsv + SV_FCU * ss,
-                               fsv + SV_FPHI * ss, fsv + SV_FPSI * ss};
-  double f[5][kSK];
-  line_gather<5>(T, L, fv, tile, f);
-  const double* fm = f[0];
-  const double* fid = f[1];
-  const double* fcu = f[2];
-  const double* fph = f[3];
-  const double* fps = f[4];
+  auto fv_at = [&](int slot) { return reinterpret_cast<const float*>(fsv + slot * ss); };
+  const float* const fv[5] = {fv_at(SV_FM), fv_at(SV_FID), fv_at(SV_FCU), fv_at(SV_FPHI),
+                              fv_at(SV_FPSI)};
+  float f[5][kSK];
+  line_gather<5, float>(T, L, fv, tile, f);
+  const float* fm = f[0];
+  const float* fid = f[1];
+  const float* fcu = f[2];
+  const float* fph = f[3];
+  const float* fps = f[4];
   const bool full = (L.nval == kSK);
   const int ne = L.nval < kSK - 1 ? L.nval : kSK - 1;
   // forward elimination over the eliminated unknowns 0..ne-1
@@ -552,7 +563,7 @@ __global__ void __launch_bounds__(kWLT) wide_setup_kernel(WideArgs w) {
   double* sv = wide_sv(w);
   SLane L;
   wide_lane<D>(g, L);
-  linepre_setup_lane<OPC, D>(g, tl, a.dt, a.amp, sv, w.ss, sv + SV_S * w.ss, L);
+  linepre_setup_lane<OPC, D, float>(g, tl, a.dt, a.amp, sv, w.ss, sv + SV_S * w.ss, L);
 }
 
 // Step transition (point-wise; step j): finish step j-1 (B = x + forcing,
