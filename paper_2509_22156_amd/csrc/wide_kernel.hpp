@@ -28,6 +28,7 @@
 #pragma once
 
 #include "stream_kernel.hpp"
+#include "wide_map.h"
 
 namespace ctm {
 
@@ -43,44 +44,28 @@ __device__ __forceinline__ int wide_line_blocks(const GridDev& g) {
   return (waves + kWLW - 1) / kWLW;
 }
 
-// Work-group placement. The dispatcher deals a launch's work-groups to the
-// eight XCDs round robin in linear order (y * gridDim.x + x), and each XCD
-// has its own L2. Left in that order, every task's blocks spread over all
-// eight, so the cache lines that neighbouring blocks share (stencil halos;
-// the neighbouring lines of a grid whose stiff axis is not the fastest) are
-// fetched into several L2s. Instead, the tasks of a launch are taken in
-// groups of eight: the eight gridDim.x-block rows of a group form one range
-// of linear ids, a multiple of eight long, whose ids on XCD k all become
-// blocks of task k of the group (block = position among them). A task then
-// runs on one XCD, and consecutive tasks (normally intervals of the same
-// grid, equal work) on different ones. A last group of fewer than eight
-// tasks keeps the plain order. Any bijection of (task, block) is valid: the
-// kernels depend on it only through the blocks' partial-sum slots, which
-// are indexed by the same mapped block.
-__device__ __forceinline__ bool wide_grouped() {
-  return blockIdx.y < (gridDim.y & ~7u);
-}
+// Work-group placement (wide_map.h): each task's work-groups on one XCD,
+// so that the cache lines its blocks share (stencil halos; the neighbouring
+// lines of a grid whose stiff axis is not the fastest) are fetched into one
+// L2. Any bijection of (task, block) is valid: the kernels depend on it only
+// through the blocks' partial-sum slots, which are indexed by the same
+// mapped block.
+__device__ __forceinline__ bool wide_grouped() { return wide_in_group(blockIdx.y, gridDim.y); }
 __device__ __forceinline__ int wide_bx() {
-  if (!wide_grouped()) return (int)blockIdx.x;
-  return (int)(((blockIdx.y & 7u) * gridDim.x + blockIdx.x) >> 3);
+  return wide_map(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y).x;
 }
 __device__ __forceinline__ int wide_by() {
-  if (!wide_grouped()) return (int)blockIdx.y;
-  return (int)((blockIdx.y & ~7u) + (((blockIdx.y & 7u) * gridDim.x + blockIdx.x) & 7u));
+  return wide_map(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y).y;
 }
 
-// Virtual line block. In a last group of fewer than eight tasks (plain
-// order: a task's consecutive blocks on different XCDs) the blocks of a grid
-// whose stiff axis is not the fastest are regrouped, so that the blocks of
-// one XCD (b, b + 8, b + 16, ...) take q = nb / 8 consecutive virtual blocks:
-// neighbouring lines, which share cache lines. Blocks from 8 q on keep
-// their index.
+// Virtual line block: in a last group of fewer than eight tasks (plain
+// order), the line blocks of a grid whose stiff axis is not the fastest are
+// regrouped per XCD (wide_line_regroup), so that neighbouring lines share
+// one L2.
 __device__ __forceinline__ int wide_line_vblock(const GridDev& g) {
   const int b = wide_bx();
   if (wide_grouped() || g.sax == g.d - 1) return b;
-  const int q = wide_line_blocks(g) >> 3;
-  if (b >= 8 * q) return b;
-  return (b & 7) * q + (b >> 3);
+  return wide_line_regroup(b, wide_line_blocks(g));
 }
 
 struct WideSmem {
