@@ -209,6 +209,23 @@ def test_streaming_wide_many_tasks(krylov):
     assert_state_close(p, out[ALL], out[0], 1e-11)
 
 
+@pytest.mark.parametrize("nsteps", [20, 28, 36])
+@pytest.mark.parametrize("krylov", ["cg", "bicgstab"])
+def test_streaming_wide_task_groups(nsteps, krylov):
+    # 2 streaming grids x nsteps / 4 intervals: relaxation launches of 10,
+    # 14 and 18 tasks, i.e. full groups of eight tasks (each task's
+    # work-groups on one XCD) together with a last group of 2, 6 and 2 in
+    # plain order; against the oracle
+    p = _heat2d_big(nsteps=nsteps, cf=4, krylov=krylov)
+    _say(f"streaming task groups nsteps={nsteps} {krylov}")
+    plan = ctm.Plan(p)
+    plan.set_wide(ALL)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-11)
+
+
 @pytest.mark.parametrize("tight", [False, True])
 def test_streaming_paper_size_oscillator(tight):
     # the benchmark's streaming workload at full size (Section 4.4, L = 14,
