@@ -354,9 +354,11 @@ ctm_status ctm_plan_set_grid_shape(ctm_plan* plan, int g, int waves, int per_lan
  * most max_tasks such tasks (grid, interval) runs on the wide solver, which
  * spreads every task over many work-groups (one launch per Krylov phase for
  * all tasks of the launch, sums across work-groups); a larger launch keeps
- * one 1,024-thread work-group per task. Both use the same operator,
- * preconditioner, Krylov method and stopping test (Section 4.1), so results
- * agree to rounding. A wide launch waits on the host once per step for its
+ * one 1,024-thread work-group per task. Both use the same operator, Krylov
+ * method and stopping test (Section 4.1) and the same line-block
+ * preconditioner (the wide solver stores its factors in FP32, its
+ * arithmetic staying FP64), so both meet the same tolerance and their
+ * results agree to it. A wide launch waits on the host once per step for its
  * convergence test (the stream's earlier work included), so ctm_solve and
  * ctm_propagate return only when that part is done. max_tasks >= 0 (capped
  * at 65,535, the default: every streaming launch); 0 disables the wide
