@@ -46,10 +46,14 @@ STEP_BYTES_PER_DOF = 16
 # the vectors in HBM (FP64): CG fused apply+dot, fused update+dot, direction
 # update = 40 B in FP32, doubled; BiCGStab twice that
 STREAM_ALG_BYTES = {"cg": 80, "bicgstab": 160}
-# what the wide streaming solver as built moves per unknown and iteration:
-# every Krylov sweep once, plus r, z (FP64) and the five line-factor vectors
-# (FP32) of each preconditioner application
-STREAM_IMPL_BYTES = {"cg": 132, "bicgstab": 256}
+# what the wide streaming solver as built moves per unknown and iteration,
+# summed over its kernels' passes (FP64 vectors, the five line-factor
+# vectors in FP32: 20 B per preconditioner application). BiCGStab: the two
+# line kernels read x, h, s, t, p, v + factors and x, h, r, v + factors and
+# write x, r, p, h and x, s, h; the stencil kernels read h, r^ and h, s, r^
+# and write v and t: 160 B read, 72 B written. CG: r + factors -> z;
+# z, p -> p, q; x, p, r, q -> x, r: 76 B read, 40 B written.
+STREAM_IMPL_BYTES = {"cg": 116, "bicgstab": 232}
 # one-core oracle sample: every SAMPLE_STRIDE-th grid in canonical order
 # (all layers of the index set), about 15 s of host work at the 6-D size
 SAMPLE_STRIDE = 8
@@ -372,7 +376,7 @@ def _streaming(ctm, torch):
     oscillator of Section 4.4 at the paper's own levels (L = 14, L0 = 6:
     seven grids of up to 32,193 unknowns), FP64 MGRIT. Their roofline is
     HBM. Algorithmic bytes (the streaming BiCGStab iteration: 160 B per
-    unknown in FP64) and the bytes the solver as built moves (256 B: the
+    unknown in FP64) and the bytes the solver as built moves (232 B: the
     line-factor vectors of the preconditioner besides the Krylov sweeps),
     both over the wall time of the solve and over the wide solver's own
     launch time (a wide launch is its whole chain, host polls included)."""
