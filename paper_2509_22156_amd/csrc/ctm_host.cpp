@@ -469,9 +469,18 @@ bool parks_op(const ctm_plan* P, int sh, bool mixed) {
   return mixed && P->opc == OPC_VAR && sh < kNumShapes && kShapes[sh].K == 4;
 }
 
+// The chain kernel's static LDS (its copy of the grid descriptor) comes on
+// top of the dynamic LDS. A mixed plan also launches its classes in FP64
+// (the coarse MGRIT levels of coarse_in_fp64, the per-grid propagation),
+// whose layout is larger (FP64 tables and cyclic-reduction rows): both must
+// fit, or the FP64 launch is refused.
 bool shape_fits(const ctm_plan* P, const GridDev& gd, int sh) {
-  return chain_smem_bytes(sh, P->tabmax, P->mixed, P->opc == OPC_HEAT,
-                          pcr_steps(gd, kShapes[sh].K), parks_op(P, sh, P->mixed)) <= kMaxLdsBytes;
+  const int pcr = pcr_steps(gd, kShapes[sh].K);
+  const bool heat = P->opc == OPC_HEAT;
+  const size_t limit = kMaxLdsBytes - sizeof(GridDev);
+  if (chain_smem_bytes(sh, P->tabmax, P->mixed, heat, pcr, parks_op(P, sh, P->mixed)) > limit)
+    return false;
+  return !P->mixed || chain_smem_bytes(sh, P->tabmax, false, heat, pcr, false) <= limit;
 }
 
 // The default shape of grid gd among those whose LDS fits, or -1 (streaming).
@@ -781,7 +790,15 @@ ctm_status launch_range(ctm_plan* P, const ChainArgs& a, const int2* tasks, int 
   } else {
     e = launch_chain(P->opc, P->solver, mixed, shape, c, (int)count, smem, P->tab_of[shape], s);
   }
-  if (e != hipSuccess) return fail(CTM_ERR_HIP, std::string("chain launch: ") + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    char what[160];
+    if (shape == kStreamShape)
+      std::snprintf(what, sizeof what, "streaming, %lld tasks", count);
+    else
+      std::snprintf(what, sizeof what, "shape W%dK%d, %s, %zu B of LDS, %lld tasks",
+                    kShapes[shape].W, kShapes[shape].K, mixed ? "mixed" : "FP64", smem, count);
+    return fail(CTM_ERR_HIP, std::string("chain launch (") + what + "): " + hipGetErrorString(e));
+  }
   if (P->timing) CTM_HIP(hipEventRecord(e1, s));
   P->stats.chain_launches += 1;
   return CTM_OK;

@@ -123,6 +123,25 @@ def test_streaming_other_operators(name, kw):
     assert_state_close(p, u, ref, 1e-11)
 
 
+@pytest.mark.parametrize("name,kw", [("varcoef6d", dict(d=2, n=10, nsteps=16, t1=0.01, cf=4)),
+                                     ("fp_osc2d", dict(n=12, L0=3, nsteps=16, t1=0.08))])
+def test_streaming_mixed_other_operators(name, kw):
+    # mixed plans: the on-chip grids by FP32 correction solves with FP64
+    # refinement, the streaming grids on the wide solver in FP64 with its
+    # line factors stored in FP32 (CG for the variable coefficient, BiCGStab
+    # for the drift operator); the mixed bar against the oracle
+    p = make(name, **kw)
+    p.update(prec="mixed", refine_tol=1e-12, inner_tol=1e-5, mgrit_tol=1e-11,
+             mgrit_maxit=100, coarse_tol=1e-3)
+    _say(f"streaming mixed {name} {kw}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    assert any(s["K"] == 0 for s in plan.stats()["shapes"])
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-8)
+
+
 @pytest.mark.parametrize("kw", [dict(mgrit_levels=1), dict(), dict(krylov="bicgstab"),
                                 dict(relax="F", cf=8), dict(krylov="bicgstab", mgrit_levels=1)])
 def test_streaming_wide_against_narrow(kw):
