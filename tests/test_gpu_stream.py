@@ -124,12 +124,16 @@ def test_streaming_other_operators(name, kw):
 
 
 @pytest.mark.parametrize("name,kw", [("varcoef6d", dict(d=2, n=10, nsteps=16, t1=0.01, cf=4)),
-                                     ("fp_osc2d", dict(n=12, L0=3, nsteps=16, t1=0.08))])
+                                     ("fp_osc2d", dict(n=12, L0=3, nsteps=16, t1=0.08)),
+                                     ("ou4d", dict(d=2, n=10, nsteps=16, t1=0.1)),
+                                     ("cme5d", dict(d=2, n=10, hi=[1024.0] * 2, nsteps=16,
+                                                    t1=0.1))])
 def test_streaming_mixed_other_operators(name, kw):
     # mixed plans: the on-chip grids by FP32 correction solves with FP64
-    # refinement, the streaming grids on the wide solver in FP64 with its
-    # line factors stored in FP32 (CG for the variable coefficient, BiCGStab
-    # for the drift operator); the mixed bar against the oracle
+    # refinement (their coarse MGRIT levels in FP64), the streaming grids on
+    # the wide solver in FP64 with its line factors stored in FP32 (CG for
+    # the variable coefficient, BiCGStab for the drift, OU and CME
+    # operators); the mixed bar against the oracle
     p = make(name, **kw)
     p.update(prec="mixed", refine_tol=1e-12, inner_tol=1e-5, mgrit_tol=1e-11,
              mgrit_maxit=100, coarse_tol=1e-3)
