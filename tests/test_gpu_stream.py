@@ -146,6 +146,45 @@ def test_streaming_mixed_other_operators(name, kw):
     assert_state_close(p, u, ref, 1e-8)
 
 
+@pytest.mark.parametrize("name,kw", [("heat2d", dict(nrecomb=2)),
+                                     ("heat2d", dict(mgrit_levels=3, cf=2)),
+                                     ("varcoef6d", dict(nrecomb=2)),
+                                     ("varcoef6d", dict(mgrit_levels=3, cf=2))])
+def test_streaming_mixed_recombination_and_levels(name, kw):
+    # mixed plans with streaming grids, with two recombination blocks
+    # (s = 2) or three MGRIT levels (FP64 coarse launches of every class)
+    if name == "heat2d":
+        p = _heat2d_big(prec="mixed", refine_tol=1e-12, inner_tol=1e-5, mgrit_tol=1e-11,
+                        coarse_tol=1e-3)
+    else:
+        # (three MGRIT levels by default: 32 steps keep each of two
+        # recombination blocks divisible by cf^2)
+        p = make(name, d=2, n=10, nsteps=32, t1=0.01, cf=4)
+        p.update(prec="mixed", refine_tol=1e-12, inner_tol=1e-5, mgrit_tol=1e-11,
+                 mgrit_maxit=100, coarse_tol=1e-3)
+    p.update(kw)
+    _say(f"streaming mixed {name} {kw}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-8)
+
+
+def test_streaming_mixed_plan_per_grid_propagation():
+    # the per-grid propagation of a mixed plan runs every class in FP64
+    # (the layout its size classes must also fit), streaming grids included
+    p = make("fp_osc2d", n=12, L0=3, nsteps=16, t1=0.08)
+    p.update(prec="mixed", krylov_tol=1e-13, refine_tol=1e-12, inner_tol=1e-5)
+    plan = ctm.Plan(p)
+    x = random_vectors(plan.slen, 1, seed=37)[0]
+    y = plan.propagate(torch.from_numpy(x).cuda(), 2, per_grid=True).cpu().numpy()
+    ref = np.concatenate(oracle_propagate(p, x, 2))
+    parts, rparts = split(p, y), split(p, ref)
+    for a, b in zip(parts, rparts):
+        assert rel_l2(a, b) <= 1e-11
+
+
 @pytest.mark.parametrize("kw", [dict(mgrit_levels=1), dict(), dict(krylov="bicgstab"),
                                 dict(relax="F", cf=8), dict(krylov="bicgstab", mgrit_levels=1)])
 def test_streaming_wide_against_narrow(kw):
