@@ -88,6 +88,23 @@ def test_mgrit_iterations_independent_of_dimension_and_level():
     assert max(its.values()) <= 2 * min(its.values()), its
 
 
+def test_manufactured_on_streaming_grids_mixed():
+    # the same in a mixed plan: the on-chip grids by FP32 corrections with
+    # FP64 refinement, the streaming grids in FP64 on the wide solver, the
+    # forcing added per point in both
+    p = _fp64(d=2, n=12, nsteps=8, t1=2e-3)
+    p.update(prec="mixed", refine_tol=1e-12, inner_tol=1e-5, mgrit_tol=1e-11,
+             krylov_maxit=20000, cf=2)
+    _say("manufactured on streaming grids, mixed")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    assert st["status_flags"] == 0
+    assert any(c["K"] == 0 for c in st["shapes"])
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-8)
+
+
 @pytest.mark.parametrize("wide", [1 << 20, 0])
 def test_manufactured_on_streaming_grids(wide):
     # 2-D level 12: the grids with lines of 2,047 unknowns run on the

@@ -92,6 +92,22 @@ def test_residual_mode_paper_settings_oscillator():
 
 
 @pytest.mark.parametrize("relax", ["FCF", "F"])
+def test_residual_mode_streaming_grids_mixed(relax):
+    # mixed plan: the on-chip grids by one FP32 correction solve per step,
+    # the streaming grids in FP64 (wide solver); FP64 space-time residual
+    p = make("heat2d", n=10, nsteps=32, t1=0.05)
+    p.update(RES, relax=relax, cf=4, prec="mixed", mgrit_tol=1e-11)
+    _say(f"residual mode mixed with streaming grids {relax}")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    st = plan.stats()
+    assert any(s["K"] == 0 for s in st["shapes"])
+    assert st["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-8)
+
+
+@pytest.mark.parametrize("relax", ["FCF", "F"])
 def test_residual_mode_streaming_grids(relax):
     # level 10: the grids (10, 1) and (1, 10) run on the streaming kernel
     p = make("heat2d", n=10, nsteps=32, t1=0.05)
