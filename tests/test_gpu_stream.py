@@ -343,6 +343,21 @@ def test_drift_beyond_the_solver_reports_noconv():
     assert flags & (1 << ctm.ERR_NOCONV)
 
 
+def test_lines_cut_into_segments_mixed():
+    # the level-12 case in a mixed plan: on-chip grids by FP32 corrections
+    # with FP64 refinement, the segmented streaming grids in FP64 on the
+    # wide solver (FP32 line factors)
+    p = make("heat2d", n=12, nsteps=8, t1=1e-4)
+    p.update(prec="mixed", refine_tol=1e-12, inner_tol=1e-5, mgrit_tol=1e-11,
+             mgrit_maxit=100, cf=2, krylov_maxit=20000, coarse_tol=1e-3)
+    _say("segmented lines mixed n=12")
+    plan = ctm.Plan(p)
+    u = plan.solve().cpu().numpy()
+    assert plan.stats()["status_flags"] == 0
+    ref = solve.packed(solve.component_states(p))
+    assert_state_close(p, u, ref, 1e-8)
+
+
 @pytest.mark.parametrize("n,wide", [(12, ALL), (12, 0), (13, ALL), (13, 0)])
 def test_lines_cut_into_segments(n, wide):
     # levels 12 and 13: the grids (n, 1), (n - 1, 1), ... have lines of up to
